@@ -1,0 +1,141 @@
+/*
+ * clifft.h -- C-ABI of the MI355X (gfx950) sample-many engine for
+ * near-Clifford circuits (frame-factored simulation, Chase & Labib, "Clifft").
+ *
+ * The library compiles a circuit once on the host (Section 3.1 of the paper:
+ * Clifford frame absorption by Heisenberg mapping, Definition 1 / Eq. 1;
+ * Pauli localization, Lemma 1 and Appendix A) and then samples it many times
+ * on the GPU (Section 3.2: per-shot Pauli-frame updates, sparse noise
+ * sampling, active-vector expansion / rotation / measurement, Appendix B).
+ *
+ * Conventions used by every entry point:
+ *   - Circuit text: a Stim-style subset.  Gates H S S_DAG X Y Z CX (CNOT)
+ *     CZ SWAP; rotations T = exp(-i pi/8 Z), T_DAG = exp(+i pi/8 Z),
+ *     R_Z(phi) = exp(-i phi Z / 2); M MX MR R; noise DEPOLARIZE1(p)
+ *     DEPOLARIZE2(p) X_ERROR(p) Y_ERROR(p) Z_ERROR(p); DETECTOR rec[-k]...;
+ *     OBSERVABLE_INCLUDE(i) rec[-k]...; REPEAT n { ... }; TICK and
+ *     coordinates are ignored.  At most 256 qubits, k_max <= 30.
+ *   - Records are bit-packed and record-major: for a call with `shots`
+ *     shots, words = ceil(shots / 64); bit (s % 64) of word
+ *     out[r * words + s / 64] is record r of shot s.  Bits of shots beyond
+ *     `shots` in the last word are written as zero.
+ *   - Determinism: records are a pure function of (program, seed, global
+ *     shot index = shot_offset + s); they do not depend on the launch shape,
+ *     on the split of a run into calls, or on the precision for circuits
+ *     whose active dimension stays 0.
+ *   - Errors: every function returns a clifft_status; nothing is thrown
+ *     across the ABI.  clifft_last_error() returns a message for the last
+ *     failing call of the calling thread.
+ *   - Device work is queued on `stream` (a hipStream_t, NULL for the null
+ *     stream) of the current HIP device; sampling calls return after the
+ *     launch is queued, except the trace call which synchronizes.
+ */
+#ifndef CLIFFT_H
+#define CLIFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct clifft_program clifft_program; /* opaque, owned by the library */
+
+typedef enum clifft_status {
+  CLIFFT_OK = 0,
+  CLIFFT_E_PARSE = 1,              /* malformed circuit text */
+  CLIFFT_E_UNSUPPORTED = 2,        /* instruction outside the supported subset */
+  CLIFFT_E_CAPACITY = 3,           /* too many qubits, k_max too large, buffer too small */
+  CLIFFT_E_INVALID_ARG = 4,        /* null pointer where one is required, bad option */
+  CLIFFT_E_DEVICE = 5,             /* HIP error (launch, allocation, copy) */
+  CLIFFT_E_IMPOSSIBLE_OUTCOME = 6  /* trace mode: forced outcome of probability 0 */
+} clifft_status;
+
+typedef enum clifft_precision { CLIFFT_FP32 = 0, CLIFFT_FP64 = 1 } clifft_precision;
+
+typedef struct clifft_info {
+  int32_t num_qubits;        /* N */
+  int32_t frame_words;       /* W = ceil(N / 64) */
+  int32_t k_max;             /* peak active dimension (Section 2.2) */
+  int32_t num_events;        /* measurement events incl. resets */
+  int32_t num_measurements;  /* recorded measurements */
+  int32_t num_detectors;
+  int32_t num_observables;
+  int32_t num_noise_sites;
+  int32_t num_instructions;  /* length of the compiled stream */
+  int32_t num_random_events; /* dormant random measurements (Appendix B.2) */
+  int32_t num_active_events; /* measurements on the active vector */
+} clifft_info;
+
+/* Launch configuration; zero-initialize for automatic choices. */
+typedef struct clifft_launch {
+  int32_t precision;        /* clifft_precision of the active-vector amplitudes;
+                               probability reductions and renormalization
+                               factors are FP64 in both */
+  int32_t threads_per_shot; /* 0 automatic, else 1 (shot per lane), 64 (shot per
+                               wave) or 256 (shot per workgroup) */
+  int32_t grid;             /* workgroups (256 threads); 0 = fill the device */
+  int32_t vector_in_hbm;    /* 0 automatic (HBM only when LDS is too small),
+                               1 force the global workspace, -1 force LDS */
+} clifft_launch;
+
+/* Compile circuit text (len bytes, need not be NUL-terminated) into a
+ * program.  Host only; no device work.  *out receives a handle that the
+ * caller releases with clifft_program_free.  Errors: E_PARSE,
+ * E_UNSUPPORTED, E_CAPACITY, E_INVALID_ARG (null text or out). */
+clifft_status clifft_compile(const char* text, size_t len, clifft_program** out);
+
+/* Static properties of a compiled program (Theorem 1: fixed before sampling). */
+clifft_status clifft_program_info(const clifft_program* p, clifft_info* out);
+
+/* Active dimension after each compiled instruction (k(t), Theorem 1), and
+ * the class of each measurement event (0 deterministic, 1 dormant random,
+ * 2 active).  Host arrays of capacity `cap`; *n receives the full length. */
+clifft_status clifft_k_profile(const clifft_program* p, int32_t* out, size_t cap, size_t* n);
+clifft_status clifft_event_classes(const clifft_program* p, int32_t* out, size_t cap, size_t* n);
+
+/* Virtual qubit held by each active-vector slot at the end of the program
+ * (host array of k_max entries); *k receives the final active dimension. */
+clifft_status clifft_final_slots(const clifft_program* p, int32_t* slots, int32_t* k);
+
+/* Bytes of caller-provided device workspace a sample call needs with this
+ * configuration (0 when the active vectors fit in LDS). */
+clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes);
+
+/* Sample `shots` shots with global indices shot_offset .. shot_offset+shots-1
+ * and Philox seed `seed`.  meas / det / obs are device buffers of
+ * num_measurements / num_detectors / num_observables rows of
+ * ceil(shots / 64) uint64 words (any may be NULL to skip it).  workspace is
+ * a device buffer of at least clifft_workspace_size bytes (may be NULL when
+ * that size is 0).  cfg may be NULL (automatic).  The program is uploaded to
+ * the current device on first use and kept in the handle.  The call only
+ * queues work on `stream`; launch errors are returned as E_DEVICE. */
+clifft_status clifft_sample(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                            const clifft_launch* cfg, void* workspace, size_t workspace_bytes, uint64_t* meas,
+                            uint64_t* det, uint64_t* obs, void* stream);
+
+/* Trace mode (testing): like clifft_sample, and in addition
+ *   forced_m       device [shots][num_events] uint32 outcomes to force, or NULL
+ *   forced_faults  device [shots][num_noise_sites] int32 fault outcome index
+ *                  (-1 none) replacing the noise sampler, or NULL
+ *   probs          device [shots][num_events] double, P(m = 1) of each event
+ *   phi            device [shots][2^k_max][2] double, final active vector
+ * Synchronizes `stream`; returns E_IMPOSSIBLE_OUTCOME if a forced outcome
+ * had zero probability. */
+clifft_status clifft_sample_trace(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                                  const clifft_launch* cfg, const uint32_t* forced_m, const int32_t* forced_faults,
+                                  double* probs, double* phi, void* workspace, size_t workspace_bytes,
+                                  uint64_t* meas, uint64_t* det, uint64_t* obs, void* stream);
+
+/* Release a program and its device copies. */
+void clifft_program_free(clifft_program* p);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* clifft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLIFFT_H */

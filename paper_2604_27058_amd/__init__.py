@@ -1,0 +1,163 @@
+"""MI355X (gfx950) sample-many engine for near-Clifford circuits.
+
+Thin ctypes binding over libclifft.so (declared in include/clifft.h): the
+functions keep the C names; this module only marshals arguments.  All
+compilation runs in the library's host compiler and all sampling runs in its
+HIP kernels; PyTorch only provides device memory and streams.  If the
+library is missing this module raises instead of falling back to anything.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclifft.so")
+
+CLIFFT_FP32, CLIFFT_FP64 = 0, 1
+STATUS = {0: "OK", 1: "E_PARSE", 2: "E_UNSUPPORTED", 3: "E_CAPACITY", 4: "E_INVALID_ARG", 5: "E_DEVICE",
+          6: "E_IMPOSSIBLE_OUTCOME"}
+
+
+class ClifftError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class clifft_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "num_qubits", "frame_words", "k_max", "num_events", "num_measurements", "num_detectors",
+        "num_observables", "num_noise_sites", "num_instructions", "num_random_events", "num_active_events")]
+
+
+class clifft_launch(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("threads_per_shot", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("vector_in_hbm", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libclifft.so (built in-tree by build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libclifft.so is not built (run paper_2604_27058_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, sz, i32p = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32)
+        L.clifft_compile.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(vp)]
+        L.clifft_program_info.argtypes = [vp, ctypes.POINTER(clifft_info)]
+        L.clifft_k_profile.argtypes = [vp, i32p, sz, ctypes.POINTER(sz)]
+        L.clifft_event_classes.argtypes = [vp, i32p, sz, ctypes.POINTER(sz)]
+        L.clifft_final_slots.argtypes = [vp, i32p, i32p]
+        L.clifft_workspace_size.argtypes = [vp, ctypes.POINTER(clifft_launch), ctypes.POINTER(sz)]
+        L.clifft_sample.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, sz, vp, vp, vp, vp]
+        L.clifft_sample_trace.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp, vp, sz,
+                                          vp, vp, vp, vp]
+        L.clifft_program_free.argtypes = [vp]
+        L.clifft_last_error.restype = ctypes.c_char_p
+        for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
+                  "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_trace"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise ClifftError(st, lib().clifft_last_error().decode())
+
+
+def make_launch(precision="f32", threads_per_shot=0, grid=0, vector_in_hbm=0):
+    p = CLIFFT_FP64 if precision in ("f64", CLIFFT_FP64) else CLIFFT_FP32
+    return clifft_launch(p, threads_per_shot, grid, vector_in_hbm)
+
+
+class Program:
+    """A compiled circuit (clifft_compile)."""
+
+    def __init__(self, text):
+        h = ctypes.c_void_p()
+        b = text.encode()
+        _check(lib().clifft_compile(b, len(b), ctypes.byref(h)))
+        self._h = h
+        inf = clifft_info()
+        _check(lib().clifft_program_info(h, ctypes.byref(inf)))
+        self.info = {f: getattr(inf, f) for f, _ in clifft_info._fields_}
+        for f, _ in clifft_info._fields_:
+            setattr(self, f, getattr(inf, f))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.clifft_program_free(self._h)
+            self._h = None
+
+    def _arr(self, fn):
+        n = ctypes.c_size_t()
+        _check(fn(self._h, None, 0, ctypes.byref(n)))
+        out = (ctypes.c_int32 * max(n.value, 1))()
+        _check(fn(self._h, out, n.value, ctypes.byref(n)))
+        return list(out)[: n.value]
+
+    def k_profile(self):
+        return self._arr(lib().clifft_k_profile)
+
+    def event_classes(self):
+        return self._arr(lib().clifft_event_classes)
+
+    def final_slots(self):
+        out = (ctypes.c_int32 * max(self.k_max, 1))()
+        k = ctypes.c_int32()
+        _check(lib().clifft_final_slots(self._h, out, ctypes.byref(k)))
+        return list(out)[: k.value]
+
+    def workspace_size(self, launch=None):
+        n = ctypes.c_size_t()
+        _check(lib().clifft_workspace_size(self._h, None if launch is None else ctypes.byref(launch),
+                                           ctypes.byref(n)))
+        return n.value
+
+    # ---- sampling through torch-owned device buffers
+    def alloc_outputs(self, shots, device="cuda"):
+        import torch
+        words = (shots + 63) // 64
+        mk = lambda rows: torch.empty((rows, words), dtype=torch.int64, device=device)
+        return mk(self.num_measurements), mk(self.num_detectors), mk(self.num_observables)
+
+    def alloc_workspace(self, launch=None, device="cuda"):
+        import torch
+        n = self.workspace_size(launch)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=device) if n else None
+
+    def sample(self, shots, seed=0, offset=0, launch=None, outputs=None, workspace=None, stream=None):
+        """Queue clifft_sample on the current stream; returns (meas, det, obs)
+        int64 device tensors holding the bit-packed uint64 record words."""
+        import torch
+        meas, det, obs = outputs if outputs is not None else self.alloc_outputs(shots)
+        if workspace is None:
+            workspace = self.alloc_workspace(launch)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        ptr = lambda t: t.data_ptr() if (t is not None and t.numel()) else None
+        _check(lib().clifft_sample(self._h, shots, seed, offset, None if launch is None else ctypes.byref(launch),
+                                   ptr(workspace), 0 if workspace is None else workspace.numel(), ptr(meas),
+                                   ptr(det), ptr(obs), s.cuda_stream))
+        return meas, det, obs
+
+    def sample_trace(self, shots, seed=0, offset=0, launch=None, forced_m=None, forced_faults=None):
+        """Trace mode (testing).  Returns dict of device tensors: meas, det,
+        obs, probs [shots, events], phi [shots, 2^k_max] complex128."""
+        import torch
+        meas, det, obs = self.alloc_outputs(shots)
+        probs = torch.zeros((shots, max(self.num_events, 1)), dtype=torch.float64, device="cuda")
+        phi = torch.zeros((shots, 1 << self.k_max, 2), dtype=torch.float64, device="cuda")
+        ws = self.alloc_workspace(launch)
+        fm = None if forced_m is None else forced_m.to(device="cuda", dtype=torch.int32).contiguous()
+        ff = None if forced_faults is None else forced_faults.to(device="cuda", dtype=torch.int32).contiguous()
+        ptr = lambda t: t.data_ptr() if (t is not None and t.numel()) else None
+        s = torch.cuda.current_stream()
+        _check(lib().clifft_sample_trace(self._h, shots, seed, offset,
+                                         None if launch is None else ctypes.byref(launch), ptr(fm), ptr(ff),
+                                         ptr(probs), ptr(phi), ptr(ws), 0 if ws is None else ws.numel(),
+                                         ptr(meas), ptr(det), ptr(obs), s.cuda_stream))
+        return dict(meas=meas, det=det, obs=obs, probs=probs[:, : self.num_events],
+                    phi=torch.view_as_complex(phi))

@@ -1,0 +1,51 @@
+"""Build libclifft.so (HIP kernels for gfx950 + host compiler + C-ABI runtime) in-tree."""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libclifft.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-result",
+          "-I" + os.path.join(os.path.dirname(HERE), "include")]
+# Packed FP32 VALU ops stay disabled in device code on this target.
+DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+SOURCES = [("kernels.hip", True), ("runtime.cpp", True), ("compiler.cpp", False)]
+
+
+def _obj(name):
+    return os.path.join(HERE, "_build", name + ".o")
+
+
+def _compile(item):
+    name, hip = item
+    src = os.path.join(CSRC, name)
+    cmd = [HIPCC] + COMMON + (DEVICE + ["-x", "hip"] if name.endswith(".hip") else []) + ["-c", src, "-o", _obj(name)]
+    if not hip:
+        cmd = ["g++"] + COMMON + ["-c", src, "-o", _obj(name)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    return r.stderr
+
+
+def build(verbose=False):
+    os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    with ThreadPoolExecutor(max_workers=3) as ex:
+        logs = list(ex.map(_compile, SOURCES))
+    if verbose:
+        for l in logs:
+            if l.strip():
+                print(l, file=sys.stderr)
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + [_obj(n) for n, _ in SOURCES]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,630 @@
+// Host-side compiler: circuit text -> flat wave-uniform instruction stream.
+//
+// Follows the paper's compile-once pipeline (Section 3.1): physical Clifford
+// gates are absorbed into the Clifford frame U_C (Definition 1, Eq. 1); each
+// active operation's generator is mapped to the virtual basis and localized
+// to one virtual qubit (Lemma 1, Appendix A) with sequences that respect
+// dormant invariance (Lemma 2); the result is classified into the update
+// cases of Appendix B.  Because of Theorem 1 all of this is shot independent,
+// so the GPU only runs the resulting stream.
+//
+// Differences from a gate-by-gate lowering: the fan of CNOTs (or CZs) that
+// shares one pivot is emitted as one frame instruction acting on W 64-bit
+// words, and its array part (if any) as one pass; expansion and the first
+// rotation on the new axis are one instruction (the paper's fused
+// expand+rotation); consecutive noise sites form one block (the paper's
+// noise coalescing); a demoted slot is refilled by the top slot instead of
+// shifting all slots above it down.
+#include "compiler.h"
+
+#include <cctype>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace clifft {
+
+namespace {
+
+// ---------------------------------------------------------------- parsing
+enum PK { K_H, K_S, K_SDAG, K_X, K_Y, K_Z, K_CX, K_CZ, K_SWAP, K_ROTZ, K_M, K_MX, K_MR, K_R, K_NOISE, K_DET, K_OBS };
+
+struct PhysOp {
+  int kind;
+  int a, b;
+  double arg;  // rotation angle theta of exp(-i theta Z), or probability
+  int ntype;
+  int obs;
+  std::vector<int> refs;  // absolute record indices
+};
+
+struct Parsed {
+  std::vector<PhysOp> ops;
+  int nq = 0;
+  int nrec = 0;
+  int ndet = 0;
+  int nobs = 0;
+};
+
+struct Lines {
+  std::vector<std::string> v;
+  std::vector<int> lineno;
+};
+
+static std::string strip(const std::string& s) {
+  size_t a = 0, b = s.size();
+  while (a < b && isspace((unsigned char)s[a])) a++;
+  while (b > a && isspace((unsigned char)s[b - 1])) b--;
+  return s.substr(a, b - a);
+}
+
+static bool parse_range(const Lines& L, size_t& i, Parsed& P, int depth, std::string& err, int& code);
+
+static bool fail(std::string& err, int& code, int c, int line, const std::string& msg) {
+  char buf[64];
+  snprintf(buf, sizeof buf, "line %d: ", line);
+  err = buf + msg;
+  code = c;
+  return false;
+}
+
+static bool parse_line(const std::string& raw, int line, Parsed& P, std::string& err, int& code) {
+  size_t i = 0;
+  std::string name;
+  while (i < raw.size() && !isspace((unsigned char)raw[i]) && raw[i] != '(') name += (char)toupper((unsigned char)raw[i++]);
+  while (i < raw.size() && isspace((unsigned char)raw[i])) i++;
+  double arg = 0;
+  bool has_arg = false;
+  if (i < raw.size() && raw[i] == '(') {
+    size_t e = raw.find(')', i);
+    if (e == std::string::npos) return fail(err, code, 1, line, "missing ')'");
+    arg = strtod(raw.c_str() + i + 1, nullptr);
+    has_arg = true;
+    i = e + 1;
+  }
+  std::vector<long> tg;
+  std::vector<bool> isrec;
+  while (i < raw.size()) {
+    while (i < raw.size() && isspace((unsigned char)raw[i])) i++;
+    if (i >= raw.size()) break;
+    size_t j = i;
+    while (j < raw.size() && !isspace((unsigned char)raw[j])) j++;
+    std::string t = raw.substr(i, j - i);
+    i = j;
+    if (t.compare(0, 4, "rec[") == 0) {
+      tg.push_back(strtol(t.c_str() + 4, nullptr, 10));
+      isrec.push_back(true);
+    } else {
+      char* end = nullptr;
+      long v = strtol(t.c_str(), &end, 10);
+      if (end == t.c_str() || *end || v < 0 || v >= 65535) return fail(err, code, 1, line, "bad target '" + t + "'");
+      tg.push_back(v);
+      isrec.push_back(false);
+      if (v + 1 > P.nq) P.nq = (int)v + 1;
+    }
+  }
+  if (name == "TICK" || name == "QUBIT_COORDS" || name == "SHIFT_COORDS") return true;
+  struct G { const char* nm; int kind, arity; };
+  static const G gates[] = {{"H", K_H, 1},    {"S", K_S, 1},     {"S_DAG", K_SDAG, 1}, {"X", K_X, 1},   {"Y", K_Y, 1},
+                            {"Z", K_Z, 1},    {"CX", K_CX, 2},   {"CNOT", K_CX, 2},    {"ZCX", K_CX, 2}, {"CZ", K_CZ, 2},
+                            {"SWAP", K_SWAP, 2}, {"M", K_M, 1},  {"MZ", K_M, 1},       {"MX", K_MX, 1}, {"MR", K_MR, 1},
+                            {"MRZ", K_MR, 1}, {"R", K_R, 1},     {"RZ", K_R, 1}};
+  for (const G& g : gates) {
+    if (name != g.nm) continue;
+    if (tg.size() % g.arity) return fail(err, code, 1, line, name + " needs target pairs");
+    for (size_t t = 0; t < tg.size(); t += g.arity) {
+      if (isrec[t]) return fail(err, code, 1, line, "record target on a gate");
+      PhysOp o{};
+      o.kind = g.kind;
+      o.a = (int)tg[t];
+      o.b = g.arity == 2 ? (int)tg[t + 1] : -1;
+      if (o.a == o.b) return fail(err, code, 1, line, "repeated qubit");
+      P.ops.push_back(o);
+      if (g.kind == K_M || g.kind == K_MX || g.kind == K_MR) P.nrec++;
+    }
+    return true;
+  }
+  if (name == "T" || name == "T_DAG" || name == "R_Z") {
+    double th;
+    if (name == "T") th = M_PI / 8;
+    else if (name == "T_DAG") th = -M_PI / 8;
+    else {
+      if (!has_arg) return fail(err, code, 1, line, "R_Z needs an angle");
+      th = arg / 2;  // R_Z(phi) = exp(-i phi Z / 2)
+    }
+    for (long t : tg) {
+      PhysOp o{};
+      o.kind = K_ROTZ;
+      o.a = (int)t;
+      o.b = -1;
+      o.arg = th;
+      P.ops.push_back(o);
+    }
+    return true;
+  }
+  struct N { const char* nm; int type, arity; };
+  static const N noises[] = {{"DEPOLARIZE1", S_DEP1, 1}, {"DEPOLARIZE2", S_DEP2, 2}, {"X_ERROR", S_XERR, 1},
+                             {"Y_ERROR", S_YERR, 1},     {"Z_ERROR", S_ZERR, 1}};
+  for (const N& nn : noises) {
+    if (name != nn.nm) continue;
+    if (!has_arg || !(arg >= 0 && arg <= 1)) return fail(err, code, 1, line, "bad probability");
+    if (tg.size() % nn.arity) return fail(err, code, 1, line, "noise needs target pairs");
+    if (arg == 0) return true;
+    for (size_t t = 0; t < tg.size(); t += nn.arity) {
+      PhysOp o{};
+      o.kind = K_NOISE;
+      o.ntype = nn.type;
+      o.a = (int)tg[t];
+      o.b = nn.arity == 2 ? (int)tg[t + 1] : -1;
+      o.arg = arg;
+      if (o.a == o.b) return fail(err, code, 1, line, "repeated qubit");
+      P.ops.push_back(o);
+    }
+    return true;
+  }
+  if (name == "DETECTOR" || name == "OBSERVABLE_INCLUDE") {
+    PhysOp o{};
+    o.kind = name == "DETECTOR" ? K_DET : K_OBS;
+    o.obs = (int)arg;
+    for (size_t t = 0; t < tg.size(); t++) {
+      if (!isrec[t] || tg[t] >= 0 || P.nrec + tg[t] < 0) return fail(err, code, 1, line, "bad record target");
+      o.refs.push_back((int)(P.nrec + tg[t]));
+    }
+    if (o.kind == K_DET) P.ndet++;
+    else if (o.obs + 1 > P.nobs) P.nobs = o.obs + 1;
+    P.ops.push_back(o);
+    return true;
+  }
+  return fail(err, code, 2, line, "unsupported instruction '" + name + "'");
+}
+
+static bool parse_range(const Lines& L, size_t& i, Parsed& P, int depth, std::string& err, int& code) {
+  while (i < L.v.size()) {
+    const std::string& s = L.v[i];
+    int line = L.lineno[i];
+    if (s == "}") {
+      if (depth == 0) return fail(err, code, 1, line, "unmatched '}'");
+      i++;
+      return true;
+    }
+    std::string up;
+    for (char c : s.substr(0, 6)) up += (char)toupper((unsigned char)c);
+    if (up == "REPEAT") {
+      char* end = nullptr;
+      long n = strtol(s.c_str() + 6, &end, 10);
+      std::string rest = strip(end ? end : "");
+      if (rest != "{" || n < 0) return fail(err, code, 1, line, "bad REPEAT");
+      size_t start = i + 1;
+      size_t after = start;
+      if (n == 0) {
+        Parsed dummy;
+        size_t j = start;
+        if (!parse_range(L, j, dummy, depth + 1, err, code)) return false;
+        after = j;
+      }
+      for (long r = 0; r < n; r++) {
+        size_t j = start;
+        if (!parse_range(L, j, P, depth + 1, err, code)) return false;
+        after = j;
+      }
+      i = after;
+      continue;
+    }
+    if (!parse_line(s, line, P, err, code)) return false;
+    i++;
+  }
+  if (depth > 0) return fail(err, code, 1, (int)L.v.size(), "missing '}'");
+  return true;
+}
+
+// ---------------------------------------------------------------- Paulis on W words
+struct Pauli {
+  std::vector<uint64_t> x, z;
+  int r = 0;  // sign bit; letters sigma(1,0)=X sigma(0,1)=Z sigma(1,1)=Y
+  Pauli() {}
+  explicit Pauli(int W) : x(W, 0), z(W, 0) {}
+  bool getx(int q) const { return (x[q >> 6] >> (q & 63)) & 1; }
+  bool getz(int q) const { return (z[q >> 6] >> (q & 63)) & 1; }
+  void flipx(int q) { x[q >> 6] ^= 1ull << (q & 63); }
+  void flipz(int q) { z[q >> 6] ^= 1ull << (q & 63); }
+  void setx(int q, bool v) { if (getx(q) != v) flipx(q); }
+  void setz(int q, bool v) { if (getz(q) != v) flipz(q); }
+};
+
+// a <- i^extra * a * b for Hermitian Paulis whose product (times i^extra) is
+// Hermitian; the power of i is computed word-parallel: with the cyclic order
+// X -> Y -> Z, a "forward" pair contributes +1 and a "backward" pair -1.
+static void mul_into(Pauli& a, const Pauli& b, int extra) {
+  int e = extra + 2 * a.r + 2 * b.r;
+  for (size_t w = 0; w < a.x.size(); w++) {
+    uint64_t X1 = a.x[w] & ~a.z[w], Y1 = a.x[w] & a.z[w], Z1 = ~a.x[w] & a.z[w];
+    uint64_t X2 = b.x[w] & ~b.z[w], Y2 = b.x[w] & b.z[w], Z2 = ~b.x[w] & b.z[w];
+    uint64_t fwd = (X1 & Y2) | (Y1 & Z2) | (Z1 & X2);
+    uint64_t bwd = (X1 & Z2) | (Y1 & X2) | (Z1 & Y2);
+    e += __builtin_popcountll(fwd) - __builtin_popcountll(bwd);
+    a.x[w] ^= b.x[w];
+    a.z[w] ^= b.z[w];
+  }
+  e = ((e % 4) + 4) % 4;
+  if (e & 1) abort();  // product is not Hermitian: caller error
+  a.r = e >> 1;
+}
+
+// Conjugation P -> G P G^dagger by the virtual gates of the localization
+// sequences (Aaronson-Gottesman update rules).
+static void cj_cx(Pauli& p, int c, int t) {
+  int xc = p.getx(c), zc = p.getz(c), xt = p.getx(t), zt = p.getz(t);
+  p.r ^= xc & zt & (xt ^ zc ^ 1);
+  p.setx(t, xt ^ xc);
+  p.setz(c, zc ^ zt);
+}
+static void cj_cz(Pauli& p, int a, int b) {
+  int xa = p.getx(a), za = p.getz(a), xb = p.getx(b), zb = p.getz(b);
+  p.r ^= xa & xb & (za ^ zb);
+  p.setz(a, za ^ xb);
+  p.setz(b, zb ^ xa);
+}
+static void cj_s(Pauli& p, int a) {
+  int xa = p.getx(a), za = p.getz(a);
+  p.r ^= xa & za;
+  p.setz(a, za ^ xa);
+}
+static void cj_h(Pauli& p, int a) {
+  int xa = p.getx(a), za = p.getz(a);
+  p.r ^= xa & za;
+  p.setx(a, za);
+  p.setz(a, xa);
+}
+
+enum VG { V_CX, V_CZ, V_S, V_H };
+
+// ---------------------------------------------------------------- compiler state
+struct Compiler {
+  int n, W;
+  std::vector<Pauli> ix, iz;  // U_C^dagger X_q U_C, U_C^dagger Z_q U_C
+  std::vector<int> slot_of;   // virtual qubit -> slot or -1
+  std::vector<int> q_at;      // slot -> virtual qubit
+  int k = 0;
+  CompiledProgram* out;
+
+  Compiler(int n_, CompiledProgram* o) : n(n_), W((n_ + 63) / 64), out(o) {
+    ix.assign(n, Pauli(W));
+    iz.assign(n, Pauli(W));
+    for (int q = 0; q < n; q++) {
+      ix[q].flipx(q);
+      iz[q].flipz(q);
+    }
+    slot_of.assign(n, -1);
+  }
+  bool active(int q) const { return slot_of[q] >= 0; }
+
+  Pauli image(int q, char letter) const {
+    if (letter == 'X') return ix[q];
+    if (letter == 'Z') return iz[q];
+    Pauli y = ix[q];
+    mul_into(y, iz[q], 1);  // Y = i X Z
+    return y;
+  }
+
+  // U_C <- G U_C (Definition 1 on the new frame): images of G^dagger P G.
+  void phys(int kind, int a, int b) {
+    switch (kind) {
+      case K_H: std::swap(ix[a], iz[a]); break;
+      case K_S: { Pauli y = image(a, 'Y'); y.r ^= 1; ix[a] = y; break; }  // S^dag X S = -Y
+      case K_SDAG: ix[a] = image(a, 'Y'); break;                          // S X S^dag = Y
+      case K_X: iz[a].r ^= 1; break;
+      case K_Z: ix[a].r ^= 1; break;
+      case K_Y: ix[a].r ^= 1; iz[a].r ^= 1; break;
+      case K_CX: mul_into(ix[a], ix[b], 0); mul_into(iz[b], iz[a], 0); break;
+      case K_CZ: mul_into(ix[a], iz[b], 0); mul_into(ix[b], iz[a], 0); break;
+      case K_SWAP: std::swap(ix[a], ix[b]); std::swap(iz[a], iz[b]); break;
+    }
+  }
+
+  // U_C <- U_C V^dagger: every image becomes V P~ V^dagger.
+  void virt(int g, int a, int b) {
+    for (int q = 0; q < n; q++)
+      for (Pauli* p : {&ix[q], &iz[q]}) {
+        if (g == V_CX) cj_cx(*p, a, b);
+        else if (g == V_CZ) cj_cz(*p, a, b);
+        else if (g == V_S) cj_s(*p, a);
+        else cj_h(*p, a);
+      }
+  }
+
+  uint32_t push_mask(const std::vector<uint64_t>& w) {
+    uint32_t off = (uint32_t)out->masks.size();
+    out->masks.insert(out->masks.end(), w.begin(), w.end());
+    return off;
+  }
+  uint32_t push_pauli(const Pauli& p) {
+    uint32_t off = push_mask(p.x);
+    push_mask(p.z);
+    return off;
+  }
+  uint32_t push_angle(double theta) {
+    uint32_t idx = (uint32_t)(out->consts.size() / 2);
+    out->consts.push_back(cos(2 * theta));
+    out->consts.push_back(sin(2 * theta));
+    return idx;
+  }
+  void emit(uint8_t op, uint8_t flags, int v, int s, uint32_t a, uint32_t b, int u = 0) {
+    GInstr in{};
+    in.op = op;
+    in.flags = flags;
+    in.v = (uint16_t)(v < 0 ? 0 : v);
+    in.s = (uint16_t)(s < 0 ? 0 : s);
+    in.u = (uint16_t)u;
+    in.a = a;
+    in.b = b;
+    out->code.push_back(in);
+    out->k_after.push_back(k);
+    if (k > out->kmax) out->kmax = k;
+  }
+  uint32_t slot_mask(const std::vector<int>& qs) const {
+    uint32_t m = 0;
+    for (int q : qs)
+      if (active(q)) m |= 1u << slot_of[q];
+    return m;
+  }
+
+  // Lemma 1 / Appendix A, case 1: pivot v with x_v = 1.  CNOT v->q fan over
+  // the rest of x, CZ v,q fan over the remaining z, S_v if a Y is left.
+  void localize_case1(Pauli& g, int v) {
+    std::vector<int> qs;
+    std::vector<uint64_t> m(W, 0);
+    for (int q = 0; q < n; q++)
+      if (q != v && g.getx(q)) { qs.push_back(q); m[q >> 6] |= 1ull << (q & 63); }
+    if (!qs.empty()) {
+      for (int q : qs) { cj_cx(g, v, q); virt(V_CX, v, q); }
+      emit(OP_FANCX, 0, v, 0, push_mask(m), 0);
+      if (active(v)) emit(OP_APERM, 0, v, slot_of[v], slot_mask(qs), 0);  // all of qs are active here
+    }
+    qs.clear();
+    m.assign(W, 0);
+    for (int q = 0; q < n; q++)
+      if (q != v && g.getz(q)) { qs.push_back(q); m[q >> 6] |= 1ull << (q & 63); }
+    if (!qs.empty()) {
+      for (int q : qs) { cj_cz(g, v, q); virt(V_CZ, v, q); }
+      emit(OP_FANCZ, 0, v, 0, push_mask(m), 0);
+      uint32_t sm = slot_mask(qs);
+      if (active(v) && sm) emit(OP_ASIGN, 0, v, slot_of[v], sm, 0);
+    }
+    if (g.getz(v)) {
+      cj_s(g, v);
+      virt(V_S, v, -1);
+      emit(OP_FS, 0, v, 0, 0, 0);
+      if (active(v)) emit(OP_AS, 0, v, slot_of[v], 0, 0);
+    }
+  }
+
+  // Lemma 1 / Appendix A, case 2: x = 0, pivot v with z_v = 1; CNOT q->v.
+  void localize_case2(Pauli& g, int v) {
+    std::vector<int> qs;
+    std::vector<uint64_t> m(W, 0);
+    for (int q = 0; q < n; q++)
+      if (q != v && g.getz(q)) { qs.push_back(q); m[q >> 6] |= 1ull << (q & 63); }
+    if (qs.empty()) return;
+    for (int q : qs) { cj_cx(g, q, v); virt(V_CX, q, v); }
+    emit(OP_FAN2, 0, v, 0, push_mask(m), 0);
+    uint32_t sm = slot_mask(qs);
+    if (sm) emit(OP_APERM2, 0, v, slot_of[v], sm, 0);
+  }
+
+  int lowest(const std::vector<uint64_t>& bits, bool want_active) const {
+    for (int q = 0; q < n; q++)
+      if (((bits[q >> 6] >> (q & 63)) & 1) && active(q) == want_active) return q;
+    return -1;
+  }
+  static bool nonzero(const std::vector<uint64_t>& b) {
+    for (uint64_t w : b)
+      if (w) return true;
+    return false;
+  }
+
+  // Appendix B.1: rotation exp(-i theta Z_q).
+  void rotation(int q, double theta) {
+    Pauli g = iz[q];
+    int vd = lowest(g.x, false);
+    int va = lowest(g.x, true);
+    if (vd >= 0) {
+      localize_case1(g, vd);  // -> +-X_v, v dormant
+      cj_h(g, vd);            // H_v promotes v: |0> -> |+>
+      virt(V_H, vd, -1);
+      int s = k;
+      slot_of[vd] = s;
+      q_at.push_back(vd);
+      k++;
+      emit(OP_EXPAND, 0, vd, s, push_angle(g.r ? -theta : theta), 0);
+    } else if (va >= 0) {
+      localize_case1(g, va);  // -> +-X_v, v active
+      cj_h(g, va);
+      virt(V_H, va, -1);
+      emit(OP_FH, 0, va, 0, 0, 0);
+      emit(OP_AH, 0, va, slot_of[va], 0, 0);
+      emit(OP_AROT, 0, va, slot_of[va], push_angle(g.r ? -theta : theta), 0);
+    } else {
+      int vz = lowest(g.z, true);
+      if (vz >= 0) {
+        localize_case2(g, vz);
+        emit(OP_AROT, 0, vz, slot_of[vz], push_angle(g.r ? -theta : theta), 0);
+      }
+      // otherwise: a scalar phase on gamma only (global phase, not tracked on the GPU)
+    }
+  }
+
+  void demote(int v) {
+    int s = slot_of[v];
+    int top = k - 1;
+    if (s != top) {
+      int qt = q_at[top];
+      q_at[s] = qt;
+      slot_of[qt] = s;
+    }
+    q_at.pop_back();
+    slot_of[v] = -1;
+    k--;
+  }
+
+  // Appendix B.2: measurement of `letter` on physical qubit q.
+  int measure(int q, char letter, int rec) {
+    Pauli g = image(q, letter);
+    int j = out->nevents++;
+    out->ev_rec.push_back(rec);
+    bool anyx = nonzero(g.x);
+    int xd = lowest(g.x, false);
+    if (!anyx && lowest(g.z, true) < 0) {
+      out->ev_class.push_back(0);
+      emit(OP_MSTATIC, g.r ? F_SIGN : 0, 0, 0, push_mask(g.z), (uint32_t)j);
+    } else if (xd >= 0) {
+      localize_case1(g, xd);
+      virt(V_H, xd, -1);  // H_v absorbed after the outcome
+      out->ev_class.push_back(1);
+      emit(OP_MRANDOM, g.r ? F_SIGN : 0, xd, 0, 0, (uint32_t)j);
+    } else {
+      int v;
+      uint8_t op;
+      if (anyx) {
+        v = lowest(g.x, true);
+        localize_case1(g, v);
+        virt(V_H, v, -1);
+        op = OP_MACTX;
+      } else {
+        v = lowest(g.z, true);
+        localize_case2(g, v);
+        op = OP_MACTZ;
+      }
+      int s = slot_of[v];
+      out->ev_class.push_back(2);
+      demote(v);
+      emit(op, g.r ? F_SIGN : 0, v, s, 0, (uint32_t)j);
+    }
+    return j;
+  }
+
+  void reset_fix(int q, int j) {
+    Pauli xq = image(q, 'X');
+    emit(OP_CPAULI, 0, 0, 0, push_pauli(xq), (uint32_t)j);
+  }
+
+  void noise(const PhysOp& o) {
+    uint32_t site = (uint32_t)out->site_type.size();
+    out->site_type.push_back((uint8_t)o.ntype);
+    out->site_p.push_back(o.arg);
+    out->site_img.push_back((uint32_t)out->masks.size());
+    push_pauli(ix[o.a]);
+    push_pauli(iz[o.a]);
+    if (o.ntype == S_DEP2) {
+      push_pauli(ix[o.b]);
+      push_pauli(iz[o.b]);
+    }
+    if (!out->code.empty() && out->code.back().op == OP_NOISE && out->code.back().b == site) {
+      out->code.back().b = site + 1;  // extend the current block
+    } else {
+      emit(OP_NOISE, 0, 0, 0, site, site + 1);
+    }
+  }
+};
+
+}  // namespace
+
+// Survival products of the cumulative hazard (Section 3.2) per chunk:
+// S[0] = 1, S[i+1] = S[i] * (1 - p_i) in FP64 with no contraction.
+static void survival_tables(CompiledProgram& P) {
+  int ns = (int)P.site_p.size();
+  P.nchunks = (ns + kChunk - 1) / kChunk;
+  P.surv.assign((size_t)P.nchunks * (kChunk + 1), 0.0);
+  for (int c = 0; c < P.nchunks; c++) {
+    volatile double s = 1.0;
+    double* S = &P.surv[(size_t)c * (kChunk + 1)];
+    S[0] = s;
+    int lo = c * kChunk, hi = std::min(ns, lo + kChunk);
+    for (int i = lo; i < hi; i++) {
+      volatile double q = 1.0 - P.site_p[i];
+      s = s * q;
+      S[i - lo + 1] = s;
+    }
+    for (int i = hi - lo + 1; i <= kChunk; i++) S[i] = 0.0;  // beyond the chunk: never fires
+  }
+}
+
+int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& err) {
+  Lines L;
+  {
+    std::string all(text, len);
+    size_t pos = 0;
+    int line = 0;
+    while (pos <= all.size()) {
+      size_t e = all.find('\n', pos);
+      if (e == std::string::npos) e = all.size();
+      std::string s = all.substr(pos, e - pos);
+      line++;
+      size_t h = s.find('#');
+      if (h != std::string::npos) s = s.substr(0, h);
+      s = strip(s);
+      if (!s.empty()) {
+        L.v.push_back(s);
+        L.lineno.push_back(line);
+      }
+      if (e == all.size()) break;
+      pos = e + 1;
+    }
+  }
+  Parsed ps;
+  size_t i = 0;
+  int code = 0;
+  if (!parse_range(L, i, ps, 0, err, code)) return code;
+  int n = ps.nq > 0 ? ps.nq : 1;
+  if (n > 64 * kMaxWords) {
+    err = "more than 256 qubits";
+    return 3;
+  }
+  P = CompiledProgram();
+  P.nq = n;
+  P.W = (n + 63) / 64;
+  Compiler C(n, &P);
+  int rec = 0;
+  for (const PhysOp& o : ps.ops) {
+    switch (o.kind) {
+      case K_H: case K_S: case K_SDAG: case K_X: case K_Y: case K_Z: case K_CX: case K_CZ: case K_SWAP:
+        C.phys(o.kind, o.a, o.b);
+        break;
+      case K_ROTZ: C.rotation(o.a, o.arg); break;
+      case K_M: C.measure(o.a, 'Z', rec++); break;
+      case K_MX: C.measure(o.a, 'X', rec++); break;
+      case K_MR: { int j = C.measure(o.a, 'Z', rec++); C.reset_fix(o.a, j); break; }
+      case K_R: { int j = C.measure(o.a, 'Z', -1); C.reset_fix(o.a, j); break; }
+      case K_NOISE: C.noise(o); break;
+      case K_DET:
+      case K_OBS: {
+        uint32_t off = (uint32_t)P.refs.size();
+        for (int r : o.refs) P.refs.push_back((uint32_t)r);
+        if (o.refs.size() > 65535) { err = "too many detector references"; return 3; }
+        uint32_t idx = o.kind == K_DET ? (uint32_t)P.ndet++ : (uint32_t)o.obs;
+        C.emit(o.kind == K_DET ? OP_DET : OP_OBS, 0, 0, 0, off, idx, (int)o.refs.size());
+        break;
+      }
+    }
+    if (P.kmax > kMaxK) {
+      err = "active dimension exceeds the format limit";
+      return 3;
+    }
+  }
+  C.emit(OP_END, 0, 0, 0, 0, 0);
+  P.nrec = rec;
+  P.nobs = ps.nobs;
+  P.final_slots = C.q_at;
+  survival_tables(P);
+  if (P.masks.empty()) P.masks.push_back(0);
+  if (P.consts.empty()) { P.consts.push_back(1.0); P.consts.push_back(0.0); }
+  if (P.refs.empty()) P.refs.push_back(0);
+  if (P.ev_rec.empty()) P.ev_rec.push_back(-1);
+  if (P.site_type.empty()) { P.site_type.push_back(0); P.site_img.push_back(0); }
+  if (P.surv.empty()) P.surv.assign(kChunk + 1, 0.0);
+  return 0;
+}
+
+}  // namespace clifft

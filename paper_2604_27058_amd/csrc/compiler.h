@@ -1,0 +1,32 @@
+// Host compiler interface (circuit text -> CompiledProgram).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "program.h"
+
+namespace clifft {
+
+struct CompiledProgram {
+  int nq = 0, W = 1, kmax = 0;
+  int nevents = 0, nrec = 0, ndet = 0, nobs = 0, nchunks = 0;
+  std::vector<GInstr> code;
+  std::vector<int> k_after;        // active dimension after each instruction
+  std::vector<uint64_t> masks;     // W-word masks and 2W-word Pauli images
+  std::vector<double> consts;      // (cos 2theta, sin 2theta) pairs
+  std::vector<uint32_t> refs;      // detector / observable record references
+  std::vector<int32_t> ev_rec;     // event -> record index or -1
+  std::vector<int> ev_class;       // event -> 0 deterministic, 1 dormant random, 2 active
+  std::vector<uint8_t> site_type;  // per noise site
+  std::vector<double> site_p;      // per noise site probability
+  std::vector<uint32_t> site_img;  // per site offset of its images in masks
+  std::vector<double> surv;        // nchunks x (kChunk + 1) survival products
+  std::vector<int> final_slots;    // virtual qubit held by each slot at the end
+};
+
+// Returns 0 on success, 1 parse error, 2 unsupported instruction, 3 capacity.
+int compile_text(const char* text, size_t len, CompiledProgram& out, std::string& err);
+
+}  // namespace clifft

@@ -1,0 +1,789 @@
+// HIP kernels for gfx950: persistent shot-parallel interpreter of the
+// compiled instruction stream (the paper's sample-time virtual machine,
+// Section 3.2), re-designed for CDNA4.
+//
+// Execution shapes (template G = threads per shot):
+//   G = 1    shot per lane: 64 shots per wave; Pauli frames live in VGPRs as
+//            W 64-bit words per lane; the active vector of each lane lives in
+//            LDS, interleaved so that amplitude i of the 64 lanes is one
+//            contiguous 512-byte row (conflict-free).
+//   G = 64   shot per wave: the frames are wave-uniform (SGPR/SALU); the 2^k
+//            amplitudes are spread over the lanes (LDS).
+//   G = 256  shot per workgroup: as G = 64 with workgroup barriers between
+//            array passes; the active vector is in LDS or in a global
+//            workspace slice (HBM) for large k.
+// Records are bit-packed 64 shots per word (record-major) and staged in LDS
+// per 64-shot tile.
+//
+// Paper passages: Definition 2 (frame-factored state), Appendix B.1
+// (rotations: phase / expansion / active), Appendix B.2 (measurements:
+// dormant deterministic, dormant random, active mask / interfere),
+// Appendix B.3 (conditional Paulis: noise and feed-forward), Section 3.2
+// (sparse noise sampling by jumping to the next fault).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "program.h"
+
+namespace clifft {
+
+#define DEV static __device__ __forceinline__
+#define MDEV __device__ __forceinline__
+
+// ------------------------------------------------------------------ RNG
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11); one mulhi/mullo pair per
+// multiplier per round.
+struct U4 { uint32_t w0, w1, w2, w3; };
+
+DEV U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+DEV U4 draw(uint32_t index, uint32_t purpose, uint64_t shot, uint64_t seed) {
+  return philox(index, purpose, (uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+DEV double uniform53(const U4& w) {
+  uint64_t v = ((uint64_t)w.w1 << 32) | w.w0;
+  return (double)(v >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------------------ helpers
+template <typename R> struct cpx { R re, im; };
+
+DEV uint32_t ins0(uint32_t p, int s) { return ((p >> s) << (s + 1)) | (p & ((1u << s) - 1u)); }
+
+template <int W>
+struct Frame {
+  uint64_t x[W], z[W];
+};
+
+template <int W>
+DEV uint32_t getbit(const uint64_t (&a)[W], int q) {
+  uint64_t v = a[0];
+#pragma unroll
+  for (int w = 1; w < W; w++)
+    if ((q >> 6) == w) v = a[w];
+  return (uint32_t)(v >> (q & 63)) & 1u;
+}
+
+template <int W>
+DEV void xorbit(uint64_t (&a)[W], int q, uint32_t b) {
+#pragma unroll
+  for (int w = 0; w < W; w++)
+    if ((q >> 6) == w) a[w] ^= (uint64_t)b << (q & 63);
+}
+
+template <int W>
+DEV uint32_t parity_and(const uint64_t (&a)[W], const uint64_t* m) {
+  uint64_t acc = 0;
+#pragma unroll
+  for (int w = 0; w < W; w++) acc ^= a[w] & m[w];
+  return (uint32_t)__popcll(acc) & 1u;
+}
+
+// Fan of CNOT v->q (q in mask): x ^= x_v * mask, z_v ^= parity(z & mask).
+template <int W>
+DEV void fan_cx(Frame<W>& f, int v, const uint64_t* m) {
+  uint64_t sel = 0ull - (uint64_t)getbit<W>(f.x, v);
+  uint32_t pz = parity_and<W>(f.z, m);
+#pragma unroll
+  for (int w = 0; w < W; w++) f.x[w] ^= sel & m[w];
+  xorbit<W>(f.z, v, pz);
+}
+// Fan of CZ v,q: z ^= x_v * mask, z_v ^= parity(x & mask).
+template <int W>
+DEV void fan_cz(Frame<W>& f, int v, const uint64_t* m) {
+  uint64_t sel = 0ull - (uint64_t)getbit<W>(f.x, v);
+  uint32_t px = parity_and<W>(f.x, m);
+#pragma unroll
+  for (int w = 0; w < W; w++) f.z[w] ^= sel & m[w];
+  xorbit<W>(f.z, v, px);
+}
+// Fan of CNOT q->v: x_v ^= parity(x & mask), z ^= z_v * mask.
+template <int W>
+DEV void fan_2(Frame<W>& f, int v, const uint64_t* m) {
+  uint64_t sel = 0ull - (uint64_t)getbit<W>(f.z, v);
+  uint32_t px = parity_and<W>(f.x, m);
+#pragma unroll
+  for (int w = 0; w < W; w++) f.z[w] ^= sel & m[w];
+  xorbit<W>(f.x, v, px);
+}
+template <int W>
+DEV void frame_s(Frame<W>& f, int v) { xorbit<W>(f.z, v, getbit<W>(f.x, v)); }
+template <int W>
+DEV void frame_h(Frame<W>& f, int v) {
+  uint32_t d = getbit<W>(f.x, v) ^ getbit<W>(f.z, v);
+  xorbit<W>(f.x, v, d);
+  xorbit<W>(f.z, v, d);
+}
+template <int W>
+DEV void frame_xor(Frame<W>& f, const uint64_t* px, const uint64_t* pz) {
+#pragma unroll
+  for (int w = 0; w < W; w++) { f.x[w] ^= px[w]; f.z[w] ^= pz[w]; }
+}
+
+// Scalar (SMEM) view of program data: uniform addresses read through the
+// constant address space so that the compiler issues s_load.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+DEV cptr<T> as_const(const T* p) { return (cptr<T>)(p); }
+
+DEV uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One 16-byte instruction through the scalar cache.
+DEV GInstr load_instr(const GInstr* code, int pc) {
+  cptr<uint32_t> w = (cptr<uint32_t>)(as_const(code) + pc);
+  uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
+  GInstr in;
+  in.op = (uint8_t)(w0 & 0xFF);
+  in.flags = (uint8_t)((w0 >> 8) & 0xFF);
+  in.v = (uint16_t)(w0 >> 16);
+  in.s = (uint16_t)(w1 & 0xFFFF);
+  in.u = (uint16_t)(w1 >> 16);
+  in.a = w2;
+  in.b = w3;
+  return in;
+}
+DEV double rfl(double v) {
+  uint64_t b = __double_as_longlong(v);
+  uint32_t lo = rfl((uint32_t)b), hi = rfl((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// ------------------------------------------------------------------ group context
+template <int G>
+struct Group {
+  int tid;  // thread index inside the shot group
+  __device__ void sync() const {
+    if constexpr (G == 256) __syncthreads();
+    else if constexpr (G == 64) { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+  }
+  __device__ double sum(double v, double* red) const {
+    if constexpr (G == 1) {
+      return v;
+    } else {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if constexpr (G == 64) {
+        return rfl(v);
+      } else {
+        int wv = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[wv] = v;
+        __syncthreads();
+        double t = red[0] + red[1] + red[2] + red[3];
+        return rfl(t);
+      }
+    }
+  }
+};
+
+// Amplitude storage: G == 1 lane-interleaved (element i of lane l at i*64+l),
+// otherwise element i of the group's vector at i.
+template <int G, typename R>
+struct Vec {
+  cpx<R>* base;
+  int lane;
+  __device__ cpx<R>& operator[](uint32_t i) const {
+    if constexpr (G == 1) return base[(size_t)i * 64 + lane];
+    else return base[i];
+  }
+};
+
+// Iterate p over [0, n) split among the threads of a group.
+#define FOR_GROUP(p, n) for (uint32_t p = (G == 1 ? 0u : (uint32_t)grp.tid); p < (n); p += (G == 1 ? 1u : (uint32_t)G))
+
+template <typename R>
+DEV cpx<R> cmul(cpx<R> a, R cr, R ci) { return cpx<R>{a.re * cr - a.im * ci, a.re * ci + a.im * cr}; }
+template <typename R>
+DEV double norm2(cpx<R> a) { return (double)a.re * (double)a.re + (double)a.im * (double)a.im; }
+
+// ------------------------------------------------------------------ noise state
+struct Noise {
+  uint32_t chunk, ord, nf, nf_out;
+};
+
+DEV uint32_t nout_of(uint32_t t) { return t == S_DEP1 ? 3u : t == S_DEP2 ? 15u : 1u; }
+
+// Next fault at or after local index cur of the current chunk (Section 3.2,
+// jump to the next realized fault).  tau = u * S[cur]; the fault is the
+// smallest j with S[j+1] <= tau, j == len meaning none left in the chunk.
+DEV void next_fault(const DevProgram& P, Noise& ns, uint32_t cur, uint64_t shot, uint64_t seed) {
+  U4 w = draw(ns.ord++, kPurposeNoise | ns.chunk, shot, seed);
+  const double* S = P.surv + (size_t)ns.chunk * (kChunk + 1);
+  uint32_t len = min((uint32_t)kChunk, (uint32_t)P.nsites - ns.chunk * (uint32_t)kChunk);
+  double tau = uniform53(w) * S[cur];
+  uint32_t lo = cur, hi = len;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (S[mid + 1] <= tau) hi = mid;
+    else lo = mid + 1;
+  }
+  ns.nf = ns.chunk * (uint32_t)kChunk + lo;
+  if (lo < len) {
+    uint64_t w64 = ((uint64_t)w.w3 << 32) | w.w2;
+    ns.nf_out = (uint32_t)__umul64hi(w64, (uint64_t)nout_of(P.site_type[ns.nf]));
+  }
+}
+
+template <int W>
+DEV void apply_fault(const DevProgram& P, Frame<W>& T, Frame<W>& N, uint32_t site, uint32_t o) {
+  uint32_t t = P.site_type[site];
+  const uint64_t* img = P.masks + P.site_img[site];
+  uint32_t la, lb = 0;
+  if (t == S_DEP1) la = o + 1;
+  else if (t == S_DEP2) { la = (o + 1) >> 2; lb = (o + 1) & 3; }
+  else la = t - 1;  // X_ERROR 1, Y_ERROR 2, Z_ERROR 3
+  uint64_t ex[W], ez[W];
+#pragma unroll
+  for (int w = 0; w < W; w++) { ex[w] = 0; ez[w] = 0; }
+  // image layout per qubit: X~ (x words, z words) then Z~ (x words, z words)
+  const uint32_t L[2] = {la, lb};
+#pragma unroll
+  for (int qi = 0; qi < 2; qi++) {
+    uint32_t l = L[qi];
+    const uint64_t* ix = img + (size_t)qi * 4 * W;
+    const uint64_t* iz = ix + 2 * W;
+    uint64_t ux = (l == 1 || l == 2) ? ~0ull : 0ull;
+    uint64_t uz = (l == 2 || l == 3) ? ~0ull : 0ull;
+    if (qi == 1 && t != S_DEP2) break;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+      ex[w] ^= (ix[w] & ux) ^ (iz[w] & uz);
+      ez[w] ^= (ix[W + w] & ux) ^ (iz[W + w] & uz);
+    }
+  }
+  frame_xor<W>(T, ex, ez);
+  frame_xor<W>(N, ex, ez);
+}
+
+// ------------------------------------------------------------------ one shot
+template <int W, int G, typename R, bool DBG>
+struct Shot {
+  const DevProgram& P;
+  const KArgs& A;
+  Group<G> grp;
+  Vec<G, R> vec;
+  uint64_t* rec;  // LDS record words of the tile (R + D + O)
+  double* red;    // LDS reduction scratch (G == 256)
+  int slane;      // shot index inside the 64-shot tile
+  uint64_t shot;  // global shot index (G == 1: per lane)
+  uint64_t local; // shot index relative to the call (debug buffers)
+
+  MDEV bool writer() const { return (G == 1 || grp.tid == 0) && local < A.shots; }
+
+  MDEV void put(uint32_t r, uint32_t m) {
+    if constexpr (G == 1) {
+      uint64_t word = __ballot(m);
+      if ((threadIdx.x & 63) == 0) rec[r] = word;
+    } else {
+      if (grp.tid == 0) rec[r] |= (uint64_t)m << slane;
+    }
+  }
+  MDEV uint32_t xor_refs(uint32_t a, uint32_t u) {
+    // G == 1: whole 64-shot words; otherwise this shot's bit
+    uint64_t acc = 0;
+    cptr<uint32_t> refs = as_const(P.refs);
+    for (uint32_t i = 0; i < u; i++) acc ^= rec[refs[a + i]];
+    if constexpr (G == 1) {
+      uint32_t lane = threadIdx.x & 63;
+      return (uint32_t)(acc >> lane) & 1u;
+    } else {
+      return (uint32_t)(acc >> slane) & 1u;
+    }
+  }
+
+  __device__ void run() {
+    Frame<W> T, N;
+#pragma unroll
+    for (int w = 0; w < W; w++) { T.x[w] = T.z[w] = N.x[w] = N.z[w] = 0; }
+    const uint64_t seed = A.seed;
+    int k = 0;
+    uint32_t last_m = 0, last_pn = 0;
+    uint32_t rb_blk = 0xFFFFFFFFu;
+    U4 rb{0, 0, 0, 0};
+    Noise ns{0, 0, 0xFFFFFFFFu, 0};
+    if (P.nsites > 0) {
+      if (DBG && A.forced_faults) ns.nf = 0xFFFFFFFFu;
+      else next_fault(P, ns, 0, shot, seed);
+    }
+    if (P.kmax > 0) {
+      FOR_GROUP(p, 1u) vec[p] = cpx<R>{(R)1, (R)0};
+      grp.sync();
+    }
+    cptr<uint64_t> masks = as_const(P.masks);
+    for (int pc = 0;; pc++) {
+      const GInstr in = load_instr(P.code, pc);
+      const int v = in.v;
+      const int s = in.s;
+      switch (in.op) {
+        case OP_END:
+          goto done;
+        case OP_FANCX: {
+          uint64_t m[W];
+#pragma unroll
+          for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
+          fan_cx<W>(T, v, m);
+          fan_cx<W>(N, v, m);
+          break;
+        }
+        case OP_FANCZ: {
+          uint64_t m[W];
+#pragma unroll
+          for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
+          fan_cz<W>(T, v, m);
+          fan_cz<W>(N, v, m);
+          break;
+        }
+        case OP_FAN2: {
+          uint64_t m[W];
+#pragma unroll
+          for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
+          fan_2<W>(T, v, m);
+          fan_2<W>(N, v, m);
+          break;
+        }
+        case OP_FS: frame_s<W>(T, v); frame_s<W>(N, v); break;
+        case OP_FH: frame_h<W>(T, v); frame_h<W>(N, v); break;
+        case OP_APERM: {
+          // for i with bit s set: swap i <-> i ^ tm; representative has the
+          // lowest target bit t0 clear
+          uint32_t tm = in.a;
+          int t0 = __ffs(tm) - 1;
+          int lo = min(s, t0), hi = max(s, t0);
+          uint32_t n = 1u << (k - 2);
+          FOR_GROUP(p, n) {
+            uint32_t i = ins0(ins0(p, lo), hi);
+            i |= 1u << s;
+            cpx<R> a = vec[i], b = vec[i ^ tm];
+            vec[i] = b;
+            vec[i ^ tm] = a;
+          }
+          grp.sync();
+          break;
+        }
+        case OP_ASIGN: {
+          uint32_t sm = in.a;
+          uint32_t n = 1u << (k - 1);
+          FOR_GROUP(p, n) {
+            uint32_t i = ins0(p, s) | (1u << s);
+            if (__popc(i & sm) & 1) { cpx<R> a = vec[i]; vec[i] = cpx<R>{-a.re, -a.im}; }
+          }
+          grp.sync();
+          break;
+        }
+        case OP_APERM2: {
+          uint32_t sm = in.a;
+          uint32_t n = 1u << (k - 1);
+          FOR_GROUP(p, n) {
+            uint32_t i0 = ins0(p, s);
+            if (__popc(i0 & sm) & 1) {
+              uint32_t i1 = i0 | (1u << s);
+              cpx<R> a = vec[i0], b = vec[i1];
+              vec[i0] = b;
+              vec[i1] = a;
+            }
+          }
+          grp.sync();
+          break;
+        }
+        case OP_AS: {
+          uint32_t n = 1u << (k - 1);
+          FOR_GROUP(p, n) {
+            uint32_t i = ins0(p, s) | (1u << s);
+            cpx<R> a = vec[i];
+            vec[i] = cpx<R>{-a.im, a.re};
+          }
+          grp.sync();
+          break;
+        }
+        case OP_AH: {
+          const R h = (R)0.70710678118654752440;
+          uint32_t n = 1u << (k - 1);
+          FOR_GROUP(p, n) {
+            uint32_t i0 = ins0(p, s), i1 = i0 | (1u << s);
+            cpx<R> a = vec[i0], b = vec[i1];
+            vec[i0] = cpx<R>{h * (a.re + b.re), h * (a.im + b.im)};
+            vec[i1] = cpx<R>{h * (a.re - b.re), h * (a.im - b.im)};
+          }
+          grp.sync();
+          break;
+        }
+        case OP_EXPAND: {
+          // Appendix B.1 case 2: H_v takes |0>_v to |+>_v (frames conjugated);
+          // then exp(-i theta' Z_v) on the new axis, theta' sign-flipped by
+          // x_v of the frame.  The common phase e^{-i theta'} is global, so
+          // the new half is the old one times e^{2 i theta'}.
+          frame_h<W>(T, v);
+          frame_h<W>(N, v);
+          double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
+          if (getbit<W>(T.x, v)) s2 = -s2;
+          R cr = (R)c2, ci = (R)s2;
+          uint32_t n = 1u << k;
+          FOR_GROUP(p, n) vec[p | n] = cmul(vec[p], cr, ci);
+          k++;
+          grp.sync();
+          break;
+        }
+        case OP_AROT: {
+          double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
+          if (getbit<W>(T.x, v)) s2 = -s2;
+          R cr = (R)c2, ci = (R)s2;
+          uint32_t n = 1u << (k - 1);
+          FOR_GROUP(p, n) {
+            uint32_t i = ins0(p, s) | (1u << s);
+            vec[i] = cmul(vec[i], cr, ci);
+          }
+          grp.sync();
+          break;
+        }
+        case OP_MSTATIC: {
+          uint64_t m[W];
+#pragma unroll
+          for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
+          uint32_t mm = parity_and<W>(T.x, m) ^ (uint32_t)(in.flags & F_SIGN);
+          last_pn = parity_and<W>(N.x, m);
+          if constexpr (DBG) {
+            if (A.probs && writer()) A.probs[local * P.nevents + in.b] = (double)mm;
+            if (A.forced_m && writer() && A.forced_m[local * P.nevents + in.b] != mm) atomicOr(A.error, 2);
+          }
+          last_m = mm;
+          int r = as_const(P.ev_rec)[in.b];
+          if (r >= 0) put((uint32_t)r, mm);
+          break;
+        }
+        case OP_MRANDOM: {
+          uint32_t j = in.b;
+          uint32_t p = getbit<W>(T.z, v), pn = getbit<W>(N.z, v);
+          uint32_t mm;
+          if constexpr (DBG) {
+            if (A.probs && writer()) A.probs[local * P.nevents + j] = 0.5;
+          }
+          if (DBG && A.forced_m) {
+            mm = local < A.shots ? A.forced_m[local * P.nevents + j] : 0u;
+            if constexpr (G > 1) mm = rfl(mm);
+          } else {
+            if ((j >> 7) != rb_blk) {
+              rb_blk = j >> 7;
+              rb = draw(rb_blk, kPurposeRbit, shot, seed);
+            }
+            uint32_t bi = j & 127, word = bi >> 5;
+            uint32_t wv = word == 0 ? rb.w0 : word == 1 ? rb.w1 : word == 2 ? rb.w2 : rb.w3;
+            mm = ((wv >> (bi & 31)) & 1u) ^ pn;
+          }
+          uint32_t b = mm ^ (uint32_t)(in.flags & F_SIGN) ^ p;
+          frame_h<W>(T, v);
+          frame_h<W>(N, v);
+          xorbit<W>(T.x, v, b);
+          last_m = mm;
+          last_pn = pn;
+          int r = as_const(P.ev_rec)[j];
+          if (r >= 0) put((uint32_t)r, mm);
+          break;
+        }
+        case OP_MACTZ:
+        case OP_MACTX: {
+          const bool isx = in.op == OP_MACTX;
+          uint32_t j = in.b;
+          uint32_t sign = in.flags & F_SIGN;
+          uint32_t p = isx ? getbit<W>(T.z, v) : getbit<W>(T.x, v);
+          uint32_t pn = isx ? getbit<W>(N.z, v) : getbit<W>(N.x, v);
+          const uint32_t bs = 1u << s;
+          const uint32_t half = 1u << (k - 1);
+          double s0 = 0, s1 = 0;
+          FOR_GROUP(q, half) {
+            uint32_t i0 = ins0(q, s);
+            cpx<R> a = vec[i0], b = vec[i0 | bs];
+            if (isx) {
+              s0 += norm2(cpx<R>{a.re + b.re, a.im + b.im});
+              s1 += norm2(cpx<R>{a.re - b.re, a.im - b.im});
+            } else {
+              s0 += norm2(a);
+              s1 += norm2(b);
+            }
+          }
+          s0 = grp.sum(s0, red);
+          s1 = grp.sum(s1, red);
+          if (isx) { s0 *= 0.5; s1 *= 0.5; }
+          double tot = s0 + s1;
+          uint32_t bm1 = 1u ^ sign ^ p;  // virtual branch of m = 1
+          double sb1 = bm1 ? s1 : s0;
+          uint32_t mm;
+          if constexpr (DBG) {
+            if (A.probs && writer()) A.probs[local * P.nevents + j] = sb1 / tot;
+          }
+          if (DBG && A.forced_m) {
+            mm = local < A.shots ? A.forced_m[local * P.nevents + j] : 0u;
+            if constexpr (G > 1) mm = rfl(mm);
+          } else {
+            U4 w = draw(j, kPurposeAmeas, shot, seed);
+            double pref1 = ((bm1 ^ pn) ? s1 : s0) / tot;  // P(m_ref = 1)
+            mm = (uniform53(w) < pref1 ? 1u : 0u) ^ pn;
+          }
+          uint32_t b = mm ^ sign ^ p;
+          double sb = b ? s1 : s0;
+          if (!(sb > 1e-300 * tot)) {
+            if constexpr (DBG) {
+              if (writer()) atomicOr(A.error, 2);
+            }
+            sb = tot > 0 ? tot : 1.0;
+          }
+          const R scale = (R)(1.0 / sqrt(sb));
+          const R fs = isx ? (R)0.70710678118654752440 : (R)1;
+          const R sgn = b ? (R)-1 : (R)1;
+          // collapse: the kept half (or fold) is written in place; the top
+          // slot k-1 takes the place of slot s (no hazard: every thread
+          // owns its two outputs and reads only them and the top half)
+          const int top = k - 1;
+          if (s == top) {
+            FOR_GROUP(q, half) {
+              cpx<R> a = vec[q], c = vec[q | bs];
+              cpx<R> o;
+              if (isx) o = cpx<R>{fs * scale * (a.re + sgn * c.re), fs * scale * (a.im + sgn * c.im)};
+              else o = b ? cpx<R>{scale * c.re, scale * c.im} : cpx<R>{scale * a.re, scale * a.im};
+              vec[q] = o;
+            }
+          } else {
+            const uint32_t tb = 1u << top;
+            uint32_t n4 = half >> 1;
+            FOR_GROUP(q, n4) {
+              uint32_t j0 = ins0(q, s);  // k-1 bit index with bit s clear (bit top clear)
+              uint32_t j1 = j0 | bs;
+              cpx<R> a0 = vec[j0], a1 = vec[j1], c0 = vec[j0 | tb], c1 = vec[j1 | tb];
+              cpx<R> o0, o1;
+              if (isx) {
+                o0 = cpx<R>{fs * scale * (a0.re + sgn * a1.re), fs * scale * (a0.im + sgn * a1.im)};
+                o1 = cpx<R>{fs * scale * (c0.re + sgn * c1.re), fs * scale * (c0.im + sgn * c1.im)};
+              } else if (b) {
+                o0 = cpx<R>{scale * a1.re, scale * a1.im};
+                o1 = cpx<R>{scale * c1.re, scale * c1.im};
+              } else {
+                o0 = cpx<R>{scale * a0.re, scale * a0.im};
+                o1 = cpx<R>{scale * c0.re, scale * c0.im};
+              }
+              vec[j0] = o0;
+              vec[j1] = o1;
+            }
+          }
+          k--;
+          grp.sync();
+          if (isx) { frame_h<W>(T, v); frame_h<W>(N, v); }
+          xorbit<W>(T.x, v, b);
+          last_m = mm;
+          last_pn = pn;
+          int r = as_const(P.ev_rec)[j];
+          if (r >= 0) put((uint32_t)r, mm);
+          break;
+        }
+        case OP_CPAULI: {
+          uint64_t px[W], pz[W], zero[W];
+#pragma unroll
+          for (int w = 0; w < W; w++) {
+            px[w] = masks[in.a + w];
+            pz[w] = masks[in.a + W + w];
+            zero[w] = 0;
+          }
+          uint64_t mm = 0ull - (uint64_t)last_m, mp = 0ull - (uint64_t)last_pn;
+          uint64_t ax[W], az[W], bx[W], bz[W];
+#pragma unroll
+          for (int w = 0; w < W; w++) {
+            ax[w] = px[w] & mm; az[w] = pz[w] & mm;
+            bx[w] = px[w] & mp; bz[w] = pz[w] & mp;
+          }
+          (void)zero;
+          frame_xor<W>(T, ax, az);
+          frame_xor<W>(N, bx, bz);
+          break;
+        }
+        case OP_NOISE: {
+          if constexpr (DBG) {
+            if (A.forced_faults) {
+              for (uint32_t st = in.a; st < in.b; st++) {
+                int o = local < A.shots ? A.forced_faults[local * P.nsites + st] : -1;
+                if (o >= 0) apply_fault<W>(P, T, N, st, (uint32_t)o);
+              }
+              break;
+            }
+          }
+          const uint32_t hi = in.b;
+          while (ns.nf < hi) {
+            uint32_t cend = min((ns.chunk + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
+            if (ns.nf >= cend) {
+              ns.chunk++;
+              ns.ord = 0;
+              next_fault(P, ns, 0, shot, seed);
+              continue;
+            }
+            apply_fault<W>(P, T, N, ns.nf, ns.nf_out);
+            next_fault(P, ns, ns.nf - ns.chunk * (uint32_t)kChunk + 1, shot, seed);
+          }
+          break;
+        }
+        case OP_DET: {
+          uint32_t d = xor_refs(in.a, in.u);
+          put((uint32_t)P.nrec + in.b, d);
+          break;
+        }
+        case OP_OBS: {
+          uint32_t d = xor_refs(in.a, in.u);
+          uint32_t r = (uint32_t)P.nrec + (uint32_t)P.ndet + in.b;
+          if constexpr (G == 1) {
+            uint64_t word = __ballot(d);
+            if ((threadIdx.x & 63) == 0) rec[r] ^= word;
+          } else {
+            if (grp.tid == 0) rec[r] ^= (uint64_t)d << slane;
+          }
+          break;
+        }
+        default:
+          break;
+      }
+    }
+  done:
+    if constexpr (DBG) {
+      if (A.phi_out && local < A.shots && P.kmax == 0) {
+        // no active vector exists: the state is the trivial [1]
+        if (G == 1 || grp.tid == 0) {
+          A.phi_out[local * 2] = 1.0;
+          A.phi_out[local * 2 + 1] = 0.0;
+        }
+      } else if (A.phi_out && local < A.shots) {
+        // final active vector (its length 2^k is program-determined)
+        FOR_GROUP(p, (1u << k)) {
+          cpx<R> a = vec[p];
+          A.phi_out[(local << P.kmax) * 2 + 2 * p] = (double)a.re;
+          A.phi_out[(local << P.kmax) * 2 + 2 * p + 1] = (double)a.im;
+        }
+      }
+    }
+    grp.sync();
+  }
+};
+
+// ------------------------------------------------------------------ kernel
+// One persistent launch: units (lanes-of-a-wave for G = 1, waves for G = 64,
+// workgroups for G = 256) take 64-shot tiles round-robin.
+template <int W, int G, typename R, bool GLOBAL, bool DBG>
+__global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int units_per_block = G == 256 ? 1 : 4;
+  const int unit_in_block = G == 256 ? 0 : (int)rfl(threadIdx.x >> 6);
+  const uint64_t unit = (uint64_t)blockIdx.x * units_per_block + unit_in_block;
+  const uint64_t nunits = (uint64_t)gridDim.x * units_per_block;
+  const uint32_t nwords_rec = (uint32_t)(P.nrec + P.ndet + P.nobs);
+  const uint32_t rec_stride = (nwords_rec + 1) & ~1u;  // keep 16-byte alignment
+  uint64_t* rec = (uint64_t*)smem + (size_t)unit_in_block * rec_stride;
+  unsigned char* after_rec = smem + (size_t)units_per_block * rec_stride * 8;
+  double* red = (double*)after_rec;
+  cpx<R>* arr_lds = (cpx<R>*)(after_rec + 64);
+  const size_t vec_elems = (size_t)1 << P.kmax;
+  cpx<R>* base;
+  if constexpr (GLOBAL) {
+    base = (cpx<R>*)A.workspace + unit * vec_elems * (G == 1 ? 64 : 1);
+  } else {
+    base = arr_lds + (size_t)unit_in_block * vec_elems * (G == 1 ? 64 : 1);
+  }
+  const int lane = threadIdx.x & 63;
+  const int tid = G == 256 ? (int)threadIdx.x : lane;
+  const uint64_t ntiles = (A.shots + 63) / 64;
+  const uint64_t words = ntiles;
+  for (uint64_t tile = unit; tile < ntiles; tile += nunits) {
+    for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += (G == 256 ? 256 : 64)) rec[r] = 0;
+    if constexpr (G == 256) __syncthreads();
+    else { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+    if constexpr (G == 1) {
+      Shot<W, G, R, DBG> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
+                            A.offset + tile * 64 + lane, tile * 64 + lane};
+      sh.run();
+    } else {
+      uint32_t nsh = (uint32_t)min((uint64_t)64, A.shots - tile * 64);
+      for (uint32_t sl = 0; sl < nsh; sl++) {
+        uint64_t g = rfl((uint32_t)(tile * 64 + sl)) | ((tile * 64 + sl) & 0xFFFFFFFF00000000ull);
+        Shot<W, G, R, DBG> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, (int)sl, A.offset + g, g};
+        sh.run();
+      }
+    }
+    if constexpr (G == 256) __syncthreads();
+    else { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+    // flush the tile's record words (bits of shots beyond the end cleared)
+    const uint64_t nvalid = min((uint64_t)64, A.shots - tile * 64);
+    const uint64_t vmask = nvalid == 64 ? ~0ull : ((1ull << nvalid) - 1ull);
+    for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += (G == 256 ? 256 : 64)) {
+      uint64_t v = rec[r] & vmask;
+      if (r < (uint32_t)P.nrec) {
+        if (A.meas) A.meas[(size_t)r * words + tile] = v;
+      } else if (r < (uint32_t)(P.nrec + P.ndet)) {
+        if (A.det) A.det[(size_t)(r - P.nrec) * words + tile] = v;
+      } else {
+        if (A.obs) A.obs[(size_t)(r - P.nrec - P.ndet) * words + tile] = v;
+      }
+    }
+    if constexpr (G == 256) __syncthreads();
+    else { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+  }
+}
+
+// ------------------------------------------------------------------ dispatch table
+template <int W, int G, typename R, bool GLOBAL, bool DBG>
+static hipError_t launch_one(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
+  static bool attr = false;  // allow the whole 160 KB of LDS for dynamic use
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG>), dim3(grid), dim3(256), lds, st, P, A);
+  return hipGetLastError();
+}
+
+template <int G, typename R, bool GLOBAL, bool DBG>
+static hipError_t launch_w(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
+  switch (P.W) {
+    case 1: return launch_one<1, G, R, GLOBAL, DBG>(P, A, grid, lds, st);
+    case 2: return launch_one<2, G, R, GLOBAL, DBG>(P, A, grid, lds, st);
+    case 3: return launch_one<3, G, R, GLOBAL, DBG>(P, A, grid, lds, st);
+    case 4: return launch_one<4, G, R, GLOBAL, DBG>(P, A, grid, lds, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R, bool DBG>
+static hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t st) {
+  if (L.G == 1) return launch_w<1, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+  if (L.G == 64) return launch_w<64, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+  if (L.global_vec) return launch_w<256, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
+  return launch_w<256, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+}
+
+hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool debug,
+                         hipStream_t st) {
+  if (fp64) return debug ? launch_g<double, true>(P, A, L, st) : launch_g<double, false>(P, A, L, st);
+  return debug ? launch_g<float, true>(P, A, L, st) : launch_g<float, false>(P, A, L, st);
+}
+
+size_t lds_bytes_for(const DevProgram& P, int G, bool global_vec, bool fp64) {
+  const int units = G == 256 ? 1 : 4;
+  const size_t nwords_rec = (size_t)(P.nrec + P.ndet + P.nobs);
+  const size_t rec_stride = (nwords_rec + 1) & ~(size_t)1;
+  size_t bytes = units * rec_stride * 8 + 64;
+  if (!global_vec && P.kmax > 0) {
+    size_t el = (size_t)1 << P.kmax;
+    size_t amp = fp64 ? 16 : 8;
+    bytes += units * el * amp * (G == 1 ? 64 : 1);
+  }
+  return bytes;
+}
+
+}  // namespace clifft

@@ -1,0 +1,80 @@
+// Compiled program layout shared by the host compiler, the runtime and the
+// HIP kernels.  Everything here is plain data: a flat 16-byte instruction
+// stream plus side tables, uploaded once per program and read through the
+// scalar cache by every wave (the stream is wave-uniform by Theorem 1: the
+// Clifford frame, the active set and k(t) do not depend on any sample).
+#pragma once
+#include <stdint.h>
+
+namespace clifft {
+
+constexpr int kChunk = 4096;      // noise sites per survival table (gap sampler)
+constexpr int kMaxWords = 4;      // frames up to 256 qubits
+constexpr int kMaxK = 30;         // active dimension limit of the format
+
+// Opcodes.  F* act on the Pauli frames only (both the full frame and the
+// noise-only frame); A* act on the active vector only; the measurement and
+// expansion opcodes do both.
+enum Op : uint8_t {
+  OP_END = 0,
+  OP_FANCX,    // CNOT v->q for q in mask (v is the control)      v, a=mask
+  OP_FANCZ,    // CZ v,q for q in mask                              v, a=mask
+  OP_FAN2,     // CNOT q->v for q in mask (v is the target)         v, a=mask
+  OP_FS,       // S on v                                            v
+  OP_FH,       // H on v                                            v
+  OP_APERM,    // array part of a CNOT fan: control slot s, targets slots a
+  OP_ASIGN,    // array part of a CZ fan: slot s with slots a
+  OP_APERM2,   // array part of a target fan: target slot s, controls slots a
+  OP_AS,       // array S on slot s
+  OP_AH,       // array H on slot s
+  OP_EXPAND,   // H on dormant v, new slot s = k, then rotation      v, s, a=const
+  OP_AROT,     // diagonal rotation on active v at slot s            v, s, a=const
+  OP_MSTATIC,  // deterministic Z-string measurement                 a=mask(z, W words), b=event
+  OP_MRANDOM,  // dormant X_v measurement, then H_v absorbed         v, b=event
+  OP_MACTZ,    // active Z_v measurement (mask), demote slot s       v, s, b=event
+  OP_MACTX,    // active X_v measurement (interfere), demote slot s  v, s, b=event
+  OP_CPAULI,   // reset correction X^m (noise part X^pn)             a=mask(x,z), b=event
+  OP_NOISE,    // noise sites [a, b)
+  OP_DET,      // detector b = XOR of records refs[a .. a+u)
+  OP_OBS,      // observable b ^= XOR of records refs[a .. a+u)
+  OP_COUNT
+};
+
+// flags
+constexpr uint8_t F_SIGN = 1;   // sign bit of the localized observable
+
+struct GInstr {
+  uint8_t op;
+  uint8_t flags;
+  uint16_t v;   // virtual qubit
+  uint16_t s;   // slot (array axis)
+  uint16_t u;   // small count
+  uint32_t a;   // mask offset / slot mask / const index / site lo / refs offset
+  uint32_t b;   // event / site hi / detector or observable index
+};
+static_assert(sizeof(GInstr) == 16, "instruction must be 16 bytes");
+
+// Noise site types
+enum SiteType : uint8_t { S_DEP1 = 0, S_DEP2 = 1, S_XERR = 2, S_YERR = 3, S_ZERR = 4 };
+
+// Philox counter purposes of the stochastic contract
+constexpr uint32_t kPurposeNoise = 0x4E000000u;  // | chunk
+constexpr uint32_t kPurposeRbit = 0x52000000u;
+constexpr uint32_t kPurposeAmeas = 0x41000000u;
+
+// Device-side view of one program (all pointers are device addresses).
+struct DevProgram {
+  const GInstr* code;
+  const uint64_t* masks;     // W-word Pauli masks
+  const double* consts;      // (cos 2theta, sin 2theta) pairs
+  const uint32_t* refs;      // record references of detectors / observables
+  const int32_t* ev_rec;     // event -> record index or -1
+  const uint8_t* site_type;  // per noise site
+  const uint32_t* site_img;  // per site: offset of its images in masks (2 or 4 images x 2W words)
+  const double* surv;        // per chunk: kChunk + 1 survival products
+  int32_t nq, W, kmax, ncode;
+  int32_t nevents, nrec, ndet, nobs;
+  int32_t nsites, nchunks;
+};
+
+}  // namespace clifft

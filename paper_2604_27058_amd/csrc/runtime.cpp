@@ -1,0 +1,313 @@
+// C-ABI implementation: program handles, device upload, launch-shape
+// selection and the sampling entry points declared in include/clifft.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/clifft.h"
+#include "compiler.h"
+#include "kernels.h"
+
+using namespace clifft;
+
+namespace {
+
+thread_local std::string g_err;
+
+clifft_status fail(clifft_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+struct DeviceCopy {
+  DevProgram view{};
+  std::vector<void*> allocs;
+};
+
+}  // namespace
+
+struct clifft_program {
+  CompiledProgram host;
+  std::mutex mu;
+  std::map<int, DeviceCopy> dev;
+};
+
+namespace {
+
+template <typename T>
+hipError_t upload_vec(const std::vector<T>& v, const T** dst, std::vector<void*>& allocs) {
+  void* d = nullptr;
+  size_t bytes = v.size() * sizeof(T);
+  hipError_t e = hipMalloc(&d, bytes ? bytes : 16);
+  if (e != hipSuccess) return e;
+  allocs.push_back(d);
+  if (bytes) {
+    e = hipMemcpy(d, v.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  *dst = (const T*)d;
+  return hipSuccess;
+}
+
+clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
+  clifft_program* p = const_cast<clifft_program*>(cp);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(CLIFFT_E_DEVICE, "no HIP device");
+  std::lock_guard<std::mutex> lock(p->mu);
+  auto it = p->dev.find(dev);
+  if (it != p->dev.end()) {
+    *out = &it->second.view;
+    return CLIFFT_OK;
+  }
+  DeviceCopy dc;
+  const CompiledProgram& H = p->host;
+  DevProgram& v = dc.view;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload_vec(H.code, &v.code, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.masks, &v.masks, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.consts, &v.consts, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.refs, &v.refs, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.ev_rec, &v.ev_rec, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.site_type, &v.site_type, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.site_img, &v.site_img, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.surv, &v.surv, dc.allocs);
+  if (e != hipSuccess) {
+    for (void* a : dc.allocs) (void)hipFree(a);
+    return fail(CLIFFT_E_DEVICE, std::string("program upload failed: ") + hipGetErrorString(e));
+  }
+  v.nq = H.nq;
+  v.W = H.W;
+  v.kmax = H.kmax;
+  v.ncode = (int)H.code.size();
+  v.nevents = H.nevents;
+  v.nrec = H.nrec;
+  v.ndet = H.ndet;
+  v.nobs = H.nobs;
+  v.nsites = (int)H.site_p.size();
+  v.nchunks = H.nchunks;
+  auto res = p->dev.emplace(dev, std::move(dc));
+  *out = &res.first->second.view;
+  return CLIFFT_OK;
+}
+
+constexpr size_t kLdsLimit = 160 * 1024;
+
+int device_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+  return n;
+}
+
+// Launch shape: the tier follows the active-vector size (threads per shot
+// and storage), the grid fills the device with persistent workgroups.
+clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const clifft_launch* cfg, uint64_t shots,
+                           LaunchShape* L, bool* fp64) {
+  clifft_launch c{};
+  if (cfg) c = *cfg;
+  if (c.precision != CLIFFT_FP32 && c.precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
+  *fp64 = c.precision == CLIFFT_FP64;
+  const size_t amp = *fp64 ? 16 : 8;
+  const size_t vec = (size_t)1 << H.kmax;
+  int G = c.threads_per_shot;
+  if (G != 0 && G != 1 && G != 64 && G != 256) return fail(CLIFFT_E_INVALID_ARG, "threads_per_shot must be 0, 1, 64 or 256");
+  if (G == 0) {
+    if (H.kmax == 0 || 4 * vec * 64 * amp <= 64 * 1024) G = 1;
+    else if (4 * vec * amp <= 64 * 1024) G = 64;
+    else G = 256;
+  }
+  bool global_vec = false;
+  if (H.kmax > 0) {
+    size_t need = (G == 256 ? 1 : 4) * vec * amp * (G == 1 ? 64 : 1);
+    if (c.vector_in_hbm == 1) global_vec = true;
+    else if (c.vector_in_hbm == -1) global_vec = false;
+    else global_vec = need > kLdsLimit - 16 * 1024;
+    if (global_vec && G != 256) return fail(CLIFFT_E_CAPACITY, "the HBM tier needs threads_per_shot = 256");
+  }
+  DevProgram tmp{};
+  tmp.nrec = H.nrec;
+  tmp.ndet = H.ndet;
+  tmp.nobs = H.nobs;
+  tmp.kmax = H.kmax;
+  size_t lds = lds_bytes_for(D ? *D : tmp, G, global_vec, *fp64);
+  if (lds > kLdsLimit) return fail(CLIFFT_E_CAPACITY, "records and active vectors exceed LDS; use a larger tier");
+  const int units_per_block = G == 256 ? 1 : 4;
+  uint64_t tiles = (shots + 63) / 64;
+  uint64_t blocks_needed = (tiles + units_per_block - 1) / units_per_block;
+  int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, kLdsLimit / std::max<size_t>(lds, 1)));
+  int grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
+  if ((uint64_t)grid > blocks_needed) grid = (int)std::max<uint64_t>(1, blocks_needed);
+  L->G = G;
+  L->grid = grid;
+  L->lds_bytes = lds;
+  L->global_vec = global_vec;
+  return CLIFFT_OK;
+}
+
+size_t workspace_bytes(const CompiledProgram& H, const LaunchShape& L, bool fp64) {
+  if (!L.global_vec) return 0;
+  size_t amp = fp64 ? 16 : 8;
+  size_t units = (size_t)L.grid * (L.G == 256 ? 1 : 4);
+  return units * ((size_t)1 << H.kmax) * amp * (L.G == 1 ? 64 : 1);
+}
+
+clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t offset,
+                        const clifft_launch* cfg, void* ws, size_t ws_bytes, uint64_t* meas, uint64_t* det,
+                        uint64_t* obs, void* stream, const uint32_t* forced_m, const int32_t* forced_faults,
+                        double* probs, double* phi, bool trace) {
+  if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
+  if (shots == 0) return CLIFFT_OK;
+  const DevProgram* D = nullptr;
+  clifft_status st = ensure_device(p, &D);
+  if (st != CLIFFT_OK) return st;
+  LaunchShape L{};
+  bool fp64 = false;
+  st = choose_shape(p->host, D, cfg, shots, &L, &fp64);
+  if (st != CLIFFT_OK) return st;
+  size_t need = workspace_bytes(p->host, L, fp64);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "workspace of %zu bytes needed", need);
+    return fail(CLIFFT_E_CAPACITY, buf);
+  }
+  KArgs A{};
+  A.shots = shots;
+  A.seed = seed;
+  A.offset = offset;
+  A.meas = meas;
+  A.det = det;
+  A.obs = obs;
+  A.workspace = ws;
+  hipStream_t s = (hipStream_t)stream;
+  int* dflag = nullptr;
+  if (trace) {
+    A.forced_m = forced_m;
+    A.forced_faults = forced_faults;
+    A.probs = probs;
+    A.phi_out = phi;
+    if (hipMalloc(&dflag, sizeof(int)) != hipSuccess) return fail(CLIFFT_E_DEVICE, "flag allocation failed");
+    (void)hipMemsetAsync(dflag, 0, sizeof(int), s);
+    A.error = dflag;
+  }
+  hipError_t e = launch_sample(*D, A, L, fp64, trace, s);
+  if (e != hipSuccess) {
+    if (dflag) (void)hipFree(dflag);
+    return fail(CLIFFT_E_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  }
+  if (trace) {
+    int h = 0;
+    e = hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dflag);
+    if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("trace failed: ") + hipGetErrorString(e));
+    if (h & 2) return fail(CLIFFT_E_IMPOSSIBLE_OUTCOME, "a forced outcome has probability zero");
+  }
+  return CLIFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+clifft_status clifft_compile(const char* text, size_t len, clifft_program** out) {
+  if (!text || !out) return fail(CLIFFT_E_INVALID_ARG, "null argument");
+  *out = nullptr;
+  clifft_program* p = new clifft_program();
+  std::string err;
+  int rc = compile_text(text, len, p->host, err);
+  if (rc != 0) {
+    delete p;
+    return fail(rc == 1 ? CLIFFT_E_PARSE : rc == 2 ? CLIFFT_E_UNSUPPORTED : CLIFFT_E_CAPACITY, err);
+  }
+  *out = p;
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_program_info(const clifft_program* p, clifft_info* o) {
+  if (!p || !o) return fail(CLIFFT_E_INVALID_ARG, "null argument");
+  const CompiledProgram& H = p->host;
+  o->num_qubits = H.nq;
+  o->frame_words = H.W;
+  o->k_max = H.kmax;
+  o->num_events = H.nevents;
+  o->num_measurements = H.nrec;
+  o->num_detectors = H.ndet;
+  o->num_observables = H.nobs;
+  o->num_noise_sites = (int32_t)H.site_p.size();
+  o->num_instructions = (int32_t)H.code.size();
+  int nr = 0, na = 0;
+  for (int c : H.ev_class) { nr += c == 1; na += c == 2; }
+  o->num_random_events = nr;
+  o->num_active_events = na;
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_k_profile(const clifft_program* p, int32_t* out, size_t cap, size_t* n) {
+  if (!p || !n) return fail(CLIFFT_E_INVALID_ARG, "null argument");
+  const auto& v = p->host.k_after;
+  *n = v.size();
+  for (size_t i = 0; out && i < v.size() && i < cap; i++) out[i] = v[i];
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_event_classes(const clifft_program* p, int32_t* out, size_t cap, size_t* n) {
+  if (!p || !n) return fail(CLIFFT_E_INVALID_ARG, "null argument");
+  const auto& v = p->host.ev_class;
+  *n = v.size();
+  for (size_t i = 0; out && i < v.size() && i < cap; i++) out[i] = v[i];
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_final_slots(const clifft_program* p, int32_t* slots, int32_t* k) {
+  if (!p || !k) return fail(CLIFFT_E_INVALID_ARG, "null argument");
+  const auto& v = p->host.final_slots;
+  *k = (int32_t)v.size();
+  for (size_t i = 0; slots && i < v.size(); i++) slots[i] = v[i];
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes) {
+  if (!p || !bytes) return fail(CLIFFT_E_INVALID_ARG, "null argument");
+  LaunchShape L{};
+  bool fp64 = false;
+  clifft_status st = choose_shape(p->host, nullptr, cfg, ~0ull >> 8, &L, &fp64);
+  if (st != CLIFFT_OK) return st;
+  *bytes = workspace_bytes(p->host, L, fp64);
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_sample(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                            const clifft_launch* cfg, void* workspace, size_t workspace_bytes, uint64_t* meas,
+                            uint64_t* det, uint64_t* obs, void* stream) {
+  return do_sample(p, shots, seed, shot_offset, cfg, workspace, workspace_bytes, meas, det, obs, stream, nullptr,
+                   nullptr, nullptr, nullptr, false);
+}
+
+clifft_status clifft_sample_trace(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                                  const clifft_launch* cfg, const uint32_t* forced_m, const int32_t* forced_faults,
+                                  double* probs, double* phi, void* workspace, size_t workspace_bytes,
+                                  uint64_t* meas, uint64_t* det, uint64_t* obs, void* stream) {
+  return do_sample(p, shots, seed, shot_offset, cfg, workspace, workspace_bytes, meas, det, obs, stream, forced_m,
+                   forced_faults, probs, phi, true);
+}
+
+void clifft_program_free(clifft_program* p) {
+  if (!p) return;
+  for (auto& kv : p->dev) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(kv.first);
+    for (void* a : kv.second.allocs) (void)hipFree(a);
+    (void)hipSetDevice(cur);
+  }
+  delete p;
+}
+
+const char* clifft_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

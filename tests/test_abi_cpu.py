@@ -1,0 +1,91 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/clifft.h declares, its host compiler agrees with the oracle's on the
+physical invariants of each workload, and errors come back as status codes.
+No device work runs here."""
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle
+import paper_2604_27058_amd as pk
+from paper_2604_27058_amd import circuits
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    hdr = open(os.path.join(ROOT, "include", "clifft.h")).read()
+    return sorted(set(re.findall(r"\b(clifft_[a-z_]+)\s*\(", hdr)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert "clifft_sample" in names and "clifft_compile" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", pk.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = pk.lib()
+    for n in names:
+        assert hasattr(L, n)
+
+
+@pytest.mark.parametrize("name", ["random_clifford_t_n8", "surface_d3_r3", "surface_d5_r5_t10", "large_active_k20"])
+def test_compiler_agrees_with_oracle_on_invariants(name):
+    w = circuits.workload(name)
+    text = w["texts"][0]
+    p = pk.Program(text)
+    o = oracle.Program(text)
+    assert p.k_max == o.kmax == w["kmax"]
+    assert p.num_qubits == o.nq
+    assert p.num_measurements == o.nrec
+    assert p.num_detectors == o.ndet
+    assert p.num_observables == o.nobs
+    assert p.num_noise_sites == o.nsites
+    assert p.num_events == o.nevents
+    assert p.event_classes() == [int(c) for c in o.event_classes()]
+    kp = p.k_profile()
+    assert max(kp) == p.k_max and kp[-1] == o.k_profile()[-1]
+
+
+def test_compiler_agrees_with_oracle_on_batched_set():
+    for c in circuits.batched_set()[:16]:
+        p = pk.Program(c["text"])
+        o = oracle.Program(c["text"])
+        assert p.k_max == o.kmax == c["k"]
+        assert p.event_classes() == [int(x) for x in o.event_classes()]
+
+
+def test_final_slots_hold_the_oracles_active_qubits():
+    # slot order may differ (the GPU compiler refills a demoted slot from the
+    # top), the set of active virtual qubits may not
+    text = circuits.random_clifford_t(8, 40, 4, 0.0, seed=1000).replace("M 0 1 2 3 4 5 6 7", "")
+    p = pk.Program(text)
+    t = oracle.Program(text).trace(0, 0)
+    assert sorted(p.final_slots()) == sorted(int(q) for q in t["slots"])
+
+
+def test_status_codes():
+    with pytest.raises(pk.ClifftError) as e:
+        pk.Program("FOO 1\n")
+    assert e.value.status == 2
+    with pytest.raises(pk.ClifftError) as e:
+        pk.Program("REPEAT 2 {\nH 0\n")
+    assert e.value.status == 1
+    with pytest.raises(pk.ClifftError) as e:
+        pk.Program("H 300\n")
+    assert e.value.status == 3
+    with pytest.raises(pk.ClifftError) as e:
+        pk.Program("DETECTOR rec[-1]\n")
+    assert e.value.status == 1
+
+
+def test_workspace_size_host_only():
+    p = pk.Program(circuits.workload("large_active_k20")["texts"][0])
+    n = p.workspace_size(pk.make_launch("f32", threads_per_shot=256, grid=4))
+    assert n == 4 * (1 << 20) * 8
+    small = pk.Program(circuits.workload("surface_d3_r3")["texts"][0])
+    assert small.workspace_size() == 0

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bar: records bit-exact for Pauli-frame-only circuits; with
+FP64 amplitudes records bit-exact on every circuit (the only possible
+difference is a uniform draw falling between two probabilities that differ
+by rounding); with FP32 amplitudes records identical except for such
+near-threshold shots, bounded here; forced-outcome probabilities within
+1e-12 (FP64) and 2e-5 relative (FP32); final active vectors equal after
+slot permutation and global-phase alignment within the same tolerances.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import paper_2604_27058_amd as pk
+from paper_2604_27058_amd import circuits
+from test_oracle_pins import random_small_circuit
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    yield
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def gpu_sample(text_or_prog, shots, seed=0, offset=0, **launch):
+    p = text_or_prog if isinstance(text_or_prog, pk.Program) else pk.Program(text_or_prog)
+    L = pk.make_launch(**launch) if launch else None
+    m, d, o = p.sample(shots, seed=seed, offset=offset, launch=L)
+    torch.cuda.synchronize()
+    return u64(m), u64(d), u64(o)
+
+
+def mismatched_shots(a, b, shots):
+    """Shots whose records differ between two record-major bit arrays."""
+    if a.size == 0:
+        return 0
+    diff = np.bitwise_or.reduce(a ^ b, axis=0)
+    return int(sum(bin(int(w)).count("1") for w in diff))
+
+
+def test_in_tree_library_is_the_one_loaded():
+    gpu_sample(circuits.surface_code_memory(3, 1, 1e-3), 64)
+    maps = open("/proc/self/maps").read()
+    assert pk.LIB_PATH in maps
+
+
+@pytest.mark.parametrize("G", [1, 64, 256])
+def test_surface_d3_bit_exact(G):
+    text = circuits.workload("surface_d3_r3")["texts"][0]
+    shots = 20000 + 37  # ragged last tile
+    om, od, oo = oracle.Program(text).sample(shots, seed=11, threads=8)
+    gm, gd, go = gpu_sample(text, shots, seed=11, threads_per_shot=G)
+    assert np.array_equal(gm, om)
+    assert np.array_equal(gd, od)
+    assert np.array_equal(go, oo)
+
+
+def test_surface_d3_high_noise_bit_exact_multi_chunk():
+    # many faults per shot and more than one 4096-site survival chunk
+    text = circuits.surface_code_memory(3, 120, 2e-2)
+    p = oracle.Program(text)
+    assert p.nchunks >= 2
+    shots = 3000
+    om, od, oo = p.sample(shots, seed=5, threads=8)
+    gm, gd, go = gpu_sample(text, shots, seed=5)
+    assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
+
+
+def test_shard_resume_bit_identical_gpu():
+    text = circuits.surface_code_memory(3, 3, 1e-2)
+    a = gpu_sample(text, 1024, seed=5)
+    b = gpu_sample(text, 512, seed=5, offset=0)
+    c = gpu_sample(text, 512, seed=5, offset=512)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, np.concatenate([y, z], axis=1))
+
+
+@pytest.mark.parametrize("case", range(16))
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_random_circuits_records(case, precision):
+    rng = np.random.default_rng(100 + case)
+    n = int(rng.integers(2, 6))
+    text = random_small_circuit(rng, n, int(rng.integers(10, 45)))
+    shots = 700
+    om, od, oo = oracle.Program(text).sample(shots, seed=case, threads=4)
+    gm, gd, go = gpu_sample(text, shots, seed=case, precision=precision)
+    bad = mismatched_shots(np.vstack([om, od, oo]) if om.size else om, np.vstack([gm, gd, go]) if gm.size else gm,
+                           shots)
+    if precision == "f64":
+        assert bad == 0
+    else:
+        assert bad <= 2
+
+
+def _phi_in_oracle_order(phi_g, gslots, oslots):
+    """Permute a GPU active vector (slot s holds virtual qubit gslots[s]) to
+    the oracle's slot order."""
+    pos = {q: t for t, q in enumerate(oslots)}
+    out = np.zeros_like(phi_g)
+    for i in range(len(phi_g)):
+        j = 0
+        for s, q in enumerate(gslots):
+            if (i >> s) & 1:
+                j |= 1 << pos[q]
+        out[j] = phi_g[i]
+    return out
+
+
+def _align(a, b):
+    """Normalise both and remove the global phase of a relative to b."""
+    a = a / np.linalg.norm(a)
+    b = b / np.linalg.norm(b)
+    ov = np.vdot(a, b)
+    return a * (ov / abs(ov)), b
+
+
+@pytest.mark.parametrize("case", range(12))
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
+def test_forced_probabilities_and_amplitudes(case, precision, tol):
+    rng = np.random.default_rng(700 + case)
+    n = int(rng.integers(2, 6))
+    text = random_small_circuit(rng, n, int(rng.integers(10, 45))).rsplit("M ", 1)[0]  # keep the final vector
+    op = oracle.Program(text)
+    gp = pk.Program(text)
+    shots = 8
+    fm = np.zeros((shots, max(op.nevents, 1)), np.uint32)
+    ff = np.full((shots, max(op.nsites, 1)), -1, np.int32)
+    traces = []
+    for s in range(shots):
+        # force the faults and outcomes of an oracle shot (plus extra faults)
+        faults = op.faults(case, s)
+        for i in range(op.nsites):
+            if rng.random() < 0.2:
+                faults[i] = int(rng.integers(0, 1 if "ERROR" in text else 3))
+        t0 = op.trace(case, s, forced_faults=faults)
+        t = op.trace(case, s, forced_m=t0["m"], forced_faults=faults)
+        assert t["error"] == 0
+        fm[s, : op.nevents] = t["m"]
+        ff[s, : op.nsites] = faults
+        traces.append(t)
+    L = pk.make_launch(precision)
+    res = gp.sample_trace(shots, seed=case, launch=L, forced_m=torch.from_numpy(fm[:, : max(op.nevents, 0)]),
+                          forced_faults=torch.from_numpy(ff[:, : max(op.nsites, 0)]))
+    torch.cuda.synchronize()
+    probs = res["probs"].cpu().numpy()
+    phi = res["phi"].cpu().numpy()
+    gslots = gp.final_slots()
+    for s, t in enumerate(traces):
+        if op.nevents:
+            np.testing.assert_allclose(probs[s], t["probs"], atol=tol, rtol=0)
+        k = t["k"]
+        assert len(gslots) == k
+        a, b = _align(_phi_in_oracle_order(phi[s, : 1 << k], gslots, list(t["slots"])), t["phi"])
+        assert np.linalg.norm(a - b) <= tol * 10
+
+
+@pytest.mark.parametrize("G", [1, 64, 256])
+def test_clifford_t_n8_fp64_bit_exact(G):
+    w = circuits.workload("random_clifford_t_n8")
+    text = w["texts"][0]
+    shots = w["shots"]
+    om, _, _ = oracle.Program(text).sample(shots, seed=0, threads=8)
+    gm, _, _ = gpu_sample(text, shots, seed=0, precision="f64", threads_per_shot=G)
+    assert np.array_equal(gm, om)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_surface_d5_t10_records(precision):
+    text = circuits.workload("surface_d5_r5_t10")["texts"][0]
+    shots = 4096 + 5
+    om, od, oo = oracle.Program(text).sample(shots, seed=3, threads=8)
+    gm, gd, go = gpu_sample(text, shots, seed=3, precision=precision)
+    bad = mismatched_shots(np.vstack([om, od, oo]), np.vstack([gm, gd, go]), shots)
+    if precision == "f64":
+        assert bad == 0
+    else:
+        assert bad <= 3
+
+
+def test_large_active_k20_sampled_shots():
+    text = circuits.workload("large_active_k20")["texts"][0]
+    op = oracle.Program(text)
+    shots = 4
+    gm, _, _ = gpu_sample(text, shots, seed=0, precision="f32", threads_per_shot=256)
+    om, _, _ = op.sample(shots, seed=0, threads=4)
+    assert mismatched_shots(om, gm, shots) == 0
