@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the sample-many path on one MI355X.
+
+A step is one clifft_sample call over the whole workload (every shot of the
+batch through the compiled stream: frames, noise, active vector, records),
+with the program resident on the device and the outputs preallocated.
+Prints one JSON line (driver contract).
+
+Default workload: rotated surface-code memory d = 3, 3 rounds,
+circuit-level depolarizing p = 1e-3, 1e7 shots (the Pauli-frame
+configuration of the benchmark table).  Other workloads: --workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shots/sec at matched detector-rate accuracy, FP32-batched vs FP64-plain"
+PEAK_INT_OPS = 256 * 64 * 2.4e9      # 32-bit VALU lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+PEAK_FP32 = 157.3e12                 # FP32 vector FLOP/s
+PEAK_FP64 = 78.6e12                  # FP64 vector FLOP/s
+PEAK_HBM = 8.0e12                    # HBM3E bytes/s
+PEAK_LDS = 256 * 128 * 2.4e9         # LDS bytes/s: 128 B/clk/CU
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "program.h", "kernels.h"):
+        h.update(open(os.path.join(ROOT, "paper_2604_27058_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, precision):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, precision))
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(text, shots_hint, seed):
+    """The FP64 oracle timed on the host cores on a bounded sample."""
+    import oracle
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    prog = oracle.Program(text)
+    n = 4096
+    t0 = time.perf_counter()
+    prog.sample(n, seed=seed, threads=threads)
+    dt = time.perf_counter() - t0
+    # scale the sample to about 10 s of CPU time, within the workload's shots
+    target = min(shots_hint, max(64, int(n * 10.0 / max(dt, 1e-6))))
+    target = (target + 63) // 64 * 64
+    t0 = time.perf_counter()
+    meas, det, obs = prog.sample(target, seed=seed, threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=target / dt, unit="shots/s", cores=threads, kind="oracle",
+                sample="first %d shots of the workload (seed %d), FP64 oracle, %d threads, %.1f s"
+                       % (target, seed, threads, dt)), (target, meas, det, obs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="surface_d3_r3")
+    ap.add_argument("--precision", default=None, help="f32 or f64 (default: the workload's)")
+    ap.add_argument("--threads-per-shot", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (shards would run "
+              "independent shot ranges, see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2604_27058_amd as pk
+    from paper_2604_27058_amd import circuits
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    w = circuits.workload(args.workload)
+    precision = args.precision or w["precision"]
+    shots = w["shots"]
+    seed = 0
+    if len(w["texts"]) != 1:
+        print("batched workloads are benchmarked by bench_batch (not part of this line)", file=sys.stderr)
+        sys.exit(2)
+    text = w["texts"][0]
+    prog = pk.Program(text)
+    launch = pk.make_launch(precision, threads_per_shot=args.threads_per_shot, grid=args.grid)
+    outs = prog.alloc_outputs(shots)
+    ws = prog.alloc_workspace(launch)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        prog.sample(shots, seed=seed, launch=launch, outputs=outs, workspace=ws)
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        prog.sample(shots, seed=seed, launch=launch, outputs=outs, workspace=ws)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
+    ms_per_step = wall * 1e3 / args.steps
+    value = shots * args.steps / wall
+
+    cost = prog.cost_model(precision)
+    k = prog.k_max
+    if k == 0:
+        achieved = cost["int_ops"] * shots / (kernel_ms * 1e-3)
+        roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT_OPS / 1e12, unit="Tops/s",
+                    frac=achieved / PEAK_INT_OPS)
+    elif k <= 14:
+        achieved = cost["vector_bytes"] * shots / (kernel_ms * 1e-3)
+        roof = dict(bound="lds", achieved=achieved / 1e9, peak=PEAK_LDS / 1e9, unit="GB/s", frac=achieved / PEAK_LDS)
+    else:
+        achieved = cost["vector_bytes"] * shots / (kernel_ms * 1e-3)
+        roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=achieved / PEAK_HBM)
+    traffic = load_traffic(args.workload, precision)
+    roof["traffic"] = traffic
+    roof["kernel_ms"] = kernel_ms
+    roof["work_per_shot"] = {kk: round(v, 3) for kk, v in cost.items()}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64" if k == 0 else precision, "data": "synthetic",
+        "config": {"workload": args.workload, "shots": shots, "qubits": prog.num_qubits, "k_max": k,
+                   "detectors": prog.num_detectors, "noise_sites": prog.num_noise_sites,
+                   "precision": precision, "parallelism": "shots across lanes/waves of one GPU"},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        import numpy as np
+        cb, (n, om, od, oo) = cpu_baseline(text, shots, seed)
+        line["cpu_baseline"] = cb
+        # records of the sampled shots must equal the oracle's
+        words = (n + 63) // 64
+        gm = outs[0][:, :words].cpu().numpy().view(np.uint64)
+        gd = outs[1][:, :words].cpu().numpy().view(np.uint64)
+        go = outs[2][:, :words].cpu().numpy().view(np.uint64)
+        diff = np.zeros(words, np.uint64)
+        for g, o in ((gm, om), (gd, od), (go, oo)):
+            if g.size:
+                diff |= np.bitwise_or.reduce(g ^ o, axis=0)
+        line["cpu_baseline"]["gpu_records_differing_on_sample"] = int(
+            sum(bin(int(x)).count("1") for x in diff))
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

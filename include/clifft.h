@@ -99,6 +99,22 @@ clifft_status clifft_event_classes(const clifft_program* p, int32_t* out, size_t
  * (host array of k_max entries); *k receives the final active dimension. */
 clifft_status clifft_final_slots(const clifft_program* p, int32_t* slots, int32_t* k);
 
+/* Algorithmic work of one shot, summed over the compiled stream with the
+ * active dimension in force at each instruction (the per-shot cost of
+ * Section 2.5, Eq. for the per-shot cost, made concrete).  Integer work
+ * counts 32-bit lane operations (a 64-bit word operation is two); noise work
+ * uses the expected number of realized faults; vector traffic is the bytes
+ * an unfused pass per instruction reads and writes at `precision`. */
+typedef struct clifft_cost {
+  double int_ops;         /* 32-bit integer lane-operations (frames, noise, records) */
+  double flops;           /* floating-point operations on the active vector */
+  double vector_bytes;    /* active-vector bytes read + written */
+  double record_bytes;    /* bit-packed record bytes written */
+  double expected_faults; /* mean number of realized faults */
+  double instructions;    /* compiled instructions executed */
+} clifft_cost;
+clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clifft_cost* out);
+
 /* Bytes of caller-provided device workspace a sample call needs with this
  * configuration (0 when the active vectors fit in LDS). */
 clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes);

@@ -29,6 +29,11 @@ class clifft_info(ctypes.Structure):
         "num_observables", "num_noise_sites", "num_instructions", "num_random_events", "num_active_events")]
 
 
+class clifft_cost(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "int_ops", "flops", "vector_bytes", "record_bytes", "expected_faults", "instructions")]
+
+
 class clifft_launch(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("threads_per_shot", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("vector_in_hbm", ctypes.c_int32)]
@@ -54,10 +59,12 @@ def lib():
         L.clifft_sample.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, sz, vp, vp, vp, vp]
         L.clifft_sample_trace.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp, vp, sz,
                                           vp, vp, vp, vp]
+        L.clifft_cost_model.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(clifft_cost)]
         L.clifft_program_free.argtypes = [vp]
         L.clifft_last_error.restype = ctypes.c_char_p
         for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
-                  "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_trace"):
+                  "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_trace",
+                  "clifft_cost_model"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -110,6 +117,13 @@ class Program:
         k = ctypes.c_int32()
         _check(lib().clifft_final_slots(self._h, out, ctypes.byref(k)))
         return list(out)[: k.value]
+
+    def cost_model(self, precision="f32"):
+        """Per-shot algorithmic work (clifft_cost_model) as a dict."""
+        c = clifft_cost()
+        _check(lib().clifft_cost_model(self._h, CLIFFT_FP64 if precision == "f64" else CLIFFT_FP32,
+                                       ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in clifft_cost._fields_}
 
     def workspace_size(self, launch=None):
         n = ctypes.c_size_t()

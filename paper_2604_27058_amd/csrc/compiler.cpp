@@ -18,6 +18,7 @@
 #include "compiler.h"
 
 #include <cctype>
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -549,6 +550,58 @@ static void survival_tables(CompiledProgram& P) {
     }
     for (int i = hi - lo + 1; i <= kChunk; i++) S[i] = 0.0;  // beyond the chunk: never fires
   }
+}
+
+// Per-shot algorithmic work, summed over the compiled stream with the k in
+// force at each instruction (A = 2^k amplitudes before the instruction, a =
+// bytes per amplitude, W = frame words; a 64-bit word operation counts as two
+// 32-bit lane operations; both Pauli frames are updated by frame operations).
+//   fan (CX / CZ / target fan)   16W + 12 int ops
+//   frame S or H                 12 int ops
+//   deterministic measurement    8W + 8 int ops
+//   dormant random measurement   22 int ops
+//   reset correction             16W int ops
+//   noise block                  2 int ops, + 158 + 24W per expected fault
+//                                (draw, search, apply), + 158 per chunk
+//   detector / observable        2/64 int op per reference (word XOR)
+//   EXPAND        6A flops,  2A a bytes     AROT   3A flops,  A a bytes
+//   AH            4A flops,  2A a bytes     AS / ASIGN / APERM / APERM2: A a bytes
+//   active Z meas 5A flops,  2A a bytes     active X meas 8A flops, 2.5A a bytes
+//                 (+ 110 int ops: draw and bookkeeping)
+CostModel cost_model(const CompiledProgram& P, bool fp64) {
+  CostModel c;
+  const double W = P.W, a = fp64 ? 16.0 : 8.0;
+  for (size_t i = 0; i < P.code.size(); i++) {
+    const GInstr& in = P.code[i];
+    int kb = (int)(i == 0 ? 0 : P.k_after[i - 1]);
+    double A = std::ldexp(1.0, kb);
+    c.instructions += 1;
+    switch (in.op) {
+      case OP_FANCX: case OP_FANCZ: case OP_FAN2: c.int_ops += 16 * W + 12; break;
+      case OP_FS: case OP_FH: c.int_ops += 12; break;
+      case OP_APERM: case OP_APERM2: case OP_ASIGN: case OP_AS: c.vector_bytes += A * a; c.int_ops += 4; break;
+      case OP_AH: c.flops += 4 * A; c.vector_bytes += 2 * A * a; break;
+      case OP_EXPAND: c.flops += 6 * A; c.vector_bytes += 2 * A * a; c.int_ops += 12; break;
+      case OP_AROT: c.flops += 3 * A; c.vector_bytes += A * a; c.int_ops += 4; break;
+      case OP_MSTATIC: c.int_ops += 8 * W + 8; break;
+      case OP_MRANDOM: c.int_ops += 22; break;
+      case OP_MACTZ: c.flops += 5 * A; c.vector_bytes += 2 * A * a; c.int_ops += 110; break;
+      case OP_MACTX: c.flops += 8 * A; c.vector_bytes += 2.5 * A * a; c.int_ops += 110; break;
+      case OP_CPAULI: c.int_ops += 16 * W; break;
+      case OP_NOISE: {
+        double f = 0;
+        for (uint32_t s = in.a; s < in.b; s++) f += P.site_p[s];
+        c.expected_faults += f;
+        c.int_ops += 2 + f * (158 + 24 * W);
+        break;
+      }
+      case OP_DET: case OP_OBS: c.int_ops += in.u * 2.0 / 64.0; break;
+      default: break;
+    }
+  }
+  c.int_ops += 158.0 * P.nchunks;
+  c.record_bytes = (P.nrec + P.ndet + P.nobs) / 8.0;
+  return c;
 }
 
 int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& err) {

@@ -26,6 +26,17 @@ struct CompiledProgram {
   std::vector<int> final_slots;    // virtual qubit held by each slot at the end
 };
 
+// Algorithmic work of one shot (see cost_model in compiler.cpp).
+struct CostModel {
+  double int_ops = 0;          // 32-bit integer lane-operations
+  double flops = 0;            // floating-point operations on the active vector
+  double vector_bytes = 0;     // active-vector bytes read + written (unfused)
+  double record_bytes = 0;     // bit-packed record bytes written
+  double expected_faults = 0;  // mean realized faults
+  double instructions = 0;     // compiled instructions executed
+};
+CostModel cost_model(const CompiledProgram& P, bool fp64);
+
 // Returns 0 on success, 1 parse error, 2 unsupported instruction, 3 capacity.
 int compile_text(const char* text, size_t len, CompiledProgram& out, std::string& err);
 

@@ -204,6 +204,94 @@ struct Vec {
 // Iterate p over [0, n) split among the threads of a group.
 #define FOR_GROUP(p, n) for (uint32_t p = (G == 1 ? 0u : (uint32_t)grp.tid); p < (n); p += (G == 1 ? 1u : (uint32_t)G))
 
+// Unrolled passes over the active vector.  Iteration p touches an element
+// set disjoint from every other iteration's, so a batch of U iterations
+// issues all its loads before its stores (U independent loads in flight per
+// lane) without any hazard.
+constexpr int kUnroll = 4;
+
+// Read-modify-write of one element per iteration: i = idx(p).
+template <int G, typename R, typename IdxF, typename BodyF>
+DEV void pass1(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body) {
+  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
+  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += kUnroll * st) {
+    uint32_t ii[kUnroll];
+    cpx<R> a[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+      uint32_t p = base + u * st;
+      ii[u] = idx(p < n ? p : base);
+      if (p < n) a[u] = vec[ii[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++)
+      if (base + u * st < n) vec[ii[u]] = body(a[u]);
+  }
+}
+
+// Read-modify-write of a pair per iteration: (i0, i1) = idx(p).
+template <int G, typename R, typename IdxF, typename BodyF>
+DEV void pass2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body) {
+  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
+  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += kUnroll * st) {
+    uint32_t i0[kUnroll], i1[kUnroll];
+    cpx<R> a[kUnroll], b[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+      uint32_t p = base + u * st;
+      idx(p < n ? p : base, i0[u], i1[u]);
+      if (p < n) { a[u] = vec[i0[u]]; b[u] = vec[i1[u]]; }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++)
+      if (base + u * st < n) {
+        body(a[u], b[u]);
+        vec[i0[u]] = a[u];
+        vec[i1[u]] = b[u];
+      }
+  }
+}
+
+// Two reads, one write per iteration: out[wi(p)] = body(in[r0(p)], in[r1(p)])
+// (r1 may equal r0).  Used where a pass writes fewer elements than it reads.
+template <int G, typename R, typename IdxF, typename BodyF>
+DEV void pass21(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body) {
+  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
+  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += kUnroll * st) {
+    uint32_t r0[kUnroll], r1[kUnroll], wi[kUnroll];
+    cpx<R> a[kUnroll], b[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+      uint32_t p = base + u * st;
+      idx(p < n ? p : base, r0[u], r1[u], wi[u]);
+      if (p < n) { a[u] = vec[r0[u]]; b[u] = vec[r1[u]]; }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++)
+      if (base + u * st < n) vec[wi[u]] = body(a[u], b[u]);
+  }
+}
+
+// Read-only pairs accumulated into two FP64 sums.
+template <int G, typename R, typename IdxF, typename BodyF>
+DEV void reduce2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body, double& s0,
+                 double& s1) {
+  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
+  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += kUnroll * st) {
+    cpx<R> a[kUnroll], b[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+      uint32_t p = base + u * st;
+      uint32_t i0, i1;
+      idx(p < n ? p : base, i0, i1);
+      if (p < n) { a[u] = vec[i0]; b[u] = vec[i1]; }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++)
+      if (base + u * st < n) body(a[u], b[u], s0, s1);
+  }
+}
+
 template <typename R>
 DEV cpx<R> cmul(cpx<R> a, R cr, R ci) { return cpx<R>{a.re * cr - a.im * ci, a.re * ci + a.im * cr}; }
 template <typename R>
@@ -269,7 +357,7 @@ DEV void apply_fault(const DevProgram& P, Frame<W>& T, Frame<W>& N, uint32_t sit
 }
 
 // ------------------------------------------------------------------ one shot
-template <int W, int G, typename R, bool DBG>
+template <int W, int G, typename R, bool DBG, bool VEC>
 struct Shot {
   const DevProgram& P;
   const KArgs& A;
@@ -318,7 +406,7 @@ struct Shot {
       if (DBG && A.forced_faults) ns.nf = 0xFFFFFFFFu;
       else next_fault(P, ns, 0, shot, seed);
     }
-    if (P.kmax > 0) {
+    if (VEC && P.kmax > 0) {
       FOR_GROUP(p, 1u) vec[p] = cpx<R>{(R)1, (R)0};
       grp.sync();
     }
@@ -357,70 +445,85 @@ struct Shot {
         case OP_FS: frame_s<W>(T, v); frame_s<W>(N, v); break;
         case OP_FH: frame_h<W>(T, v); frame_h<W>(N, v); break;
         case OP_APERM: {
-          // for i with bit s set: swap i <-> i ^ tm; representative has the
-          // lowest target bit t0 clear
-          uint32_t tm = in.a;
-          int t0 = __ffs(tm) - 1;
-          int lo = min(s, t0), hi = max(s, t0);
-          uint32_t n = 1u << (k - 2);
-          FOR_GROUP(p, n) {
-            uint32_t i = ins0(ins0(p, lo), hi);
-            i |= 1u << s;
-            cpx<R> a = vec[i], b = vec[i ^ tm];
-            vec[i] = b;
-            vec[i ^ tm] = a;
-          }
+          if constexpr (!VEC) break;
+          else {
+          // control slot s, targets tm: i -> i ^ tm for i with bit s set; each
+          // pair is visited once from the member with target bit t0 clear
+          const uint32_t tm = in.a, bs = 1u << s;
+          const int t0 = __ffs(tm) - 1;
+          const int lo = min(s, t0), hi = max(s, t0);
+          pass2<G, R>(grp, vec, 1u << (k - 2),
+                      [&](uint32_t p, uint32_t& i0, uint32_t& i1) { i0 = ins0(ins0(p, lo), hi) | bs; i1 = i0 ^ tm; },
+                      [](cpx<R>& a, cpx<R>& b) { cpx<R> t = a; a = b; b = t; });
           grp.sync();
+          }
           break;
         }
         case OP_ASIGN: {
-          uint32_t sm = in.a;
-          uint32_t n = 1u << (k - 1);
-          FOR_GROUP(p, n) {
-            uint32_t i = ins0(p, s) | (1u << s);
-            if (__popc(i & sm) & 1) { cpx<R> a = vec[i]; vec[i] = cpx<R>{-a.re, -a.im}; }
-          }
+          if constexpr (!VEC) break;
+          else {
+          // -1 on i with bit s set and odd parity of i & sm: enumerate i with
+          // bits s and c (lowest of sm) free, then fix bit c to make it odd
+          const uint32_t sm = in.a, bs = 1u << s;
+          const int c = __ffs(sm) - 1;
+          const int lo = min(s, c), hi = max(s, c);
+          pass1<G, R>(grp, vec, 1u << (k - 2),
+                      [&](uint32_t p) {
+                        uint32_t i = ins0(ins0(p, lo), hi) | bs;
+                        return i | ((uint32_t)((__popc(i & sm) & 1) ^ 1) << c);
+                      },
+                      [](cpx<R> a) { return cpx<R>{-a.re, -a.im}; });
           grp.sync();
+          }
           break;
         }
         case OP_APERM2: {
-          uint32_t sm = in.a;
-          uint32_t n = 1u << (k - 1);
-          FOR_GROUP(p, n) {
-            uint32_t i0 = ins0(p, s);
-            if (__popc(i0 & sm) & 1) {
-              uint32_t i1 = i0 | (1u << s);
-              cpx<R> a = vec[i0], b = vec[i1];
-              vec[i0] = b;
-              vec[i1] = a;
-            }
-          }
+          if constexpr (!VEC) break;
+          else {
+          // flip bit s where parity(i & sm) is odd: pairs along s with odd parity
+          const uint32_t sm = in.a, bs = 1u << s;
+          const int c = __ffs(sm) - 1;
+          const int lo = min(s, c), hi = max(s, c);
+          pass2<G, R>(grp, vec, 1u << (k - 2),
+                      [&](uint32_t p, uint32_t& i0, uint32_t& i1) {
+                        uint32_t i = ins0(ins0(p, lo), hi);
+                        i0 = i | ((uint32_t)((__popc(i & sm) & 1) ^ 1) << c);
+                        i1 = i0 | bs;
+                      },
+                      [](cpx<R>& a, cpx<R>& b) { cpx<R> t = a; a = b; b = t; });
           grp.sync();
+          }
           break;
         }
         case OP_AS: {
-          uint32_t n = 1u << (k - 1);
-          FOR_GROUP(p, n) {
-            uint32_t i = ins0(p, s) | (1u << s);
-            cpx<R> a = vec[i];
-            vec[i] = cpx<R>{-a.im, a.re};
-          }
+          if constexpr (!VEC) break;
+          else {
+          const uint32_t bs = 1u << s;
+          pass1<G, R>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
+                      [](cpx<R> a) { return cpx<R>{-a.im, a.re}; });
           grp.sync();
+          }
           break;
         }
         case OP_AH: {
+          if constexpr (!VEC) break;
+          else {
           const R h = (R)0.70710678118654752440;
-          uint32_t n = 1u << (k - 1);
-          FOR_GROUP(p, n) {
-            uint32_t i0 = ins0(p, s), i1 = i0 | (1u << s);
-            cpx<R> a = vec[i0], b = vec[i1];
-            vec[i0] = cpx<R>{h * (a.re + b.re), h * (a.im + b.im)};
-            vec[i1] = cpx<R>{h * (a.re - b.re), h * (a.im - b.im)};
-          }
+          const uint32_t bs = 1u << s;
+          pass2<G, R>(grp, vec, 1u << (k - 1),
+                      [&](uint32_t p, uint32_t& i0, uint32_t& i1) { i0 = ins0(p, s); i1 = i0 | bs; },
+                      [h](cpx<R>& a, cpx<R>& b) {
+                        cpx<R> x{h * (a.re + b.re), h * (a.im + b.im)};
+                        b = cpx<R>{h * (a.re - b.re), h * (a.im - b.im)};
+                        a = x;
+                      });
           grp.sync();
+          }
           break;
         }
         case OP_EXPAND: {
+          if constexpr (!VEC) break;
+          else {
           // Appendix B.1 case 2: H_v takes |0>_v to |+>_v (frames conjugated);
           // then exp(-i theta' Z_v) on the new axis, theta' sign-flipped by
           // x_v of the frame.  The common phase e^{-i theta'} is global, so
@@ -429,23 +532,26 @@ struct Shot {
           frame_h<W>(N, v);
           double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
           if (getbit<W>(T.x, v)) s2 = -s2;
-          R cr = (R)c2, ci = (R)s2;
-          uint32_t n = 1u << k;
-          FOR_GROUP(p, n) vec[p | n] = cmul(vec[p], cr, ci);
+          const R cr = (R)c2, ci = (R)s2;
+          const uint32_t n = 1u << k;
+          pass21<G, R>(grp, vec, n, [&](uint32_t p, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = r1 = p; w = p | n; },
+                       [cr, ci](cpx<R> a, cpx<R>) { return cmul(a, cr, ci); });
           k++;
           grp.sync();
+          }
           break;
         }
         case OP_AROT: {
+          if constexpr (!VEC) break;
+          else {
           double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
           if (getbit<W>(T.x, v)) s2 = -s2;
-          R cr = (R)c2, ci = (R)s2;
-          uint32_t n = 1u << (k - 1);
-          FOR_GROUP(p, n) {
-            uint32_t i = ins0(p, s) | (1u << s);
-            vec[i] = cmul(vec[i], cr, ci);
-          }
+          const R cr = (R)c2, ci = (R)s2;
+          const uint32_t bs = 1u << s;
+          pass1<G, R>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
+                      [cr, ci](cpx<R> a) { return cmul(a, cr, ci); });
           grp.sync();
+          }
           break;
         }
         case OP_MSTATIC: {
@@ -494,6 +600,8 @@ struct Shot {
         }
         case OP_MACTZ:
         case OP_MACTX: {
+          if constexpr (!VEC) break;
+          else {
           const bool isx = in.op == OP_MACTX;
           uint32_t j = in.b;
           uint32_t sign = in.flags & F_SIGN;
@@ -502,17 +610,16 @@ struct Shot {
           const uint32_t bs = 1u << s;
           const uint32_t half = 1u << (k - 1);
           double s0 = 0, s1 = 0;
-          FOR_GROUP(q, half) {
-            uint32_t i0 = ins0(q, s);
-            cpx<R> a = vec[i0], b = vec[i0 | bs];
-            if (isx) {
-              s0 += norm2(cpx<R>{a.re + b.re, a.im + b.im});
-              s1 += norm2(cpx<R>{a.re - b.re, a.im - b.im});
-            } else {
-              s0 += norm2(a);
-              s1 += norm2(b);
-            }
-          }
+          reduce2<G, R>(grp, vec, half, [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = i0 | bs; },
+                        [isx](cpx<R> a, cpx<R> b, double& x0, double& x1) {
+                          if (isx) {
+                            x0 += norm2(cpx<R>{a.re + b.re, a.im + b.im});
+                            x1 += norm2(cpx<R>{a.re - b.re, a.im - b.im});
+                          } else {
+                            x0 += norm2(a);
+                            x1 += norm2(b);
+                          }
+                        }, s0, s1);
           s0 = grp.sum(s0, red);
           s1 = grp.sum(s1, red);
           if (isx) { s0 *= 0.5; s1 *= 0.5; }
@@ -546,34 +653,40 @@ struct Shot {
           // slot k-1 takes the place of slot s (no hazard: every thread
           // owns its two outputs and reads only them and the top half)
           const int top = k - 1;
+          auto out1 = [&](cpx<R> a, cpx<R> c) -> cpx<R> {
+            if (isx) return cpx<R>{fs * scale * (a.re + sgn * c.re), fs * scale * (a.im + sgn * c.im)};
+            return b ? cpx<R>{scale * c.re, scale * c.im} : cpx<R>{scale * a.re, scale * a.im};
+          };
           if (s == top) {
-            FOR_GROUP(q, half) {
-              cpx<R> a = vec[q], c = vec[q | bs];
-              cpx<R> o;
-              if (isx) o = cpx<R>{fs * scale * (a.re + sgn * c.re), fs * scale * (a.im + sgn * c.im)};
-              else o = b ? cpx<R>{scale * c.re, scale * c.im} : cpx<R>{scale * a.re, scale * a.im};
-              vec[q] = o;
-            }
+            pass21<G, R>(grp, vec, half,
+                         [&](uint32_t q, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = w = q; r1 = q | bs; },
+                         [&](cpx<R> a, cpx<R> c) { return out1(a, c); });
           } else {
+            // pair (j0, j1 = j0 | bs) of outputs reads its own two elements and
+            // the two above them in the top slot
             const uint32_t tb = 1u << top;
-            uint32_t n4 = half >> 1;
-            FOR_GROUP(q, n4) {
-              uint32_t j0 = ins0(q, s);  // k-1 bit index with bit s clear (bit top clear)
-              uint32_t j1 = j0 | bs;
-              cpx<R> a0 = vec[j0], a1 = vec[j1], c0 = vec[j0 | tb], c1 = vec[j1 | tb];
-              cpx<R> o0, o1;
-              if (isx) {
-                o0 = cpx<R>{fs * scale * (a0.re + sgn * a1.re), fs * scale * (a0.im + sgn * a1.im)};
-                o1 = cpx<R>{fs * scale * (c0.re + sgn * c1.re), fs * scale * (c0.im + sgn * c1.im)};
-              } else if (b) {
-                o0 = cpx<R>{scale * a1.re, scale * a1.im};
-                o1 = cpx<R>{scale * c1.re, scale * c1.im};
-              } else {
-                o0 = cpx<R>{scale * a0.re, scale * a0.im};
-                o1 = cpx<R>{scale * c0.re, scale * c0.im};
+            const uint32_t n4 = half >> 1;
+            const uint32_t st = G == 1 ? 1u : (uint32_t)G;
+            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += kUnroll * st) {
+              uint32_t jj[kUnroll];
+              cpx<R> a0[kUnroll], a1[kUnroll], c0[kUnroll], c1[kUnroll];
+#pragma unroll
+              for (int u = 0; u < kUnroll; u++) {
+                uint32_t q = base + u * st;
+                jj[u] = ins0(q < n4 ? q : base, s);
+                if (q < n4) {
+                  a0[u] = vec[jj[u]];
+                  a1[u] = vec[jj[u] | bs];
+                  c0[u] = vec[jj[u] | tb];
+                  c1[u] = vec[jj[u] | bs | tb];
+                }
               }
-              vec[j0] = o0;
-              vec[j1] = o1;
+#pragma unroll
+              for (int u = 0; u < kUnroll; u++)
+                if (base + u * st < n4) {
+                  vec[jj[u]] = out1(a0[u], a1[u]);
+                  vec[jj[u] | bs] = out1(c0[u], c1[u]);
+                }
             }
           }
           k--;
@@ -584,6 +697,7 @@ struct Shot {
           last_pn = pn;
           int r = as_const(P.ev_rec)[j];
           if (r >= 0) put((uint32_t)r, mm);
+          }
           break;
         }
         case OP_CPAULI: {
@@ -658,7 +772,7 @@ struct Shot {
           A.phi_out[local * 2] = 1.0;
           A.phi_out[local * 2 + 1] = 0.0;
         }
-      } else if (A.phi_out && local < A.shots) {
+      } else if (VEC && A.phi_out && local < A.shots) {
         // final active vector (its length 2^k is program-determined)
         FOR_GROUP(p, (1u << k)) {
           cpx<R> a = vec[p];
@@ -674,7 +788,7 @@ struct Shot {
 // ------------------------------------------------------------------ kernel
 // One persistent launch: units (lanes-of-a-wave for G = 1, waves for G = 64,
 // workgroups for G = 256) take 64-shot tiles round-robin.
-template <int W, int G, typename R, bool GLOBAL, bool DBG>
+template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC>
 __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int units_per_block = G == 256 ? 1 : 4;
@@ -703,14 +817,14 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
     if constexpr (G == 256) __syncthreads();
     else { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
     if constexpr (G == 1) {
-      Shot<W, G, R, DBG> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
+      Shot<W, G, R, DBG, VEC> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
                             A.offset + tile * 64 + lane, tile * 64 + lane};
       sh.run();
     } else {
       uint32_t nsh = (uint32_t)min((uint64_t)64, A.shots - tile * 64);
       for (uint32_t sl = 0; sl < nsh; sl++) {
         uint64_t g = rfl((uint32_t)(tile * 64 + sl)) | ((tile * 64 + sl) & 0xFFFFFFFF00000000ull);
-        Shot<W, G, R, DBG> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, (int)sl, A.offset + g, g};
+        Shot<W, G, R, DBG, VEC> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, (int)sl, A.offset + g, g};
         sh.run();
       }
     }
@@ -735,33 +849,38 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
 }
 
 // ------------------------------------------------------------------ dispatch table
-template <int W, int G, typename R, bool GLOBAL, bool DBG>
+template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC>
 static hipError_t launch_one(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
   static bool attr = false;  // allow the whole 160 KB of LDS for dynamic use
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG, VEC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG>), dim3(grid), dim3(256), lds, st, P, A);
+  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG, VEC>), dim3(grid), dim3(256), lds, st, P, A);
   return hipGetLastError();
 }
 
-template <int G, typename R, bool GLOBAL, bool DBG>
+template <int G, typename R, bool GLOBAL, bool DBG, bool VEC = true>
 static hipError_t launch_w(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
   switch (P.W) {
-    case 1: return launch_one<1, G, R, GLOBAL, DBG>(P, A, grid, lds, st);
-    case 2: return launch_one<2, G, R, GLOBAL, DBG>(P, A, grid, lds, st);
-    case 3: return launch_one<3, G, R, GLOBAL, DBG>(P, A, grid, lds, st);
-    case 4: return launch_one<4, G, R, GLOBAL, DBG>(P, A, grid, lds, st);
+    case 1: return launch_one<1, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
+    case 2: return launch_one<2, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
+    case 3: return launch_one<3, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
+    case 4: return launch_one<4, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename R, bool DBG>
 static hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t st) {
-  if (L.G == 1) return launch_w<1, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+  if (L.G == 1) {
+    // Pauli-frame-only programs get an instantiation without any active-vector code
+    if (P.kmax == 0) return launch_w<1, R, false, DBG, false>(P, A, L.grid, L.lds_bytes, st);
+    if (L.global_vec) return launch_w<1, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
+    return launch_w<1, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+  }
   if (L.G == 64) return launch_w<64, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
   if (L.global_vec) return launch_w<256, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
   return launch_w<256, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);

@@ -96,6 +96,8 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
 }
 
 constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kLaneMaxK = 12;                              // shot-per-lane tier up to this k_max
+constexpr size_t kWorkspaceBudget = (size_t)4 << 30;       // default global vector workspace
 
 int device_cus() {
   int dev = 0, n = 0;
@@ -116,18 +118,17 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
   const size_t vec = (size_t)1 << H.kmax;
   int G = c.threads_per_shot;
   if (G != 0 && G != 1 && G != 64 && G != 256) return fail(CLIFFT_E_INVALID_ARG, "threads_per_shot must be 0, 1, 64 or 256");
-  if (G == 0) {
-    if (H.kmax == 0 || 4 * vec * 64 * amp <= 64 * 1024) G = 1;
-    else if (4 * vec * amp <= 64 * 1024) G = 64;
-    else G = 256;
-  }
+  // Tiers: frames shot-per-lane whenever the vectors of 64 shots fit the
+  // global budget (k <= 12), else one shot per workgroup; vectors in LDS when
+  // they fit, else in the caller's workspace (HBM).
+  if (G == 0) G = (H.kmax <= kLaneMaxK) ? 1 : 256;
   bool global_vec = false;
   if (H.kmax > 0) {
     size_t need = (G == 256 ? 1 : 4) * vec * amp * (G == 1 ? 64 : 1);
     if (c.vector_in_hbm == 1) global_vec = true;
     else if (c.vector_in_hbm == -1) global_vec = false;
     else global_vec = need > kLdsLimit - 16 * 1024;
-    if (global_vec && G != 256) return fail(CLIFFT_E_CAPACITY, "the HBM tier needs threads_per_shot = 256");
+    if (global_vec && G == 64) return fail(CLIFFT_E_CAPACITY, "shot-per-wave vectors must fit in LDS");
   }
   DevProgram tmp{};
   tmp.nrec = H.nrec;
@@ -141,6 +142,12 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
   uint64_t blocks_needed = (tiles + units_per_block - 1) / units_per_block;
   int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, kLdsLimit / std::max<size_t>(lds, 1)));
   int grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
+  if (global_vec && c.grid <= 0) {
+    // keep the default workspace within budget
+    size_t per_block = (size_t)(G == 256 ? 1 : 4) * vec * amp * (G == 1 ? 64 : 1);
+    size_t cap = std::max<size_t>(1, kWorkspaceBudget / per_block);
+    if ((size_t)grid > cap) grid = (int)cap;
+  }
   if ((uint64_t)grid > blocks_needed) grid = (int)std::max<uint64_t>(1, blocks_needed);
   L->G = G;
   L->grid = grid;
@@ -268,6 +275,19 @@ clifft_status clifft_final_slots(const clifft_program* p, int32_t* slots, int32_
   const auto& v = p->host.final_slots;
   *k = (int32_t)v.size();
   for (size_t i = 0; slots && i < v.size(); i++) slots[i] = v[i];
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clifft_cost* out) {
+  if (!p || !out) return fail(CLIFFT_E_INVALID_ARG, "null argument");
+  if (precision != CLIFFT_FP32 && precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
+  CostModel c = cost_model(p->host, precision == CLIFFT_FP64);
+  out->int_ops = c.int_ops;
+  out->flops = c.flops;
+  out->vector_bytes = c.vector_bytes;
+  out->record_bytes = c.record_bytes;
+  out->expected_faults = c.expected_faults;
+  out->instructions = c.instructions;
   return CLIFFT_OK;
 }
 

@@ -167,22 +167,37 @@ def test_forced_probabilities_and_amplitudes(case, precision, tol):
         assert np.linalg.norm(a - b) <= tol * 10
 
 
-@pytest.mark.parametrize("G", [1, 64, 256])
-def test_clifford_t_n8_fp64_bit_exact(G):
+TIERS = [(1, -1), (1, 1), (64, -1), (256, -1), (256, 1)]  # (threads per shot, vector in HBM)
+
+
+@pytest.mark.parametrize("G,hbm", TIERS)
+def test_clifford_t_n8_fp64_bit_exact(G, hbm):
     w = circuits.workload("random_clifford_t_n8")
     text = w["texts"][0]
     shots = w["shots"]
     om, _, _ = oracle.Program(text).sample(shots, seed=0, threads=8)
-    gm, _, _ = gpu_sample(text, shots, seed=0, precision="f64", threads_per_shot=G)
+    gm, _, _ = gpu_sample(text, shots, seed=0, precision="f64", threads_per_shot=G, vector_in_hbm=hbm)
     assert np.array_equal(gm, om)
 
 
+@pytest.mark.parametrize("G,hbm", TIERS)
+def test_random_circuits_every_tier_fp64(G, hbm):
+    for case in range(4):
+        rng = np.random.default_rng(900 + case)
+        text = random_small_circuit(rng, 5, 40)
+        shots = 300
+        om, od, oo = oracle.Program(text).sample(shots, seed=case, threads=4)
+        gm, gd, go = gpu_sample(text, shots, seed=case, precision="f64", threads_per_shot=G, vector_in_hbm=hbm)
+        assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_surface_d5_t10_records(precision):
+@pytest.mark.parametrize("G", [0, 64])
+def test_surface_d5_t10_records(precision, G):
     text = circuits.workload("surface_d5_r5_t10")["texts"][0]
     shots = 4096 + 5
     om, od, oo = oracle.Program(text).sample(shots, seed=3, threads=8)
-    gm, gd, go = gpu_sample(text, shots, seed=3, precision=precision)
+    gm, gd, go = gpu_sample(text, shots, seed=3, precision=precision, threads_per_shot=G)
     bad = mismatched_shots(np.vstack([om, od, oo]), np.vstack([gm, gd, go]), shots)
     if precision == "f64":
         assert bad == 0
