@@ -11,7 +11,6 @@ circuit-level depolarizing p = 1e-3, 1e7 shots (the Pauli-frame
 configuration of the benchmark table).  Other workloads: --workload.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -28,14 +27,8 @@ PEAK_HBM = 8.0e12                    # HBM3E bytes/s
 PEAK_LDS = 256 * 128 * 2.4e9         # LDS bytes/s: 128 B/clk/CU
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "program.h", "kernels.h"):
-        h.update(open(os.path.join(ROOT, "paper_2604_27058_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(workload, precision):
+    from paper_2604_27058_amd.profiling import kernel_source_hash
     """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
     were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, precision))
@@ -80,6 +73,8 @@ def main():
     ap.add_argument("--threads-per-shot", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="run one plain device copy of this many bytes first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (shards would run "
@@ -107,6 +102,13 @@ def main():
     ws = prog.alloc_workspace(launch)
     stream = torch.cuda.current_stream()
 
+    if args.calibrate_copy:
+        src = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         prog.sample(shots, seed=seed, launch=launch, outputs=outs, workspace=ws)
     torch.cuda.synchronize()
@@ -126,18 +128,21 @@ def main():
 
     cost = prog.cost_model(precision)
     k = prog.k_max
+    shape = prog.resolve_launch(shots, launch)
     if k == 0:
         achieved = cost["int_ops"] * shots / (kernel_ms * 1e-3)
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT_OPS / 1e12, unit="Tops/s",
                     frac=achieved / PEAK_INT_OPS)
-    elif k <= 14:
-        achieved = cost["vector_bytes"] * shots / (kernel_ms * 1e-3)
-        roof = dict(bound="lds", achieved=achieved / 1e9, peak=PEAK_LDS / 1e9, unit="GB/s", frac=achieved / PEAK_LDS)
-    else:
+    elif shape["vector_in_hbm"] == 1:
         achieved = cost["vector_bytes"] * shots / (kernel_ms * 1e-3)
         roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=achieved / PEAK_HBM)
+    else:
+        achieved = cost["vector_bytes"] * shots / (kernel_ms * 1e-3)
+        roof = dict(bound="lds", achieved=achieved / 1e9, peak=PEAK_LDS / 1e9, unit="GB/s", frac=achieved / PEAK_LDS)
     traffic = load_traffic(args.workload, precision)
     roof["traffic"] = traffic
+    if traffic:
+        roof["traffic_over_algorithmic"] = traffic / max(1.0, (cost["vector_bytes"] + cost["record_bytes"]) * shots)
     roof["kernel_ms"] = kernel_ms
     roof["work_per_shot"] = {kk: round(v, 3) for kk, v in cost.items()}
 
@@ -147,7 +152,9 @@ def main():
         "vs_baseline": None, "dtype": "u64" if k == 0 else precision, "data": "synthetic",
         "config": {"workload": args.workload, "shots": shots, "qubits": prog.num_qubits, "k_max": k,
                    "detectors": prog.num_detectors, "noise_sites": prog.num_noise_sites,
-                   "precision": precision, "parallelism": "shots across lanes/waves of one GPU"},
+                   "precision": precision, "threads_per_shot": shape["threads_per_shot"],
+                   "vector_in_hbm": shape["vector_in_hbm"] == 1, "grid": shape["grid"],
+                   "parallelism": "shots across lanes/waves of one GPU"},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -115,6 +115,13 @@ typedef struct clifft_cost {
 } clifft_cost;
 clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clifft_cost* out);
 
+/* The launch configuration a sample call of `shots` shots would use with
+ * `cfg` (NULL = automatic): *out receives precision, threads_per_shot,
+ * grid and vector_in_hbm (1 HBM workspace, -1 LDS) after the automatic
+ * choices are made.  Host only. */
+clifft_status clifft_resolve_launch(const clifft_program* p, const clifft_launch* cfg, uint64_t shots,
+                                    clifft_launch* out);
+
 /* Bytes of caller-provided device workspace a sample call needs with this
  * configuration (0 when the active vectors fit in LDS). */
 clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes);

@@ -60,11 +60,12 @@ def lib():
         L.clifft_sample_trace.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp, vp, sz,
                                           vp, vp, vp, vp]
         L.clifft_cost_model.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(clifft_cost)]
+        L.clifft_resolve_launch.argtypes = [vp, ctypes.POINTER(clifft_launch), u64, ctypes.POINTER(clifft_launch)]
         L.clifft_program_free.argtypes = [vp]
         L.clifft_last_error.restype = ctypes.c_char_p
         for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
                   "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_trace",
-                  "clifft_cost_model"):
+                  "clifft_cost_model", "clifft_resolve_launch"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -124,6 +125,13 @@ class Program:
         _check(lib().clifft_cost_model(self._h, CLIFFT_FP64 if precision == "f64" else CLIFFT_FP32,
                                        ctypes.byref(c)))
         return {f: getattr(c, f) for f, _ in clifft_cost._fields_}
+
+    def resolve_launch(self, shots, launch=None):
+        """The configuration clifft_sample would use (dict)."""
+        out = clifft_launch()
+        _check(lib().clifft_resolve_launch(self._h, None if launch is None else ctypes.byref(launch), shots,
+                                           ctypes.byref(out)))
+        return {f: getattr(out, f) for f, _ in clifft_launch._fields_}
 
     def workspace_size(self, launch=None):
         n = ctypes.c_size_t()

@@ -291,6 +291,20 @@ clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clif
   return CLIFFT_OK;
 }
 
+clifft_status clifft_resolve_launch(const clifft_program* p, const clifft_launch* cfg, uint64_t shots,
+                                    clifft_launch* out) {
+  if (!p || !out) return fail(CLIFFT_E_INVALID_ARG, "null argument");
+  LaunchShape L{};
+  bool fp64 = false;
+  clifft_status st = choose_shape(p->host, nullptr, cfg, shots ? shots : 1, &L, &fp64);
+  if (st != CLIFFT_OK) return st;
+  out->precision = fp64 ? CLIFFT_FP64 : CLIFFT_FP32;
+  out->threads_per_shot = L.G;
+  out->grid = L.grid;
+  out->vector_in_hbm = L.global_vec ? 1 : -1;
+  return CLIFFT_OK;
+}
+
 clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes) {
   if (!p || !bytes) return fail(CLIFFT_E_INVALID_ARG, "null argument");
   LaunchShape L{};

@@ -1,0 +1,77 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+    python -m paper_2604_27058_amd.profiling stats DIR           kernel-trace --stats CSVs -> text table
+    python -m paper_2604_27058_amd.profiling traffic FETCH_DIR WRITE_DIR COPY_BYTES WORKLOAD PREC OUT.json
+        HBM bytes per launch of the sampling kernel from two --pmc runs
+        (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by the
+        counter's reading for the plain copy kernel of COPY_BYTES bytes
+        (bench.py --calibrate-copy), stamped with the kernel source hash.
+"""
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "program.h", "kernels.h"):
+        h.update(open(os.path.join(ROOT, "paper_2604_27058_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _csv(d, suffix):
+    files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not files:
+        raise FileNotFoundError("no *%s under %s" % (suffix, d))
+    return list(csv.DictReader(open(files[0])))
+
+
+def stats(d):
+    rows = _csv(d, "kernel_stats.csv")
+    out = ["%-72s %8s %14s %14s %7s" % ("kernel", "calls", "total_ns", "average_ns", "pct")]
+    for r in rows:
+        out.append("%-72s %8s %14s %14s %7.2f" % (r["Name"][:72], r["Calls"], r["TotalDurationNs"],
+                                                   r["AverageNs"], float(r["Percentage"])))
+    return "\n".join(out)
+
+
+def _pmc(d, counter):
+    rows = _csv(d, "counter_collection.csv")
+    per = {}
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        per.setdefault((r["Kernel_Name"], r["Dispatch_Id"]), 0.0)
+        per[(r["Kernel_Name"], r["Dispatch_Id"])] += float(r["Counter_Value"])
+    return per
+
+
+def traffic(fetch_dir, write_dir, copy_bytes, workload, prec):
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = _pmc(d, counter)
+        copy = [v for (k, _), v in per.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        samp = [v for (k, _), v in per.items() if "k_sample" in k]
+        if not copy or not samp:
+            raise RuntimeError("missing copy or sampling dispatches for " + counter)
+        kib_copy = max(copy)
+        factor = kib_copy * 1024.0 / copy_bytes
+        res[counter] = dict(kib_per_dispatch=sum(samp) / len(samp), copy_kib=kib_copy, factor=factor,
+                            bytes_per_launch=sum(samp) / len(samp) * 1024.0 / factor)
+    return dict(workload=workload, precision=prec, kernel_source_hash=kernel_source_hash(),
+                bytes_per_launch=res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"],
+                fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"], copy_bytes=copy_bytes)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        print(stats(sys.argv[2]))
+    elif sys.argv[1] == "traffic":
+        d = traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], sys.argv[6])
+        json.dump(d, open(sys.argv[7], "w"), indent=1)
+        print(json.dumps(d))
