@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "program.h"
 
@@ -812,10 +814,35 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
   const int tid = G == 256 ? (int)threadIdx.x : lane;
   const uint64_t ntiles = (A.shots + 63) / 64;
   const uint64_t words = ntiles;
+  if constexpr (G == 256) {
+    // One shot per workgroup: shots (not tiles) are spread over the
+    // workgroups so that small shot counts still fill the device; record bits
+    // are staged per shot (bit 0) and ORed into the zero-filled outputs.
+    for (uint64_t sh_i = unit; sh_i < A.shots; sh_i += nunits) {
+      for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 256) rec[r] = 0;
+      __syncthreads();
+      uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
+      Shot<W, G, R, DBG, VEC> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0, A.offset + g, g};
+      sh.run();
+      __syncthreads();
+      const uint64_t bit = 1ull << (g & 63);
+      const size_t word = (size_t)(g >> 6);
+      for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 256) {
+        if (!(rec[r] & 1ull)) continue;
+        uint64_t* dst;
+        if (r < (uint32_t)P.nrec) dst = A.meas ? A.meas + (size_t)r * words + word : nullptr;
+        else if (r < (uint32_t)(P.nrec + P.ndet)) dst = A.det ? A.det + (size_t)(r - P.nrec) * words + word : nullptr;
+        else dst = A.obs ? A.obs + (size_t)(r - P.nrec - P.ndet) * words + word : nullptr;
+        if (dst) atomicOr((unsigned long long*)dst, (unsigned long long)bit);
+      }
+      __syncthreads();
+    }
+    return;
+  }
   for (uint64_t tile = unit; tile < ntiles; tile += nunits) {
-    for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += (G == 256 ? 256 : 64)) rec[r] = 0;
-    if constexpr (G == 256) __syncthreads();
-    else { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+    for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 64) rec[r] = 0;
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if constexpr (G == 1) {
       Shot<W, G, R, DBG, VEC> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
                             A.offset + tile * 64 + lane, tile * 64 + lane};
@@ -828,12 +855,12 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
         sh.run();
       }
     }
-    if constexpr (G == 256) __syncthreads();
-    else { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     // flush the tile's record words (bits of shots beyond the end cleared)
     const uint64_t nvalid = min((uint64_t)64, A.shots - tile * 64);
     const uint64_t vmask = nvalid == 64 ? ~0ull : ((1ull << nvalid) - 1ull);
-    for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += (G == 256 ? 256 : 64)) {
+    for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 64) {
       uint64_t v = rec[r] & vmask;
       if (r < (uint32_t)P.nrec) {
         if (A.meas) A.meas[(size_t)r * words + tile] = v;
@@ -843,9 +870,15 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
         if (A.obs) A.obs[(size_t)(r - P.nrec - P.ndet) * words + tile] = v;
       }
     }
-    if constexpr (G == 256) __syncthreads();
-    else { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
+}
+
+// Zero-fill of record rows (a plain kernel rather than a memset node, so the
+// whole call can be captured in a graph).
+__global__ void k_zero(uint64_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // ------------------------------------------------------------------ dispatch table
@@ -888,6 +921,17 @@ static hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShap
 
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool debug,
                          hipStream_t st) {
+  if (L.G == 256) {
+    const size_t words = (A.shots + 63) / 64;
+    uint64_t* rows[3] = {A.meas, A.det, A.obs};
+    const size_t counts[3] = {(size_t)P.nrec, (size_t)P.ndet, (size_t)P.nobs};
+    for (int i = 0; i < 3; i++) {
+      size_t n = counts[i] * words;
+      if (!rows[i] || n == 0) continue;
+      int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
+      hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, rows[i], n);
+    }
+  }
   if (fp64) return debug ? launch_g<double, true>(P, A, L, st) : launch_g<double, false>(P, A, L, st);
   return debug ? launch_g<float, true>(P, A, L, st) : launch_g<float, false>(P, A, L, st);
 }

@@ -137,9 +137,8 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
   tmp.kmax = H.kmax;
   size_t lds = lds_bytes_for(D ? *D : tmp, G, global_vec, *fp64);
   if (lds > kLdsLimit) return fail(CLIFFT_E_CAPACITY, "records and active vectors exceed LDS; use a larger tier");
-  const int units_per_block = G == 256 ? 1 : 4;
-  uint64_t tiles = (shots + 63) / 64;
-  uint64_t blocks_needed = (tiles + units_per_block - 1) / units_per_block;
+  // work items: 64-shot tiles per wave (G = 1, 64) or single shots per workgroup (G = 256)
+  uint64_t blocks_needed = G == 256 ? shots : ((shots + 63) / 64 + 3) / 4;
   int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, kLdsLimit / std::max<size_t>(lds, 1)));
   int grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
   if (global_vec && c.grid <= 0) {
