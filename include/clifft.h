@@ -151,6 +151,39 @@ clifft_status clifft_sample_trace(const clifft_program* p, uint64_t shots, uint6
                                   double* probs, double* phi, void* workspace, size_t workspace_bytes,
                                   uint64_t* meas, uint64_t* det, uint64_t* obs, void* stream);
 
+/* ---- Batched launch: many programs of different width and active
+ * dimension sampled by one persistent launch (work items: 64-shot tiles of
+ * shot-per-lane programs and single shots of shot-per-workgroup programs,
+ * ordered longest first by the cost model, claimed dynamically). */
+typedef struct clifft_batch clifft_batch; /* opaque, owned by the library */
+
+/* Prepare a batch of n programs (which must stay alive while the batch
+ * exists), shots[i] shots of program i with Philox seed seeds[i] (host
+ * arrays).  cfg: precision, optional threads_per_shot (0 automatic per
+ * program, 1 or 256 for all) and grid.  Uploads the item table to the
+ * current device (allocates device memory, owned by the batch). */
+clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n, const uint64_t* shots,
+                                  const uint64_t* seeds, const clifft_launch* cfg, clifft_batch** out);
+
+/* Sizes of the three output buffers in uint64 words, the workspace in bytes
+ * and (if not NULL, n entries) the threads per shot chosen per program. */
+clifft_status clifft_batch_sizes(const clifft_batch* b, uint64_t* meas_words, uint64_t* det_words,
+                                 uint64_t* obs_words, size_t* workspace_bytes, int32_t* threads_per_shot);
+
+/* Offsets (uint64 words) of program i's rows inside the three output
+ * buffers; program i's records are then laid out as in clifft_sample. */
+clifft_status clifft_batch_layout(const clifft_batch* b, int32_t i, uint64_t* meas_off, uint64_t* det_off,
+                                  uint64_t* obs_off);
+
+/* Sample every program of the batch in one launch on `stream` (plus small
+ * zero-fill kernels for the outputs).  meas / det / obs: device buffers of
+ * the sizes above (any may be NULL); workspace: device buffer of at least
+ * the size above.  Records equal those of clifft_sample on each program. */
+clifft_status clifft_batch_sample(const clifft_batch* b, void* workspace, size_t workspace_bytes, uint64_t* meas,
+                                  uint64_t* det, uint64_t* obs, void* stream);
+
+void clifft_batch_free(clifft_batch* b);
+
 /* Release a program and its device copies. */
 void clifft_program_free(clifft_program* p);
 

@@ -61,11 +61,20 @@ def lib():
                                           vp, vp, vp, vp]
         L.clifft_cost_model.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(clifft_cost)]
         L.clifft_resolve_launch.argtypes = [vp, ctypes.POINTER(clifft_launch), u64, ctypes.POINTER(clifft_launch)]
+        L.clifft_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                          ctypes.POINTER(clifft_launch), ctypes.POINTER(vp)]
+        L.clifft_batch_sizes.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                         ctypes.POINTER(sz), i32p]
+        L.clifft_batch_layout.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                          ctypes.POINTER(u64)]
+        L.clifft_batch_sample.argtypes = [vp, vp, sz, vp, vp, vp, vp]
+        L.clifft_batch_free.argtypes = [vp]
         L.clifft_program_free.argtypes = [vp]
         L.clifft_last_error.restype = ctypes.c_char_p
         for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
                   "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_trace",
-                  "clifft_cost_model", "clifft_resolve_launch"):
+                  "clifft_cost_model", "clifft_resolve_launch", "clifft_batch_create", "clifft_batch_sizes",
+                  "clifft_batch_layout", "clifft_batch_sample"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -183,3 +192,62 @@ class Program:
                                          ptr(meas), ptr(det), ptr(obs), s.cuda_stream))
         return dict(meas=meas, det=det, obs=obs, probs=probs[:, : self.num_events],
                     phi=torch.view_as_complex(phi))
+
+
+class Batch:
+    """Many programs sampled by one persistent launch (clifft_batch_*)."""
+
+    def __init__(self, programs, shots, seeds, precision="f32", threads_per_shot=0, grid=0):
+        n = len(programs)
+        self.programs = list(programs)  # keep the programs alive
+        hs = (ctypes.c_void_p * n)(*[p._h.value for p in programs])
+        sh = (ctypes.c_uint64 * n)(*shots)
+        sd = (ctypes.c_uint64 * n)(*seeds)
+        cfg = make_launch(precision, threads_per_shot=threads_per_shot, grid=grid)
+        h = ctypes.c_void_p()
+        _check(lib().clifft_batch_create(hs, n, sh, sd, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.shots = list(shots)
+        mw, dw, ow, ws = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_size_t()
+        tps = (ctypes.c_int32 * n)()
+        _check(lib().clifft_batch_sizes(h, ctypes.byref(mw), ctypes.byref(dw), ctypes.byref(ow), ctypes.byref(ws),
+                                        tps))
+        self.meas_words, self.det_words, self.obs_words = mw.value, dw.value, ow.value
+        self.workspace_bytes = ws.value
+        self.threads_per_shot = list(tps)
+        self.layout = []
+        for i in range(n):
+            a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+            _check(lib().clifft_batch_layout(h, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+            self.layout.append((a.value, b.value, c.value))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.clifft_batch_free(self._h)
+            self._h = None
+
+    def alloc(self, device="cuda"):
+        import torch
+        mk = lambda n: torch.empty(max(n, 1), dtype=torch.int64, device=device)
+        ws = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
+        return (mk(self.meas_words), mk(self.det_words), mk(self.obs_words)), ws
+
+    def sample(self, outputs=None, workspace=None, stream=None):
+        import torch
+        if outputs is None or workspace is None:
+            outputs, workspace = self.alloc()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        m, d, o = outputs
+        _check(lib().clifft_batch_sample(self._h, workspace.data_ptr(), workspace.numel(), m.data_ptr(),
+                                         d.data_ptr(), o.data_ptr(), s.cuda_stream))
+        return outputs
+
+    def records(self, outputs, i):
+        """Program i's (meas, det, obs) rows as [rows, words] views."""
+        p = self.programs[i]
+        words = (self.shots[i] + 63) // 64
+        mo, do, oo = self.layout[i]
+        m, d, o = outputs
+        return (m[mo: mo + p.num_measurements * words].view(p.num_measurements, words),
+                d[do: do + p.num_detectors * words].view(p.num_detectors, words),
+                o[oo: oo + p.num_observables * words].view(p.num_observables, words))

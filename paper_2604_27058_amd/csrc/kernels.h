@@ -28,6 +28,32 @@ struct LaunchShape {
   bool global_vec;  // active vectors in the global workspace
 };
 
+// Batched launch: many programs, one persistent kernel.
+struct BatchProgram {
+  DevProgram P;
+  uint64_t shots, seed, offset;
+  uint64_t meas_off, det_off, obs_off;  // row-block offsets (uint64 words) in the batch outputs
+  int32_t G;                            // 1 (64-shot tiles per wave) or 256 (one shot per workgroup)
+  int32_t pad;
+};
+struct BatchItem {
+  uint32_t prog;   // index into the program table
+  uint32_t kind;   // 1: four 64-shot tiles (one per wave); 256: one shot
+  uint64_t first;  // first tile (kind 1) or shot (kind 256)
+};
+struct BatchArgs {
+  const BatchProgram* progs;
+  const BatchItem* items;
+  uint64_t nitems;
+  uint32_t* counter;      // zeroed before the launch
+  uint64_t *meas, *det, *obs;
+  void* workspace;
+  uint64_t slot_bytes;    // workspace bytes per workgroup
+  uint32_t rec_words;     // max records + detectors + observables over programs
+};
+hipError_t launch_batch(const BatchArgs& B, int grid, size_t lds_bytes, bool fp64, hipStream_t stream);
+
+hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t stream);
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool trace,
                          hipStream_t stream);
 size_t lds_bytes_for(const DevProgram& P, int G, bool global_vec, bool fp64);

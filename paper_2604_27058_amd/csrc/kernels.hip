@@ -881,6 +881,137 @@ __global__ void k_zero(uint64_t* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// ------------------------------------------------------------------ batched launch
+// One persistent launch over many programs of different width and active
+// dimension.  Workgroups claim items in the order the host sorted them
+// (longest first) from an atomic counter; an item is either four 64-shot
+// tiles of a shot-per-lane program (one tile per wave) or one shot of a
+// shot-per-workgroup program.  Every active vector lives in the workgroup's
+// slice of the global workspace.
+template <int W, typename R>
+__device__ void batch_item(const BatchArgs& B, const BatchProgram& bp, const BatchItem& it, uint64_t* rec,
+                           double* red, unsigned char* slot) {
+  const DevProgram& P = bp.P;
+  KArgs A{};
+  A.shots = bp.shots;
+  A.seed = bp.seed;
+  A.offset = bp.offset;
+  A.meas = B.meas ? B.meas + bp.meas_off : nullptr;
+  A.det = B.det ? B.det + bp.det_off : nullptr;
+  A.obs = B.obs ? B.obs + bp.obs_off : nullptr;
+  const uint32_t nwords_rec = (uint32_t)(P.nrec + P.ndet + P.nobs);
+  const uint64_t words = (bp.shots + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  if (it.kind == 1) {
+    const int wv = (int)rfl(threadIdx.x >> 6);
+    const uint64_t tile = it.first + (uint64_t)wv;
+    uint64_t* wrec = rec + (size_t)wv * B.rec_words;
+    if (tile < words) {
+      for (uint32_t r = (uint32_t)lane; r < nwords_rec; r += 64) wrec[r] = 0;
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      cpx<R>* base = (cpx<R>*)slot + (size_t)wv * 64 * ((size_t)1 << P.kmax);
+      if (P.kmax == 0) {
+        Shot<W, 1, R, false, false> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
+                                       A.offset + tile * 64 + lane, tile * 64 + lane};
+        sh.run();
+      } else {
+        Shot<W, 1, R, false, true> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
+                                      A.offset + tile * 64 + lane, tile * 64 + lane};
+        sh.run();
+      }
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      const uint64_t nvalid = min((uint64_t)64, A.shots - tile * 64);
+      const uint64_t vmask = nvalid == 64 ? ~0ull : ((1ull << nvalid) - 1ull);
+      for (uint32_t r = (uint32_t)lane; r < nwords_rec; r += 64) {
+        uint64_t v = wrec[r] & vmask;
+        if (r < (uint32_t)P.nrec) {
+          if (A.meas) A.meas[(size_t)r * words + tile] = v;
+        } else if (r < (uint32_t)(P.nrec + P.ndet)) {
+          if (A.det) A.det[(size_t)(r - P.nrec) * words + tile] = v;
+        } else {
+          if (A.obs) A.obs[(size_t)(r - P.nrec - P.ndet) * words + tile] = v;
+        }
+      }
+    }
+  } else {
+    const uint64_t g = rfl((uint32_t)it.first) | (it.first & 0xFFFFFFFF00000000ull);
+    for (uint32_t r = threadIdx.x; r < nwords_rec; r += 256) rec[r] = 0;
+    __syncthreads();
+    Shot<W, 256, R, false, true> sh{P, A, Group<256>{(int)threadIdx.x}, Vec<256, R>{(cpx<R>*)slot, lane}, rec, red,
+                                    0, A.offset + g, g};
+    sh.run();
+    __syncthreads();
+    const uint64_t bit = 1ull << (g & 63);
+    const size_t word = (size_t)(g >> 6);
+    for (uint32_t r = threadIdx.x; r < nwords_rec; r += 256) {
+      if (!(rec[r] & 1ull)) continue;
+      uint64_t* dst;
+      if (r < (uint32_t)P.nrec) dst = A.meas ? A.meas + (size_t)r * words + word : nullptr;
+      else if (r < (uint32_t)(P.nrec + P.ndet)) dst = A.det ? A.det + (size_t)(r - P.nrec) * words + word : nullptr;
+      else dst = A.obs ? A.obs + (size_t)(r - P.nrec - P.ndet) * words + word : nullptr;
+      if (dst) atomicOr((unsigned long long*)dst, (unsigned long long)bit);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* rec = (uint64_t*)smem;  // 4 * rec_words
+  double* red = (double*)(smem + (size_t)4 * B.rec_words * 8);
+  uint32_t* claim = (uint32_t*)(smem + (size_t)4 * B.rec_words * 8 + 64);
+  unsigned char* slot = (unsigned char*)B.workspace + (size_t)blockIdx.x * B.slot_bytes;
+  for (;;) {
+    if (threadIdx.x == 0) *claim = atomicAdd(B.counter, 1u);
+    __syncthreads();
+    const uint32_t item = rfl(*claim);
+    __syncthreads();
+    if ((uint64_t)item >= B.nitems) break;
+    const BatchItem it = B.items[item];
+    const BatchProgram& bp = B.progs[it.prog];
+    switch (bp.P.W) {
+      case 1: batch_item<1, R>(B, bp, it, rec, red, slot); break;
+      case 2: batch_item<2, R>(B, bp, it, rec, red, slot); break;
+      case 3: batch_item<3, R>(B, bp, it, rec, red, slot); break;
+      default: batch_item<4, R>(B, bp, it, rec, red, slot); break;
+    }
+  }
+}
+
+hipError_t launch_batch(const BatchArgs& B, int grid, size_t lds_bytes, bool fp64, hipStream_t st) {
+  // the claim counter is one 32-bit word in a 64-bit slot: zero the slot
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (uint64_t*)B.counter, (size_t)1);
+  static bool attr32 = false, attr64 = false;
+  if (fp64) {
+    if (!attr64) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_batch<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         160 * 1024);
+      if (e != hipSuccess) return e;
+      attr64 = true;
+    }
+    hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(256), lds_bytes, st, B);
+  } else {
+    if (!attr32) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_batch<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         160 * 1024);
+      if (e != hipSuccess) return e;
+      attr32 = true;
+    }
+    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(256), lds_bytes, st, B);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t st) {
+  if (!p || n == 0) return hipSuccess;
+  int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ dispatch table
 template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC>
 static hipError_t launch_one(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {

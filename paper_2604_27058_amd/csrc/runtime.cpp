@@ -2,6 +2,7 @@
 // selection and the sampling entry points declared in include/clifft.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -97,6 +98,7 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
 
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kLaneMaxK = 12;                              // shot-per-lane tier up to this k_max
+constexpr int kBatchLaneMaxK = 10;                         // the same inside a batched launch
 constexpr size_t kWorkspaceBudget = (size_t)4 << 30;       // default global vector workspace
 
 int device_cus() {
@@ -218,6 +220,22 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
 
 }  // namespace
 
+struct clifft_batch {
+  std::vector<const clifft_program*> progs;
+  std::vector<BatchProgram> table;  // device pointers of each program's upload
+  std::vector<BatchItem> items;
+  bool fp64 = false;
+  int device = 0;
+  int grid = 0;
+  size_t lds = 0;
+  uint64_t slot_bytes = 0;
+  uint32_t rec_words = 0;
+  uint64_t meas_words = 0, det_words = 0, obs_words = 0;
+  BatchProgram* d_table = nullptr;
+  BatchItem* d_items = nullptr;
+  uint64_t* d_counter = nullptr;
+};
+
 extern "C" {
 
 clifft_status clifft_compile(const char* text, size_t len, clifft_program** out) {
@@ -327,6 +345,158 @@ clifft_status clifft_sample_trace(const clifft_program* p, uint64_t shots, uint6
                                   uint64_t* meas, uint64_t* det, uint64_t* obs, void* stream) {
   return do_sample(p, shots, seed, shot_offset, cfg, workspace, workspace_bytes, meas, det, obs, stream, forced_m,
                    forced_faults, probs, phi, true);
+}
+
+clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n, const uint64_t* shots,
+                                  const uint64_t* seeds, const clifft_launch* cfg, clifft_batch** out) {
+  if (!progs || !shots || !seeds || !out || n <= 0) return fail(CLIFFT_E_INVALID_ARG, "bad batch arguments");
+  *out = nullptr;
+  clifft_launch c{};
+  if (cfg) c = *cfg;
+  if (c.precision != CLIFFT_FP32 && c.precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
+  clifft_batch* b = new clifft_batch();
+  b->fp64 = c.precision == CLIFFT_FP64;
+  (void)hipGetDevice(&b->device);
+  const size_t amp = b->fp64 ? 16 : 8;
+  std::vector<double> item_cost;
+  for (int i = 0; i < n; i++) {
+    if (!progs[i]) { delete b; return fail(CLIFFT_E_INVALID_ARG, "null program in batch"); }
+    const DevProgram* D = nullptr;
+    clifft_status st = ensure_device(progs[i], &D);
+    if (st != CLIFFT_OK) { delete b; return st; }
+    const CompiledProgram& H = progs[i]->host;
+    BatchProgram bp{};
+    bp.P = *D;
+    bp.shots = shots[i];
+    bp.seed = seeds[i];
+    bp.offset = 0;
+    const uint64_t words = (shots[i] + 63) / 64;
+    bp.meas_off = b->meas_words;
+    bp.det_off = b->det_words;
+    bp.obs_off = b->obs_words;
+    b->meas_words += (uint64_t)H.nrec * words;
+    b->det_words += (uint64_t)H.ndet * words;
+    b->obs_words += (uint64_t)H.nobs * words;
+    // tier: frames shot-per-lane while 64 vectors per wave stay small,
+    // else one shot per workgroup
+    int G = c.threads_per_shot == 256 ? 256 : c.threads_per_shot == 1 ? 1 : (H.kmax <= kBatchLaneMaxK ? 1 : 256);
+    bp.G = G;
+    const uint64_t vec = (uint64_t)1 << H.kmax;
+    b->slot_bytes = std::max<uint64_t>(b->slot_bytes, G == 1 ? 4 * 64 * vec * amp : vec * amp);
+    b->rec_words = std::max<uint32_t>(b->rec_words, (uint32_t)(H.nrec + H.ndet + H.nobs));
+    b->progs.push_back(progs[i]);
+    b->table.push_back(bp);
+    // per-shot cost estimate (only used to order the items, longest first)
+    CostModel cm = cost_model(H, b->fp64);
+    // rough item durations: a lane item runs one shot per lane (its time is
+    // one shot's per-lane work), a workgroup item spreads one shot over 256
+    // threads
+    const double lane_item = 20.0 * cm.instructions + cm.int_ops + cm.vector_bytes;
+    const double block_item = 20.0 * cm.instructions + (cm.vector_bytes + cm.flops) / 64.0;
+    if (G == 1) {
+      for (uint64_t t = 0; t < words; t += 4) {
+        b->items.push_back(BatchItem{(uint32_t)i, 1u, t});
+        item_cost.push_back(lane_item);
+      }
+    } else {
+      for (uint64_t s = 0; s < shots[i]; s++) {
+        b->items.push_back(BatchItem{(uint32_t)i, 256u, s});
+        item_cost.push_back(block_item);
+      }
+    }
+  }
+  std::vector<size_t> order(b->items.size());
+  for (size_t i = 0; i < order.size(); i++) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c2) { return item_cost[a] > item_cost[c2]; });
+  std::vector<BatchItem> sorted(order.size());
+  for (size_t i = 0; i < order.size(); i++) sorted[i] = b->items[order[i]];
+  b->items.swap(sorted);
+  b->rec_words = (b->rec_words + 1) & ~1u;
+  b->lds = (size_t)4 * b->rec_words * 8 + 64 + 64;
+  if (b->lds > kLdsLimit) { delete b; return fail(CLIFFT_E_CAPACITY, "too many records for the batched launch"); }
+  int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, kLdsLimit / b->lds));
+  b->grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
+  size_t cap = std::max<size_t>(1, kWorkspaceBudget / std::max<uint64_t>(b->slot_bytes, 1));
+  if (c.grid <= 0 && (size_t)b->grid > cap) b->grid = (int)cap;
+  if ((uint64_t)b->grid > b->items.size()) b->grid = (int)b->items.size();
+  hipError_t e = hipMalloc((void**)&b->d_table, sizeof(BatchProgram) * b->table.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_items, sizeof(BatchItem) * b->items.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, 64);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_table, b->table.data(), sizeof(BatchProgram) * b->table.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_items, b->items.data(), sizeof(BatchItem) * b->items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    clifft_batch_free(b);
+    return fail(CLIFFT_E_DEVICE, std::string("batch upload failed: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_batch_layout(const clifft_batch* b, int32_t i, uint64_t* meas_off, uint64_t* det_off,
+                                  uint64_t* obs_off) {
+  if (!b || i < 0 || (size_t)i >= b->table.size()) return fail(CLIFFT_E_INVALID_ARG, "bad batch index");
+  if (meas_off) *meas_off = b->table[i].meas_off;
+  if (det_off) *det_off = b->table[i].det_off;
+  if (obs_off) *obs_off = b->table[i].obs_off;
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_batch_sizes(const clifft_batch* b, uint64_t* meas_words, uint64_t* det_words,
+                                 uint64_t* obs_words, size_t* workspace_bytes, int32_t* threads_per_shot) {
+  if (!b) return fail(CLIFFT_E_INVALID_ARG, "null batch");
+  if (meas_words) *meas_words = b->meas_words;
+  if (det_words) *det_words = b->det_words;
+  if (obs_words) *obs_words = b->obs_words;
+  if (workspace_bytes) *workspace_bytes = (size_t)b->grid * b->slot_bytes;
+  if (threads_per_shot)
+    for (size_t i = 0; i < b->table.size(); i++) threads_per_shot[i] = b->table[i].G;
+  return CLIFFT_OK;
+}
+
+clifft_status clifft_batch_sample(const clifft_batch* b, void* workspace, size_t workspace_bytes, uint64_t* meas,
+                                  uint64_t* det, uint64_t* obs, void* stream) {
+  if (!b) return fail(CLIFFT_E_INVALID_ARG, "null batch");
+  const size_t need = (size_t)b->grid * b->slot_bytes;
+  if (need > 0 && (!workspace || workspace_bytes < need)) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "workspace of %zu bytes needed", need);
+    return fail(CLIFFT_E_CAPACITY, buf);
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev != b->device) return fail(CLIFFT_E_INVALID_ARG, "batch belongs to another device");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_zero(meas, b->meas_words, s);
+  if (e == hipSuccess) e = launch_zero(det, b->det_words, s);
+  if (e == hipSuccess) e = launch_zero(obs, b->obs_words, s);
+  BatchArgs A{};
+  A.progs = b->d_table;
+  A.items = b->d_items;
+  A.nitems = b->items.size();
+  A.counter = (uint32_t*)b->d_counter;
+  A.meas = meas;
+  A.det = det;
+  A.obs = obs;
+  A.workspace = workspace;
+  A.slot_bytes = b->slot_bytes;
+  A.rec_words = b->rec_words;
+  if (e == hipSuccess) e = launch_batch(A, b->grid, b->lds, b->fp64, s);
+  if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
+  return CLIFFT_OK;
+}
+
+void clifft_batch_free(clifft_batch* b) {
+  if (!b) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(b->device);
+  if (b->d_table) (void)hipFree(b->d_table);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_counter) (void)hipFree(b->d_counter);
+  (void)hipSetDevice(cur);
+  delete b;
 }
 
 void clifft_program_free(clifft_program* p) {

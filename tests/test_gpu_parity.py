@@ -212,3 +212,27 @@ def test_large_active_k20_sampled_shots():
     gm, _, _ = gpu_sample(text, shots, seed=0, precision="f32", threads_per_shot=256)
     om, _, _ = op.sample(shots, seed=0, threads=4)
     assert mismatched_shots(om, gm, shots) == 0
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batched_launch_matches_single_program_and_oracle(precision):
+    """A heterogeneous batch (both tiers, k_max 4..16, W = 1 and 2) in one
+    launch: every program's records equal its single-program call (FP64:
+    exactly; FP32: up to near-threshold shots) and, on a prefix, the oracle."""
+    specs = circuits.batched_set(count=12, seed=4100)
+    progs = [pk.Program(c["text"]) for c in specs]
+    shots = [1000 + 37 * i for i in range(len(progs))]
+    seeds = [11 + i for i in range(len(progs))]
+    B = pk.Batch(progs, shots, seeds, precision=precision)
+    assert set(B.threads_per_shot) == {1, 256}
+    outs = B.sample()
+    torch.cuda.synchronize()
+    for i, (c, p) in enumerate(zip(specs, progs)):
+        bm = [u64(x) for x in B.records(outs, i)]
+        sm = gpu_sample(p, shots[i], seed=seeds[i], precision=precision)
+        bad = mismatched_shots(np.vstack([x for x in bm if x.size]), np.vstack([x for x in sm if x.size]), shots[i])
+        assert bad == 0 if precision == "f64" else bad <= 2, (i, bad)
+        n = 64 if p.k_max <= 12 else 16
+        om, _, _ = oracle.Program(c["text"]).sample(n, seed=seeds[i], threads=8)
+        bad = mismatched_shots(om[:, :1], bm[0][:, :1] & np.uint64((1 << n) - 1 if n < 64 else ~np.uint64(0)), n)
+        assert bad == 0 if precision == "f64" else bad <= 1, (i, bad)
