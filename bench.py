@@ -72,6 +72,9 @@ def bench_batch(args, w, pk, torch):
     seeds = list(range(len(texts)))
     progs = [pk.Program(t) for t in texts]
     precision = args.precision or "f32"
+    if not args.no_autotune and not args.threads_per_shot:
+        for p in progs:
+            p.autotune(shots[0], precision)
     B = pk.Batch(progs, shots, seeds, precision=precision, threads_per_shot=args.threads_per_shot, grid=args.grid)
     outs, ws = B.alloc()
     stream = torch.cuda.current_stream()
@@ -139,6 +142,7 @@ def main():
     ap.add_argument("--threads-per-shot", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="skip clifft_autotune before timing")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="run one plain device copy of this many bytes first (HBM counter calibration)")
     args = ap.parse_args()
@@ -163,6 +167,9 @@ def main():
         return
     text = w["texts"][0]
     prog = pk.Program(text)
+    tuned = None
+    if not args.no_autotune and not args.threads_per_shot and not args.grid:
+        tuned = prog.autotune(shots, precision)
     launch = pk.make_launch(precision, threads_per_shot=args.threads_per_shot, grid=args.grid)
     outs = prog.alloc_outputs(shots)
     ws = prog.alloc_workspace(launch)
@@ -219,7 +226,7 @@ def main():
         "config": {"workload": args.workload, "shots": shots, "qubits": prog.num_qubits, "k_max": k,
                    "detectors": prog.num_detectors, "noise_sites": prog.num_noise_sites,
                    "precision": precision, "threads_per_shot": shape["threads_per_shot"],
-                   "vector_in_hbm": shape["vector_in_hbm"] == 1, "grid": shape["grid"],
+                   "vector_in_hbm": shape["vector_in_hbm"] == 1, "grid": shape["grid"], "autotuned": tuned is not None,
                    "parallelism": "shots across lanes/waves of one GPU"},
         "roofline": roof,
     }

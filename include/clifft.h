@@ -122,6 +122,15 @@ clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clif
 clifft_status clifft_resolve_launch(const clifft_program* p, const clifft_launch* cfg, uint64_t shots,
                                     clifft_launch* out);
 
+/* Launch-shape autotuner: times the candidate tiers (threads per shot 1,
+ * 64, 256; vectors in LDS or HBM) and grid sizes (1, 2, 4, 8 workgroups per
+ * CU) on a trial of up to `shots` shots at `precision`, on `stream` of the
+ * current device, and stores the fastest in the program.  Later calls whose
+ * cfg leaves threads_per_shot, grid and vector_in_hbm at 0 use it (also for
+ * clifft_workspace_size).  Allocates and frees temporary device buffers;
+ * synchronizes.  *out (optional) receives the chosen configuration. */
+clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precision, void* stream, clifft_launch* out);
+
 /* Bytes of caller-provided device workspace a sample call needs with this
  * configuration (0 when the active vectors fit in LDS). */
 clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes);

@@ -69,12 +69,13 @@ def lib():
                                           ctypes.POINTER(u64)]
         L.clifft_batch_sample.argtypes = [vp, vp, sz, vp, vp, vp, vp]
         L.clifft_batch_free.argtypes = [vp]
+        L.clifft_autotune.argtypes = [vp, u64, ctypes.c_int32, vp, ctypes.POINTER(clifft_launch)]
         L.clifft_program_free.argtypes = [vp]
         L.clifft_last_error.restype = ctypes.c_char_p
         for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
                   "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_trace",
                   "clifft_cost_model", "clifft_resolve_launch", "clifft_batch_create", "clifft_batch_sizes",
-                  "clifft_batch_layout", "clifft_batch_sample"):
+                  "clifft_batch_layout", "clifft_batch_sample", "clifft_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -140,6 +141,14 @@ class Program:
         out = clifft_launch()
         _check(lib().clifft_resolve_launch(self._h, None if launch is None else ctypes.byref(launch), shots,
                                            ctypes.byref(out)))
+        return {f: getattr(out, f) for f, _ in clifft_launch._fields_}
+
+    def autotune(self, shots, precision="f32"):
+        """clifft_autotune: time the launch shapes, keep the fastest (dict)."""
+        import torch
+        out = clifft_launch()
+        _check(lib().clifft_autotune(self._h, shots, CLIFFT_FP64 if precision == "f64" else CLIFFT_FP32,
+                                     torch.cuda.current_stream().cuda_stream, ctypes.byref(out)))
         return {f: getattr(out, f) for f, _ in clifft_launch._fields_}
 
     def workspace_size(self, launch=None):

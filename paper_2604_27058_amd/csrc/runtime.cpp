@@ -36,6 +36,7 @@ struct clifft_program {
   CompiledProgram host;
   std::mutex mu;
   std::map<int, DeviceCopy> dev;
+  std::map<std::pair<int, int>, clifft_launch> tuned;  // (device, precision) -> autotuned launch
 };
 
 namespace {
@@ -111,11 +112,18 @@ int device_cus() {
 // Launch shape: the tier follows the active-vector size (threads per shot
 // and storage), the grid fills the device with persistent workgroups.
 clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const clifft_launch* cfg, uint64_t shots,
-                           LaunchShape* L, bool* fp64) {
+                           LaunchShape* L, bool* fp64,
+                           const std::map<std::pair<int, int>, clifft_launch>* tuned = nullptr) {
   clifft_launch c{};
   if (cfg) c = *cfg;
   if (c.precision != CLIFFT_FP32 && c.precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
   *fp64 = c.precision == CLIFFT_FP64;
+  if (tuned && c.threads_per_shot == 0 && c.grid == 0 && c.vector_in_hbm == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto it = tuned->find({dev, c.precision});
+    if (it != tuned->end()) c = it->second;
+  }
   const size_t amp = *fp64 ? 16 : 8;
   const size_t vec = (size_t)1 << H.kmax;
   int G = c.threads_per_shot;
@@ -175,7 +183,7 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
   if (st != CLIFFT_OK) return st;
   LaunchShape L{};
   bool fp64 = false;
-  st = choose_shape(p->host, D, cfg, shots, &L, &fp64);
+  st = choose_shape(p->host, D, cfg, shots, &L, &fp64, &p->tuned);
   if (st != CLIFFT_OK) return st;
   size_t need = workspace_bytes(p->host, L, fp64);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) {
@@ -313,7 +321,7 @@ clifft_status clifft_resolve_launch(const clifft_program* p, const clifft_launch
   if (!p || !out) return fail(CLIFFT_E_INVALID_ARG, "null argument");
   LaunchShape L{};
   bool fp64 = false;
-  clifft_status st = choose_shape(p->host, nullptr, cfg, shots ? shots : 1, &L, &fp64);
+  clifft_status st = choose_shape(p->host, nullptr, cfg, shots ? shots : 1, &L, &fp64, &p->tuned);
   if (st != CLIFFT_OK) return st;
   out->precision = fp64 ? CLIFFT_FP64 : CLIFFT_FP32;
   out->threads_per_shot = L.G;
@@ -326,7 +334,7 @@ clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch
   if (!p || !bytes) return fail(CLIFFT_E_INVALID_ARG, "null argument");
   LaunchShape L{};
   bool fp64 = false;
-  clifft_status st = choose_shape(p->host, nullptr, cfg, ~0ull >> 8, &L, &fp64);
+  clifft_status st = choose_shape(p->host, nullptr, cfg, ~0ull >> 8, &L, &fp64, &p->tuned);
   if (st != CLIFFT_OK) return st;
   *bytes = workspace_bytes(p->host, L, fp64);
   return CLIFFT_OK;
@@ -380,6 +388,12 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
     // tier: frames shot-per-lane while 64 vectors per wave stay small,
     // else one shot per workgroup
     int G = c.threads_per_shot == 256 ? 256 : c.threads_per_shot == 1 ? 1 : (H.kmax <= kBatchLaneMaxK ? 1 : 256);
+    if (c.threads_per_shot == 0) {
+      // an autotuned program keeps its tier inside the batch
+      auto it = progs[i]->tuned.find({b->device, c.precision});
+      if (it != progs[i]->tuned.end() && (H.kmax <= kLaneMaxK || it->second.threads_per_shot != 1))
+        G = it->second.threads_per_shot == 1 ? 1 : 256;
+    }
     bp.G = G;
     const uint64_t vec = (uint64_t)1 << H.kmax;
     b->slot_bytes = std::max<uint64_t>(b->slot_bytes, G == 1 ? 4 * 64 * vec * amp : vec * amp);
@@ -497,6 +511,87 @@ void clifft_batch_free(clifft_batch* b) {
   if (b->d_counter) (void)hipFree(b->d_counter);
   (void)hipSetDevice(cur);
   delete b;
+}
+
+clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precision, void* stream, clifft_launch* out) {
+  if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
+  if (precision != CLIFFT_FP32 && precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
+  const CompiledProgram& H = p->host;
+  const int cus = device_cus();
+  // trial size: enough work to fill the device a few times over
+  uint64_t trial = H.kmax == 0 ? ((uint64_t)1 << 22) : H.kmax <= 12 ? ((uint64_t)1 << 18) : (uint64_t)cus * 8;
+  if (shots > 0 && shots < trial) trial = shots;
+  std::vector<clifft_launch> cands;
+  const int mult[4] = {1, 2, 4, 8};
+  for (int G : {1, 64, 256}) {
+    if (H.kmax == 0 && G != 1) continue;
+    for (int hbm : {-1, 1}) {
+      if (H.kmax == 0 && hbm == 1) continue;
+      if (G == 64 && hbm == 1) continue;
+      if (G == 1 && H.kmax > kLaneMaxK) continue;
+      for (int m : mult) cands.push_back(clifft_launch{precision, G, cus * m, H.kmax == 0 ? 0 : hbm});
+    }
+  }
+  const DevProgram* D = nullptr;
+  clifft_status st = ensure_device(p, &D);
+  if (st != CLIFFT_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t words = (trial + 63) / 64;
+  uint64_t *meas = nullptr, *det = nullptr, *obs = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc((void**)&meas, (H.nrec + 1) * words * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&det, (H.ndet + 1) * words * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&obs, (H.nobs + 1) * words * 8);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best_ms = 1e30f;
+  clifft_launch best{};
+  bool found = false;
+  for (const clifft_launch& c : cands) {
+    if (e != hipSuccess) break;
+    LaunchShape L{};
+    bool fp64 = false;
+    if (choose_shape(H, D, &c, trial, &L, &fp64) != CLIFFT_OK) continue;
+    size_t wsb = workspace_bytes(H, L, fp64);
+    void* ws = nullptr;
+    if (wsb && hipMalloc(&ws, wsb) != hipSuccess) { (void)hipGetLastError(); continue; }
+    KArgs A{};
+    A.shots = trial;
+    A.seed = 0;
+    A.meas = meas;
+    A.det = det;
+    A.obs = obs;
+    A.workspace = ws;
+    float ms = 0;
+    for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
+      e = hipEventRecord(e0, s);
+      if (e == hipSuccess) e = launch_sample(*D, A, L, fp64, false, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (ws) (void)hipFree(ws);
+    if (e == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = clifft_launch{precision, L.G, L.grid, L.global_vec ? 1 : -1};
+      found = true;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (meas) (void)hipFree(meas);
+  if (det) (void)hipFree(det);
+  if (obs) (void)hipFree(obs);
+  if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("autotune failed: ") + hipGetErrorString(e));
+  if (!found) return fail(CLIFFT_E_CAPACITY, "no launch shape fits this program");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> lock(p->mu);
+    p->tuned[{dev, precision}] = best;
+  }
+  if (out) *out = best;
+  return CLIFFT_OK;
 }
 
 void clifft_program_free(clifft_program* p) {
