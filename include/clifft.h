@@ -74,7 +74,9 @@ typedef struct clifft_launch {
                                probability reductions and renormalization
                                factors are FP64 in both */
   int32_t threads_per_shot; /* 0 automatic, else 1 (shot per lane), 64 (shot per
-                               wave) or 256 (shot per workgroup) */
+                               wave), 256 (shot per workgroup) or -32 (32 shots
+                               per lane, bit-sliced Pauli frames; k_max = 0 only,
+                               not in trace mode) */
   int32_t grid;             /* workgroups (256 threads); 0 = fill the device */
   int32_t vector_in_hbm;    /* 0 automatic (HBM only when LDS is too small),
                                1 force the global workspace, -1 force LDS */

@@ -670,6 +670,81 @@ int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& 
   P.nrec = rec;
   P.nobs = ps.nobs;
   P.final_slots = C.q_at;
+  // Accumulator rows for kernels that XOR detectors and observables
+  // incrementally: a detector's row is live from its first record to its
+  // DETECTOR instruction, so rows are allocated like registers over those
+  // intervals (the DET instruction carries its row in `s` and the kernel
+  // clears the row after emitting it); observables keep rows to the end.
+  // rec_tgt lists the rows each record feeds (a record counted twice cancels).
+  {
+    std::vector<int> rec_at(P.nrec, 0);  // instruction producing each record
+    for (size_t i = 0; i < P.code.size(); i++) {
+      const GInstr& in = P.code[i];
+      if (in.op == OP_MSTATIC || in.op == OP_MRANDOM || in.op == OP_MACTZ || in.op == OP_MACTX) {
+        int r = P.ev_rec[in.b];
+        if (r >= 0) rec_at[r] = (int)i;
+      }
+    }
+    struct Iv { int start, end; size_t instr; };
+    std::vector<Iv> ivs;
+    for (size_t i = 0; i < P.code.size(); i++) {
+      const GInstr& in = P.code[i];
+      if (in.op != OP_DET) continue;
+      int start = (int)i;
+      for (uint32_t k = 0; k < in.u; k++) start = std::min(start, rec_at[P.refs[in.a + k]]);
+      ivs.push_back(Iv{start, (int)i, i});
+    }
+    std::vector<Iv> by_start = ivs;
+    std::stable_sort(by_start.begin(), by_start.end(), [](const Iv& x, const Iv& y) { return x.start < y.start; });
+    std::vector<int> slot_end;  // per slot: end of its current interval (-1 free)
+    std::vector<uint32_t> det_row(P.ndet, 0);
+    for (const Iv& iv : by_start) {
+      int s = -1;
+      for (size_t k = 0; k < slot_end.size(); k++)
+        if (slot_end[k] < iv.start) { s = (int)k; break; }
+      if (s < 0) { s = (int)slot_end.size(); slot_end.push_back(0); }
+      slot_end[s] = iv.end;
+      P.code[iv.instr].s = (uint16_t)s;
+      det_row[P.code[iv.instr].b] = (uint32_t)s;
+    }
+    P.ndet_rows = (int)slot_end.size();
+    std::vector<std::vector<uint32_t>> tg(P.nrec);
+    auto toggle = [&](uint32_t r, uint32_t t) {
+      auto& v = tg[r];
+      auto it = std::find(v.begin(), v.end(), t);
+      if (it == v.end()) v.push_back(t);
+      else v.erase(it);
+    };
+    for (const GInstr& in : P.code) {
+      if (in.op != OP_DET && in.op != OP_OBS) continue;
+      uint32_t t = in.op == OP_DET ? det_row[in.b] : (uint32_t)P.ndet_rows + in.b;
+      for (uint32_t i = 0; i < in.u; i++) toggle(P.refs[in.a + i], t);
+    }
+    P.rec_tgt_off.assign(1, 0);
+    for (int r = 0; r < P.nrec; r++) {
+      for (uint32_t t : tg[r]) P.rec_tgt.push_back(t);
+      P.rec_tgt_off.push_back((uint32_t)P.rec_tgt.size());
+    }
+    if (P.rec_tgt.empty()) P.rec_tgt.push_back(0);
+  }
+  // Dormant random events per 128-event block; each MRANDOM learns its index.
+  {
+    int nblocks = (P.nevents + 127) / 128;
+    std::vector<std::vector<int>> blk(nblocks > 0 ? nblocks : 1);
+    for (GInstr& in : P.code) {
+      if (in.op != OP_MRANDOM) continue;
+      auto& v = blk[in.b >> 7];
+      in.u = (uint16_t)v.size();
+      v.push_back((int)(in.b & 127));
+    }
+    P.rblk_off.assign(1, 0);
+    for (auto& v : blk) {
+      for (int e : v) P.rblk_ev.push_back((uint8_t)e);
+      P.rblk_off.push_back((uint32_t)P.rblk_ev.size());
+      P.rblk_max = std::max<int>(P.rblk_max, (int)v.size());
+    }
+    if (P.rblk_ev.empty()) P.rblk_ev.push_back(0);
+  }
   survival_tables(P);
   if (P.masks.empty()) P.masks.push_back(0);
   if (P.consts.empty()) { P.consts.push_back(1.0); P.consts.push_back(0.0); }

@@ -24,6 +24,11 @@ struct CompiledProgram {
   std::vector<uint32_t> site_img;  // per site offset of its images in masks
   std::vector<double> surv;        // nchunks x (kChunk + 1) survival products
   std::vector<int> final_slots;    // virtual qubit held by each slot at the end
+  std::vector<uint32_t> rec_tgt_off, rec_tgt;  // record -> detector/observable accumulator rows
+  int ndet_rows = 0;                           // detector accumulator rows (reused over time)
+  std::vector<uint32_t> rblk_off;              // 128-event block -> its dormant random events
+  std::vector<uint8_t> rblk_ev;
+  int rblk_max = 0;
 };
 
 // Algorithmic work of one shot (see cost_model in compiler.cpp).

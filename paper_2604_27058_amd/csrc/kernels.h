@@ -54,6 +54,10 @@ struct BatchArgs {
 hipError_t launch_batch(const BatchArgs& B, int grid, size_t lds_bytes, bool fp64, hipStream_t stream);
 
 hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t stream);
+// Bit-sliced Pauli-frame kernel (k_max = 0): 32 shots per lane, one 64-thread
+// workgroup per 2048-shot tile.
+hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStream_t stream);
+size_t frames_lds_rows(const DevProgram& P);
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool trace,
                          hipStream_t stream);
 size_t lds_bytes_for(const DevProgram& P, int G, bool global_vec, bool fp64);

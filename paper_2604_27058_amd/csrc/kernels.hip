@@ -32,6 +32,7 @@ namespace clifft {
 
 #define DEV static __device__ __forceinline__
 #define MDEV __device__ __forceinline__
+#define DEV_HOST_INLINE static __host__ __device__ __forceinline__
 
 // ------------------------------------------------------------------ RNG
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11); one mulhi/mullo pair per
@@ -315,6 +316,7 @@ DEV void next_fault(const DevProgram& P, Noise& ns, uint32_t cur, uint64_t shot,
   uint32_t len = min((uint32_t)kChunk, (uint32_t)P.nsites - ns.chunk * (uint32_t)kChunk);
   double tau = uniform53(w) * S[cur];
   uint32_t lo = cur, hi = len;
+  if (S[len] > tau) lo = len;  // no fault in the rest of the chunk (same answer as the search)
   while (lo < hi) {
     uint32_t mid = (lo + hi) >> 1;
     if (S[mid + 1] <= tau) hi = mid;
@@ -881,6 +883,308 @@ __global__ void k_zero(uint64_t* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// ------------------------------------------------------------------ bit-sliced frames
+// Pauli-frame-only programs (k_max = 0): every lane carries 32 shots, one bit
+// per shot, so a frame bit of one virtual qubit for the 64 x 32 shots of a
+// wave is one 256-byte LDS row (lane l owns word l: conflict free).  Frame
+// instructions become a few word operations per touched qubit for 2048
+// shots; dispatch is paid once per 2048 shots.  The stochastic contract is
+// the per-shot one of the other kernels (each shot keeps its own gap-sampler
+// cursor), so records are identical.
+constexpr int kShotsPerLane = 32;
+
+struct FrameRows {
+  uint32_t* base;  // LDS rows of 64 words
+  int lane;
+  __device__ uint32_t& operator()(uint32_t row) const { return base[row * 64u + (uint32_t)lane]; }
+};
+
+// first fault at or after local index cur of `chunk` for one shot; returns
+// the absolute site (chunk end when none) and advances *ord
+template <bool LDS_SURV>
+DEV uint32_t bs_next_fault(const DevProgram& P, const double* surv_lds, uint32_t chunk, uint32_t cur, uint32_t* ord,
+                           uint64_t shot, uint64_t seed) {
+  U4 w = draw((*ord)++, kPurposeNoise | chunk, shot, seed);
+  const double* S = LDS_SURV ? surv_lds : P.surv + (size_t)chunk * (kChunk + 1);
+  uint32_t len = min((uint32_t)kChunk, (uint32_t)P.nsites - chunk * (uint32_t)kChunk);
+  double tau = uniform53(w) * S[cur];
+  uint32_t lo = cur, hi = len;
+  if (S[len] > tau) lo = len;  // no fault in the rest of the chunk (same answer as the search)
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (S[mid + 1] <= tau) hi = mid;
+    else lo = mid + 1;
+  }
+  return chunk * (uint32_t)kChunk + lo;
+}
+
+template <int W>
+DEV void bs_apply_fault(const DevProgram& P, const FrameRows& F, uint32_t N, uint32_t site, uint32_t o, uint32_t bit) {
+  uint32_t t = P.site_type[site];
+  const uint64_t* img = P.masks + P.site_img[site];
+  uint32_t la, lb = 0;
+  if (t == S_DEP1) la = o + 1;
+  else if (t == S_DEP2) { la = (o + 1) >> 2; lb = (o + 1) & 3; }
+  else la = t - 1;
+  for (int qi = 0; qi < (t == S_DEP2 ? 2 : 1); qi++) {
+    const uint32_t l = qi ? lb : la;
+    const uint64_t ux = (l == 1 || l == 2) ? ~0ull : 0ull, uz = (l == 2 || l == 3) ? ~0ull : 0ull;
+    const uint64_t* ix = img + (size_t)qi * 4 * W;
+    const uint64_t* iz = ix + 2 * W;
+    for (int w = 0; w < W; w++) {
+      uint64_t ex = (ix[w] & ux) ^ (iz[w] & uz);
+      uint64_t ez = (ix[W + w] & ux) ^ (iz[W + w] & uz);
+      while (ex) {
+        uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)ex) - 1);
+        ex &= ex - 1;
+        F(q) ^= bit;          // full x
+        F(2 * N + q) ^= bit;  // noise x
+      }
+      while (ez) {
+        uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)ez) - 1);
+        ez &= ez - 1;
+        F(N + q) ^= bit;      // full z
+        F(3 * N + q) ^= bit;  // noise z
+      }
+    }
+  }
+}
+
+// LDS rows: [0,4N) frames (full x, full z, noise x, noise z), then one row
+// per detector and observable accumulator, then the dormant-random bit rows
+// of the current 128-event block, then per-shot noise cursors (site; draw
+// ordinal | chunk << 16).
+constexpr int kSurvLdsMax = 2048;  // survival products staged in LDS (single chunk, up to this many sites)
+DEV_HOST_INLINE bool frames_surv_in_lds(const DevProgram& P) { return P.nchunks == 1 && P.nsites < kSurvLdsMax; }
+size_t frames_lds_rows(const DevProgram& P) {
+  size_t rows = (size_t)4 * P.nq + P.ndet_rows + P.nobs + (P.rblk_max > 0 ? P.rblk_max : 1) + 2 * kShotsPerLane;
+  if (frames_surv_in_lds(P)) rows += ((size_t)(P.nsites + 1) * 8 + 255) / 256;  // doubles, in 256-byte rows
+  return rows;
+}
+
+template <int W, bool LDS_SURV>
+__global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
+  extern __shared__ __align__(16) uint32_t sm[];
+  const int lane = threadIdx.x;
+  const uint32_t N = (uint32_t)P.nq;
+  const FrameRows F{sm, lane};
+  const uint32_t ACC = 4 * N, RB = ACC + (uint32_t)(P.ndet_rows + P.nobs);
+  const uint32_t NF = RB + (uint32_t)(P.rblk_max > 0 ? P.rblk_max : 1), OC = NF + kShotsPerLane;
+  double* surv = (double*)(sm + (size_t)(OC + kShotsPerLane) * 64);
+  if (LDS_SURV) {
+    for (int i = lane; i <= P.nsites; i += 64) surv[i] = P.surv[i];
+    __syncthreads();
+  }
+  const uint64_t seed = A.seed;
+  const uint64_t words64 = (A.shots + 63) / 64;
+  const uint64_t tiles = (A.shots + 64 * kShotsPerLane - 1) / (64 * kShotsPerLane);
+  uint32_t* meas32 = (uint32_t*)A.meas;
+  uint32_t* det32 = (uint32_t*)A.det;
+  uint32_t* obs32 = (uint32_t*)A.obs;
+  cptr<uint64_t> masks = as_const(P.masks);
+  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const uint64_t s0 = tile * (64 * kShotsPerLane) + (uint64_t)lane * kShotsPerLane;  // first shot of the lane
+    const uint32_t valid = s0 >= A.shots ? 0u : (A.shots - s0 >= 32 ? ~0u : ((1u << (A.shots - s0)) - 1u));
+    const size_t col = (size_t)(s0 >> 5);  // 32-bit column of this lane in the record rows
+    const bool store = col < 2 * words64;  // inside the buffer (bits past the last shot are written as 0)
+    for (uint32_t r = 0; r < RB; r++) F(r) = 0;
+    // per-shot noise cursors
+    uint32_t min_nf = 0xFFFFFFFFu;
+    if (P.nsites > 0) {
+      for (int j = 0; j < kShotsPerLane; j++) {
+        uint32_t ord = 0;
+        uint32_t nf = bs_next_fault<LDS_SURV>(P, surv, 0, 0, &ord, A.offset + s0 + j, seed);
+        F(NF + j) = nf;
+        F(OC + j) = ord;
+        min_nf = min(min_nf, nf);
+      }
+    }
+    uint32_t last_m = 0, last_pn = 0;
+    uint32_t rblk = 0xFFFFFFFFu;
+    for (int pc = 0;; pc++) {
+      const GInstr in = load_instr(P.code, pc);
+      const uint32_t v = in.v;
+      if (in.op == OP_END) break;
+      switch (in.op) {
+        case OP_FANCX:
+        case OP_FANCZ:
+        case OP_FAN2: {
+          // per frame: the pivot word, the masked qubits' words
+          for (uint32_t c = 0; c < 4; c += 2) {
+            const uint32_t X = c * N, Z = c * N + N;
+            const uint32_t xv = F(X + v), zv = F(Z + v);
+            uint32_t par = 0;
+            for (int w = 0; w < W; w++) {
+              uint64_t m = masks[in.a + w];
+              while (m) {
+                const uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)m) - 1);
+                m &= m - 1;
+                if (in.op == OP_FANCX) { F(X + q) ^= xv; par ^= F(Z + q); }
+                else if (in.op == OP_FANCZ) { F(Z + q) ^= xv; par ^= F(X + q); }
+                else { F(Z + q) ^= zv; par ^= F(X + q); }
+              }
+            }
+            if (in.op == OP_FAN2) F(X + v) ^= par;
+            else F(Z + v) ^= par;
+          }
+          break;
+        }
+        case OP_FS:
+          F(N + v) ^= F(v);
+          F(3 * N + v) ^= F(2 * N + v);
+          break;
+        case OP_FH: {
+          uint32_t t = F(v); F(v) = F(N + v); F(N + v) = t;
+          t = F(2 * N + v); F(2 * N + v) = F(3 * N + v); F(3 * N + v) = t;
+          break;
+        }
+        case OP_MSTATIC:
+        case OP_MRANDOM: {
+          uint32_t mm, pn;
+          if (in.op == OP_MSTATIC) {
+            mm = (in.flags & F_SIGN) ? ~0u : 0u;
+            pn = 0;
+            for (int w = 0; w < W; w++) {
+              uint64_t m = masks[in.a + w];
+              while (m) {
+                const uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)m) - 1);
+                m &= m - 1;
+                mm ^= F(q);
+                pn ^= F(2 * N + q);
+              }
+            }
+          } else {
+            const uint32_t j = in.b, blk = j >> 7;
+            if (blk != rblk) {
+              // bits of this block's dormant random events for the lane's 32 shots
+              const uint32_t o0 = P.rblk_off[blk], o1 = P.rblk_off[blk + 1];
+              for (uint32_t k = o0; k < o1; k++) F(RB + (k - o0)) = 0;
+              for (int s = 0; s < kShotsPerLane; s++) {
+                U4 w = draw(blk, kPurposeRbit, A.offset + s0 + s, seed);
+                for (uint32_t k = o0; k < o1; k++) {
+                  const uint32_t e = P.rblk_ev[k];
+                  const uint32_t wv = (e >> 5) == 0 ? w.w0 : (e >> 5) == 1 ? w.w1 : (e >> 5) == 2 ? w.w2 : w.w3;
+                  F(RB + (k - o0)) |= ((wv >> (e & 31)) & 1u) << s;
+                }
+              }
+              rblk = blk;
+            }
+            const uint32_t p = F(N + v);
+            pn = F(3 * N + v);
+            mm = F(RB + in.u) ^ pn;
+            const uint32_t b = mm ^ p ^ ((in.flags & F_SIGN) ? ~0u : 0u);
+            uint32_t t = F(v); F(v) = F(N + v); F(N + v) = t;
+            t = F(2 * N + v); F(2 * N + v) = F(3 * N + v); F(3 * N + v) = t;
+            F(v) ^= b;
+          }
+          last_m = mm;
+          last_pn = pn;
+          const int r = as_const(P.ev_rec)[in.b];
+          if (r >= 0) {
+            if (meas32 && store) meas32[(size_t)r * 2 * words64 + col] = mm & valid;
+            const uint32_t t0 = P.rec_tgt_off[r], t1 = P.rec_tgt_off[r + 1];
+            for (uint32_t t = t0; t < t1; t++) F(ACC + P.rec_tgt[t]) ^= mm;
+          }
+          break;
+        }
+        case OP_CPAULI: {
+          for (int w = 0; w < W; w++) {
+            uint64_t mx = masks[in.a + w], mz = masks[in.a + W + w];
+            while (mx) {
+              const uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)mx) - 1);
+              mx &= mx - 1;
+              F(q) ^= last_m;
+              F(2 * N + q) ^= last_pn;
+            }
+            while (mz) {
+              const uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)mz) - 1);
+              mz &= mz - 1;
+              F(N + q) ^= last_m;
+              F(3 * N + q) ^= last_pn;
+            }
+          }
+          break;
+        }
+        case OP_NOISE: {
+          const uint32_t hi = in.b;
+          if (min_nf < hi) {
+            // which of the lane's shots have a fault before hi: 32 independent
+            // LDS loads, then a mask
+            uint32_t due = 0;
+#pragma unroll
+            for (int s = 0; s < kShotsPerLane; s++) due |= (uint32_t)(F(NF + s) < hi) << s;
+            while (due) {
+              const int s = __ffs(due) - 1;
+              due &= due - 1;
+              uint32_t nf = F(NF + s);
+              {
+                uint32_t oc = F(OC + s);
+                uint32_t chunk = oc >> 16, ord = oc & 0xFFFFu;
+                const uint64_t shot = A.offset + s0 + s;
+                while (nf < hi) {
+                  const uint32_t cend = min((chunk + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
+                  if (nf >= cend) {
+                    chunk++;
+                    ord = 0;
+                    nf = bs_next_fault<LDS_SURV>(P, surv, chunk, 0, &ord, shot, seed);
+                    continue;
+                  }
+                  // the outcome comes from the draw that placed this fault
+                  U4 w = draw(ord - 1, kPurposeNoise | chunk, shot, seed);
+                  const uint64_t w64 = ((uint64_t)w.w3 << 32) | w.w2;
+                  const uint32_t o = (uint32_t)__umul64hi(w64, (uint64_t)nout_of(P.site_type[nf]));
+                  bs_apply_fault<W>(P, F, N, nf, o, 1u << s);
+                  nf = bs_next_fault<LDS_SURV>(P, surv, chunk, nf - chunk * (uint32_t)kChunk + 1, &ord, shot, seed);
+                }
+                F(NF + s) = nf;
+                F(OC + s) = ord | (chunk << 16);
+              }
+            }
+            uint32_t nmin = 0xFFFFFFFFu;
+#pragma unroll
+            for (int s = 0; s < kShotsPerLane; s++) nmin = min(nmin, F(NF + s));
+            min_nf = nmin;
+          }
+          break;
+        }
+        case OP_DET:
+          if (det32 && store) det32[(size_t)in.b * 2 * words64 + col] = F(ACC + in.s) & valid;
+          F(ACC + in.s) = 0;  // the row is reused by a later detector
+          break;
+        default:  // OP_OBS: accumulated from its records; no active-vector ops exist here
+          break;
+      }
+    }
+    if (obs32 && store)
+      for (int o = 0; o < P.nobs; o++) obs32[(size_t)o * 2 * words64 + col] = F(ACC + P.ndet_rows + o) & valid;
+  }
+}
+
+template <bool LS>
+static hipError_t launch_frames_t(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
+  static bool attr[5] = {false, false, false, false, false};
+  const void* fn = P.W == 1 ? (const void*)k_frames<1, LS> : P.W == 2 ? (const void*)k_frames<2, LS>
+                   : P.W == 3 ? (const void*)k_frames<3, LS> : (const void*)k_frames<4, LS>;
+  if (!attr[P.W]) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr[P.W] = true;
+  }
+  switch (P.W) {
+    case 1: hipLaunchKernelGGL((k_frames<1, LS>), dim3(grid), dim3(64), lds, st, P, A); break;
+    case 2: hipLaunchKernelGGL((k_frames<2, LS>), dim3(grid), dim3(64), lds, st, P, A); break;
+    case 3: hipLaunchKernelGGL((k_frames<3, LS>), dim3(grid), dim3(64), lds, st, P, A); break;
+    default: hipLaunchKernelGGL((k_frames<4, LS>), dim3(grid), dim3(64), lds, st, P, A); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStream_t st) {
+  const size_t lds = frames_lds_rows(P) * 64 * 4;
+  if (frames_surv_in_lds(P)) return launch_frames_t<true>(P, A, grid, lds, st);
+  return launch_frames_t<false>(P, A, grid, lds, st);
+}
+
 // ------------------------------------------------------------------ batched launch
 // One persistent launch over many programs of different width and active
 // dimension.  Workgroups claim items in the order the host sorted them
@@ -1052,6 +1356,7 @@ static hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShap
 
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool debug,
                          hipStream_t st) {
+  if (L.G < 0) return launch_frames(P, A, L.grid, st);
   if (L.G == 256) {
     const size_t words = (A.shots + 63) / 64;
     uint64_t* rows[3] = {A.meas, A.det, A.obs};

@@ -30,12 +30,13 @@ enum Op : uint8_t {
   OP_EXPAND,   // H on dormant v, new slot s = k, then rotation      v, s, a=const
   OP_AROT,     // diagonal rotation on active v at slot s            v, s, a=const
   OP_MSTATIC,  // deterministic Z-string measurement                 a=mask(z, W words), b=event
-  OP_MRANDOM,  // dormant X_v measurement, then H_v absorbed         v, b=event
+  OP_MRANDOM,  // dormant X_v measurement, then H_v absorbed         v, b=event, u=index among the
+               //   dormant random events of the event's 128-block
   OP_MACTZ,    // active Z_v measurement (mask), demote slot s       v, s, b=event
   OP_MACTX,    // active X_v measurement (interfere), demote slot s  v, s, b=event
   OP_CPAULI,   // reset correction X^m (noise part X^pn)             a=mask(x,z), b=event
   OP_NOISE,    // noise sites [a, b)
-  OP_DET,      // detector b = XOR of records refs[a .. a+u)
+  OP_DET,      // detector b = XOR of records refs[a .. a+u); s = its accumulator row
   OP_OBS,      // observable b ^= XOR of records refs[a .. a+u)
   OP_COUNT
 };
@@ -72,9 +73,15 @@ struct DevProgram {
   const uint8_t* site_type;  // per noise site
   const uint32_t* site_img;  // per site: offset of its images in masks (2 or 4 images x 2W words)
   const double* surv;        // per chunk: kChunk + 1 survival products
+  const uint32_t* rec_tgt_off;  // per record: first entry in rec_tgt (nrec + 1 entries)
+  const uint32_t* rec_tgt;      // accumulators (detector d, or ndet + observable o) a record feeds
+  const uint32_t* rblk_off;     // per 128-event block: first entry in rblk_ev (nblocks + 1 entries)
+  const uint8_t* rblk_ev;       // event ordinal mod 128 of each dormant random event of the block
   int32_t nq, W, kmax, ncode;
   int32_t nevents, nrec, ndet, nobs;
   int32_t nsites, nchunks;
+  int32_t rblk_max;             // most dormant random events in one 128-event block
+  int32_t ndet_rows;            // detector accumulator rows (observables follow them)
 };
 
 }  // namespace clifft

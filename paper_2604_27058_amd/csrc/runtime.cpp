@@ -78,6 +78,10 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
   if (e == hipSuccess) e = upload_vec(H.site_type, &v.site_type, dc.allocs);
   if (e == hipSuccess) e = upload_vec(H.site_img, &v.site_img, dc.allocs);
   if (e == hipSuccess) e = upload_vec(H.surv, &v.surv, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.rec_tgt_off, &v.rec_tgt_off, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.rec_tgt, &v.rec_tgt, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.rblk_off, &v.rblk_off, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.rblk_ev, &v.rblk_ev, dc.allocs);
   if (e != hipSuccess) {
     for (void* a : dc.allocs) (void)hipFree(a);
     return fail(CLIFFT_E_DEVICE, std::string("program upload failed: ") + hipGetErrorString(e));
@@ -92,6 +96,8 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
   v.nobs = H.nobs;
   v.nsites = (int)H.site_p.size();
   v.nchunks = H.nchunks;
+  v.rblk_max = H.rblk_max;
+  v.ndet_rows = H.ndet_rows;
   auto res = p->dev.emplace(dev, std::move(dc));
   *out = &res.first->second.view;
   return CLIFFT_OK;
@@ -100,6 +106,7 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kLaneMaxK = 12;                              // shot-per-lane tier up to this k_max
 constexpr int kBatchLaneMaxK = 10;                         // the same inside a batched launch
+constexpr int kBitSliced = -32;                            // 32 shots per lane, bit-sliced frames
 constexpr size_t kWorkspaceBudget = (size_t)4 << 30;       // default global vector workspace
 
 int device_cus() {
@@ -113,7 +120,7 @@ int device_cus() {
 // and storage), the grid fills the device with persistent workgroups.
 clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const clifft_launch* cfg, uint64_t shots,
                            LaunchShape* L, bool* fp64,
-                           const std::map<std::pair<int, int>, clifft_launch>* tuned = nullptr) {
+                           const std::map<std::pair<int, int>, clifft_launch>* tuned = nullptr, bool trace = false) {
   clifft_launch c{};
   if (cfg) c = *cfg;
   if (c.precision != CLIFFT_FP32 && c.precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
@@ -122,12 +129,39 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
     int dev = 0;
     (void)hipGetDevice(&dev);
     auto it = tuned->find({dev, c.precision});
-    if (it != tuned->end()) c = it->second;
+    if (it != tuned->end() && !(trace && it->second.threads_per_shot == kBitSliced)) c = it->second;
   }
   const size_t amp = *fp64 ? 16 : 8;
   const size_t vec = (size_t)1 << H.kmax;
   int G = c.threads_per_shot;
-  if (G != 0 && G != 1 && G != 64 && G != 256) return fail(CLIFFT_E_INVALID_ARG, "threads_per_shot must be 0, 1, 64 or 256");
+  if (G != 0 && G != 1 && G != 64 && G != 256 && G != kBitSliced)
+    return fail(CLIFFT_E_INVALID_ARG, "threads_per_shot must be 0, 1, 64, 256 or -32");
+  {
+    // bit-sliced Pauli frames: k_max = 0 programs whose rows fit in LDS
+    DevProgram tmp{};
+    tmp.nq = H.nq;
+    tmp.ndet = H.ndet;
+    tmp.nobs = H.nobs;
+    tmp.rblk_max = H.rblk_max;
+    tmp.ndet_rows = H.ndet_rows;
+    tmp.nsites = (int)H.site_p.size();
+    tmp.nchunks = H.nchunks;
+    const size_t rows_bytes = frames_lds_rows(tmp) * 64 * 4;
+    const bool bs_ok = H.kmax == 0 && !trace && rows_bytes <= kLdsLimit;
+    if (G == kBitSliced && !bs_ok) return fail(CLIFFT_E_CAPACITY, "bit-sliced frames need k_max = 0 and rows in LDS");
+    if (G == 0 && bs_ok) G = kBitSliced;
+    if (G == kBitSliced) {
+      const uint64_t tiles = (shots + 2047) / 2048;
+      int per_cu = (int)std::max<size_t>(1, std::min<size_t>(16, kLdsLimit / rows_bytes));
+      int grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
+      if ((uint64_t)grid > tiles) grid = (int)std::max<uint64_t>(1, tiles);
+      L->G = kBitSliced;
+      L->grid = grid;
+      L->lds_bytes = rows_bytes;
+      L->global_vec = false;
+      return CLIFFT_OK;
+    }
+  }
   // Tiers: frames shot-per-lane whenever the vectors of 64 shots fit the
   // global budget (k <= 12), else one shot per workgroup; vectors in LDS when
   // they fit, else in the caller's workspace (HBM).
@@ -183,7 +217,7 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
   if (st != CLIFFT_OK) return st;
   LaunchShape L{};
   bool fp64 = false;
-  st = choose_shape(p->host, D, cfg, shots, &L, &fp64, &p->tuned);
+  st = choose_shape(p->host, D, cfg, shots, &L, &fp64, &p->tuned, trace);
   if (st != CLIFFT_OK) return st;
   size_t need = workspace_bytes(p->host, L, fp64);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) {
@@ -523,6 +557,8 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
   if (shots > 0 && shots < trial) trial = shots;
   std::vector<clifft_launch> cands;
   const int mult[4] = {1, 2, 4, 8};
+  if (H.kmax == 0)
+    for (int m : {1, 2, 4, 8, 16}) cands.push_back(clifft_launch{precision, kBitSliced, cus * m, 0});
   for (int G : {1, 64, 256}) {
     if (H.kmax == 0 && G != 1) continue;
     for (int hbm : {-1, 1}) {

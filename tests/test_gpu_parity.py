@@ -38,7 +38,9 @@ def u64(t):
 def gpu_sample(text_or_prog, shots, seed=0, offset=0, **launch):
     p = text_or_prog if isinstance(text_or_prog, pk.Program) else pk.Program(text_or_prog)
     L = pk.make_launch(**launch) if launch else None
-    m, d, o = p.sample(shots, seed=seed, offset=offset, launch=L)
+    # outputs start as garbage so that unwritten words are caught
+    outs = tuple(x.fill_(-1) for x in p.alloc_outputs(shots))
+    m, d, o = p.sample(shots, seed=seed, offset=offset, launch=L, outputs=outs)
     torch.cuda.synchronize()
     return u64(m), u64(d), u64(o)
 
@@ -57,7 +59,7 @@ def test_in_tree_library_is_the_one_loaded():
     assert pk.LIB_PATH in maps
 
 
-@pytest.mark.parametrize("G", [1, 64, 256])
+@pytest.mark.parametrize("G", [1, 64, 256, -32])
 def test_surface_d3_bit_exact(G):
     text = circuits.workload("surface_d3_r3")["texts"][0]
     shots = 20000 + 37  # ragged last tile
@@ -68,22 +70,38 @@ def test_surface_d3_bit_exact(G):
     assert np.array_equal(go, oo)
 
 
-def test_surface_d3_high_noise_bit_exact_multi_chunk():
+@pytest.mark.parametrize("G", [1, -32])
+def test_surface_d3_high_noise_bit_exact_multi_chunk(G):
     # many faults per shot and more than one 4096-site survival chunk
     text = circuits.surface_code_memory(3, 120, 2e-2)
     p = oracle.Program(text)
     assert p.nchunks >= 2
     shots = 3000
     om, od, oo = p.sample(shots, seed=5, threads=8)
-    gm, gd, go = gpu_sample(text, shots, seed=5)
+    gm, gd, go = gpu_sample(text, shots, seed=5, threads_per_shot=G)
     assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
 
 
-def test_shard_resume_bit_identical_gpu():
+@pytest.mark.parametrize("case", range(12))
+def test_bit_sliced_frames_random_clifford_circuits(case):
+    """Pauli-frame-only random circuits (W = 1..3 words, all noise types, MX,
+    resets, detectors, observables included twice) on the bit-sliced tier."""
+    rng = np.random.default_rng(1300 + case)
+    n = [5, 70, 100, 30][case % 4]
+    text = random_small_circuit(rng, n, 120, rotations=False)
+    text += "OBSERVABLE_INCLUDE(1) rec[-1] rec[-2]\nOBSERVABLE_INCLUDE(1) rec[-1]\n"
+    shots = 5000 + 13 * case
+    om, od, oo = oracle.Program(text).sample(shots, seed=case, threads=8)
+    gm, gd, go = gpu_sample(text, shots, seed=case, threads_per_shot=-32)
+    assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
+
+
+@pytest.mark.parametrize("G", [1, -32])
+def test_shard_resume_bit_identical_gpu(G):
     text = circuits.surface_code_memory(3, 3, 1e-2)
-    a = gpu_sample(text, 1024, seed=5)
-    b = gpu_sample(text, 512, seed=5, offset=0)
-    c = gpu_sample(text, 512, seed=5, offset=512)
+    a = gpu_sample(text, 4096, seed=5, threads_per_shot=G)
+    b = gpu_sample(text, 2048, seed=5, offset=0, threads_per_shot=G)
+    c = gpu_sample(text, 2048, seed=5, offset=2048, threads_per_shot=G)
     for x, y, z in zip(a, b, c):
         assert np.array_equal(x, np.concatenate([y, z], axis=1))
 
