@@ -19,6 +19,7 @@ struct KArgs {
   double* probs;                 // [shots][nevents] P(m = 1) or null
   double* phi_out;               // [shots][2^kmax][2] or null
   int* error;                    // device flag word (trace mode)
+  uint32_t list_cap = 0xFFFFFFFFu;  // bit-sliced fault-list capacity (tests may lower it)
 };
 
 struct LaunchShape {

@@ -903,7 +903,7 @@ struct FrameRows {
 // the absolute site (chunk end when none) and advances *ord
 template <bool LDS_SURV>
 DEV uint32_t bs_next_fault(const DevProgram& P, const double* surv_lds, uint32_t chunk, uint32_t cur, uint32_t* ord,
-                           uint64_t shot, uint64_t seed) {
+                           uint64_t shot, uint64_t seed, uint32_t* outcome = nullptr) {
   U4 w = draw((*ord)++, kPurposeNoise | chunk, shot, seed);
   const double* S = LDS_SURV ? surv_lds : P.surv + (size_t)chunk * (kChunk + 1);
   uint32_t len = min((uint32_t)kChunk, (uint32_t)P.nsites - chunk * (uint32_t)kChunk);
@@ -915,7 +915,12 @@ DEV uint32_t bs_next_fault(const DevProgram& P, const double* surv_lds, uint32_t
     if (S[mid + 1] <= tau) hi = mid;
     else lo = mid + 1;
   }
-  return chunk * (uint32_t)kChunk + lo;
+  const uint32_t nf = chunk * (uint32_t)kChunk + lo;
+  if (outcome && lo < len) {
+    const uint64_t w64 = ((uint64_t)w.w3 << 32) | w.w2;
+    *outcome = (uint32_t)__umul64hi(w64, (uint64_t)nout_of(P.site_type[nf]));
+  }
+  return nf;
 }
 
 template <int W>
@@ -955,22 +960,32 @@ DEV void bs_apply_fault(const DevProgram& P, const FrameRows& F, uint32_t N, uin
 // of the current 128-event block, then per-shot noise cursors (site; draw
 // ordinal | chunk << 16).
 constexpr int kSurvLdsMax = 2048;  // survival products staged in LDS (single chunk, up to this many sites)
+constexpr int kListCap = 32;       // faults per lane kept in the precomputed list
 DEV_HOST_INLINE bool frames_surv_in_lds(const DevProgram& P) { return P.nchunks == 1 && P.nsites < kSurvLdsMax; }
+// Low-noise programs precompute each lane's faults into a site-sorted list
+// (expected faults per lane well under the list capacity); others keep one
+// sampler cursor per shot.
+DEV_HOST_INLINE bool frames_fault_list(const DevProgram& P) {
+  return P.nsites < (1 << 23) && (double)P.exp_faults * kShotsPerLane <= kListCap / 4;
+}
 size_t frames_lds_rows(const DevProgram& P) {
-  size_t rows = (size_t)4 * P.nq + P.ndet_rows + P.nobs + (P.rblk_max > 0 ? P.rblk_max : 1) + 2 * kShotsPerLane;
+  size_t rows = (size_t)4 * P.nq + P.ndet_rows + P.nobs + (P.rblk_max > 0 ? P.rblk_max : 1);
+  rows += frames_fault_list(P) ? kListCap : 2 * kShotsPerLane;
   if (frames_surv_in_lds(P)) rows += ((size_t)(P.nsites + 1) * 8 + 255) / 256;  // doubles, in 256-byte rows
   return rows;
 }
 
-template <int W, bool LDS_SURV>
+template <int W, bool LDS_SURV, bool LIST>
 __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   extern __shared__ __align__(16) uint32_t sm[];
   const int lane = threadIdx.x;
   const uint32_t N = (uint32_t)P.nq;
   const FrameRows F{sm, lane};
   const uint32_t ACC = 4 * N, RB = ACC + (uint32_t)(P.ndet_rows + P.nobs);
+  // LIST: rows [NF, NF + kListCap) hold the fault list; otherwise per-shot
+  // cursors: next fault site at NF + s, draw ordinal | chunk << 16 at OC + s
   const uint32_t NF = RB + (uint32_t)(P.rblk_max > 0 ? P.rblk_max : 1), OC = NF + kShotsPerLane;
-  double* surv = (double*)(sm + (size_t)(OC + kShotsPerLane) * 64);
+  double* surv = (double*)(sm + (size_t)(NF + (LIST ? kListCap : 2 * kShotsPerLane)) * 64);
   if (LDS_SURV) {
     for (int i = lane; i <= P.nsites; i += 64) surv[i] = P.surv[i];
     __syncthreads();
@@ -988,9 +1003,41 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
     const size_t col = (size_t)(s0 >> 5);  // 32-bit column of this lane in the record rows
     const bool store = col < 2 * words64;  // inside the buffer (bits past the last shot are written as 0)
     for (uint32_t r = 0; r < RB; r++) F(r) = 0;
-    // per-shot noise cursors
     uint32_t min_nf = 0xFFFFFFFFu;
-    if (P.nsites > 0) {
+    uint32_t lcnt = 0, lhead = 0;
+    const uint32_t lcap = min((uint32_t)kListCap, A.list_cap);
+    bool lovf = false;
+    if (LIST && P.nsites > 0) {
+      // every fault of the lane's 32 shots, as (site << 9 | shot << 4 | outcome)
+      for (int j = 0; j < kShotsPerLane; j++) {
+        const uint64_t shot = A.offset + s0 + j;
+        for (uint32_t c = 0; c < (uint32_t)P.nchunks; c++) {
+          const uint32_t cend = min((c + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
+          uint32_t ord = 0, cur = 0;
+          for (;;) {
+            uint32_t o = 0;
+            const uint32_t nf = bs_next_fault<LDS_SURV>(P, surv, c, cur, &ord, shot, seed, &o);
+            if (nf >= cend) break;
+            if (lcnt < lcap) F(NF + lcnt) = (nf << 9) | ((uint32_t)j << 4) | o;
+            else lovf = true;
+            lcnt++;
+            cur = nf - c * (uint32_t)kChunk + 1;
+          }
+        }
+      }
+      const uint32_t n = min(lcnt, lcap);
+      for (uint32_t i = 1; i < n; i++) {  // insertion sort by site
+        const uint32_t e = F(NF + i);
+        uint32_t kk = i;
+        while (kk > 0 && F(NF + kk - 1) > e) {
+          F(NF + kk) = F(NF + kk - 1);
+          kk--;
+        }
+        F(NF + kk) = e;
+      }
+    }
+    // per-shot noise cursors
+    if (!LIST && P.nsites > 0) {
       for (int j = 0; j < kShotsPerLane; j++) {
         uint32_t ord = 0;
         uint32_t nf = bs_next_fault<LDS_SURV>(P, surv, 0, 0, &ord, A.offset + s0 + j, seed);
@@ -1107,6 +1154,35 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
         }
         case OP_NOISE: {
           const uint32_t hi = in.b;
+          if (LIST) {
+            if (!lovf) {
+              while (lhead < lcnt) {
+                const uint32_t e = F(NF + lhead);
+                if ((e >> 9) >= hi) break;
+                bs_apply_fault<W>(P, F, N, e >> 9, e & 15u, 1u << ((e >> 4) & 31u));
+                lhead++;
+              }
+            } else {
+              // list overflow (rare): re-draw this block's faults per shot from
+              // the start of each chunk it touches (stateless, same faults)
+              const uint32_t lo = in.a;
+              for (int j = 0; j < kShotsPerLane; j++) {
+                const uint64_t shot = A.offset + s0 + j;
+                for (uint32_t c = lo / (uint32_t)kChunk; c * (uint32_t)kChunk < hi; c++) {
+                  const uint32_t cend = min(min((c + 1) * (uint32_t)kChunk, (uint32_t)P.nsites), hi);
+                  uint32_t ord = 0, cur = 0;
+                  for (;;) {
+                    uint32_t o = 0;
+                    const uint32_t nf = bs_next_fault<LDS_SURV>(P, surv, c, cur, &ord, shot, seed, &o);
+                    if (nf >= cend) break;
+                    if (nf >= lo) bs_apply_fault<W>(P, F, N, nf, o, 1u << j);
+                    cur = nf - c * (uint32_t)kChunk + 1;
+                  }
+                }
+              }
+            }
+            break;
+          }
           if (min_nf < hi) {
             // which of the lane's shots have a fault before hi: 32 independent
             // LDS loads, then a mask
@@ -1160,29 +1236,32 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   }
 }
 
-template <bool LS>
+template <bool LS, bool LI>
 static hipError_t launch_frames_t(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
   static bool attr[5] = {false, false, false, false, false};
-  const void* fn = P.W == 1 ? (const void*)k_frames<1, LS> : P.W == 2 ? (const void*)k_frames<2, LS>
-                   : P.W == 3 ? (const void*)k_frames<3, LS> : (const void*)k_frames<4, LS>;
+  const void* fn = P.W == 1 ? (const void*)k_frames<1, LS, LI> : P.W == 2 ? (const void*)k_frames<2, LS, LI>
+                   : P.W == 3 ? (const void*)k_frames<3, LS, LI> : (const void*)k_frames<4, LS, LI>;
   if (!attr[P.W]) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr[P.W] = true;
   }
   switch (P.W) {
-    case 1: hipLaunchKernelGGL((k_frames<1, LS>), dim3(grid), dim3(64), lds, st, P, A); break;
-    case 2: hipLaunchKernelGGL((k_frames<2, LS>), dim3(grid), dim3(64), lds, st, P, A); break;
-    case 3: hipLaunchKernelGGL((k_frames<3, LS>), dim3(grid), dim3(64), lds, st, P, A); break;
-    default: hipLaunchKernelGGL((k_frames<4, LS>), dim3(grid), dim3(64), lds, st, P, A); break;
+    case 1: hipLaunchKernelGGL((k_frames<1, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
+    case 2: hipLaunchKernelGGL((k_frames<2, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
+    case 3: hipLaunchKernelGGL((k_frames<3, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
+    default: hipLaunchKernelGGL((k_frames<4, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStream_t st) {
   const size_t lds = frames_lds_rows(P) * 64 * 4;
-  if (frames_surv_in_lds(P)) return launch_frames_t<true>(P, A, grid, lds, st);
-  return launch_frames_t<false>(P, A, grid, lds, st);
+  const bool ls = frames_surv_in_lds(P), li = frames_fault_list(P);
+  if (ls && li) return launch_frames_t<true, true>(P, A, grid, lds, st);
+  if (ls) return launch_frames_t<true, false>(P, A, grid, lds, st);
+  if (li) return launch_frames_t<false, true>(P, A, grid, lds, st);
+  return launch_frames_t<false, false>(P, A, grid, lds, st);
 }
 
 // ------------------------------------------------------------------ batched launch

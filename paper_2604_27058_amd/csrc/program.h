@@ -82,6 +82,7 @@ struct DevProgram {
   int32_t nsites, nchunks;
   int32_t rblk_max;             // most dormant random events in one 128-event block
   int32_t ndet_rows;            // detector accumulator rows (observables follow them)
+  float exp_faults;             // expected realized faults per shot (sum of site probabilities)
 };
 
 }  // namespace clifft

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -98,6 +99,11 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
   v.nchunks = H.nchunks;
   v.rblk_max = H.rblk_max;
   v.ndet_rows = H.ndet_rows;
+  {
+    double f = 0;
+    for (double q : H.site_p) f += q;
+    v.exp_faults = (float)f;
+  }
   auto res = p->dev.emplace(dev, std::move(dc));
   *out = &res.first->second.view;
   return CLIFFT_OK;
@@ -146,6 +152,11 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
     tmp.ndet_rows = H.ndet_rows;
     tmp.nsites = (int)H.site_p.size();
     tmp.nchunks = H.nchunks;
+    {
+      double f = 0;
+      for (double q : H.site_p) f += q;
+      tmp.exp_faults = (float)f;
+    }
     const size_t rows_bytes = frames_lds_rows(tmp) * 64 * 4;
     const bool bs_ok = H.kmax == 0 && !trace && rows_bytes <= kLdsLimit;
     if (G == kBitSliced && !bs_ok) return fail(CLIFFT_E_CAPACITY, "bit-sliced frames need k_max = 0 and rows in LDS");
@@ -233,6 +244,8 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
   A.det = det;
   A.obs = obs;
   A.workspace = ws;
+  A.list_cap = 0xFFFFFFFFu;
+  if (const char* cap = getenv("CLIFFT_FRAMES_LIST_CAP")) A.list_cap = (uint32_t)strtoul(cap, nullptr, 10);
   hipStream_t s = (hipStream_t)stream;
   int* dflag = nullptr;
   if (trace) {

@@ -254,3 +254,27 @@ def test_batched_launch_matches_single_program_and_oracle(precision):
         om, _, _ = oracle.Program(c["text"]).sample(n, seed=seeds[i], threads=8)
         bad = mismatched_shots(om[:, :1], bm[0][:, :1] & np.uint64((1 << n) - 1 if n < 64 else ~np.uint64(0)), n)
         assert bad == 0 if precision == "f64" else bad <= 1, (i, bad)
+
+
+@pytest.mark.parametrize("cap", ["0", "1", "3"])
+def test_bit_sliced_fault_list_overflow_path(cap, monkeypatch):
+    """Low-noise programs precompute each lane's faults into a list; lanes
+    whose faults overflow it re-draw them per block.  Shrinking the list
+    forces that path; records must not change."""
+    text = circuits.surface_code_memory(3, 5, 1e-3)
+    shots = 40000 + 3
+    om, od, oo = oracle.Program(text).sample(shots, seed=21, threads=8)
+    monkeypatch.setenv("CLIFFT_FRAMES_LIST_CAP", cap)
+    gm, gd, go = gpu_sample(text, shots, seed=21, threads_per_shot=-32)
+    assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
+
+
+def test_bit_sliced_multi_chunk_low_noise():
+    """More than one survival chunk with the fault list (no LDS table)."""
+    text = circuits.surface_code_memory(3, 120, 5e-5)
+    p = oracle.Program(text)
+    assert p.nchunks >= 2
+    shots = 20000
+    om, od, oo = p.sample(shots, seed=8, threads=8)
+    gm, gd, go = gpu_sample(text, shots, seed=8, threads_per_shot=-32)
+    assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
