@@ -3,7 +3,8 @@
 
 A step is one clifft_sample call over the whole workload (every shot of the
 batch through the compiled stream: frames, noise, active vector, records),
-with the program resident on the device and the outputs preallocated.
+with the program resident on the device and the outputs preallocated,
+replayed from a captured HIP graph (--no-graph: launched eagerly).
 Prints one JSON line (driver contract).
 
 Default workload: rotated surface-code memory d = 3, 3 rounds,
@@ -63,6 +64,21 @@ def cpu_baseline(text, shots_hint, seed):
                        % (target, seed, threads, dt)), (target, meas, det, obs)
 
 
+def captured(fn, torch):
+    """fn captured in a HIP graph (torch.cuda.CUDAGraph) after one eager
+    call on a side stream; returns the replay callable."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g.replay, g
+
+
 def bench_batch(args, w, pk, torch):
     """Batched workload: all circuits in one persistent FP32 launch, against
     the plain FP64 form (one clifft_sample call per circuit) on the same GPU."""
@@ -78,14 +94,17 @@ def bench_batch(args, w, pk, torch):
     B = pk.Batch(progs, shots, seeds, precision=precision, threads_per_shot=args.threads_per_shot, grid=args.grid)
     outs, ws = B.alloc()
     stream = torch.cuda.current_stream()
+    step = lambda: B.sample(outs, ws)
+    if not args.no_graph:
+        step, graph = captured(step, torch)
     for _ in range(args.warmup):
-        B.sample(outs, ws)
+        step()
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
     for a, b in evs:
         a.record(stream)
-        B.sample(outs, ws)
+        step()
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -122,7 +141,7 @@ def bench_batch(args, w, pk, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": precision, "data": "synthetic",
         "config": {"workload": args.workload, "circuits": len(texts), "shots_per_circuit": shots[0],
                    "k_max": [p.k_max for p in progs], "threads_per_shot": B.threads_per_shot,
-                   "parallelism": "all circuits in one persistent launch"},
+                   "graph": not args.no_graph, "parallelism": "all circuits in one persistent launch"},
         "fp64_plain": {"value": total / plain_s, "unit": "shots/s", "ms": plain_s * 1e3,
                        "speedup_of_fp32_batched": value / (total / plain_s),
                        "records_differing_shots": differing, "records_total_shots": total},
@@ -141,8 +160,11 @@ def main():
     ap.add_argument("--precision", default=None, help="f32 or f64 (default: the workload's)")
     ap.add_argument("--threads-per-shot", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--vector-in-hbm", type=int, default=0, choices=(-1, 0, 1),
+                    help="1 active vectors in HBM, -1 on chip, 0 automatic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="skip clifft_autotune before timing")
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a captured graph")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="run one plain device copy of this many bytes first (HBM counter calibration)")
     args = ap.parse_args()
@@ -168,9 +190,10 @@ def main():
     text = w["texts"][0]
     prog = pk.Program(text)
     tuned = None
-    if not args.no_autotune and not args.threads_per_shot and not args.grid:
+    if not args.no_autotune and not args.threads_per_shot and not args.grid and not args.vector_in_hbm:
         tuned = prog.autotune(shots, precision)
-    launch = pk.make_launch(precision, threads_per_shot=args.threads_per_shot, grid=args.grid)
+    launch = pk.make_launch(precision, threads_per_shot=args.threads_per_shot, grid=args.grid,
+                            vector_in_hbm=args.vector_in_hbm)
     outs = prog.alloc_outputs(shots)
     ws = prog.alloc_workspace(launch)
     stream = torch.cuda.current_stream()
@@ -182,8 +205,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    step = lambda: prog.sample(shots, seed=seed, launch=launch, outputs=outs, workspace=ws)
+    if not args.no_graph:
+        step, graph = captured(step, torch)
     for _ in range(args.warmup):
-        prog.sample(shots, seed=seed, launch=launch, outputs=outs, workspace=ws)
+        step()
     torch.cuda.synchronize()
 
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -191,7 +217,7 @@ def main():
     t0 = time.perf_counter()
     for a, b in evs:
         a.record(stream)
-        prog.sample(shots, seed=seed, launch=launch, outputs=outs, workspace=ws)
+        step()
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -202,10 +228,17 @@ def main():
     cost = prog.cost_model(precision)
     k = prog.k_max
     shape = prog.resolve_launch(shots, launch)
+    bit_sliced = shape["threads_per_shot"] < 0
     if k == 0:
         achieved = cost["int_ops"] * shots / (kernel_ms * 1e-3)
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT_OPS / 1e12, unit="Tops/s",
                     frac=achieved / PEAK_INT_OPS)
+        if bit_sliced:
+            # the same measurement against the work the bit-sliced form itself
+            # needs (frame words shared by 32 shots, draws per shot)
+            bs = cost["int_ops_bitsliced"] * shots / (kernel_ms * 1e-3)
+            roof["bitsliced_form"] = dict(int_ops_per_shot=round(cost["int_ops_bitsliced"], 3),
+                                          achieved=bs / 1e12, frac=bs / PEAK_INT_OPS)
     elif shape["vector_in_hbm"] == 1:
         achieved = cost["vector_bytes"] * shots / (kernel_ms * 1e-3)
         roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=achieved / PEAK_HBM)
@@ -216,6 +249,7 @@ def main():
     roof["traffic"] = traffic
     if traffic:
         roof["traffic_over_algorithmic"] = traffic / max(1.0, (cost["vector_bytes"] + cost["record_bytes"]) * shots)
+    roof["kernel"] = "k_frames" if bit_sliced else "k_sample"
     roof["kernel_ms"] = kernel_ms
     roof["work_per_shot"] = {kk: round(v, 3) for kk, v in cost.items()}
 
@@ -227,6 +261,7 @@ def main():
                    "detectors": prog.num_detectors, "noise_sites": prog.num_noise_sites,
                    "precision": precision, "threads_per_shot": shape["threads_per_shot"],
                    "vector_in_hbm": shape["vector_in_hbm"] == 1, "grid": shape["grid"], "autotuned": tuned is not None,
+                   "graph": not args.no_graph,
                    "parallelism": "shots across lanes/waves of one GPU"},
         "roofline": roof,
     }

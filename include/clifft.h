@@ -114,6 +114,8 @@ typedef struct clifft_cost {
   double record_bytes;    /* bit-packed record bytes written */
   double expected_faults; /* mean number of realized faults */
   double instructions;    /* compiled instructions executed */
+  double int_ops_bitsliced; /* integer lane-operations per shot of the bit-sliced form (32 shots per
+                               frame word; per-shot random draws and outcome bits counted in full) */
 } clifft_cost;
 clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clifft_cost* out);
 

@@ -601,6 +601,52 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
   }
   c.int_ops += 158.0 * P.nchunks;
   c.record_bytes = (P.nrec + P.ndet + P.nobs) / 8.0;
+
+  // Bit-sliced form (k_max = 0): a frame word holds one bit of 32 shots, so
+  // frame, parity, accumulator and record work is shared by 32 shots, while
+  // the per-shot draws (first gap-sampler draw of every chunk, one draw per
+  // fault, one draw per 128-event block of dormant random outcomes) and the
+  // per-shot bit of each dormant random outcome are not.
+  {
+    auto bits = [&](uint32_t off, int words) {
+      double t = 0;
+      for (int w = 0; w < words; w++) t += __builtin_popcountll(P.masks[off + w]);
+      return t;
+    };
+    double shared = 0, per_shot = 158.0 * P.nchunks;
+    std::vector<char> block_seen;
+    for (const GInstr& in : P.code) {
+      switch (in.op) {
+        case OP_FANCX: case OP_FANCZ: case OP_FAN2: shared += 4 * bits(in.a, P.W) + 4; break;
+        case OP_FS: shared += 2; break;
+        case OP_MSTATIC: case OP_MRANDOM: {
+          const int r = P.ev_rec[in.b];
+          const double tg = r >= 0 ? (double)(P.rec_tgt_off[r + 1] - P.rec_tgt_off[r]) : 0.0;
+          if (in.op == OP_MSTATIC) shared += 2 * bits(in.a, P.W) + 2 + tg + 1;
+          else {
+            shared += 5 + tg + 1;
+            per_shot += 4;
+            const uint32_t blk = in.b >> 7;
+            if (block_seen.size() <= blk) block_seen.resize(blk + 1, 0);
+            if (!block_seen[blk]) per_shot += 100;
+            block_seen[blk] = 1;
+          }
+          break;
+        }
+        case OP_CPAULI: shared += 2 * bits(in.a, 2 * P.W); break;
+        case OP_NOISE: {
+          double f = 0;
+          for (uint32_t s = in.a; s < in.b; s++) f += P.site_p[s];
+          shared += 3;
+          per_shot += f * 166;
+          break;
+        }
+        case OP_DET: shared += 1; break;
+        default: break;
+      }
+    }
+    c.int_ops_bitsliced = per_shot + shared / 32.0;
+  }
   return c;
 }
 

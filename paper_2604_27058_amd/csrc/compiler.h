@@ -39,6 +39,7 @@ struct CostModel {
   double record_bytes = 0;     // bit-packed record bytes written
   double expected_faults = 0;  // mean realized faults
   double instructions = 0;     // compiled instructions executed
+  double int_ops_bitsliced = 0;  // integer lane-operations per shot when 32 shots share each frame word
 };
 CostModel cost_model(const CompiledProgram& P, bool fp64);
 

@@ -360,6 +360,7 @@ clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clif
   out->record_bytes = c.record_bytes;
   out->expected_faults = c.expected_faults;
   out->instructions = c.instructions;
+  out->int_ops_bitsliced = c.int_ops_bitsliced;
   return CLIFFT_OK;
 }
 

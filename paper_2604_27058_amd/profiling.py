@@ -15,6 +15,7 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SAMPLING_KERNELS = ("k_sample", "k_frames", "k_batch")
 
 
 def kernel_source_hash():
@@ -56,13 +57,16 @@ def traffic(fetch_dir, write_dir, copy_bytes, workload, prec):
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = _pmc(d, counter)
         copy = [v for (k, _), v in per.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-        samp = [v for (k, _), v in per.items() if "k_sample" in k]
+        # the timed launch is the last sampling dispatch (earlier ones are the
+        # launch-shape trials of the autotuner, if it ran)
+        samp = sorted(((int(d), k, v) for (k, d), v in per.items() if any(n in k for n in SAMPLING_KERNELS)))
         if not copy or not samp:
             raise RuntimeError("missing copy or sampling dispatches for " + counter)
         kib_copy = max(copy)
         factor = kib_copy * 1024.0 / copy_bytes
-        res[counter] = dict(kib_per_dispatch=sum(samp) / len(samp), copy_kib=kib_copy, factor=factor,
-                            bytes_per_launch=sum(samp) / len(samp) * 1024.0 / factor)
+        _, name, kib = samp[-1]
+        res[counter] = dict(kernel=name, kib_per_dispatch=kib, copy_kib=kib_copy, factor=factor,
+                            bytes_per_launch=kib * 1024.0 / factor)
     return dict(workload=workload, precision=prec, kernel_source_hash=kernel_source_hash(),
                 bytes_per_launch=res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"],
                 fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"], copy_bytes=copy_bytes)
