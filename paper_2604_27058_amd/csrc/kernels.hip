@@ -14,6 +14,9 @@
 //            workspace slice (HBM) for large k.
 // Records are bit-packed 64 shots per word (record-major) and staged in LDS
 // per 64-shot tile.
+// Pauli-frame-only programs (k_max = 0) also have a bit-sliced kernel
+// (k_frames: 32 shots per lane, one LDS row per frame bit), and many programs
+// can share one persistent launch (k_batch).
 //
 // Paper passages: Definition 2 (frame-factored state), Appendix B.1
 // (rotations: phase / expansion / active), Appendix B.2 (measurements:
