@@ -12,16 +12,27 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SAMPLING_KERNELS = ("k_sample", "k_frames", "k_batch")
 
 
-def kernel_source_hash():
+def code_tokens(text):
+    """Source text without comments and with whitespace collapsed, so that
+    documentation edits do not void counters taken on unchanged code."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(read=None):
+    """Hash of the device code (kernels and the layouts they read)."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "program.h", "kernels.h"):
-        h.update(open(os.path.join(ROOT, "paper_2604_27058_amd", "csrc", f), "rb").read())
+        text = read(f) if read else open(os.path.join(ROOT, "paper_2604_27058_amd", "csrc", f)).read()
+        h.update(code_tokens(text).encode())
     return h.hexdigest()[:16]
 
 
