@@ -80,6 +80,11 @@ typedef struct clifft_launch {
   int32_t grid;             /* workgroups (256 threads); 0 = fill the device */
   int32_t vector_in_hbm;    /* 0 automatic (HBM only when LDS is too small),
                                1 force the global workspace, -1 force LDS */
+  int32_t specialize;       /* bit-sliced only: 1 a kernel generated for this
+                               program and compiled at run time (see
+                               clifft_specialize), -1 the interpreter, 0
+                               automatic (the interpreter unless the autotuner
+                               chose the specialized kernel) */
 } clifft_launch;
 
 /* Compile circuit text (len bytes, need not be NUL-terminated) into a
@@ -127,13 +132,28 @@ clifft_status clifft_resolve_launch(const clifft_program* p, const clifft_launch
                                     clifft_launch* out);
 
 /* Launch-shape autotuner: times the candidate tiers (threads per shot 1,
- * 64, 256; vectors in LDS or HBM) and grid sizes (1, 2, 4, 8 workgroups per
- * CU) on a trial of up to `shots` shots at `precision`, on `stream` of the
- * current device, and stores the fastest in the program.  Later calls whose
- * cfg leaves threads_per_shot, grid and vector_in_hbm at 0 use it (also for
+ * 64, 256; vectors in LDS or HBM; for k_max = 0 also the bit-sliced
+ * interpreter and, when the program qualifies, its specialized kernel) and
+ * grid sizes (1 to 32 workgroups per CU) on a trial of up to `shots` shots
+ * (at most 2^24 for k_max = 0, 2^18 below k_max = 13, 8 per CU above) at
+ * `precision`, on `stream` of the current device, and stores the fastest in
+ * the program.  Later calls whose cfg leaves threads_per_shot, grid,
+ * vector_in_hbm and specialize at 0 use it (also for
  * clifft_workspace_size).  Allocates and frees temporary device buffers;
  * synchronizes.  *out (optional) receives the chosen configuration. */
 clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precision, void* stream, clifft_launch* out);
+
+/* Program-specialized bit-sliced kernel (Pauli-frame-only programs,
+ * k_max = 0): generates a HIP kernel in which the compiled stream is
+ * unrolled and every frame row is a register, and compiles it for gfx950
+ * (hiprtc).  Host only: the code object is kept in the program and loaded on
+ * a device at its first launch.  Records are identical to the interpreter's
+ * (same stochastic contract).  Idempotent.  Errors: E_UNSUPPORTED (the
+ * program does not qualify: k_max > 0, more than 200 frame and accumulator
+ * rows, more than 600 instructions, or noise too dense for the per-lane
+ * fault list), E_DEVICE (run-time compilation failed).  `log` (optional, cap
+ * bytes, NUL-terminated) receives the reason or the compiler log. */
+clifft_status clifft_specialize(clifft_program* p, char* log, size_t cap);
 
 /* Bytes of caller-provided device workspace a sample call needs with this
  * configuration (0 when the active vectors fit in LDS). */

@@ -37,7 +37,7 @@ class clifft_cost(ctypes.Structure):
 
 class clifft_launch(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("threads_per_shot", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("vector_in_hbm", ctypes.c_int32)]
+                ("vector_in_hbm", ctypes.c_int32), ("specialize", ctypes.c_int32)]
 
 
 _lib = None
@@ -71,12 +71,13 @@ def lib():
         L.clifft_batch_sample.argtypes = [vp, vp, sz, vp, vp, vp, vp]
         L.clifft_batch_free.argtypes = [vp]
         L.clifft_autotune.argtypes = [vp, u64, ctypes.c_int32, vp, ctypes.POINTER(clifft_launch)]
+        L.clifft_specialize.argtypes = [vp, ctypes.c_char_p, sz]
         L.clifft_program_free.argtypes = [vp]
         L.clifft_last_error.restype = ctypes.c_char_p
         for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
                   "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_trace",
                   "clifft_cost_model", "clifft_resolve_launch", "clifft_batch_create", "clifft_batch_sizes",
-                  "clifft_batch_layout", "clifft_batch_sample", "clifft_autotune"):
+                  "clifft_batch_layout", "clifft_batch_sample", "clifft_autotune", "clifft_specialize"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -87,9 +88,9 @@ def _check(st):
         raise ClifftError(st, lib().clifft_last_error().decode())
 
 
-def make_launch(precision="f32", threads_per_shot=0, grid=0, vector_in_hbm=0):
+def make_launch(precision="f32", threads_per_shot=0, grid=0, vector_in_hbm=0, specialize=0):
     p = CLIFFT_FP64 if precision in ("f64", CLIFFT_FP64) else CLIFFT_FP32
-    return clifft_launch(p, threads_per_shot, grid, vector_in_hbm)
+    return clifft_launch(p, threads_per_shot, grid, vector_in_hbm, specialize)
 
 
 class Program:
@@ -143,6 +144,13 @@ class Program:
         _check(lib().clifft_resolve_launch(self._h, None if launch is None else ctypes.byref(launch), shots,
                                            ctypes.byref(out)))
         return {f: getattr(out, f) for f, _ in clifft_launch._fields_}
+
+    def specialize(self):
+        """clifft_specialize: build the program-specialized bit-sliced kernel
+        (host only); returns the library's note (reason or compiler log)."""
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().clifft_specialize(self._h, buf, len(buf)))
+        return buf.value.decode(errors="replace")
 
     def autotune(self, shots, precision="f32"):
         """clifft_autotune: time the launch shapes, keep the fastest (dict)."""

@@ -11,10 +11,28 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-result",
-          "-I" + os.path.join(os.path.dirname(HERE), "include")]
+          "-I" + os.path.join(os.path.dirname(HERE), "include"), "-I" + os.path.join(HERE, "_build")]
 # Packed FP32 VALU ops stay disabled in device code on this target.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = [("kernels.hip", True), ("runtime.cpp", True), ("compiler.cpp", False)]
+SOURCES = [("kernels.hip", True), ("runtime.cpp", True), ("specialize.cpp", True), ("compiler.cpp", False)]
+# device text compiled at run time by the specialized-kernel generator
+PRELUDE = ["philox.h", "spec_args.h", "spec_prelude.h"]
+
+
+def _write_prelude():
+    """Concatenates the run-time device headers into a C++ string literal."""
+    parts = []
+    for name in PRELUDE:
+        for line in open(os.path.join(CSRC, name)):
+            if line.startswith("#pragma once") or line.startswith("#include"):
+                continue
+            parts.append(line)
+    text = "".join(parts)
+    assert ")CLIFFT_PRELUDE\"" not in text
+    out = os.path.join(HERE, "_build", "spec_prelude.inc")
+    with open(out + ".tmp", "w") as f:
+        f.write('R"CLIFFT_PRELUDE(' + text + ')CLIFFT_PRELUDE"\n')
+    os.replace(out + ".tmp", out)
 
 
 def _obj(name):
@@ -35,13 +53,15 @@ def _compile(item):
 
 def build(verbose=False):
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    with ThreadPoolExecutor(max_workers=3) as ex:
+    _write_prelude()
+    with ThreadPoolExecutor(max_workers=4) as ex:
         logs = list(ex.map(_compile, SOURCES))
     if verbose:
         for l in logs:
             if l.strip():
                 print(l, file=sys.stderr)
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + [_obj(n) for n, _ in SOURCES]
+    cmd = ([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + [_obj(n) for n, _ in SOURCES]
+           + ["-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB

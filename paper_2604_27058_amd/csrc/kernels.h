@@ -27,6 +27,7 @@ struct LaunchShape {
   int grid;         // workgroups of 256 threads
   size_t lds_bytes; // dynamic LDS per workgroup
   bool global_vec;  // active vectors in the global workspace
+  bool spec;        // bit-sliced: the program-specialized kernel
 };
 
 // Batched launch: many programs, one persistent kernel.

@@ -29,6 +29,7 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "philox.h"
 #include "program.h"
 
 namespace clifft {
@@ -38,30 +39,9 @@ namespace clifft {
 #define DEV_HOST_INLINE static __host__ __device__ __forceinline__
 
 // ------------------------------------------------------------------ RNG
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11); one mulhi/mullo pair per
-// multiplier per round.
-struct U4 { uint32_t w0, w1, w2, w3; };
-
-DEV U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; r++) {
-    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-  }
-  return U4{c0, c1, c2, c3};
-}
-
-DEV U4 draw(uint32_t index, uint32_t purpose, uint64_t shot, uint64_t seed) {
-  return philox(index, purpose, (uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)seed, (uint32_t)(seed >> 32));
-}
-
-DEV double uniform53(const U4& w) {
-  uint64_t v = ((uint64_t)w.w1 << 32) | w.w0;
-  return (double)(v >> 11) * (1.0 / 9007199254740992.0);
-}
+using clifft_rng::draw;
+using clifft_rng::U4;
+using clifft_rng::uniform53;
 
 // ------------------------------------------------------------------ helpers
 template <typename R> struct cpx { R re, im; };
@@ -960,13 +940,15 @@ DEV void bs_apply_fault(const DevProgram& P, const FrameRows& F, uint32_t N, uin
 
 // LDS rows: [0,4N) frames (full x, full z, noise x, noise z), then one row
 // per detector and observable accumulator, then the dormant-random bit rows
-// of the current 128-event block, then per-shot noise cursors (site; draw
-// ordinal | chunk << 16).
+// of the current 128-event block, then the lane's fault list (or per-shot
+// noise cursors: site; draw ordinal | chunk << 16), then a row that stays
+// zero and a row that absorbs stores of unused slots (so batched accesses
+// need no branches), then the survival products when they fit.
 constexpr int kSurvLdsMax = 2048;  // survival products staged in LDS (single chunk, up to this many sites)
-constexpr int kListCap = 32;       // faults per lane kept in the precomputed list
+constexpr int kListCap = 24;       // faults per lane kept in the precomputed list
 DEV_HOST_INLINE bool frames_surv_in_lds(const DevProgram& P) { return P.nchunks == 1 && P.nsites < kSurvLdsMax; }
 // Low-noise programs precompute each lane's faults into a site-sorted list
-// (expected faults per lane well under the list capacity); others keep one
+// (expected faults per lane at most a quarter of the list); others keep one
 // sampler cursor per shot.
 DEV_HOST_INLINE bool frames_fault_list(const DevProgram& P) {
   return P.nsites < (1 << 23) && (double)P.exp_faults * kShotsPerLane <= kListCap / 4;
@@ -974,8 +956,22 @@ DEV_HOST_INLINE bool frames_fault_list(const DevProgram& P) {
 size_t frames_lds_rows(const DevProgram& P) {
   size_t rows = (size_t)4 * P.nq + P.ndet_rows + P.nobs + (P.rblk_max > 0 ? P.rblk_max : 1);
   rows += frames_fault_list(P) ? kListCap : 2 * kShotsPerLane;
+  rows += 2;  // zero row, dump row
   if (frames_surv_in_lds(P)) rows += ((size_t)(P.nsites + 1) * 8 + 255) / 256;  // doubles, in 256-byte rows
   return rows;
+}
+
+// Up to four set bits of a wave-uniform mask word (qubit wbase + bit),
+// removed from m; returns how many.
+MDEV int take4(uint64_t& m, uint32_t wbase, uint32_t (&q)[4]) {
+  int n = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    q[i] = m ? wbase + (uint32_t)__ffsll((unsigned long long)m) - 1 : 0u;
+    n += m ? 1 : 0;
+    m &= m - 1;
+  }
+  return n;
 }
 
 template <int W, bool LDS_SURV, bool LIST>
@@ -988,11 +984,12 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   // LIST: rows [NF, NF + kListCap) hold the fault list; otherwise per-shot
   // cursors: next fault site at NF + s, draw ordinal | chunk << 16 at OC + s
   const uint32_t NF = RB + (uint32_t)(P.rblk_max > 0 ? P.rblk_max : 1), OC = NF + kShotsPerLane;
-  double* surv = (double*)(sm + (size_t)(NF + (LIST ? kListCap : 2 * kShotsPerLane)) * 64);
-  if (LDS_SURV) {
+  const uint32_t ZR = NF + (LIST ? kListCap : 2 * kShotsPerLane), DR = ZR + 1;
+  double* surv = (double*)(sm + (size_t)(DR + 1) * 64);
+  F(ZR) = 0;
+  if (LDS_SURV)
     for (int i = lane; i <= P.nsites; i += 64) surv[i] = P.surv[i];
-    __syncthreads();
-  }
+  __syncthreads();
   const uint64_t seed = A.seed;
   const uint64_t words64 = (A.shots + 63) / 64;
   const uint64_t tiles = (A.shots + 64 * kShotsPerLane - 1) / (64 * kShotsPerLane);
@@ -1000,6 +997,7 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   uint32_t* det32 = (uint32_t*)A.det;
   uint32_t* obs32 = (uint32_t*)A.obs;
   cptr<uint64_t> masks = as_const(P.masks);
+  cptr<uint32_t> rec_tgt_off = as_const(P.rec_tgt_off), rec_tgt = as_const(P.rec_tgt);
   for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const uint64_t s0 = tile * (64 * kShotsPerLane) + (uint64_t)lane * kShotsPerLane;  // first shot of the lane
     const uint32_t valid = s0 >= A.shots ? 0u : (A.shots - s0 >= 32 ? ~0u : ((1u << (A.shots - s0)) - 1u));
@@ -1059,98 +1057,167 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
         case OP_FANCX:
         case OP_FANCZ:
         case OP_FAN2: {
-          // per frame: the pivot word, the masked qubits' words
-          for (uint32_t c = 0; c < 4; c += 2) {
-            const uint32_t X = c * N, Z = c * N + N;
-            const uint32_t xv = F(X + v), zv = F(Z + v);
-            uint32_t par = 0;
-            for (int w = 0; w < W; w++) {
-              uint64_t m = masks[in.a + w];
-              while (m) {
-                const uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)m) - 1);
-                m &= m - 1;
-                if (in.op == OP_FANCX) { F(X + q) ^= xv; par ^= F(Z + q); }
-                else if (in.op == OP_FANCZ) { F(Z + q) ^= xv; par ^= F(X + q); }
-                else { F(Z + q) ^= zv; par ^= F(X + q); }
+          // target rows T ^= the pivot word, parity of rows Q into the pivot;
+          // four targets (both frames) per round trip
+          const uint32_t xv = F(v), zv = F(N + v), nxv = F(2 * N + v), nzv = F(3 * N + v);
+          const bool cx = in.op == OP_FANCX;
+          const uint32_t tf = cx ? 0u : N, qf = cx ? N : 0u;  // row offsets of T and Q in the full frame
+          const uint32_t sf = in.op == OP_FAN2 ? zv : xv, sn = in.op == OP_FAN2 ? nzv : nxv;
+          uint32_t par = 0, npar = 0;
+          for (int w = 0; w < W; w++) {
+            uint64_t m = masks[in.a + w];
+            while (m) {
+              uint32_t q[4];
+              const int n = take4(m, (uint32_t)w * 64, q);
+              uint32_t rt[4], rq[4], a[4], b[4], c[4], d[4];
+#pragma unroll
+              for (int i = 0; i < 4; i++) {
+                rt[i] = i < n ? tf + q[i] : DR;
+                rq[i] = i < n ? qf + q[i] : ZR;
+              }
+#pragma unroll
+              for (int i = 0; i < 4; i++) {
+                a[i] = F(rt[i]);
+                b[i] = F(rt[i] == DR ? DR : rt[i] + 2 * N);
+                c[i] = F(rq[i]);
+                d[i] = F(rq[i] == ZR ? ZR : rq[i] + 2 * N);
+              }
+#pragma unroll
+              for (int i = 0; i < 4; i++) {
+                F(rt[i]) = a[i] ^ sf;
+                F(rt[i] == DR ? DR : rt[i] + 2 * N) = b[i] ^ sn;
+                par ^= c[i];
+                npar ^= d[i];
               }
             }
-            if (in.op == OP_FAN2) F(X + v) ^= par;
-            else F(Z + v) ^= par;
+          }
+          if (in.op == OP_FAN2) {
+            F(v) = xv ^ par;
+            F(2 * N + v) = nxv ^ npar;
+          } else {
+            F(N + v) = zv ^ par;
+            F(3 * N + v) = nzv ^ npar;
           }
           break;
         }
-        case OP_FS:
-          F(N + v) ^= F(v);
-          F(3 * N + v) ^= F(2 * N + v);
+        case OP_FS: {
+          const uint32_t x = F(v), z = F(N + v), nx = F(2 * N + v), nz = F(3 * N + v);
+          F(N + v) = z ^ x;
+          F(3 * N + v) = nz ^ nx;
           break;
+        }
         case OP_FH: {
-          uint32_t t = F(v); F(v) = F(N + v); F(N + v) = t;
-          t = F(2 * N + v); F(2 * N + v) = F(3 * N + v); F(3 * N + v) = t;
+          const uint32_t x = F(v), z = F(N + v), nx = F(2 * N + v), nz = F(3 * N + v);
+          F(v) = z;
+          F(N + v) = x;
+          F(2 * N + v) = nz;
+          F(3 * N + v) = nx;
           break;
         }
         case OP_MSTATIC:
         case OP_MRANDOM: {
           uint32_t mm, pn;
           if (in.op == OP_MSTATIC) {
+            // parity of the x rows over the measured Z-string, both frames
             mm = (in.flags & F_SIGN) ? ~0u : 0u;
             pn = 0;
             for (int w = 0; w < W; w++) {
               uint64_t m = masks[in.a + w];
               while (m) {
-                const uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)m) - 1);
-                m &= m - 1;
-                mm ^= F(q);
-                pn ^= F(2 * N + q);
+                uint32_t q[4];
+                const int n = take4(m, (uint32_t)w * 64, q);
+                uint32_t a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                  a[i] = F(i < n ? q[i] : ZR);
+                  b[i] = F(i < n ? 2 * N + q[i] : ZR);
+                }
+                mm ^= a[0] ^ a[1] ^ a[2] ^ a[3];
+                pn ^= b[0] ^ b[1] ^ b[2] ^ b[3];
               }
             }
           } else {
             const uint32_t j = in.b, blk = j >> 7;
             if (blk != rblk) {
-              // bits of this block's dormant random events for the lane's 32 shots
+              // bits of this block's dormant random events for the lane's 32
+              // shots, eight events per pass, gathered in registers
               const uint32_t o0 = P.rblk_off[blk], o1 = P.rblk_off[blk + 1];
-              for (uint32_t k = o0; k < o1; k++) F(RB + (k - o0)) = 0;
-              for (int s = 0; s < kShotsPerLane; s++) {
-                U4 w = draw(blk, kPurposeRbit, A.offset + s0 + s, seed);
-                for (uint32_t k = o0; k < o1; k++) {
-                  const uint32_t e = P.rblk_ev[k];
-                  const uint32_t wv = (e >> 5) == 0 ? w.w0 : (e >> 5) == 1 ? w.w1 : (e >> 5) == 2 ? w.w2 : w.w3;
-                  F(RB + (k - o0)) |= ((wv >> (e & 31)) & 1u) << s;
+              for (uint32_t g = o0; g < o1; g += 8) {
+                uint32_t e[8], bits[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                  e[i] = g + i < o1 ? (uint32_t)P.rblk_ev[g + i] : 0u;
+                  bits[i] = 0;
                 }
+                for (int s = 0; s < kShotsPerLane; s++) {
+                  const U4 w = draw(blk, kPurposeRbit, A.offset + s0 + s, seed);
+#pragma unroll
+                  for (int i = 0; i < 8; i++) {
+                    const uint32_t h = e[i] >> 5;
+                    const uint32_t wv = h == 0 ? w.w0 : h == 1 ? w.w1 : h == 2 ? w.w2 : w.w3;
+                    bits[i] |= ((wv >> (e[i] & 31)) & 1u) << s;
+                  }
+                }
+#pragma unroll
+                for (int i = 0; i < 8; i++)
+                  if (g + i < o1) F(RB + (g - o0) + i) = bits[i];
               }
               rblk = blk;
             }
-            const uint32_t p = F(N + v);
-            pn = F(3 * N + v);
-            mm = F(RB + in.u) ^ pn;
-            const uint32_t b = mm ^ p ^ ((in.flags & F_SIGN) ? ~0u : 0u);
-            uint32_t t = F(v); F(v) = F(N + v); F(N + v) = t;
-            t = F(2 * N + v); F(2 * N + v) = F(3 * N + v); F(3 * N + v) = t;
-            F(v) ^= b;
+            const uint32_t x = F(v), z = F(N + v), nx = F(2 * N + v), nz = F(3 * N + v), rb = F(RB + in.u);
+            pn = nz;
+            mm = rb ^ pn;
+            const uint32_t b = mm ^ z ^ ((in.flags & F_SIGN) ? ~0u : 0u);
+            // H absorbed after the outcome, then the correction X^b
+            F(v) = z ^ b;
+            F(N + v) = x;
+            F(2 * N + v) = nz;
+            F(3 * N + v) = nx;
           }
           last_m = mm;
           last_pn = pn;
           const int r = as_const(P.ev_rec)[in.b];
           if (r >= 0) {
             if (meas32 && store) meas32[(size_t)r * 2 * words64 + col] = mm & valid;
-            const uint32_t t0 = P.rec_tgt_off[r], t1 = P.rec_tgt_off[r + 1];
-            for (uint32_t t = t0; t < t1; t++) F(ACC + P.rec_tgt[t]) ^= mm;
+            // accumulators fed by this record, four per round trip
+            const uint32_t t1 = rec_tgt_off[r + 1];
+            for (uint32_t t = rec_tgt_off[r]; t < t1; t += 4) {
+              uint32_t rr[4], a[4];
+#pragma unroll
+              for (int i = 0; i < 4; i++) rr[i] = t + i < t1 ? ACC + rec_tgt[t + i] : DR;
+#pragma unroll
+              for (int i = 0; i < 4; i++) a[i] = F(rr[i]);
+#pragma unroll
+              for (int i = 0; i < 4; i++) F(rr[i]) = a[i] ^ mm;
+            }
           }
           break;
         }
         case OP_CPAULI: {
-          for (int w = 0; w < W; w++) {
-            uint64_t mx = masks[in.a + w], mz = masks[in.a + W + w];
-            while (mx) {
-              const uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)mx) - 1);
-              mx &= mx - 1;
-              F(q) ^= last_m;
-              F(2 * N + q) ^= last_pn;
-            }
-            while (mz) {
-              const uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)mz) - 1);
-              mz &= mz - 1;
-              F(N + q) ^= last_m;
-              F(3 * N + q) ^= last_pn;
+          // X^m on the x rows (full frame), X^pn (noise frame); same for Z
+          for (int zpart = 0; zpart < 2; zpart++) {
+            const uint32_t off = zpart ? N : 0u;
+            for (int w = 0; w < W; w++) {
+              uint64_t m = masks[in.a + zpart * W + w];
+              while (m) {
+                uint32_t q[4], rf[4], rn[4], a[4], b[4];
+                const int n = take4(m, (uint32_t)w * 64, q);
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                  rf[i] = i < n ? off + q[i] : DR;
+                  rn[i] = i < n ? 2 * N + off + q[i] : DR;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                  a[i] = F(rf[i]);
+                  b[i] = F(rn[i]);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                  F(rf[i]) = a[i] ^ last_m;
+                  F(rn[i]) = b[i] ^ last_pn;
+                }
+              }
             }
           }
           break;

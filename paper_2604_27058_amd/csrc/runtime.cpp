@@ -14,6 +14,8 @@
 #include "../../include/clifft.h"
 #include "compiler.h"
 #include "kernels.h"
+#include "spec_args.h"
+#include "specialize.h"
 
 using namespace clifft;
 
@@ -29,6 +31,8 @@ clifft_status fail(clifft_status st, const std::string& msg) {
 struct DeviceCopy {
   DevProgram view{};
   std::vector<void*> allocs;
+  hipModule_t spec_mod = nullptr;  // specialized kernel, loaded at its first launch
+  hipFunction_t spec_fn = nullptr;
 };
 
 }  // namespace
@@ -38,6 +42,9 @@ struct clifft_program {
   std::mutex mu;
   std::map<int, DeviceCopy> dev;
   std::map<std::pair<int, int>, clifft_launch> tuned;  // (device, precision) -> autotuned launch
+  int spec_state = 0;          // specialized kernel: 0 not built, 1 code object ready, -1 unavailable
+  std::vector<char> spec_code;  // gfx950 code object
+  std::string spec_log;         // reason or compiler log when unavailable
 };
 
 namespace {
@@ -109,6 +116,68 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
   return CLIFFT_OK;
 }
 
+// Builds the specialized kernel's code object once (host only).
+clifft_status ensure_spec(clifft_program* p) {
+  std::lock_guard<std::mutex> lock(p->mu);
+  if (p->spec_state == 1) return CLIFFT_OK;
+  if (p->spec_state == -1) return fail(CLIFFT_E_UNSUPPORTED, p->spec_log);
+  std::string why;
+  if (!spec_supported(p->host, &why)) {
+    p->spec_state = -1;
+    p->spec_log = why;
+    return fail(CLIFFT_E_UNSUPPORTED, why);
+  }
+  std::string log;
+  if (!spec_compile(spec_source(p->host), &p->spec_code, &log)) {
+    p->spec_state = -1;
+    p->spec_log = "run-time compilation failed: " + log;
+    return fail(CLIFFT_E_DEVICE, p->spec_log);
+  }
+  p->spec_state = 1;
+  return CLIFFT_OK;
+}
+
+// The specialized kernel's function on the current device (module loaded on
+// first use).
+clifft_status spec_function(clifft_program* p, hipFunction_t* fn) {
+  clifft_status st = ensure_spec(p);
+  if (st != CLIFFT_OK) return st;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(CLIFFT_E_DEVICE, "no HIP device");
+  std::lock_guard<std::mutex> lock(p->mu);
+  auto it = p->dev.find(dev);
+  if (it == p->dev.end()) return fail(CLIFFT_E_DEVICE, "program not on this device");
+  DeviceCopy& dc = it->second;
+  if (!dc.spec_fn) {
+    hipError_t e = hipModuleLoadData(&dc.spec_mod, p->spec_code.data());
+    if (e == hipSuccess) e = hipModuleGetFunction(&dc.spec_fn, dc.spec_mod, kSpecEntry);
+    if (e != hipSuccess) {
+      if (dc.spec_mod) (void)hipModuleUnload(dc.spec_mod);
+      dc.spec_mod = nullptr;
+      dc.spec_fn = nullptr;
+      return fail(CLIFFT_E_DEVICE, std::string("loading the specialized kernel failed: ") + hipGetErrorString(e));
+    }
+  }
+  *fn = dc.spec_fn;
+  return CLIFFT_OK;
+}
+
+hipError_t launch_spec(hipFunction_t fn, const DevProgram& D, const KArgs& A, int grid, hipStream_t s) {
+  clifft_spec::SpecArgs S{};
+  S.shots = A.shots;
+  S.seed = A.seed;
+  S.offset = A.offset;
+  S.words64 = (A.shots + 63) / 64;
+  S.meas32 = (unsigned int*)A.meas;
+  S.det32 = (unsigned int*)A.det;
+  S.obs32 = (unsigned int*)A.obs;
+  S.surv = D.surv;
+  S.site_type = D.site_type;
+  S.list_cap = A.list_cap;
+  void* args[] = {&S};
+  return hipModuleLaunchKernel(fn, grid, 1, 1, 64, 1, 1, 0, s, args, nullptr);
+}
+
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kLaneMaxK = 12;                              // shot-per-lane tier up to this k_max
 constexpr int kBatchLaneMaxK = 10;                         // the same inside a batched launch
@@ -131,7 +200,7 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
   if (cfg) c = *cfg;
   if (c.precision != CLIFFT_FP32 && c.precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
   *fp64 = c.precision == CLIFFT_FP64;
-  if (tuned && c.threads_per_shot == 0 && c.grid == 0 && c.vector_in_hbm == 0) {
+  if (tuned && c.threads_per_shot == 0 && c.grid == 0 && c.vector_in_hbm == 0 && c.specialize == 0) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     auto it = tuned->find({dev, c.precision});
@@ -158,18 +227,30 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
       tmp.exp_faults = (float)f;
     }
     const size_t rows_bytes = frames_lds_rows(tmp) * 64 * 4;
-    const bool bs_ok = H.kmax == 0 && !trace && rows_bytes <= kLdsLimit;
-    if (G == kBitSliced && !bs_ok) return fail(CLIFFT_E_CAPACITY, "bit-sliced frames need k_max = 0 and rows in LDS");
+    const bool spec = c.specialize == 1;
+    const bool bs_ok = H.kmax == 0 && !trace && (spec || rows_bytes <= kLdsLimit);
+    if (c.specialize != 0 && G != 0 && G != kBitSliced)
+      return fail(CLIFFT_E_INVALID_ARG, "specialize applies to the bit-sliced tier only");
+    if ((G == kBitSliced || spec) && !bs_ok)
+      return fail(CLIFFT_E_CAPACITY, "bit-sliced frames need k_max = 0 and rows in LDS (not in trace mode)");
+    if (spec && !spec_supported(H, nullptr)) {
+      std::string why;
+      spec_supported(H, &why);
+      return fail(CLIFFT_E_UNSUPPORTED, why);
+    }
     if (G == 0 && bs_ok) G = kBitSliced;
     if (G == kBitSliced) {
       const uint64_t tiles = (shots + 2047) / 2048;
-      int per_cu = (int)std::max<size_t>(1, std::min<size_t>(16, kLdsLimit / rows_bytes));
+      // the specialized kernel keeps its rows in registers (about 8 waves per
+      // CU fit); the interpreter is bounded by LDS
+      int per_cu = spec ? 8 : (int)std::max<size_t>(1, std::min<size_t>(16, kLdsLimit / rows_bytes));
       int grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
       if ((uint64_t)grid > tiles) grid = (int)std::max<uint64_t>(1, tiles);
       L->G = kBitSliced;
       L->grid = grid;
-      L->lds_bytes = rows_bytes;
+      L->lds_bytes = spec ? 0 : rows_bytes;
       L->global_vec = false;
+      L->spec = spec;
       return CLIFFT_OK;
     }
   }
@@ -257,7 +338,15 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
     (void)hipMemsetAsync(dflag, 0, sizeof(int), s);
     A.error = dflag;
   }
-  hipError_t e = launch_sample(*D, A, L, fp64, trace, s);
+  hipError_t e = hipSuccess;
+  if (L.spec) {
+    hipFunction_t fn = nullptr;
+    st = spec_function(const_cast<clifft_program*>(p), &fn);
+    if (st != CLIFFT_OK) return st;
+    e = launch_spec(fn, *D, A, L.grid, s);
+  } else {
+    e = launch_sample(*D, A, L, fp64, trace, s);
+  }
   if (e != hipSuccess) {
     if (dflag) (void)hipFree(dflag);
     return fail(CLIFFT_E_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
@@ -375,7 +464,20 @@ clifft_status clifft_resolve_launch(const clifft_program* p, const clifft_launch
   out->threads_per_shot = L.G;
   out->grid = L.grid;
   out->vector_in_hbm = L.global_vec ? 1 : -1;
+  out->specialize = L.G == kBitSliced ? (L.spec ? 1 : -1) : 0;
   return CLIFFT_OK;
+}
+
+clifft_status clifft_specialize(clifft_program* p, char* log, size_t cap) {
+  if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
+  clifft_status st = ensure_spec(p);
+  if (log && cap) {
+    const std::string& m = p->spec_log;
+    size_t n = std::min(cap - 1, m.size());
+    memcpy(log, m.data(), n);
+    log[n] = '\0';
+  }
+  return st;
 }
 
 clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes) {
@@ -567,12 +669,17 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
   const CompiledProgram& H = p->host;
   const int cus = device_cus();
   // trial size: enough work to fill the device a few times over
-  uint64_t trial = H.kmax == 0 ? ((uint64_t)1 << 22) : H.kmax <= 12 ? ((uint64_t)1 << 18) : (uint64_t)cus * 8;
+  // (Pauli-frame programs take the workload itself up to 2^24 shots: their
+  // best grid depends on the number of 2048-shot tiles)
+  uint64_t trial = H.kmax == 0 ? ((uint64_t)1 << 24) : H.kmax <= 12 ? ((uint64_t)1 << 18) : (uint64_t)cus * 8;
   if (shots > 0 && shots < trial) trial = shots;
   std::vector<clifft_launch> cands;
   const int mult[4] = {1, 2, 4, 8};
-  if (H.kmax == 0)
-    for (int m : {1, 2, 4, 8, 16}) cands.push_back(clifft_launch{precision, kBitSliced, cus * m, 0});
+  if (H.kmax == 0) {
+    for (int m : {1, 2, 4, 5, 8, 16}) cands.push_back(clifft_launch{precision, kBitSliced, cus * m, 0, -1});
+    if (spec_supported(H, nullptr) && ensure_spec(p) == CLIFFT_OK)
+      for (int m : {4, 8, 12, 16, 24, 32}) cands.push_back(clifft_launch{precision, kBitSliced, cus * m, 0, 1});
+  }
   for (int G : {1, 64, 256}) {
     if (H.kmax == 0 && G != 1) continue;
     for (int hbm : {-1, 1}) {
@@ -612,10 +719,15 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
     A.det = det;
     A.obs = obs;
     A.workspace = ws;
+    hipFunction_t fn = nullptr;
+    if (L.spec && spec_function(p, &fn) != CLIFFT_OK) {
+      if (ws) (void)hipFree(ws);
+      continue;
+    }
     float ms = 0;
     for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
       e = hipEventRecord(e0, s);
-      if (e == hipSuccess) e = launch_sample(*D, A, L, fp64, false, s);
+      if (e == hipSuccess) e = L.spec ? launch_spec(fn, *D, A, L.grid, s) : launch_sample(*D, A, L, fp64, false, s);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -623,7 +735,7 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
     if (ws) (void)hipFree(ws);
     if (e == hipSuccess && ms < best_ms) {
       best_ms = ms;
-      best = clifft_launch{precision, L.G, L.grid, L.global_vec ? 1 : -1};
+      best = clifft_launch{precision, L.G, L.grid, L.global_vec ? 1 : -1, L.G == kBitSliced ? (L.spec ? 1 : -1) : 0};
       found = true;
     }
   }
@@ -651,6 +763,7 @@ void clifft_program_free(clifft_program* p) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(kv.first);
     for (void* a : kv.second.allocs) (void)hipFree(a);
+    if (kv.second.spec_mod) (void)hipModuleUnload(kv.second.spec_mod);
     (void)hipSetDevice(cur);
   }
   delete p;

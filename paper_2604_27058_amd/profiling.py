@@ -16,7 +16,7 @@ import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SAMPLING_KERNELS = ("k_sample", "k_frames", "k_batch")
+SAMPLING_KERNELS = ("k_sample", "k_frames", "k_batch", "clifft_frames_spec")
 
 
 def code_tokens(text):
@@ -28,9 +28,11 @@ def code_tokens(text):
 
 
 def kernel_source_hash(read=None):
-    """Hash of the device code (kernels and the layouts they read)."""
+    """Hash of the device code: the kernels built ahead of time, the layouts
+    they read, and the generator and headers of the specialized kernels."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "program.h", "kernels.h"):
+    for f in ("kernels.hip", "program.h", "kernels.h", "philox.h", "spec_args.h", "spec_prelude.h",
+              "specialize.cpp"):
         text = read(f) if read else open(os.path.join(ROOT, "paper_2604_27058_amd", "csrc", f)).read()
         h.update(code_tokens(text).encode())
     return h.hexdigest()[:16]

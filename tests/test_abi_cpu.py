@@ -89,3 +89,23 @@ def test_workspace_size_host_only():
     assert n == 4 * (1 << 20) * 8
     small = pk.Program(circuits.workload("surface_d3_r3")["texts"][0])
     assert small.workspace_size() == 0
+
+
+def test_specialize_host_only():
+    """clifft_specialize generates and compiles the program-specialized
+    bit-sliced kernel on the host (no GPU needed) and rejects programs that
+    do not qualify."""
+    p = pk.Program(circuits.surface_code_memory(3, 3, 1e-3))
+    assert p.specialize() == ""
+    assert p.specialize() == ""  # idempotent
+    L = p.resolve_launch(10 ** 6, pk.make_launch("f32", -32, specialize=1))
+    assert L["threads_per_shot"] == -32 and L["specialize"] == 1
+    assert p.resolve_launch(10 ** 6, pk.make_launch("f32", -32))["specialize"] == -1
+    with pytest.raises(pk.ClifftError, match="k_max = 0"):
+        pk.Program(circuits.workload("surface_d5_r5_t10")["texts"][0]).specialize()
+    with pytest.raises(pk.ClifftError, match="too long"):
+        pk.Program(circuits.surface_code_memory(3, 40, 1e-5)).specialize()
+    with pytest.raises(pk.ClifftError, match="too dense"):
+        pk.Program(circuits.surface_code_memory(3, 3, 2e-2)).specialize()
+    with pytest.raises(pk.ClifftError):
+        p.resolve_launch(10 ** 6, pk.make_launch("f32", 1, specialize=1))

@@ -56,6 +56,8 @@ def replay_and_check(g, outs, ref, replays=3, sizes=None):
 
 CASES = [
     ("surface d3 bit-sliced", lambda: circuits.surface_code_memory(3, 3, 1e-3), dict(threads_per_shot=-32), 50000),
+    ("surface d3 specialized", lambda: circuits.surface_code_memory(3, 3, 1e-3),
+     dict(threads_per_shot=-32, specialize=1), 50000),
     ("surface d3 shot per workgroup", lambda: circuits.surface_code_memory(3, 2, 1e-3), dict(threads_per_shot=256),
      3000),
     ("random k<=4 shot per lane FP64", lambda: random_small_circuit(np.random.default_rng(77), 7, 60),

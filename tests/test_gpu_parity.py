@@ -278,3 +278,78 @@ def test_bit_sliced_multi_chunk_low_noise():
     om, od, oo = p.sample(shots, seed=8, threads=8)
     gm, gd, go = gpu_sample(text, shots, seed=8, threads_per_shot=-32)
     assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
+
+
+# ---------------------------------------------------------------- specialized kernel
+def spec_sample(text, shots, seed=0, offset=0):
+    p = pk.Program(text)
+    p.specialize()
+    return gpu_sample(p, shots, seed=seed, offset=offset, threads_per_shot=-32, specialize=1)
+
+
+def test_specialized_surface_d3_bit_exact():
+    text = circuits.workload("surface_d3_r3")["texts"][0]
+    shots = 20000 + 37
+    om, od, oo = oracle.Program(text).sample(shots, seed=11, threads=8)
+    gm, gd, go = spec_sample(text, shots, seed=11)
+    assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_specialized_random_clifford_circuits(case):
+    """Low-noise Pauli-frame-only random circuits (all noise types, MX,
+    resets, detectors, an observable included twice) on the specialized
+    kernel."""
+    rng = np.random.default_rng(1500 + case)
+    n = [5, 30, 40, 17][case % 4]
+    text = random_small_circuit(rng, n, 90, rotations=False)
+    # keep the circuit's structure, scale its noise down to the fault-list regime
+    text = "\n".join(_scale_noise(line, 0.02) for line in text.splitlines()) + "\n"
+    text += "OBSERVABLE_INCLUDE(1) rec[-1] rec[-2]\nOBSERVABLE_INCLUDE(1) rec[-1]\n"
+    shots = 5000 + 13 * case
+    om, od, oo = oracle.Program(text).sample(shots, seed=case, threads=8)
+    gm, gd, go = spec_sample(text, shots, seed=case)
+    assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
+
+
+def _scale_noise(line, factor):
+    import re
+    m = re.match(r"^(\s*(?:DEPOLARIZE1|DEPOLARIZE2|X_ERROR|Y_ERROR|Z_ERROR))\(([^)]*)\)(.*)$", line)
+    if not m:
+        return line
+    return "%s(%r)%s" % (m.group(1), float(m.group(2)) * factor, m.group(3))
+
+
+@pytest.mark.parametrize("cap", ["1", "3"])
+def test_specialized_fault_list_refill(cap, monkeypatch):
+    """A lane whose faults exceed its list rebuilds the list above its last
+    applied fault; shrinking the list forces that path."""
+    text = circuits.surface_code_memory(3, 3, 1e-3)
+    shots = 40000 + 3
+    om, od, oo = oracle.Program(text).sample(shots, seed=21, threads=8)
+    monkeypatch.setenv("CLIFFT_FRAMES_LIST_CAP", cap)
+    gm, gd, go = spec_sample(text, shots, seed=21)
+    assert np.array_equal(gm, om) and np.array_equal(gd, od) and np.array_equal(go, oo)
+
+
+def test_specialized_shard_resume():
+    text = circuits.surface_code_memory(3, 3, 1e-3)
+    a = spec_sample(text, 4096 + 64, seed=5)
+    b = spec_sample(text, 2048, seed=5, offset=0)
+    c = spec_sample(text, 2048 + 64, seed=5, offset=2048)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, np.concatenate([y, z], axis=1))
+
+
+def test_specialized_equals_interpreter_large():
+    """At the benchmark size, the specialized kernel's records equal the
+    bit-sliced interpreter's word for word (both are checked against the
+    oracle at smaller sizes)."""
+    text = circuits.workload("surface_d3_r3")["texts"][0]
+    shots = 10_000_000
+    p = pk.Program(text)
+    p.specialize()
+    a = gpu_sample(p, shots, seed=3, threads_per_shot=-32, specialize=-1)
+    b = gpu_sample(p, shots, seed=3, threads_per_shot=-32, specialize=1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
