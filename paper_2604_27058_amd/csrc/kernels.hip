@@ -48,13 +48,19 @@ template <typename R> struct cpx { R re, im; };
 
 DEV uint32_t ins0(uint32_t p, int s) { return ((p >> s) << (s + 1)) | (p & ((1u << s) - 1u)); }
 
+// Frame words as a small vector value: a word chosen by a run-time qubit
+// index then lowers to register selects, where a plain array would be
+// turned into a variable offset into private (scratch) memory.
+template <int W>
+using Words = uint64_t __attribute__((ext_vector_type(W)));
+
 template <int W>
 struct Frame {
-  uint64_t x[W], z[W];
+  Words<W> x, z;
 };
 
 template <int W>
-DEV uint32_t getbit(const uint64_t (&a)[W], int q) {
+DEV uint32_t getbit(const Words<W>& a, int q) {
   uint64_t v = a[0];
 #pragma unroll
   for (int w = 1; w < W; w++)
@@ -63,14 +69,14 @@ DEV uint32_t getbit(const uint64_t (&a)[W], int q) {
 }
 
 template <int W>
-DEV void xorbit(uint64_t (&a)[W], int q, uint32_t b) {
+DEV void xorbit(Words<W>& a, int q, uint32_t b) {
 #pragma unroll
   for (int w = 0; w < W; w++)
     if ((q >> 6) == w) a[w] ^= (uint64_t)b << (q & 63);
 }
 
 template <int W>
-DEV uint32_t parity_and(const uint64_t (&a)[W], const uint64_t* m) {
+DEV uint32_t parity_and(const Words<W>& a, const uint64_t* m) {
   uint64_t acc = 0;
 #pragma unroll
   for (int w = 0; w < W; w++) acc ^= a[w] & m[w];
@@ -1342,7 +1348,7 @@ hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStrea
 // shot-per-workgroup program.  Every active vector lives in the workgroup's
 // slice of the global workspace.
 template <int W, typename R>
-__device__ void batch_item(const BatchArgs& B, const BatchProgram& bp, const BatchItem& it, uint64_t* rec,
+__device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgram& bp, const BatchItem& it, uint64_t* rec,
                            double* red, unsigned char* slot) {
   const DevProgram& P = bp.P;
   KArgs A{};
