@@ -73,23 +73,28 @@ __device__ __forceinline__ void list_insert(unsigned int* L, int lane, unsigned 
 __device__ __forceinline__ unsigned int build_list(const SpecArgs& A, const double* lds, unsigned int nsites,
                                                    unsigned int nchunks, unsigned long long s0, unsigned int* L,
                                                    int lane, unsigned int cap, unsigned int lo_key) {
-  unsigned int cnt = 0;
-  for (unsigned int j = 0; j < kShotsPerLane; j++) {
-    const unsigned long long shot = A.offset + s0 + j;
-    for (unsigned int c = 0; c < nchunks; c++) {
-      const unsigned int end = (c + 1) * kChunk < nsites ? (c + 1) * kChunk : nsites;
-      const double* S = chunk_surv(A, lds, c);
-      unsigned int ord = 0, cur = 0;
-      for (;;) {
-        unsigned int o = 0;
-        const unsigned int nf = next_fault(A, S, nsites, c, cur, &ord, shot, &o);
-        if (nf >= end) break;
-        const unsigned int key = (nf << 9) | (j << 4) | o;
-        if (key >= lo_key) {
-          list_insert(L, lane, cnt < cap ? cnt : cap, cap, key);
-          cnt++;
-        }
-        cur = nf - c * kChunk + 1;
+  // One draw per iteration over (shot, chunk, draw) in that order, so that
+  // lanes advance independently: the wave pays 32 x chunks draws plus the
+  // largest fault count among its lanes, not a second draw for every shot
+  // in which any lane saw a fault.
+  unsigned int cnt = 0, j = 0, c = 0, ord = 0, cur = 0;
+  while (j < kShotsPerLane) {
+    const unsigned int end = (c + 1) * kChunk < nsites ? (c + 1) * kChunk : nsites;
+    unsigned int o = 0;
+    const unsigned int nf = next_fault(A, chunk_surv(A, lds, c), nsites, c, cur, &ord, A.offset + s0 + j, &o);
+    if (nf < end) {
+      const unsigned int key = (nf << 9) | (j << 4) | o;
+      if (key >= lo_key) {
+        list_insert(L, lane, cnt < cap ? cnt : cap, cap, key);
+        cnt++;
+      }
+      cur = nf - c * kChunk + 1;
+    } else {  // no more faults in this chunk for shot j
+      ord = 0;
+      cur = 0;
+      if (++c == nchunks) {
+        c = 0;
+        j++;
       }
     }
   }
