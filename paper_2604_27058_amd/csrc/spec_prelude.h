@@ -24,15 +24,17 @@ __device__ __forceinline__ unsigned int outcomes(unsigned int type) { return typ
 // First fault at or after local index cur of `chunk` for one shot (S = the
 // chunk's survival products); returns the absolute site (chunk end when
 // none), advances *ord and sets *outcome for a fault.
-__device__ __forceinline__ unsigned int next_fault(const SpecArgs& A, const double* S, unsigned int nsites,
-                                                   unsigned int chunk, unsigned int cur, unsigned int* ord,
-                                                   unsigned long long shot, unsigned int* outcome) {
+// s_end: S[len] of the chunk when the caller knows it (single-chunk
+// programs pass it as a literal), negative to read it from S.
+__device__ __forceinline__ unsigned int next_fault(const SpecArgs& A, const double* S, double s_end,
+                                                   unsigned int nsites, unsigned int chunk, unsigned int cur,
+                                                   unsigned int* ord, unsigned long long shot, unsigned int* outcome) {
   const U4 w = draw((*ord)++, kPurposeNoise | chunk, shot, A.seed);
   const unsigned int rest = nsites - chunk * kChunk;
   const unsigned int len = rest < kChunk ? rest : kChunk;
-  const double tau = uniform53(w) * S[cur];
+  const double tau = cur ? uniform53(w) * S[cur] : uniform53(w);  // S[0] = 1
   unsigned int lo = cur, hi = len;
-  if (S[len] > tau) lo = len;  // no fault in the rest of the chunk
+  if ((s_end >= 0.0 ? s_end : S[len]) > tau) lo = len;  // no fault in the rest of the chunk
   while (lo < hi) {
     const unsigned int mid = (lo + hi) >> 1;
     if (S[mid + 1] <= tau) hi = mid;
@@ -70,9 +72,9 @@ __device__ __forceinline__ void list_insert(unsigned int* L, int lane, unsigned 
 // site order); returns how many keys >= lo_key exist.  A lane with more
 // faults than the list holds calls again with lo_key above its last applied
 // key (the draws are stateless, so the faults are the same).  cap >= 1.
-__device__ __forceinline__ unsigned int build_list(const SpecArgs& A, const double* lds, unsigned int nsites,
-                                                   unsigned int nchunks, unsigned long long s0, unsigned int* L,
-                                                   int lane, unsigned int cap, unsigned int lo_key) {
+__device__ __forceinline__ unsigned int build_list(const SpecArgs& A, const double* lds, double s_end,
+                                                   unsigned int nsites, unsigned int nchunks, unsigned long long s0,
+                                                   unsigned int* L, int lane, unsigned int cap, unsigned int lo_key) {
   // One draw per iteration over (shot, chunk, draw) in that order, so that
   // lanes advance independently: the wave pays 32 x chunks draws plus the
   // largest fault count among its lanes, not a second draw for every shot
@@ -81,7 +83,7 @@ __device__ __forceinline__ unsigned int build_list(const SpecArgs& A, const doub
   while (j < kShotsPerLane) {
     const unsigned int end = (c + 1) * kChunk < nsites ? (c + 1) * kChunk : nsites;
     unsigned int o = 0;
-    const unsigned int nf = next_fault(A, chunk_surv(A, lds, c), nsites, c, cur, &ord, A.offset + s0 + j, &o);
+    const unsigned int nf = next_fault(A, chunk_surv(A, lds, c), s_end, nsites, c, cur, &ord, A.offset + s0 + j, &o);
     if (nf < end) {
       const unsigned int key = (nf << 9) | (j << 4) | o;
       if (key >= lo_key) {

@@ -17,6 +17,7 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <sstream>
 
 namespace clifft {
@@ -100,7 +101,7 @@ struct Gen {
     o << "    // noise sites [" << lo << ", " << hi << ")\n"
       << "    for (;;) {\n"
       << "      if (lhead == lim && more) {\n"
-      << "        const unsigned int n = build_list(A, sl, " << nsites << "u, " << nchunks
+      << "        const unsigned int n = build_list(A, sl, SEND, " << nsites << "u, " << nchunks
       << "u, s0, L, lane, cap, last + 1);\n"
       << "        lim = n < cap ? n : cap; more = n > cap; lhead = 0;\n"
       << "      }\n"
@@ -137,6 +138,14 @@ struct Gen {
       << "  __shared__ unsigned int L[" << kSpecListCap * 64 << "];\n";
     if (surv_lds) o << "  __shared__ double SL[" << nsites + 1 << "];\n";
     o << "  const int lane = threadIdx.x;\n";
+    // survival product at the end of the only chunk, as an exact literal
+    if (P.nchunks == 1 && nsites > 0) {
+      char lit[64];
+      snprintf(lit, sizeof lit, "%a", P.surv[nsites]);
+      o << "  const double SEND = " << lit << ";\n";
+    } else {
+      o << "  const double SEND = -1.0;\n";
+    }
     if (surv_lds)
       o << "  for (unsigned int i = lane; i <= " << nsites << "u; i += 64) SL[i] = A.surv[i];\n"
         << "  __syncthreads();\n"
@@ -152,7 +161,7 @@ struct Gen {
       << "    const unsigned long long col = s0 >> 5;\n"
       << "    const bool st = col < 2 * A.words64;\n";
     if (nsites)
-      o << "    const unsigned int n0 = build_list(A, sl, " << nsites << "u, " << P.nchunks
+      o << "    const unsigned int n0 = build_list(A, sl, SEND, " << nsites << "u, " << P.nchunks
         << "u, s0, L, lane, cap, 0u);\n";
     else
       o << "    const unsigned int n0 = 0;\n";
