@@ -28,10 +28,10 @@ PEAK_HBM = 8.0e12                    # HBM3E bytes/s
 PEAK_LDS = 256 * 128 * 2.4e9         # LDS bytes/s: 128 B/clk/CU
 
 
-def load_traffic(workload, precision):
-    from paper_2604_27058_amd.profiling import kernel_source_hash
+def load_traffic(workload, precision, kernel):
     """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
-    were taken on the current kernel source."""
+    were taken on this kernel and its current sources."""
+    from paper_2604_27058_amd.profiling import kernel_family, kernel_source_hash
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, precision))
     if not os.path.exists(path):
         return None
@@ -39,7 +39,8 @@ def load_traffic(workload, precision):
         d = json.load(open(path))
     except ValueError:
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    family = kernel_family(kernel)
+    if d.get("kernel_family", "interpreter") != family or d.get("kernel_source_hash") != kernel_source_hash(family):
         return None
     return d.get("bytes_per_launch")
 
@@ -254,11 +255,11 @@ def main():
     else:
         achieved = cost["vector_bytes"] * shots / (kernel_ms * 1e-3)
         roof = dict(bound="lds", achieved=achieved / 1e9, peak=PEAK_LDS / 1e9, unit="GB/s", frac=achieved / PEAK_LDS)
-    traffic = load_traffic(args.workload, precision)
+    roof["kernel"] = ("clifft_frames_spec" if shape["specialize"] == 1 else "k_frames") if bit_sliced else "k_sample"
+    traffic = load_traffic(args.workload, precision, roof["kernel"])
     roof["traffic"] = traffic
     if traffic:
         roof["traffic_over_algorithmic"] = traffic / max(1.0, (cost["vector_bytes"] + cost["record_bytes"]) * shots)
-    roof["kernel"] = ("clifft_frames_spec" if shape["specialize"] == 1 else "k_frames") if bit_sliced else "k_sample"
     roof["kernel_ms"] = kernel_ms
     roof["work_per_shot"] = {kk: round(v, 3) for kk, v in cost.items()}
 

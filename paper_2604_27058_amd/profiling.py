@@ -27,12 +27,24 @@ def code_tokens(text):
     return " ".join(text.split())
 
 
-def kernel_source_hash(read=None):
-    """Hash of the device code: the kernels built ahead of time, the layouts
-    they read, and the generator and headers of the specialized kernels."""
+# Sources that decide what a kernel family executes: the device code and the
+# host compiler that produces the instruction stream it runs.
+FAMILY_SOURCES = {
+    "interpreter": ("kernels.hip", "kernels.h", "program.h", "philox.h", "compiler.cpp", "compiler.h"),
+    "specialized": ("specialize.cpp", "spec_prelude.h", "spec_args.h", "program.h", "philox.h", "compiler.cpp",
+                    "compiler.h"),
+}
+
+
+def kernel_family(kernel_name):
+    return "specialized" if "clifft_frames_spec" in kernel_name else "interpreter"
+
+
+def kernel_source_hash(family="interpreter", read=None):
+    """Hash of the sources of one kernel family (comments and whitespace
+    ignored)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "program.h", "kernels.h", "philox.h", "spec_args.h", "spec_prelude.h",
-              "specialize.cpp"):
+    for f in FAMILY_SOURCES[family]:
         text = read(f) if read else open(os.path.join(ROOT, "paper_2604_27058_amd", "csrc", f)).read()
         h.update(code_tokens(text).encode())
     return h.hexdigest()[:16]
@@ -80,7 +92,8 @@ def traffic(fetch_dir, write_dir, copy_bytes, workload, prec):
         _, name, kib = samp[-1]
         res[counter] = dict(kernel=name, kib_per_dispatch=kib, copy_kib=kib_copy, factor=factor,
                             bytes_per_launch=kib * 1024.0 / factor)
-    return dict(workload=workload, precision=prec, kernel_source_hash=kernel_source_hash(),
+    family = kernel_family(res["FETCH_SIZE"]["kernel"])
+    return dict(workload=workload, precision=prec, kernel_family=family, kernel_source_hash=kernel_source_hash(family),
                 bytes_per_launch=res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"],
                 fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"], copy_bytes=copy_bytes)
 
