@@ -200,42 +200,43 @@ struct Vec {
 // set disjoint from every other iteration's, so a batch of U iterations
 // issues all its loads before its stores (U independent loads in flight per
 // lane) without any hazard.
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 4;        // iterations in flight per lane, vectors on chip
+constexpr int kUnrollGlobal = 8;  // vectors in HBM: more bytes in flight per wave
 
 // Read-modify-write of one element per iteration: i = idx(p).
-template <int G, typename R, typename IdxF, typename BodyF>
+template <int G, typename R, int U, typename IdxF, typename BodyF>
 DEV void pass1(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body) {
   const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += kUnroll * st) {
-    uint32_t ii[kUnroll];
-    cpx<R> a[kUnroll];
+  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
+    uint32_t ii[U];
+    cpx<R> a[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
+    for (int u = 0; u < U; u++) {
       uint32_t p = base + u * st;
       ii[u] = idx(p < n ? p : base);
       if (p < n) a[u] = vec[ii[u]];
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++)
+    for (int u = 0; u < U; u++)
       if (base + u * st < n) vec[ii[u]] = body(a[u]);
   }
 }
 
 // Read-modify-write of a pair per iteration: (i0, i1) = idx(p).
-template <int G, typename R, typename IdxF, typename BodyF>
+template <int G, typename R, int U, typename IdxF, typename BodyF>
 DEV void pass2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body) {
   const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += kUnroll * st) {
-    uint32_t i0[kUnroll], i1[kUnroll];
-    cpx<R> a[kUnroll], b[kUnroll];
+  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
+    uint32_t i0[U], i1[U];
+    cpx<R> a[U], b[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
+    for (int u = 0; u < U; u++) {
       uint32_t p = base + u * st;
       idx(p < n ? p : base, i0[u], i1[u]);
       if (p < n) { a[u] = vec[i0[u]]; b[u] = vec[i1[u]]; }
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++)
+    for (int u = 0; u < U; u++)
       if (base + u * st < n) {
         body(a[u], b[u]);
         vec[i0[u]] = a[u];
@@ -246,40 +247,40 @@ DEV void pass2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, 
 
 // Two reads, one write per iteration: out[wi(p)] = body(in[r0(p)], in[r1(p)])
 // (r1 may equal r0).  Used where a pass writes fewer elements than it reads.
-template <int G, typename R, typename IdxF, typename BodyF>
+template <int G, typename R, int U, typename IdxF, typename BodyF>
 DEV void pass21(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body) {
   const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += kUnroll * st) {
-    uint32_t r0[kUnroll], r1[kUnroll], wi[kUnroll];
-    cpx<R> a[kUnroll], b[kUnroll];
+  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
+    uint32_t r0[U], r1[U], wi[U];
+    cpx<R> a[U], b[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
+    for (int u = 0; u < U; u++) {
       uint32_t p = base + u * st;
       idx(p < n ? p : base, r0[u], r1[u], wi[u]);
       if (p < n) { a[u] = vec[r0[u]]; b[u] = vec[r1[u]]; }
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++)
+    for (int u = 0; u < U; u++)
       if (base + u * st < n) vec[wi[u]] = body(a[u], b[u]);
   }
 }
 
 // Read-only pairs accumulated into two FP64 sums.
-template <int G, typename R, typename IdxF, typename BodyF>
+template <int G, typename R, int U, typename IdxF, typename BodyF>
 DEV void reduce2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body, double& s0,
                  double& s1) {
   const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += kUnroll * st) {
-    cpx<R> a[kUnroll], b[kUnroll];
+  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
+    cpx<R> a[U], b[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
+    for (int u = 0; u < U; u++) {
       uint32_t p = base + u * st;
       uint32_t i0, i1;
       idx(p < n ? p : base, i0, i1);
       if (p < n) { a[u] = vec[i0]; b[u] = vec[i1]; }
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++)
+    for (int u = 0; u < U; u++)
       if (base + u * st < n) body(a[u], b[u], s0, s1);
   }
 }
@@ -350,7 +351,7 @@ DEV void apply_fault(const DevProgram& P, Frame<W>& T, Frame<W>& N, uint32_t sit
 }
 
 // ------------------------------------------------------------------ one shot
-template <int W, int G, typename R, bool DBG, bool VEC>
+template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll>
 struct Shot {
   const DevProgram& P;
   const KArgs& A;
@@ -445,7 +446,7 @@ struct Shot {
           const uint32_t tm = in.a, bs = 1u << s;
           const int t0 = __ffs(tm) - 1;
           const int lo = min(s, t0), hi = max(s, t0);
-          pass2<G, R>(grp, vec, 1u << (k - 2),
+          pass2<G, R, U>(grp, vec, 1u << (k - 2),
                       [&](uint32_t p, uint32_t& i0, uint32_t& i1) { i0 = ins0(ins0(p, lo), hi) | bs; i1 = i0 ^ tm; },
                       [](cpx<R>& a, cpx<R>& b) { cpx<R> t = a; a = b; b = t; });
           grp.sync();
@@ -460,7 +461,7 @@ struct Shot {
           const uint32_t sm = in.a, bs = 1u << s;
           const int c = __ffs(sm) - 1;
           const int lo = min(s, c), hi = max(s, c);
-          pass1<G, R>(grp, vec, 1u << (k - 2),
+          pass1<G, R, U>(grp, vec, 1u << (k - 2),
                       [&](uint32_t p) {
                         uint32_t i = ins0(ins0(p, lo), hi) | bs;
                         return i | ((uint32_t)((__popc(i & sm) & 1) ^ 1) << c);
@@ -477,7 +478,7 @@ struct Shot {
           const uint32_t sm = in.a, bs = 1u << s;
           const int c = __ffs(sm) - 1;
           const int lo = min(s, c), hi = max(s, c);
-          pass2<G, R>(grp, vec, 1u << (k - 2),
+          pass2<G, R, U>(grp, vec, 1u << (k - 2),
                       [&](uint32_t p, uint32_t& i0, uint32_t& i1) {
                         uint32_t i = ins0(ins0(p, lo), hi);
                         i0 = i | ((uint32_t)((__popc(i & sm) & 1) ^ 1) << c);
@@ -492,7 +493,7 @@ struct Shot {
           if constexpr (!VEC) break;
           else {
           const uint32_t bs = 1u << s;
-          pass1<G, R>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
+          pass1<G, R, U>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
                       [](cpx<R> a) { return cpx<R>{-a.im, a.re}; });
           grp.sync();
           }
@@ -503,7 +504,7 @@ struct Shot {
           else {
           const R h = (R)0.70710678118654752440;
           const uint32_t bs = 1u << s;
-          pass2<G, R>(grp, vec, 1u << (k - 1),
+          pass2<G, R, U>(grp, vec, 1u << (k - 1),
                       [&](uint32_t p, uint32_t& i0, uint32_t& i1) { i0 = ins0(p, s); i1 = i0 | bs; },
                       [h](cpx<R>& a, cpx<R>& b) {
                         cpx<R> x{h * (a.re + b.re), h * (a.im + b.im)};
@@ -527,7 +528,7 @@ struct Shot {
           if (getbit<W>(T.x, v)) s2 = -s2;
           const R cr = (R)c2, ci = (R)s2;
           const uint32_t n = 1u << k;
-          pass21<G, R>(grp, vec, n, [&](uint32_t p, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = r1 = p; w = p | n; },
+          pass21<G, R, U>(grp, vec, n, [&](uint32_t p, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = r1 = p; w = p | n; },
                        [cr, ci](cpx<R> a, cpx<R>) { return cmul(a, cr, ci); });
           k++;
           grp.sync();
@@ -541,7 +542,7 @@ struct Shot {
           if (getbit<W>(T.x, v)) s2 = -s2;
           const R cr = (R)c2, ci = (R)s2;
           const uint32_t bs = 1u << s;
-          pass1<G, R>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
+          pass1<G, R, U>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
                       [cr, ci](cpx<R> a) { return cmul(a, cr, ci); });
           grp.sync();
           }
@@ -603,7 +604,7 @@ struct Shot {
           const uint32_t bs = 1u << s;
           const uint32_t half = 1u << (k - 1);
           double s0 = 0, s1 = 0;
-          reduce2<G, R>(grp, vec, half, [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = i0 | bs; },
+          reduce2<G, R, U>(grp, vec, half, [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = i0 | bs; },
                         [isx](cpx<R> a, cpx<R> b, double& x0, double& x1) {
                           if (isx) {
                             x0 += norm2(cpx<R>{a.re + b.re, a.im + b.im});
@@ -651,7 +652,7 @@ struct Shot {
             return b ? cpx<R>{scale * c.re, scale * c.im} : cpx<R>{scale * a.re, scale * a.im};
           };
           if (s == top) {
-            pass21<G, R>(grp, vec, half,
+            pass21<G, R, U>(grp, vec, half,
                          [&](uint32_t q, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = w = q; r1 = q | bs; },
                          [&](cpx<R> a, cpx<R> c) { return out1(a, c); });
           } else {
@@ -660,11 +661,11 @@ struct Shot {
             const uint32_t tb = 1u << top;
             const uint32_t n4 = half >> 1;
             const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += kUnroll * st) {
-              uint32_t jj[kUnroll];
-              cpx<R> a0[kUnroll], a1[kUnroll], c0[kUnroll], c1[kUnroll];
+            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += U * st) {
+              uint32_t jj[U];
+              cpx<R> a0[U], a1[U], c0[U], c1[U];
 #pragma unroll
-              for (int u = 0; u < kUnroll; u++) {
+              for (int u = 0; u < U; u++) {
                 uint32_t q = base + u * st;
                 jj[u] = ins0(q < n4 ? q : base, s);
                 if (q < n4) {
@@ -675,7 +676,7 @@ struct Shot {
                 }
               }
 #pragma unroll
-              for (int u = 0; u < kUnroll; u++)
+              for (int u = 0; u < U; u++)
                 if (base + u * st < n4) {
                   vec[jj[u]] = out1(a0[u], a1[u]);
                   vec[jj[u] | bs] = out1(c0[u], c1[u]);
@@ -813,7 +814,7 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
       for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 256) rec[r] = 0;
       __syncthreads();
       uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
-      Shot<W, G, R, DBG, VEC> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0, A.offset + g, g};
+      Shot<W, G, R, DBG, VEC, GLOBAL ? kUnrollGlobal : kUnroll> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0, A.offset + g, g};
       sh.run();
       __syncthreads();
       const uint64_t bit = 1ull << (g & 63);
@@ -835,14 +836,14 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if constexpr (G == 1) {
-      Shot<W, G, R, DBG, VEC> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
+      Shot<W, G, R, DBG, VEC, GLOBAL ? kUnrollGlobal : kUnroll> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
                             A.offset + tile * 64 + lane, tile * 64 + lane};
       sh.run();
     } else {
       uint32_t nsh = (uint32_t)min((uint64_t)64, A.shots - tile * 64);
       for (uint32_t sl = 0; sl < nsh; sl++) {
         uint64_t g = rfl((uint32_t)(tile * 64 + sl)) | ((tile * 64 + sl) & 0xFFFFFFFF00000000ull);
-        Shot<W, G, R, DBG, VEC> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, (int)sl, A.offset + g, g};
+        Shot<W, G, R, DBG, VEC, GLOBAL ? kUnrollGlobal : kUnroll> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, (int)sl, A.offset + g, g};
         sh.run();
       }
     }
