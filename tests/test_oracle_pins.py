@@ -1,13 +1,15 @@
 """Pins of the FP64 oracle against things other than itself.
 
-* Philox4x32-10 known-answer vectors (Random123 / SC'11) and rocRAND's
-  independent header implementation.
+* Philox4x32-10 known-answer vectors (Random123 / SC'11), rocRAND's
+  independent header implementation, chi-square uniformity of its words.
 * The paper's worked example (Section 3.1, Figs. 3-4): structure and closed
   form statistics.
 * Closed forms: T-state expectations (Appendix C), R_Z rotation angles.
 * Record-by-record and amplitude-by-amplitude agreement with an independent
   dense state-vector brute force (tests/dense_ref.py) on random circuits.
-* Gap sampler: exact inversion rule and per-site rates.
+* Gap sampler: exact inversion rule, per-site rates, and the
+  Poisson-binomial law of the fault count per shot.
+* Lemma 1: every localization takes at most 2N virtual gates.
 * Noiseless surface codes (detectors all zero), mirror circuits (records all
   zero), single-fault propagation versus GF(2) Pauli propagation.
 """
@@ -516,3 +518,63 @@ def test_consecutive_shots_equal_single_shot_traces():
         assert [(int(meas[r, s // 64]) >> (s % 64)) & 1 for r in range(p.nrec)] == list(t["recs"])
         assert [(int(det[r, s // 64]) >> (s % 64)) & 1 for r in range(p.ndet)] == list(t["dets"])
         assert [(int(obs[r, s // 64]) >> (s % 64)) & 1 for r in range(p.nobs)] == list(t["obs"])
+
+
+# ---------------------------------------------------------------- more pins
+def test_philox_words_uniform_chi_square():
+    """Each output word's top 4 bits are uniform over 16 bins (chi-square,
+    15 degrees of freedom, fixed counters; the bound is the 1e-6 quantile)."""
+    counts = np.zeros(16, dtype=np.int64)
+    n = 8000
+    for i in range(n):
+        w = oracle.philox((i, 0x4E000000, i * 2654435761 & 0xFFFFFFFF, 7), (12345, 678))
+        for x in w:
+            counts[x >> 28] += 1
+    expect = 4 * n / 16
+    chi2 = float(((counts - expect) ** 2 / expect).sum())
+    assert chi2 < 50.0, chi2
+
+
+def _poisson_binomial(ps):
+    pmf = np.zeros(len(ps) + 1)
+    pmf[0] = 1.0
+    for p in ps:
+        pmf[1:] = pmf[1:] * (1 - p) + pmf[:-1] * p
+        pmf[0] *= 1 - p
+    return pmf
+
+
+def test_fault_count_is_poisson_binomial():
+    """The number of realized faults per shot follows the Poisson-binomial
+    law of the site probabilities (Section 3.2: every site fires
+    independently with its own p), checked bin by bin within 5 sigma."""
+    ps = [0.02, 0.05, 0.1, 0.15, 0.2, 0.03, 0.08, 0.12, 0.25, 0.01, 0.3, 0.06]
+    text = "".join("X_ERROR(%r) %d\n" % (p, i) for i, p in enumerate(ps))
+    text += "".join("M %d\n" % i for i in range(len(ps)))
+    prog = oracle.Program(text)
+    shots = 12000
+    hist = np.zeros(len(ps) + 1, dtype=np.int64)
+    for s in range(shots):
+        hist[int((prog.faults(seed=3, shot=s) >= 0).sum())] += 1
+    pmf = _poisson_binomial(ps)
+    for c, p in zip(hist, pmf):
+        assert within_sigma(c, shots, p, 5.0), (hist, pmf * shots)
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_localization_gate_count_lemma1(case):
+    """Lemma 1: localizing a Pauli takes at most N - 1 CNOTs from the pivot,
+    N - 1 CZs, one S and one H, so every run of virtual Clifford gates that
+    precedes a rotation or measurement has at most 2N gates."""
+    rng = np.random.default_rng(2100 + case)
+    n = int(rng.integers(2, 9))
+    prog = oracle.Program(random_small_circuit(rng, n, 80))
+    vg = {oracle.OP_NAMES.index(k) for k in ("VCX", "VCZ", "VS", "VH")}
+    run = longest = 0
+    for kind, _, _, _ in prog.ops():
+        if kind in vg:
+            run += 1
+            longest = max(longest, run)
+        else:
+            run = 0
+    assert longest <= 2 * n, (longest, n)
