@@ -173,7 +173,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (shards would run "
-              "independent shot ranges, see DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "independent shot ranges keyed by the global shot index); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

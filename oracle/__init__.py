@@ -76,7 +76,7 @@ class OracleError(RuntimeError):
 
 
 class Program:
-    """A circuit compiled by the oracle (Stim-subset text)."""
+    """A circuit compiled by the oracle (the Stim-like text subset its parser accepts)."""
 
     def __init__(self, text):
         L = lib()

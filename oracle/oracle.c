@@ -23,7 +23,7 @@
  *   Section 3.2 (sparse error bottleneck: cumulative
  *                hazard, jump to next fault)          -> draw_faults()
  *
- * Stochastic contract (readings of the paper, written out in the design doc):
+ * Stochastic contract (the readings of the paper this oracle follows):
  *   Philox4x32-10 (Salmon et al., SC'11), key = (seed_lo, seed_hi),
  *   counter = (index, purpose, shot_lo, shot_hi).
  *   Every recorded outcome is m = m_ref XOR pn, where pn is the commutation

@@ -344,7 +344,7 @@ def large_active(n=200, depth=300, k_target=20, n_t=40, p=1e-4, seed=5000):
 
 
 # --------------------------------------------------------------------------
-# The five workloads (sizes as in the benchmark table of the design doc).
+# The five benchmark workloads and their shot counts.
 # --------------------------------------------------------------------------
 def workload(name):
     """Returns dict(texts=[...], shots=int, precision='f64'|'f32', kmax=int|None)."""

@@ -3,7 +3,7 @@
 Independent of oracle/ and of the HIP path: its own parser, its own Philox,
 its own survival products, plain 2^N state vectors and explicit gate
 matrices.  It simulates the *physical* circuit directly and applies the same
-stochastic contract (described in the design doc) in physical terms:
+stochastic contract in physical terms:
 
   * the noise-only Pauli frame E is the product of all fired noise Paulis,
     propagated through the physical Clifford gates (and corrected by resets);
