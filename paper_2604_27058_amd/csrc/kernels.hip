@@ -44,7 +44,20 @@ using clifft_rng::U4;
 using clifft_rng::uniform53;
 
 // ------------------------------------------------------------------ helpers
-template <typename R> struct cpx { R re, im; };
+// Complex amplitude.  Copies are member-wise: a struct copy of two doubles
+// otherwise lowers to memcpy and keeps pass buffers in scratch memory.
+template <typename R>
+struct cpx {
+  R re, im;
+  cpx() = default;
+  __host__ __device__ constexpr cpx(R r, R i) : re(r), im(i) {}
+  __host__ __device__ constexpr cpx(const cpx& o) : re(o.re), im(o.im) {}
+  __host__ __device__ cpx& operator=(const cpx& o) {
+    re = o.re;
+    im = o.im;
+    return *this;
+  }
+};
 
 DEV uint32_t ins0(uint32_t p, int s) { return ((p >> s) << (s + 1)) | (p & ((1u << s) - 1u)); }
 
@@ -201,7 +214,9 @@ struct Vec {
 // issues all its loads before its stores (U independent loads in flight per
 // lane) without any hazard.
 constexpr int kUnroll = 4;        // iterations in flight per lane, vectors on chip
-constexpr int kUnrollGlobal = 8;  // vectors in HBM: more bytes in flight per wave
+constexpr int kUnrollGlobal = 8;  // FP32 vectors in HBM: more bytes in flight per wave
+template <typename R, bool GLOBAL>
+constexpr int unroll_for() { return GLOBAL && sizeof(R) == 4 ? kUnrollGlobal : kUnroll; }
 
 // Read-modify-write of one element per iteration: i = idx(p).
 template <int G, typename R, int U, typename IdxF, typename BodyF>
@@ -814,7 +829,7 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
       for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 256) rec[r] = 0;
       __syncthreads();
       uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
-      Shot<W, G, R, DBG, VEC, GLOBAL ? kUnrollGlobal : kUnroll> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0, A.offset + g, g};
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>()> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0, A.offset + g, g};
       sh.run();
       __syncthreads();
       const uint64_t bit = 1ull << (g & 63);
@@ -836,14 +851,14 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if constexpr (G == 1) {
-      Shot<W, G, R, DBG, VEC, GLOBAL ? kUnrollGlobal : kUnroll> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>()> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
                             A.offset + tile * 64 + lane, tile * 64 + lane};
       sh.run();
     } else {
       uint32_t nsh = (uint32_t)min((uint64_t)64, A.shots - tile * 64);
       for (uint32_t sl = 0; sl < nsh; sl++) {
         uint64_t g = rfl((uint32_t)(tile * 64 + sl)) | ((tile * 64 + sl) & 0xFFFFFFFF00000000ull);
-        Shot<W, G, R, DBG, VEC, GLOBAL ? kUnrollGlobal : kUnroll> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, (int)sl, A.offset + g, g};
+        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>()> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, (int)sl, A.offset + g, g};
         sh.run();
       }
     }
