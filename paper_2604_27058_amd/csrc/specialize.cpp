@@ -56,13 +56,13 @@ struct Gen {
     return s;
   }
 
-  // One case of the fault switch: the Pauli of outcome o (variable `o`) at
-  // site s, on the shot bit `bit`, XORed into both frames.
-  void site_case(int s) {
+  // The Pauli of outcome o (variable `o`) at site s, on the shot bit `bit`,
+  // XORed into both frames.
+  void site_body(int s) {
     const int t = P.site_type[s];
     const uint32_t img = P.site_img[s];
     const int ncomp = t == S_DEP2 ? 2 : 1;
-    o << "        case " << s << ": {";
+    o << "        {";
     if (t == S_DEP1)
       o << " const unsigned int x0 = o < 2u ? bit : 0u, z0 = o >= 1u ? bit : 0u;";
     else if (t == S_DEP2)
@@ -91,31 +91,35 @@ struct Gen {
       if (!tz[q].empty())
         o << " { const unsigned int t = " << tz[q] << "; " << f(N + q) << " ^= t; " << f(3 * N + q) << " ^= t; }";
     }
-    o << " break; }\n";
+    o << " }\n";
   }
 
-  // Faults of sites [lo, hi): every lane applies its list entries below hi
-  // in key order; a lane whose list ran out while more faults remain
-  // rebuilds it above its last applied key.
+  // Faults of sites [lo, hi).  Each lane's next unapplied fault is kept in
+  // `e` (its key, 0xFFFFFFFF when none).  The block sweeps its sites in
+  // order; a lane applies its entry for a site when the sweep reaches it
+  // (keys are ascending, so sites come in order).  The sweep repeats while a
+  // lane still holds an entry of the block (a second fault at a site
+  // already passed) or ran out of list while more faults remain (it then
+  // rebuilds the list above its last applied key).
   void noise(uint32_t lo, uint32_t hi, uint32_t nsites, uint32_t nchunks) {
     o << "    // noise sites [" << lo << ", " << hi << ")\n"
-      << "    for (;;) {\n"
-      << "      if (lhead == lim && more) {\n"
+      << "    for (;;) {\n";
+    for (uint32_t s = lo; s < hi; s++) {
+      o << "      if ((e >> 9) == " << s << "u) {\n"
+        << "        const unsigned int bit = 1u << ((e >> 4) & 31u), o = e & 15u;\n";
+      site_body((int)s);
+      o << "        last = e; lhead++;\n"
+        << "        e = lhead < lim ? L[lhead * 64 + lane] : 0xFFFFFFFFu;\n"
+        << "      }\n";
+    }
+    // another sweep for a second fault of the lane at a site already passed
+    // (two of its shots at one site) or after a refill
+    o << "      const bool rf = lhead == lim && more;\n"
+      << "      if (__ballot(rf || (e >> 9) < " << hi << "u) == 0) break;\n"
+      << "      if (rf) {\n"
       << "        const unsigned int n = build_list(A, sl, SEND, " << nsites << "u, " << nchunks
       << "u, s0, L, lane, cap, last + 1);\n"
-      << "        lim = n < cap ? n : cap; more = n > cap; lhead = 0;\n"
-      << "      }\n"
-      << "      const unsigned int e = lhead < lim ? L[lhead * 64 + lane] : 0xFFFFFFFFu;\n"
-      << "      const bool act = (e >> 9) < " << hi << "u;\n"
-      << "      if (__ballot(act) == 0) break;\n"
-      << "      if (act) {\n"
-      << "        const unsigned int bit = 1u << ((e >> 4) & 31u), o = e & 15u;\n"
-      << "        switch (e >> 9) {\n";
-    for (uint32_t s = lo; s < hi; s++) site_case((int)s);
-    o << "        default: break;\n"
-      << "        }\n"
-      << "        last = e;\n"
-      << "        lhead++;\n"
+      << "        lim = n < cap ? n : cap; more = n > cap; lhead = 0; e = L[lane];\n"
       << "      }\n"
       << "    }\n";
   }
@@ -167,7 +171,8 @@ struct Gen {
       o << "    const unsigned int n0 = 0;\n";
     o << "    unsigned int lim = n0 < cap ? n0 : cap, lhead = 0, last = 0;\n"
       << "    bool more = n0 > cap;\n"
-      << "    (void)lim; (void)lhead; (void)last; (void)more;\n"
+      << "    unsigned int e = lim ? L[lane] : 0xFFFFFFFFu;\n"
+      << "    (void)lim; (void)lhead; (void)last; (void)more; (void)e;\n"
       << "    unsigned int f[" << 4 * N << "];\n"
       << "#pragma unroll\n"
       << "    for (int i = 0; i < " << 4 * N << "; i++) f[i] = 0;\n"
