@@ -92,6 +92,7 @@ def bench_batch(args, w, pk, torch):
     if not args.no_autotune and not args.threads_per_shot:
         for p in progs:
             p.autotune(shots[0], precision)
+            p.autotune(shots[0], "f64")  # the plain FP64 form below uses its own tuned shapes
     B = pk.Batch(progs, shots, seeds, precision=precision, threads_per_shot=args.threads_per_shot, grid=args.grid)
     outs, ws = B.alloc()
     stream = torch.cuda.current_stream()

@@ -43,17 +43,22 @@ struct BatchItem {
   uint32_t kind;   // 1: four 64-shot tiles (one per wave); 256: one shot
   uint64_t first;  // first tile (kind 1) or shot (kind 256)
 };
+// One queue of a batched launch (all items of one kind).
 struct BatchArgs {
   const BatchProgram* progs;
   const BatchItem* items;
   uint64_t nitems;
-  uint32_t* counter;      // zeroed before the launch
+  uint32_t* counter;      // claim counter, zeroed before the launch
   uint64_t *meas, *det, *obs;
   void* workspace;
   uint64_t slot_bytes;    // workspace bytes per workgroup
   uint32_t rec_words;     // max records + detectors + observables over programs
 };
-hipError_t launch_batch(const BatchArgs& B, int grid, size_t lds_bytes, bool fp64, hipStream_t stream);
+// The shot-per-workgroup queue, then the shot-per-lane queue, as two
+// persistent kernels on the stream (they share the workspace).  The two
+// counters are the 32-bit words at groups.counter and groups.counter + 2.
+hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArgs& lanes, int grid_lanes,
+                        size_t lds_bytes, bool fp64, hipStream_t stream);
 
 hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t stream);
 // Bit-sliced Pauli-frame kernel (k_max = 0): 32 shots per lane, one 64-thread

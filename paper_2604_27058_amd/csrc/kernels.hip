@@ -1363,7 +1363,7 @@ hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStrea
 // tiles of a shot-per-lane program (one tile per wave) or one shot of a
 // shot-per-workgroup program.  Every active vector lives in the workgroup's
 // slice of the global workspace.
-template <int W, typename R>
+template <int W, typename R, int KIND>
 __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgram& bp, const BatchItem& it, uint64_t* rec,
                            double* red, unsigned char* slot) {
   const DevProgram& P = bp.P;
@@ -1377,7 +1377,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
   const uint32_t nwords_rec = (uint32_t)(P.nrec + P.ndet + P.nobs);
   const uint64_t words = (bp.shots + 63) / 64;
   const int lane = threadIdx.x & 63;
-  if (it.kind == 1) {
+  if constexpr (KIND == 1) {
     const int wv = (int)rfl(threadIdx.x >> 6);
     const uint64_t tile = it.first + (uint64_t)wv;
     uint64_t* wrec = rec + (size_t)wv * B.rec_words;
@@ -1414,7 +1414,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
     const uint64_t g = rfl((uint32_t)it.first) | (it.first & 0xFFFFFFFF00000000ull);
     for (uint32_t r = threadIdx.x; r < nwords_rec; r += 256) rec[r] = 0;
     __syncthreads();
-    Shot<W, 256, R, false, true> sh{P, A, Group<256>{(int)threadIdx.x}, Vec<256, R>{(cpx<R>*)slot, lane}, rec, red,
+    Shot<W, 256, R, false, true, unroll_for<R, true>()> sh{P, A, Group<256>{(int)threadIdx.x}, Vec<256, R>{(cpx<R>*)slot, lane}, rec, red,
                                     0, A.offset + g, g};
     sh.run();
     __syncthreads();
@@ -1432,7 +1432,9 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
   __syncthreads();
 }
 
-template <typename R>
+// KIND 256: the shot-per-workgroup queue; KIND 1: the shot-per-lane tiles.
+// Separate kernels, so that each path gets the registers it needs.
+template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* rec = (uint64_t*)smem;  // 4 * rec_words
@@ -1448,36 +1450,39 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     const BatchItem it = B.items[item];
     const BatchProgram& bp = B.progs[it.prog];
     switch (bp.P.W) {
-      case 1: batch_item<1, R>(B, bp, it, rec, red, slot); break;
-      case 2: batch_item<2, R>(B, bp, it, rec, red, slot); break;
-      case 3: batch_item<3, R>(B, bp, it, rec, red, slot); break;
-      default: batch_item<4, R>(B, bp, it, rec, red, slot); break;
+      case 1: batch_item<1, R, KIND>(B, bp, it, rec, red, slot); break;
+      case 2: batch_item<2, R, KIND>(B, bp, it, rec, red, slot); break;
+      case 3: batch_item<3, R, KIND>(B, bp, it, rec, red, slot); break;
+      default: batch_item<4, R, KIND>(B, bp, it, rec, red, slot); break;
     }
   }
 }
 
-hipError_t launch_batch(const BatchArgs& B, int grid, size_t lds_bytes, bool fp64, hipStream_t st) {
-  // the claim counter is one 32-bit word in a 64-bit slot: zero the slot
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (uint64_t*)B.counter, (size_t)1);
-  static bool attr32 = false, attr64 = false;
-  if (fp64) {
-    if (!attr64) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_batch<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         160 * 1024);
-      if (e != hipSuccess) return e;
-      attr64 = true;
-    }
-    hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(256), lds_bytes, st, B);
-  } else {
-    if (!attr32) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_batch<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         160 * 1024);
-      if (e != hipSuccess) return e;
-      attr32 = true;
-    }
-    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(256), lds_bytes, st, B);
+template <typename R, int KIND>
+static hipError_t launch_batch_t(const BatchArgs& B, int grid, size_t lds_bytes, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_batch<R, KIND>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
   }
+  hipLaunchKernelGGL((k_batch<R, KIND>), dim3(grid), dim3(256), lds_bytes, st, B);
   return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArgs& lanes, int grid_lanes,
+                        size_t lds_bytes, bool fp64, hipStream_t st) {
+  // both claim counters (32-bit words at the starts of two 64-bit slots)
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (uint64_t*)groups.counter, (size_t)2);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && groups.nitems)
+    e = fp64 ? launch_batch_t<double, 256>(groups, grid_groups, lds_bytes, st)
+             : launch_batch_t<float, 256>(groups, grid_groups, lds_bytes, st);
+  if (e == hipSuccess && lanes.nitems)
+    e = fp64 ? launch_batch_t<double, 1>(lanes, grid_lanes, lds_bytes, st)
+             : launch_batch_t<float, 1>(lanes, grid_lanes, lds_bytes, st);
+  return e;
 }
 
 hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t st) {

@@ -255,15 +255,17 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
     }
   }
   // Tiers: frames shot-per-lane whenever the vectors of 64 shots fit the
-  // global budget (k <= 12), else one shot per workgroup; vectors in LDS when
-  // they fit, else in the caller's workspace (HBM).
+  // global budget (k <= 12), else one shot per workgroup.  Shot-per-lane
+  // vectors go to LDS when they fit.  A shot-per-workgroup vector stays in
+  // LDS only while four workgroups per CU fit (32 KB); beyond that the HBM
+  // workspace serves it faster, with more workgroups streaming per CU.
   if (G == 0) G = (H.kmax <= kLaneMaxK) ? 1 : 256;
   bool global_vec = false;
   if (H.kmax > 0) {
     size_t need = (G == 256 ? 1 : 4) * vec * amp * (G == 1 ? 64 : 1);
     if (c.vector_in_hbm == 1) global_vec = true;
     else if (c.vector_in_hbm == -1) global_vec = false;
-    else global_vec = need > kLdsLimit - 16 * 1024;
+    else global_vec = need > (G == 256 ? (size_t)32 * 1024 : kLdsLimit - 16 * 1024);
     if (global_vec && G == 64) return fail(CLIFFT_E_CAPACITY, "shot-per-wave vectors must fit in LDS");
   }
   DevProgram tmp{};
@@ -367,17 +369,22 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
 struct clifft_batch {
   std::vector<const clifft_program*> progs;
   std::vector<BatchProgram> table;  // device pointers of each program's upload
-  std::vector<BatchItem> items;
+  // two queues: single shots of shot-per-workgroup programs, and 64-shot
+  // tile groups of shot-per-lane programs; each sorted longest first
+  std::vector<BatchItem> items_g, items_l;
   bool fp64 = false;
   int device = 0;
-  int grid = 0;
+  int grid_g = 0, grid_l = 0;
   size_t lds = 0;
-  uint64_t slot_bytes = 0;
+  uint64_t slot_g = 0, slot_l = 0;  // workspace bytes per workgroup of each queue
   uint32_t rec_words = 0;
   uint64_t meas_words = 0, det_words = 0, obs_words = 0;
   BatchProgram* d_table = nullptr;
-  BatchItem* d_items = nullptr;
+  BatchItem* d_items_g = nullptr;
+  BatchItem* d_items_l = nullptr;
   uint64_t* d_counter = nullptr;
+
+  size_t workspace_bytes() const { return std::max((size_t)grid_g * slot_g, (size_t)grid_l * slot_l); }
 };
 
 extern "C" {
@@ -516,7 +523,7 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
   b->fp64 = c.precision == CLIFFT_FP64;
   (void)hipGetDevice(&b->device);
   const size_t amp = b->fp64 ? 16 : 8;
-  std::vector<double> item_cost;
+  std::vector<double> cost_g, cost_l;
   for (int i = 0; i < n; i++) {
     if (!progs[i]) { delete b; return fail(CLIFFT_E_INVALID_ARG, "null program in batch"); }
     const DevProgram* D = nullptr;
@@ -546,7 +553,8 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
     }
     bp.G = G;
     const uint64_t vec = (uint64_t)1 << H.kmax;
-    b->slot_bytes = std::max<uint64_t>(b->slot_bytes, G == 1 ? 4 * 64 * vec * amp : vec * amp);
+    if (G == 1) b->slot_l = std::max<uint64_t>(b->slot_l, 4 * 64 * vec * amp);
+    else b->slot_g = std::max<uint64_t>(b->slot_g, vec * amp);
     b->rec_words = std::max<uint32_t>(b->rec_words, (uint32_t)(H.nrec + H.ndet + H.nobs));
     b->progs.push_back(progs[i]);
     b->table.push_back(bp);
@@ -559,37 +567,51 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
     const double block_item = 20.0 * cm.instructions + (cm.vector_bytes + cm.flops) / 64.0;
     if (G == 1) {
       for (uint64_t t = 0; t < words; t += 4) {
-        b->items.push_back(BatchItem{(uint32_t)i, 1u, t});
-        item_cost.push_back(lane_item);
+        b->items_l.push_back(BatchItem{(uint32_t)i, 1u, t});
+        cost_l.push_back(lane_item);
       }
     } else {
       for (uint64_t s = 0; s < shots[i]; s++) {
-        b->items.push_back(BatchItem{(uint32_t)i, 256u, s});
-        item_cost.push_back(block_item);
+        b->items_g.push_back(BatchItem{(uint32_t)i, 256u, s});
+        cost_g.push_back(block_item);
       }
     }
   }
-  std::vector<size_t> order(b->items.size());
-  for (size_t i = 0; i < order.size(); i++) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c2) { return item_cost[a] > item_cost[c2]; });
-  std::vector<BatchItem> sorted(order.size());
-  for (size_t i = 0; i < order.size(); i++) sorted[i] = b->items[order[i]];
-  b->items.swap(sorted);
+  auto longest_first = [](std::vector<BatchItem>& items, const std::vector<double>& cost) {
+    std::vector<size_t> order(items.size());
+    for (size_t i = 0; i < order.size(); i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c2) { return cost[a] > cost[c2]; });
+    std::vector<BatchItem> sorted(order.size());
+    for (size_t i = 0; i < order.size(); i++) sorted[i] = items[order[i]];
+    items.swap(sorted);
+  };
+  longest_first(b->items_g, cost_g);
+  longest_first(b->items_l, cost_l);
   b->rec_words = (b->rec_words + 1) & ~1u;
   b->lds = (size_t)4 * b->rec_words * 8 + 64 + 64;
   if (b->lds > kLdsLimit) { delete b; return fail(CLIFFT_E_CAPACITY, "too many records for the batched launch"); }
-  int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, kLdsLimit / b->lds));
-  b->grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
-  size_t cap = std::max<size_t>(1, kWorkspaceBudget / std::max<uint64_t>(b->slot_bytes, 1));
-  if (c.grid <= 0 && (size_t)b->grid > cap) b->grid = (int)cap;
-  if ((uint64_t)b->grid > b->items.size()) b->grid = (int)b->items.size();
+  const int cus = device_cus();
+  auto grid_for = [&](int per_cu, uint64_t slot, size_t nitems) {
+    int g = c.grid > 0 ? c.grid : cus * per_cu;
+    const size_t cap = std::max<size_t>(1, kWorkspaceBudget / std::max<uint64_t>(slot, 1));
+    if (c.grid <= 0 && (size_t)g > cap) g = (int)cap;
+    if ((size_t)g > nitems) g = (int)std::max<size_t>(1, nitems);
+    return g;
+  };
+  // the workgroup queue is bounded by registers (about two workgroups per
+  // CU resident), the lane queue by LDS
+  b->grid_g = grid_for(4, b->slot_g, b->items_g.size());
+  b->grid_l = grid_for((int)std::max<size_t>(1, std::min<size_t>(8, kLdsLimit / b->lds)), b->slot_l, b->items_l.size());
   hipError_t e = hipMalloc((void**)&b->d_table, sizeof(BatchProgram) * b->table.size());
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_items, sizeof(BatchItem) * b->items.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_items_g, sizeof(BatchItem) * std::max<size_t>(1, b->items_g.size()));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_items_l, sizeof(BatchItem) * std::max<size_t>(1, b->items_l.size()));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, 64);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_table, b->table.data(), sizeof(BatchProgram) * b->table.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_items, b->items.data(), sizeof(BatchItem) * b->items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !b->items_g.empty())
+    e = hipMemcpy(b->d_items_g, b->items_g.data(), sizeof(BatchItem) * b->items_g.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !b->items_l.empty())
+    e = hipMemcpy(b->d_items_l, b->items_l.data(), sizeof(BatchItem) * b->items_l.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     clifft_batch_free(b);
     return fail(CLIFFT_E_DEVICE, std::string("batch upload failed: ") + hipGetErrorString(e));
@@ -613,7 +635,7 @@ clifft_status clifft_batch_sizes(const clifft_batch* b, uint64_t* meas_words, ui
   if (meas_words) *meas_words = b->meas_words;
   if (det_words) *det_words = b->det_words;
   if (obs_words) *obs_words = b->obs_words;
-  if (workspace_bytes) *workspace_bytes = (size_t)b->grid * b->slot_bytes;
+  if (workspace_bytes) *workspace_bytes = b->workspace_bytes();
   if (threads_per_shot)
     for (size_t i = 0; i < b->table.size(); i++) threads_per_shot[i] = b->table[i].G;
   return CLIFFT_OK;
@@ -622,7 +644,7 @@ clifft_status clifft_batch_sizes(const clifft_batch* b, uint64_t* meas_words, ui
 clifft_status clifft_batch_sample(const clifft_batch* b, void* workspace, size_t workspace_bytes, uint64_t* meas,
                                   uint64_t* det, uint64_t* obs, void* stream) {
   if (!b) return fail(CLIFFT_E_INVALID_ARG, "null batch");
-  const size_t need = (size_t)b->grid * b->slot_bytes;
+  const size_t need = b->workspace_bytes();
   if (need > 0 && (!workspace || workspace_bytes < need)) {
     char buf[128];
     snprintf(buf, sizeof buf, "workspace of %zu bytes needed", need);
@@ -635,18 +657,23 @@ clifft_status clifft_batch_sample(const clifft_batch* b, void* workspace, size_t
   hipError_t e = launch_zero(meas, b->meas_words, s);
   if (e == hipSuccess) e = launch_zero(det, b->det_words, s);
   if (e == hipSuccess) e = launch_zero(obs, b->obs_words, s);
-  BatchArgs A{};
-  A.progs = b->d_table;
-  A.items = b->d_items;
-  A.nitems = b->items.size();
-  A.counter = (uint32_t*)b->d_counter;
-  A.meas = meas;
-  A.det = det;
-  A.obs = obs;
-  A.workspace = workspace;
-  A.slot_bytes = b->slot_bytes;
-  A.rec_words = b->rec_words;
-  if (e == hipSuccess) e = launch_batch(A, b->grid, b->lds, b->fp64, s);
+  BatchArgs G{};
+  G.progs = b->d_table;
+  G.items = b->d_items_g;
+  G.nitems = b->items_g.size();
+  G.counter = (uint32_t*)b->d_counter;
+  G.meas = meas;
+  G.det = det;
+  G.obs = obs;
+  G.workspace = workspace;
+  G.slot_bytes = b->slot_g;
+  G.rec_words = b->rec_words;
+  BatchArgs L = G;
+  L.items = b->d_items_l;
+  L.nitems = b->items_l.size();
+  L.counter = (uint32_t*)b->d_counter + 2;
+  L.slot_bytes = b->slot_l;
+  if (e == hipSuccess) e = launch_batch(G, b->grid_g, L, b->grid_l, b->lds, b->fp64, s);
   if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
   return CLIFFT_OK;
 }
@@ -657,7 +684,8 @@ void clifft_batch_free(clifft_batch* b) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(b->device);
   if (b->d_table) (void)hipFree(b->d_table);
-  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_items_g) (void)hipFree(b->d_items_g);
+  if (b->d_items_l) (void)hipFree(b->d_items_l);
   if (b->d_counter) (void)hipFree(b->d_counter);
   (void)hipSetDevice(cur);
   delete b;
