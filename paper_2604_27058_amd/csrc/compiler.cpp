@@ -791,6 +791,28 @@ int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& 
     }
     if (P.rblk_ev.empty()) P.rblk_ev.push_back(0);
   }
+  // Look-ahead fusion of active measurements: when the next instruction that
+  // touches the active vector is again an active measurement, the first
+  // one's collapse pass computes the second's branch sums.
+  {
+    auto touches_vector = [](uint8_t op) {
+      return (op >= OP_APERM && op <= OP_AROT) || op == OP_MACTZ || op == OP_MACTX;
+    };
+    for (size_t i = 0; i < P.code.size(); i++) {
+      GInstr& in = P.code[i];
+      if (in.op != OP_MACTZ && in.op != OP_MACTX) continue;
+      for (size_t j = i + 1; j < P.code.size(); j++) {
+        if (!touches_vector(P.code[j].op)) continue;
+        GInstr& nx = P.code[j];
+        if (nx.op == OP_MACTZ || nx.op == OP_MACTX) {
+          in.flags |= F_FUSE_NEXT | (nx.op == OP_MACTX ? F_NEXT_X : 0);
+          in.u = nx.s;
+          nx.flags |= F_SUMS_READY;
+        }
+        break;
+      }
+    }
+  }
   survival_tables(P);
   if (P.masks.empty()) P.masks.push_back(0);
   if (P.consts.empty()) { P.consts.push_back(1.0); P.consts.push_back(0.0); }

@@ -410,6 +410,7 @@ struct Shot {
     uint32_t last_m = 0, last_pn = 0;
     uint32_t rb_blk = 0xFFFFFFFFu;
     U4 rb{0, 0, 0, 0};
+    double carry0 = 0, carry1 = 0;  // branch sums of the next active measurement (fused)
     Noise ns{0, 0, 0xFFFFFFFFu, 0};
     if (P.nsites > 0) {
       if (DBG && A.forced_faults) ns.nf = 0xFFFFFFFFu;
@@ -618,19 +619,29 @@ struct Shot {
           uint32_t pn = isx ? getbit<W>(N.z, v) : getbit<W>(N.x, v);
           const uint32_t bs = 1u << s;
           const uint32_t half = 1u << (k - 1);
+          // branch sums (Appendix B.2): |a|^2 per half along the axis, or
+          // |a +- b|^2 of the fold for an X-type measurement
+          auto branch_sums = [](bool x, cpx<R> a, cpx<R> b, double& x0, double& x1) {
+            if (x) {
+              x0 += norm2(cpx<R>{a.re + b.re, a.im + b.im});
+              x1 += norm2(cpx<R>{a.re - b.re, a.im - b.im});
+            } else {
+              x0 += norm2(a);
+              x1 += norm2(b);
+            }
+          };
           double s0 = 0, s1 = 0;
-          reduce2<G, R, U>(grp, vec, half, [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = i0 | bs; },
-                        [isx](cpx<R> a, cpx<R> b, double& x0, double& x1) {
-                          if (isx) {
-                            x0 += norm2(cpx<R>{a.re + b.re, a.im + b.im});
-                            x1 += norm2(cpx<R>{a.re - b.re, a.im - b.im});
-                          } else {
-                            x0 += norm2(a);
-                            x1 += norm2(b);
-                          }
-                        }, s0, s1);
-          s0 = grp.sum(s0, red);
-          s1 = grp.sum(s1, red);
+          if (in.flags & F_SUMS_READY) {
+            // accumulated by the previous measurement's collapse pass
+            s0 = carry0;
+            s1 = carry1;
+          } else {
+            reduce2<G, R, U>(grp, vec, half, [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = i0 | bs; },
+                             [&](cpx<R> a, cpx<R> b, double& x0, double& x1) { branch_sums(isx, a, b, x0, x1); }, s0,
+                             s1);
+            s0 = grp.sum(s0, red);
+            s1 = grp.sum(s1, red);
+          }
           if (isx) { s0 *= 0.5; s1 *= 0.5; }
           double tot = s0 + s1;
           uint32_t bm1 = 1u ^ sign ^ p;  // virtual branch of m = 1
@@ -666,16 +677,88 @@ struct Shot {
             if (isx) return cpx<R>{fs * scale * (a.re + sgn * c.re), fs * scale * (a.im + sgn * c.im)};
             return b ? cpx<R>{scale * c.re, scale * c.im} : cpx<R>{scale * a.re, scale * a.im};
           };
-          if (s == top) {
+          const bool fuse = (in.flags & F_FUSE_NEXT) && k >= 2;
+          const bool nx = in.flags & F_NEXT_X;
+          const uint32_t s2 = in.u, b2 = 1u << s2;  // next measurement's axis after this demotion
+          const uint32_t st = G == 1 ? 1u : (uint32_t)G;
+          const uint32_t tb = 1u << top;
+          double n0 = 0, n1 = 0;
+          if (fuse && s == top) {
+            // outputs o < half read in[o], in[o | tb]; each iteration writes
+            // the pair (o, o | b2) of the next axis and sums it
+            constexpr int UP = U >= 4 ? U / 4 : 1;
+            const uint32_t n2 = half >> 1;
+            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n2; base += UP * st) {
+              uint32_t oo[UP];
+              cpx<R> x0[UP], x1[UP], y0[UP], y1[UP];
+#pragma unroll
+              for (int u = 0; u < UP; u++) {
+                const uint32_t q = base + u * st;
+                oo[u] = ins0(q < n2 ? q : base, s2);
+                if (q < n2) {
+                  x0[u] = vec[oo[u]];
+                  x1[u] = vec[oo[u] | tb];
+                  y0[u] = vec[oo[u] | b2];
+                  y1[u] = vec[oo[u] | b2 | tb];
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < UP; u++)
+                if (base + u * st < n2) {
+                  const cpx<R> lo = out1(x0[u], x1[u]), hi = out1(y0[u], y1[u]);
+                  vec[oo[u]] = lo;
+                  vec[oo[u] | b2] = hi;
+                  branch_sums(nx, lo, hi, n0, n1);
+                }
+            }
+          } else if (fuse && s2 != s) {
+            // four outputs {o, o|bs, o|b2, o|bs|b2} from eight inputs (new
+            // bit s of an output is the former top bit of its inputs); the
+            // next axis pairs (o, o|b2) and (o|bs, o|bs|b2)
+            constexpr int UQ = 1;
+            const uint32_t n4 = half >> 2;
+            const int lo_b = min((int)s, (int)s2), hi_b = max((int)s, (int)s2);
+            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += UQ * st) {
+              uint32_t oo[UQ];
+              cpx<R> in8[UQ][8];
+#pragma unroll
+              for (int u = 0; u < UQ; u++) {
+                const uint32_t q = base + u * st;
+                oo[u] = ins0(ins0(q < n4 ? q : base, lo_b), hi_b);
+                if (q < n4) {
+                  const uint32_t o = oo[u];
+                  in8[u][0] = vec[o];
+                  in8[u][1] = vec[o | bs];
+                  in8[u][2] = vec[o | tb];
+                  in8[u][3] = vec[o | tb | bs];
+                  in8[u][4] = vec[o | b2];
+                  in8[u][5] = vec[o | b2 | bs];
+                  in8[u][6] = vec[o | b2 | tb];
+                  in8[u][7] = vec[o | b2 | tb | bs];
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < UQ; u++)
+                if (base + u * st < n4) {
+                  const uint32_t o = oo[u];
+                  const cpx<R> r0 = out1(in8[u][0], in8[u][1]), r1 = out1(in8[u][2], in8[u][3]);
+                  const cpx<R> r2 = out1(in8[u][4], in8[u][5]), r3 = out1(in8[u][6], in8[u][7]);
+                  vec[o] = r0;
+                  vec[o | bs] = r1;
+                  vec[o | b2] = r2;
+                  vec[o | bs | b2] = r3;
+                  branch_sums(nx, r0, r2, n0, n1);
+                  branch_sums(nx, r1, r3, n0, n1);
+                }
+            }
+          } else if (s == top) {
             pass21<G, R, U>(grp, vec, half,
                          [&](uint32_t q, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = w = q; r1 = q | bs; },
                          [&](cpx<R> a, cpx<R> c) { return out1(a, c); });
           } else {
             // pair (j0, j1 = j0 | bs) of outputs reads its own two elements and
             // the two above them in the top slot
-            const uint32_t tb = 1u << top;
             const uint32_t n4 = half >> 1;
-            const uint32_t st = G == 1 ? 1u : (uint32_t)G;
             for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += U * st) {
               uint32_t jj[U];
               cpx<R> a0[U], a1[U], c0[U], c1[U];
@@ -693,10 +776,17 @@ struct Shot {
 #pragma unroll
               for (int u = 0; u < U; u++)
                 if (base + u * st < n4) {
-                  vec[jj[u]] = out1(a0[u], a1[u]);
-                  vec[jj[u] | bs] = out1(c0[u], c1[u]);
+                  const cpx<R> lo = out1(a0[u], a1[u]), hi = out1(c0[u], c1[u]);
+                  vec[jj[u]] = lo;
+                  vec[jj[u] | bs] = hi;
+                  // next axis == s: the two outputs are its pair
+                  if (fuse) branch_sums(nx, lo, hi, n0, n1);
                 }
             }
+          }
+          if (fuse) {
+            carry0 = grp.sum(n0, red);
+            carry1 = grp.sum(n1, red);
           }
           k--;
           grp.sync();

@@ -32,8 +32,8 @@ enum Op : uint8_t {
   OP_MSTATIC,  // deterministic Z-string measurement                 a=mask(z, W words), b=event
   OP_MRANDOM,  // dormant X_v measurement, then H_v absorbed         v, b=event, u=index among the
                //   dormant random events of the event's 128-block
-  OP_MACTZ,    // active Z_v measurement (mask), demote slot s       v, s, b=event
-  OP_MACTX,    // active X_v measurement (interfere), demote slot s  v, s, b=event
+  OP_MACTZ,    // active Z_v measurement (mask), demote slot s       v, s, b=event (u, flags: fusion)
+  OP_MACTX,    // active X_v measurement (interfere), demote slot s  v, s, b=event (u, flags: fusion)
   OP_CPAULI,   // reset correction X^m (noise part X^pn)             a=mask(x,z), b=event
   OP_NOISE,    // noise sites [a, b)
   OP_DET,      // detector b = XOR of records refs[a .. a+u); s = its accumulator row
@@ -42,7 +42,15 @@ enum Op : uint8_t {
 };
 
 // flags
-constexpr uint8_t F_SIGN = 1;   // sign bit of the localized observable
+constexpr uint8_t F_SIGN = 1;        // sign bit of the localized observable
+// Active measurements: the next instruction that touches the active vector
+// is also an active measurement.  Its branch sums are accumulated by this
+// measurement's collapse pass (F_FUSE_NEXT, with u = its slot after this
+// demotion and F_NEXT_X for an X-type one), and it skips its own reduction
+// pass (F_SUMS_READY).
+constexpr uint8_t F_FUSE_NEXT = 2;
+constexpr uint8_t F_NEXT_X = 4;
+constexpr uint8_t F_SUMS_READY = 8;
 
 struct GInstr {
   uint8_t op;
