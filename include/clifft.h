@@ -156,7 +156,9 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
 clifft_status clifft_specialize(clifft_program* p, char* log, size_t cap);
 
 /* Bytes of caller-provided device workspace a sample call needs with this
- * configuration (0 when the active vectors fit in LDS). */
+ * configuration (0 when the active vectors fit in LDS).  Vectors in HBM take
+ * two buffers of 2^k_max amplitudes per shot in flight: active measurements
+ * collapse from one into the other. */
 clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes);
 
 /* Sample `shots` shots with global indices shot_offset .. shot_offset+shots-1

@@ -791,26 +791,37 @@ int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& 
     }
     if (P.rblk_ev.empty()) P.rblk_ev.push_back(0);
   }
-  // Look-ahead fusion of active measurements: when the next instruction that
-  // touches the active vector is again an active measurement, the first
-  // one's collapse pass computes the second's branch sums.
+  // Fusion marks for the active-vector passes (see program.h): the
+  // localization passes of an active measurement that can be read through,
+  // and measurements whose successor's branch sums their collapse computes.
   {
     auto touches_vector = [](uint8_t op) {
       return (op >= OP_APERM && op <= OP_AROT) || op == OP_MACTZ || op == OP_MACTX;
     };
-    for (size_t i = 0; i < P.code.size(); i++) {
-      GInstr& in = P.code[i];
-      if (in.op != OP_MACTZ && in.op != OP_MACTX) continue;
-      for (size_t j = i + 1; j < P.code.size(); j++) {
-        if (!touches_vector(P.code[j].op)) continue;
-        GInstr& nx = P.code[j];
-        if (nx.op == OP_MACTZ || nx.op == OP_MACTX) {
-          in.flags |= F_FUSE_NEXT | (nx.op == OP_MACTX ? F_NEXT_X : 0);
-          in.u = nx.s;
-          nx.flags |= F_SUMS_READY;
+    auto is_meas = [](uint8_t op) { return op == OP_MACTZ || op == OP_MACTX; };
+    std::vector<size_t> vecops;
+    for (size_t i = 0; i < P.code.size(); i++)
+      if (touches_vector(P.code[i].op)) vecops.push_back(i);
+    for (size_t n = 0; n < vecops.size(); n++) {
+      const GInstr& m = P.code[vecops[n]];
+      if (!is_meas(m.op)) continue;
+      size_t j = n;
+      const uint8_t order[3] = {OP_AS, OP_ASIGN, OP_APERM};  // backwards from the measurement
+      for (uint8_t want : order) {
+        if (j == 0) break;
+        GInstr& g = P.code[vecops[j - 1]];
+        if (g.op == want && g.s == m.s) {
+          g.flags |= F_FOLD_NEXT;
+          j--;
         }
-        break;
       }
+    }
+    for (size_t n = 0; n < vecops.size(); n++) {
+      GInstr& in = P.code[vecops[n]];
+      if (!is_meas(in.op)) continue;
+      size_t j = n + 1;
+      while (j < vecops.size() && (P.code[vecops[j]].flags & F_FOLD_NEXT)) j++;
+      if (j < vecops.size() && is_meas(P.code[vecops[j]].op)) in.flags |= F_FUSE_NEXT;
     }
   }
   survival_tables(P);

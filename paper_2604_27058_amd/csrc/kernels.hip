@@ -280,7 +280,8 @@ DEV void pass21(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx,
   }
 }
 
-// Read-only pairs accumulated into two FP64 sums.
+// Read-only pairs accumulated into two FP64 sums (the body also gets the
+// iteration index).
 template <int G, typename R, int U, typename IdxF, typename BodyF>
 DEV void reduce2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body, double& s0,
                  double& s1) {
@@ -296,7 +297,27 @@ DEV void reduce2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx
     }
 #pragma unroll
     for (int u = 0; u < U; u++)
-      if (base + u * st < n) body(a[u], b[u], s0, s1);
+      if (base + u * st < n) body(a[u], b[u], base + u * st, s0, s1);
+  }
+}
+
+// Gather pass into another buffer: dst[p] = gen(p) for p in [0, n) (gen
+// reads the source); all U values of a batch are formed before the stores.
+template <int G, typename R, int U, typename GenF>
+DEV void pass1_to(const Group<G>& grp, const Vec<G, R>& dst, uint32_t n, GenF gen) {
+  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
+  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
+    cpx<R> v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t p = base + u * st;
+      if (p < n) v[u] = gen(p);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t p = base + u * st;
+      if (p < n) dst[p] = v[u];
+    }
   }
 }
 
@@ -366,7 +387,10 @@ DEV void apply_fault(const DevProgram& P, Frame<W>& T, Frame<W>& N, uint32_t sit
 }
 
 // ------------------------------------------------------------------ one shot
-template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll>
+// OOP: active vectors in HBM with a second buffer of the same size; active
+// measurements collapse out of place (alternating buffers) and read through
+// their folded localization passes.
+template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OOP = false>
 struct Shot {
   const DevProgram& P;
   const KArgs& A;
@@ -377,6 +401,25 @@ struct Shot {
   int slane;      // shot index inside the 64-shot tile
   uint64_t shot;  // global shot index (G == 1: per lane)
   uint64_t local; // shot index relative to the call (debug buffers)
+  cpx<R>* alt = nullptr;  // OOP: the other buffer
+
+  // The next active measurement after instruction pc (whose collapse fuses
+  // it): its slot and type and the localization passes folded into it.
+  MDEV void peek_next_measurement(int pc, uint32_t& s2, bool& x2, uint32_t& tm2, uint32_t& sm2, bool& as2) const {
+    tm2 = sm2 = 0;
+    as2 = false;
+    for (int q = pc + 1;; q++) {
+      const GInstr g = load_instr(P.code, q);
+      if (g.op == OP_APERM) tm2 = g.a;
+      else if (g.op == OP_ASIGN) sm2 = g.a;
+      else if (g.op == OP_AS) as2 = true;
+      else if (g.op == OP_MACTZ || g.op == OP_MACTX || g.op == OP_END) {
+        s2 = g.s;
+        x2 = g.op == OP_MACTX;
+        return;
+      }
+    }
+  }
 
   MDEV bool writer() const { return (G == 1 || grp.tid == 0) && local < A.shots; }
 
@@ -411,6 +454,9 @@ struct Shot {
     uint32_t rb_blk = 0xFFFFFFFFu;
     U4 rb{0, 0, 0, 0};
     double carry0 = 0, carry1 = 0;  // branch sums of the next active measurement (fused)
+    bool carry_valid = false;
+    uint32_t pend_tm = 0, pend_sm = 0;  // folded localization passes of the next measurement
+    bool pend_as = false;
     Noise ns{0, 0, 0xFFFFFFFFu, 0};
     if (P.nsites > 0) {
       if (DBG && A.forced_faults) ns.nf = 0xFFFFFFFFu;
@@ -457,6 +503,11 @@ struct Shot {
         case OP_APERM: {
           if constexpr (!VEC) break;
           else {
+          if (OOP && (in.flags & F_FOLD_NEXT)) {  // read through by the next measurement
+            pend_tm = in.a;
+            break;
+          }
+          carry_valid = false;
           // control slot s, targets tm: i -> i ^ tm for i with bit s set; each
           // pair is visited once from the member with target bit t0 clear
           const uint32_t tm = in.a, bs = 1u << s;
@@ -472,6 +523,11 @@ struct Shot {
         case OP_ASIGN: {
           if constexpr (!VEC) break;
           else {
+          if (OOP && (in.flags & F_FOLD_NEXT)) {
+            pend_sm = in.a;
+            break;
+          }
+          carry_valid = false;
           // -1 on i with bit s set and odd parity of i & sm: enumerate i with
           // bits s and c (lowest of sm) free, then fix bit c to make it odd
           const uint32_t sm = in.a, bs = 1u << s;
@@ -490,6 +546,7 @@ struct Shot {
         case OP_APERM2: {
           if constexpr (!VEC) break;
           else {
+          carry_valid = false;
           // flip bit s where parity(i & sm) is odd: pairs along s with odd parity
           const uint32_t sm = in.a, bs = 1u << s;
           const int c = __ffs(sm) - 1;
@@ -508,6 +565,11 @@ struct Shot {
         case OP_AS: {
           if constexpr (!VEC) break;
           else {
+          if (OOP && (in.flags & F_FOLD_NEXT)) {
+            pend_as = true;
+            break;
+          }
+          carry_valid = false;
           const uint32_t bs = 1u << s;
           pass1<G, R, U>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
                       [](cpx<R> a) { return cpx<R>{-a.im, a.re}; });
@@ -518,6 +580,7 @@ struct Shot {
         case OP_AH: {
           if constexpr (!VEC) break;
           else {
+          carry_valid = false;
           const R h = (R)0.70710678118654752440;
           const uint32_t bs = 1u << s;
           pass2<G, R, U>(grp, vec, 1u << (k - 1),
@@ -534,6 +597,7 @@ struct Shot {
         case OP_EXPAND: {
           if constexpr (!VEC) break;
           else {
+          carry_valid = false;
           // Appendix B.1 case 2: H_v takes |0>_v to |+>_v (frames conjugated);
           // then exp(-i theta' Z_v) on the new axis, theta' sign-flipped by
           // x_v of the frame.  The common phase e^{-i theta'} is global, so
@@ -554,6 +618,7 @@ struct Shot {
         case OP_AROT: {
           if constexpr (!VEC) break;
           else {
+          carry_valid = false;
           double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
           if (getbit<W>(T.x, v)) s2 = -s2;
           const R cr = (R)c2, ci = (R)s2;
@@ -630,15 +695,26 @@ struct Shot {
               x1 += norm2(b);
             }
           };
+          // the partner (measured bit set) of a pair, read through the folded
+          // localization passes: element (i1 ^ tm) times the phase at i1
+          const uint32_t tm = pend_tm, sm = pend_sm;
+          const bool fas = pend_as;
+          auto partner = [&](cpx<R> x, uint32_t i1) {
+            cpx<R> y = (__popc(i1 & sm) & 1) ? cpx<R>{-x.re, -x.im} : x;
+            return fas ? cpx<R>{-y.im, y.re} : y;
+          };
           double s0 = 0, s1 = 0;
-          if (in.flags & F_SUMS_READY) {
+          if (carry_valid) {
             // accumulated by the previous measurement's collapse pass
             s0 = carry0;
             s1 = carry1;
           } else {
-            reduce2<G, R, U>(grp, vec, half, [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = i0 | bs; },
-                             [&](cpx<R> a, cpx<R> b, double& x0, double& x1) { branch_sums(isx, a, b, x0, x1); }, s0,
-                             s1);
+            reduce2<G, R, U>(grp, vec, half,
+                             [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = (i0 | bs) ^ tm; },
+                             [&](cpx<R> a, cpx<R> c, uint32_t q, double& x0, double& x1) {
+                               branch_sums(isx, a, partner(c, ins0(q, s) | bs), x0, x1);
+                             },
+                             s0, s1);
             s0 = grp.sum(s0, red);
             s1 = grp.sum(s1, red);
           }
@@ -669,122 +745,159 @@ struct Shot {
           const R scale = (R)(1.0 / sqrt(sb));
           const R fs = isx ? (R)0.70710678118654752440 : (R)1;
           const R sgn = b ? (R)-1 : (R)1;
-          // collapse: the kept half (or fold) is written in place; the top
-          // slot k-1 takes the place of slot s (no hazard: every thread
-          // owns its two outputs and reads only them and the top half)
           const int top = k - 1;
+          const uint32_t tb = 1u << top;
           auto out1 = [&](cpx<R> a, cpx<R> c) -> cpx<R> {
             if (isx) return cpx<R>{fs * scale * (a.re + sgn * c.re), fs * scale * (a.im + sgn * c.im)};
             return b ? cpx<R>{scale * c.re, scale * c.im} : cpx<R>{scale * a.re, scale * a.im};
           };
+          // the next measurement (after this demotion), when fused: its slot,
+          // type and folded localization passes
           const bool fuse = (in.flags & F_FUSE_NEXT) && k >= 2;
-          const bool nx = in.flags & F_NEXT_X;
-          const uint32_t s2 = in.u, b2 = 1u << s2;  // next measurement's axis after this demotion
+          uint32_t s2 = 0, tm2 = 0, sm2 = 0;
+          bool nx = false, as2 = false;
+          if (fuse) peek_next_measurement(pc, s2, nx, tm2, sm2, as2);
+          const uint32_t b2 = 1u << s2;
+          auto partner2 = [&](cpx<R> x, uint32_t i1) {
+            cpx<R> y = (__popc(i1 & sm2) & 1) ? cpx<R>{-x.re, -x.im} : x;
+            return as2 ? cpx<R>{-y.im, y.re} : y;
+          };
           const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-          const uint32_t tb = 1u << top;
           double n0 = 0, n1 = 0;
-          if (fuse && s == top) {
-            // outputs o < half read in[o], in[o | tb]; each iteration writes
-            // the pair (o, o | b2) of the next axis and sums it
-            constexpr int UP = U >= 4 ? U / 4 : 1;
-            const uint32_t n2 = half >> 1;
-            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n2; base += UP * st) {
-              uint32_t oo[UP];
-              cpx<R> x0[UP], x1[UP], y0[UP], y1[UP];
+          bool fused_sums = false;
+          if constexpr (OOP) {
+            // out of place into the other buffer: output o (new slot s holds
+            // the former top bit) reads its pair through the folded passes
+            const Vec<G, R> dst{alt, vec.lane};
+            auto one = [&](uint32_t o) {
+              const uint32_t base = s == top ? o : ((o & ~bs) | (((o >> s) & 1u) << top));
+              const uint32_t i1 = base | bs;
+              return out1(vec[base], partner(vec[i1 ^ tm], i1));
+            };
+            if (fuse) {
+              // outputs (j0, j1): the next measurement's pair through its own
+              // folded passes, summed as it is written
+              constexpr int UP = U >= 2 ? U / 2 : 1;
+              const uint32_t n2 = half >> 1;
+              for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n2; base += UP * st) {
+                uint32_t j0[UP];
+                cpx<R> y0[UP], y1[UP];
 #pragma unroll
-              for (int u = 0; u < UP; u++) {
-                const uint32_t q = base + u * st;
-                oo[u] = ins0(q < n2 ? q : base, s2);
-                if (q < n2) {
-                  x0[u] = vec[oo[u]];
-                  x1[u] = vec[oo[u] | tb];
-                  y0[u] = vec[oo[u] | b2];
-                  y1[u] = vec[oo[u] | b2 | tb];
+                for (int u = 0; u < UP; u++) {
+                  const uint32_t q = base + u * st;
+                  j0[u] = ins0(q < n2 ? q : base, s2);
+                  if (q < n2) {
+                    y0[u] = one(j0[u]);
+                    y1[u] = one((j0[u] | b2) ^ tm2);
+                  }
                 }
+#pragma unroll
+                for (int u = 0; u < UP; u++)
+                  if (base + u * st < n2) {
+                    dst[j0[u]] = y0[u];
+                    dst[(j0[u] | b2) ^ tm2] = y1[u];
+                    branch_sums(nx, y0[u], partner2(y1[u], j0[u] | b2), n0, n1);
+                  }
               }
-#pragma unroll
-              for (int u = 0; u < UP; u++)
-                if (base + u * st < n2) {
-                  const cpx<R> lo = out1(x0[u], x1[u]), hi = out1(y0[u], y1[u]);
-                  vec[oo[u]] = lo;
-                  vec[oo[u] | b2] = hi;
-                  branch_sums(nx, lo, hi, n0, n1);
-                }
+              fused_sums = true;
+            } else {
+              pass1_to<G, R, U>(grp, dst, half, one);
             }
-          } else if (fuse && s2 != s) {
-            // four outputs {o, o|bs, o|b2, o|bs|b2} from eight inputs (new
-            // bit s of an output is the former top bit of its inputs); the
-            // next axis pairs (o, o|b2) and (o|bs, o|bs|b2)
-            constexpr int UQ = 1;
-            const uint32_t n4 = half >> 2;
-            const int lo_b = min((int)s, (int)s2), hi_b = max((int)s, (int)s2);
-            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += UQ * st) {
-              uint32_t oo[UQ];
-              cpx<R> in8[UQ][8];
-#pragma unroll
-              for (int u = 0; u < UQ; u++) {
-                const uint32_t q = base + u * st;
-                oo[u] = ins0(ins0(q < n4 ? q : base, lo_b), hi_b);
-                if (q < n4) {
-                  const uint32_t o = oo[u];
-                  in8[u][0] = vec[o];
-                  in8[u][1] = vec[o | bs];
-                  in8[u][2] = vec[o | tb];
-                  in8[u][3] = vec[o | tb | bs];
-                  in8[u][4] = vec[o | b2];
-                  in8[u][5] = vec[o | b2 | bs];
-                  in8[u][6] = vec[o | b2 | tb];
-                  in8[u][7] = vec[o | b2 | tb | bs];
-                }
-              }
-#pragma unroll
-              for (int u = 0; u < UQ; u++)
-                if (base + u * st < n4) {
-                  const uint32_t o = oo[u];
-                  const cpx<R> r0 = out1(in8[u][0], in8[u][1]), r1 = out1(in8[u][2], in8[u][3]);
-                  const cpx<R> r2 = out1(in8[u][4], in8[u][5]), r3 = out1(in8[u][6], in8[u][7]);
-                  vec[o] = r0;
-                  vec[o | bs] = r1;
-                  vec[o | b2] = r2;
-                  vec[o | bs | b2] = r3;
-                  branch_sums(nx, r0, r2, n0, n1);
-                  branch_sums(nx, r1, r3, n0, n1);
-                }
-            }
-          } else if (s == top) {
-            pass21<G, R, U>(grp, vec, half,
-                         [&](uint32_t q, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = w = q; r1 = q | bs; },
-                         [&](cpx<R> a, cpx<R> c) { return out1(a, c); });
+            cpx<R>* t = vec.base;
+            vec.base = alt;
+            alt = t;
           } else {
-            // pair (j0, j1 = j0 | bs) of outputs reads its own two elements and
-            // the two above them in the top slot
-            const uint32_t n4 = half >> 1;
-            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += U * st) {
-              uint32_t jj[U];
-              cpx<R> a0[U], a1[U], c0[U], c1[U];
+            // in place (on-chip vectors; folded passes are never skipped here,
+            // so only a directly following measurement is fused): the kept
+            // half (or fold) is written in place; the top slot k-1 takes the
+            // place of slot s (no hazard: every thread owns its outputs and
+            // reads only them and the elements above them)
+            const bool fuse_here = fuse && tm2 == 0 && sm2 == 0 && !as2;
+            if (fuse_here && s == top) {
+              constexpr int UP = U >= 4 ? U / 4 : 1;
+              const uint32_t n2 = half >> 1;
+              for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n2; base += UP * st) {
+                uint32_t oo[UP];
+                cpx<R> x0[UP], x1[UP], y0[UP], y1[UP];
 #pragma unroll
-              for (int u = 0; u < U; u++) {
-                uint32_t q = base + u * st;
-                jj[u] = ins0(q < n4 ? q : base, s);
-                if (q < n4) {
-                  a0[u] = vec[jj[u]];
-                  a1[u] = vec[jj[u] | bs];
-                  c0[u] = vec[jj[u] | tb];
-                  c1[u] = vec[jj[u] | bs | tb];
+                for (int u = 0; u < UP; u++) {
+                  const uint32_t q = base + u * st;
+                  oo[u] = ins0(q < n2 ? q : base, s2);
+                  if (q < n2) {
+                    x0[u] = vec[oo[u]];
+                    x1[u] = vec[oo[u] | tb];
+                    y0[u] = vec[oo[u] | b2];
+                    y1[u] = vec[oo[u] | b2 | tb];
+                  }
                 }
+#pragma unroll
+                for (int u = 0; u < UP; u++)
+                  if (base + u * st < n2) {
+                    const cpx<R> lo = out1(x0[u], x1[u]), hi = out1(y0[u], y1[u]);
+                    vec[oo[u]] = lo;
+                    vec[oo[u] | b2] = hi;
+                    branch_sums(nx, lo, hi, n0, n1);
+                  }
               }
+              fused_sums = true;
+            } else if (fuse_here && s2 != s) {
+              // four outputs {o, o|bs, o|b2, o|bs|b2} from eight inputs (new
+              // bit s of an output is the former top bit of its inputs); the
+              // next axis pairs (o, o|b2) and (o|bs, o|bs|b2)
+              const uint32_t n4 = half >> 2;
+              const int lo_b = min((int)s, (int)s2), hi_b = max((int)s, (int)s2);
+              for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += st) {
+                const uint32_t o = ins0(ins0(base, lo_b), hi_b);
+                const cpx<R> i0 = vec[o], i1 = vec[o | bs], i2 = vec[o | tb], i3 = vec[o | tb | bs];
+                const cpx<R> i4 = vec[o | b2], i5 = vec[o | b2 | bs], i6 = vec[o | b2 | tb], i7 = vec[o | b2 | tb | bs];
+                const cpx<R> r0 = out1(i0, i1), r1 = out1(i2, i3), r2 = out1(i4, i5), r3 = out1(i6, i7);
+                vec[o] = r0;
+                vec[o | bs] = r1;
+                vec[o | b2] = r2;
+                vec[o | bs | b2] = r3;
+                branch_sums(nx, r0, r2, n0, n1);
+                branch_sums(nx, r1, r3, n0, n1);
+              }
+              fused_sums = true;
+            } else if (s == top) {
+              pass21<G, R, U>(grp, vec, half,
+                              [&](uint32_t q, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = w = q; r1 = q | bs; },
+                              [&](cpx<R> a, cpx<R> c) { return out1(a, c); });
+            } else {
+              // pair (j0, j1 = j0 | bs) of outputs reads its own two elements
+              // and the two above them in the top slot
+              const uint32_t n4 = half >> 1;
+              for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += U * st) {
+                uint32_t jj[U];
+                cpx<R> a0[U], a1[U], c0[U], c1[U];
 #pragma unroll
-              for (int u = 0; u < U; u++)
-                if (base + u * st < n4) {
-                  const cpx<R> lo = out1(a0[u], a1[u]), hi = out1(c0[u], c1[u]);
-                  vec[jj[u]] = lo;
-                  vec[jj[u] | bs] = hi;
-                  // next axis == s: the two outputs are its pair
-                  if (fuse) branch_sums(nx, lo, hi, n0, n1);
+                for (int u = 0; u < U; u++) {
+                  uint32_t q = base + u * st;
+                  jj[u] = ins0(q < n4 ? q : base, s);
+                  if (q < n4) {
+                    a0[u] = vec[jj[u]];
+                    a1[u] = vec[jj[u] | bs];
+                    c0[u] = vec[jj[u] | tb];
+                    c1[u] = vec[jj[u] | bs | tb];
+                  }
                 }
+#pragma unroll
+                for (int u = 0; u < U; u++)
+                  if (base + u * st < n4) {
+                    const cpx<R> lo = out1(a0[u], a1[u]), hi = out1(c0[u], c1[u]);
+                    vec[jj[u]] = lo;
+                    vec[jj[u] | bs] = hi;
+                    // next axis == s: the two outputs are its pair
+                    if (fuse_here) branch_sums(nx, lo, hi, n0, n1);
+                  }
+              }
+              fused_sums = fuse_here;
             }
           }
-          if (fuse) {
+          pend_tm = pend_sm = 0;
+          pend_as = false;
+          carry_valid = fused_sums;
+          if (fused_sums) {
             carry0 = grp.sum(n0, red);
             carry1 = grp.sum(n1, red);
           }
@@ -902,8 +1015,12 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
   cpx<R>* arr_lds = (cpx<R>*)(after_rec + 64);
   const size_t vec_elems = (size_t)1 << P.kmax;
   cpx<R>* base;
+  cpx<R>* alt = nullptr;
   if constexpr (GLOBAL) {
-    base = (cpx<R>*)A.workspace + unit * vec_elems * (G == 1 ? 64 : 1);
+    // two buffers per unit (active measurements collapse from one into the other)
+    const size_t per = vec_elems * (G == 1 ? 64 : 1);
+    base = (cpx<R>*)A.workspace + unit * per * 2;
+    alt = base + per;
   } else {
     base = arr_lds + (size_t)unit_in_block * vec_elems * (G == 1 ? 64 : 1);
   }
@@ -919,7 +1036,8 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
       for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 256) rec[r] = 0;
       __syncthreads();
       uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>()> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0, A.offset + g, g};
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0,
+                                                                  A.offset + g, g, alt};
       sh.run();
       __syncthreads();
       const uint64_t bit = 1ull << (g & 63);
@@ -941,14 +1059,15 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if constexpr (G == 1) {
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>()> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
-                            A.offset + tile * 64 + lane, tile * 64 + lane};
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
+                                                                  A.offset + tile * 64 + lane, tile * 64 + lane, alt};
       sh.run();
     } else {
       uint32_t nsh = (uint32_t)min((uint64_t)64, A.shots - tile * 64);
       for (uint32_t sl = 0; sl < nsh; sl++) {
         uint64_t g = rfl((uint32_t)(tile * 64 + sl)) | ((tile * 64 + sl) & 0xFFFFFFFF00000000ull);
-        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>()> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, (int)sl, A.offset + g, g};
+        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red,
+                                                                    (int)sl, A.offset + g, g, alt};
         sh.run();
       }
     }
@@ -1475,14 +1594,15 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
       for (uint32_t r = (uint32_t)lane; r < nwords_rec; r += 64) wrec[r] = 0;
       __builtin_amdgcn_wave_barrier();
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      cpx<R>* base = (cpx<R>*)slot + (size_t)wv * 64 * ((size_t)1 << P.kmax);
+      const size_t per = 64 * ((size_t)1 << P.kmax);  // each wave: two buffers
+      cpx<R>* base = (cpx<R>*)slot + (size_t)wv * 2 * per;
       if (P.kmax == 0) {
         Shot<W, 1, R, false, false> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
                                        A.offset + tile * 64 + lane, tile * 64 + lane};
         sh.run();
       } else {
-        Shot<W, 1, R, false, true> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
-                                      A.offset + tile * 64 + lane, tile * 64 + lane};
+        Shot<W, 1, R, false, true, kUnroll, true> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
+                                                      A.offset + tile * 64 + lane, tile * 64 + lane, base + per};
         sh.run();
       }
       __builtin_amdgcn_wave_barrier();
@@ -1504,8 +1624,9 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
     const uint64_t g = rfl((uint32_t)it.first) | (it.first & 0xFFFFFFFF00000000ull);
     for (uint32_t r = threadIdx.x; r < nwords_rec; r += 256) rec[r] = 0;
     __syncthreads();
-    Shot<W, 256, R, false, true, unroll_for<R, true>()> sh{P, A, Group<256>{(int)threadIdx.x}, Vec<256, R>{(cpx<R>*)slot, lane}, rec, red,
-                                    0, A.offset + g, g};
+    Shot<W, 256, R, false, true, unroll_for<R, true>(), true> sh{P, A, Group<256>{(int)threadIdx.x},
+                                                              Vec<256, R>{(cpx<R>*)slot, lane}, rec, red, 0, A.offset + g,
+                                                              g, (cpx<R>*)slot + ((size_t)1 << P.kmax)};
     sh.run();
     __syncthreads();
     const uint64_t bit = 1ull << (g & 63);

@@ -43,14 +43,17 @@ enum Op : uint8_t {
 
 // flags
 constexpr uint8_t F_SIGN = 1;        // sign bit of the localized observable
-// Active measurements: the next instruction that touches the active vector
-// is also an active measurement.  Its branch sums are accumulated by this
-// measurement's collapse pass (F_FUSE_NEXT, with u = its slot after this
-// demotion and F_NEXT_X for an X-type one), and it skips its own reduction
-// pass (F_SUMS_READY).
+// Localization passes of an active measurement (Appendix A with an active
+// pivot): an OP_APERM, then an OP_ASIGN, then an OP_AS, each optional, on
+// the measured slot and directly before the measurement among the vector
+// instructions.  They permute and rephase only the elements whose measured
+// bit is set, so kernels that collapse out of place skip them
+// (F_FOLD_NEXT) and read the measurement through them.
+constexpr uint8_t F_FOLD_NEXT = 8;
+// Active measurement whose next vector instruction, after folded passes, is
+// again an active measurement: this measurement's collapse pass accumulates
+// that one's branch sums (F_FUSE_NEXT), and it skips its own reduction.
 constexpr uint8_t F_FUSE_NEXT = 2;
-constexpr uint8_t F_NEXT_X = 4;
-constexpr uint8_t F_SUMS_READY = 8;
 
 struct GInstr {
   uint8_t op;

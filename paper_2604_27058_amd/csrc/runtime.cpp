@@ -281,7 +281,7 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
   int grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
   if (global_vec && c.grid <= 0) {
     // keep the default workspace within budget
-    size_t per_block = (size_t)(G == 256 ? 1 : 4) * vec * amp * (G == 1 ? 64 : 1);
+    size_t per_block = 2 * (size_t)(G == 256 ? 1 : 4) * vec * amp * (G == 1 ? 64 : 1);
     size_t cap = std::max<size_t>(1, kWorkspaceBudget / per_block);
     if ((size_t)grid > cap) grid = (int)cap;
   }
@@ -297,7 +297,8 @@ size_t workspace_bytes(const CompiledProgram& H, const LaunchShape& L, bool fp64
   if (!L.global_vec) return 0;
   size_t amp = fp64 ? 16 : 8;
   size_t units = (size_t)L.grid * (L.G == 256 ? 1 : 4);
-  return units * ((size_t)1 << H.kmax) * amp * (L.G == 1 ? 64 : 1);
+  // two buffers per unit: active measurements collapse from one into the other
+  return 2 * units * ((size_t)1 << H.kmax) * amp * (L.G == 1 ? 64 : 1);
 }
 
 clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t offset,
@@ -553,8 +554,9 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
     }
     bp.G = G;
     const uint64_t vec = (uint64_t)1 << H.kmax;
-    if (G == 1) b->slot_l = std::max<uint64_t>(b->slot_l, 4 * 64 * vec * amp);
-    else b->slot_g = std::max<uint64_t>(b->slot_g, vec * amp);
+    // two buffers per shot vector (out-of-place collapses)
+    if (G == 1) b->slot_l = std::max<uint64_t>(b->slot_l, 2 * 4 * 64 * vec * amp);
+    else b->slot_g = std::max<uint64_t>(b->slot_g, 2 * vec * amp);
     b->rec_words = std::max<uint32_t>(b->rec_words, (uint32_t)(H.nrec + H.ndet + H.nobs));
     b->progs.push_back(progs[i]);
     b->table.push_back(bp);

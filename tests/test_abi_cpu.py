@@ -86,7 +86,7 @@ def test_status_codes():
 def test_workspace_size_host_only():
     p = pk.Program(circuits.workload("large_active_k20")["texts"][0])
     n = p.workspace_size(pk.make_launch("f32", threads_per_shot=256, grid=4))
-    assert n == 4 * (1 << 20) * 8
+    assert n == 2 * 4 * (1 << 20) * 8  # two 2^20-amplitude buffers per workgroup
     small = pk.Program(circuits.workload("surface_d3_r3")["texts"][0])
     assert small.workspace_size() == 0
 
