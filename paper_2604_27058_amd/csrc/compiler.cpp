@@ -602,6 +602,30 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
   c.int_ops += 158.0 * P.nchunks;
   c.record_bytes = (P.nrec + P.ndet + P.nobs) / 8.0;
 
+  // Fused passes of the HBM tiers: localization passes folded into the next
+  // measurement move nothing; an active measurement's collapse reads the
+  // vector and writes half of it; its reduction pass is skipped when the
+  // previous measurement's collapse carried its branch sums.
+  {
+    bool carried = false;
+    for (size_t i = 0; i < P.code.size(); i++) {
+      const GInstr& in = P.code[i];
+      const double A = std::ldexp(1.0, (int)(i == 0 ? 0 : P.k_after[i - 1]));
+      switch (in.op) {
+        case OP_APERM: case OP_ASIGN: case OP_AS:
+          if (!(in.flags & F_FOLD_NEXT)) { c.vector_bytes_fused += A * a; carried = false; }
+          break;
+        case OP_APERM2: case OP_AROT: c.vector_bytes_fused += A * a; carried = false; break;
+        case OP_AH: case OP_EXPAND: c.vector_bytes_fused += 2 * A * a; carried = false; break;
+        case OP_MACTZ: case OP_MACTX:
+          c.vector_bytes_fused += (carried ? 0.0 : A * a) + 1.5 * A * a;
+          carried = (in.flags & F_FUSE_NEXT) != 0;
+          break;
+        default: break;
+      }
+    }
+  }
+
   // Bit-sliced form (k_max = 0): a frame word holds one bit of 32 shots, so
   // frame, parity, accumulator and record work is shared by 32 shots, while
   // the per-shot draws (first gap-sampler draw of every chunk, one draw per

@@ -40,6 +40,7 @@ struct CostModel {
   double expected_faults = 0;  // mean realized faults
   double instructions = 0;     // compiled instructions executed
   double int_ops_bitsliced = 0;  // integer lane-operations per shot when 32 shots share each frame word
+  double vector_bytes_fused = 0;  // active-vector bytes of the HBM tiers' fused passes
 };
 CostModel cost_model(const CompiledProgram& P, bool fp64);
 

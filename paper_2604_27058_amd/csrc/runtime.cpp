@@ -458,6 +458,7 @@ clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clif
   out->expected_faults = c.expected_faults;
   out->instructions = c.instructions;
   out->int_ops_bitsliced = c.int_ops_bitsliced;
+  out->vector_bytes_fused = c.vector_bytes_fused;
   return CLIFFT_OK;
 }
 
