@@ -80,11 +80,11 @@ typedef struct clifft_launch {
   int32_t grid;             /* workgroups (256 threads); 0 = fill the device */
   int32_t vector_in_hbm;    /* 0 automatic (HBM only when LDS is too small),
                                1 force the global workspace, -1 force LDS */
-  int32_t specialize;       /* bit-sliced only: 1 a kernel generated for this
+  int32_t specialize;       /* 1 a bit-sliced kernel generated for this
                                program and compiled at run time (see
-                               clifft_specialize), -1 the interpreter, 0
-                               automatic (the interpreter unless the autotuner
-                               chose the specialized kernel) */
+                               clifft_specialize; an error on any other tier),
+                               -1 never, 0 automatic (the interpreter unless
+                               the autotuner chose the specialized kernel) */
 } clifft_launch;
 
 /* Compile circuit text (len bytes, need not be NUL-terminated) into a

@@ -603,23 +603,49 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
   c.record_bytes = (P.nrec + P.ndet + P.nobs) / 8.0;
 
   // Fused passes of the HBM tiers: localization passes folded into the next
-  // measurement move nothing; an active measurement's collapse reads the
-  // vector and writes half of it; its reduction pass is skipped when the
-  // previous measurement's collapse carried its branch sums.
+  // measurement move nothing; up to kDeferMax trailing expansions move
+  // nothing until the next active measurement reads the stored 2^(k-d)
+  // elements (once for its branch sums, once for its collapse, which writes
+  // all 2^(k-1) outputs and carries nothing), an expansion beyond them
+  // applies the oldest one (reads and writes 2^(k-d) elements), and any
+  // other vector instruction first writes the deferred part; a collapse
+  // reads the vector and writes half of it; its reduction pass is skipped
+  // when the previous measurement's collapse carried its branch sums.
   {
     bool carried = false;
+    int dfr = 0;
     for (size_t i = 0; i < P.code.size(); i++) {
       const GInstr& in = P.code[i];
-      const double A = std::ldexp(1.0, (int)(i == 0 ? 0 : P.k_after[i - 1]));
+      const int k = i == 0 ? 0 : P.k_after[i - 1];
+      const double A = std::ldexp(1.0, k);
+      const double stored = std::ldexp(1.0, k - dfr);
+      auto materialize = [&]() {
+        if (dfr) c.vector_bytes_fused += (stored + (A - stored)) * a;
+        dfr = 0;
+      };
       switch (in.op) {
         case OP_APERM: case OP_ASIGN: case OP_AS:
-          if (!(in.flags & F_FOLD_NEXT)) { c.vector_bytes_fused += A * a; carried = false; }
+          if (!(in.flags & F_FOLD_NEXT)) { materialize(); c.vector_bytes_fused += A * a; carried = false; }
           break;
-        case OP_APERM2: case OP_AROT: c.vector_bytes_fused += A * a; carried = false; break;
-        case OP_AH: case OP_EXPAND: c.vector_bytes_fused += 2 * A * a; carried = false; break;
+        case OP_APERM2: case OP_AROT: materialize(); c.vector_bytes_fused += A * a; carried = false; break;
+        case OP_AH: materialize(); c.vector_bytes_fused += 2 * A * a; carried = false; break;
+        case OP_EXPAND:
+          if (dfr == kDeferMax) {
+            c.vector_bytes_fused += 2 * stored * a;
+            dfr--;
+          }
+          dfr++;
+          carried = false;
+          break;
         case OP_MACTZ: case OP_MACTX:
-          c.vector_bytes_fused += (carried ? 0.0 : A * a) + 1.5 * A * a;
-          carried = (in.flags & F_FUSE_NEXT) != 0;
+          if (dfr) {
+            c.vector_bytes_fused += 2 * stored * a + 0.5 * A * a;
+            carried = false;
+          } else {
+            c.vector_bytes_fused += (carried ? 0.0 : A * a) + 1.5 * A * a;
+            carried = (in.flags & F_FUSE_NEXT) != 0;
+          }
+          dfr = 0;
           break;
         default: break;
       }

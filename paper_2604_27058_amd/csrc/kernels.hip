@@ -206,6 +206,11 @@ struct Vec {
   }
 };
 
+template <int N>
+struct IntC {
+  static constexpr int value = N;
+};
+
 // Iterate p over [0, n) split among the threads of a group.
 #define FOR_GROUP(p, n) for (uint32_t p = (G == 1 ? 0u : (uint32_t)grp.tid); p < (n); p += (G == 1 ? 1u : (uint32_t)G))
 
@@ -457,6 +462,55 @@ struct Shot {
     bool carry_valid = false;
     uint32_t pend_tm = 0, pend_sm = 0;  // folded localization passes of the next measurement
     bool pend_as = false;
+    // Out of place: the last dfr expansions are not applied yet; element x
+    // is vec[x mod 2^(k-dfr)] times beta[t] for every set bit t of
+    // x >> (k-dfr) (an expansion multiplies its new upper half by a phase).
+    constexpr int ND = OOP ? kDeferMax : 1;
+    // passes through the factors run one iteration at a time: their reads
+    // mostly hit the cache (each stored element serves up to 2^dfr outputs)
+    // and a deeper unroll would cost the whole kernel occupancy
+    constexpr int UD = 1;
+    int dfr = 0;
+    cpx<R> beta[ND];
+#pragma unroll
+    for (int t = 0; t < ND; t++) beta[t] = cpx<R>{(R)1, (R)0};
+    auto fac = [&](uint32_t c) {
+      cpx<R> f = (c & 1u) ? beta[0] : cpx<R>{(R)1, (R)0};
+#pragma unroll
+      for (int t = 1; t < ND; t++) {
+        const cpx<R> b = ((c >> t) & 1u) ? beta[t] : cpx<R>{(R)1, (R)0};
+        f = cpx<R>{f.re * b.re - f.im * b.im, f.re * b.im + f.im * b.re};
+      }
+      return f;
+    };
+    // writes the deferred part: x = lo | c << (k-dfr) for c != 0, with c the
+    // fastest index so that each stored element is read once per group of c
+    auto materialize = [&]() {
+      if constexpr (OOP) {
+        if (dfr == 0) return;
+        const int m = k - dfr;
+        const uint32_t n = 1u << k, cm = (1u << dfr) - 1u;
+        const uint32_t st = G == 1 ? 1u : (uint32_t)G;
+        for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += UD * st) {
+          cpx<R> y[UD];
+#pragma unroll
+          for (int u = 0; u < UD; u++) {
+            const uint32_t qq = base + u * st;
+            if (qq < n && (qq & cm)) {
+              const cpx<R> a = vec[qq >> dfr], f = fac(qq & cm);
+              y[u] = cpx<R>{a.re * f.re - a.im * f.im, a.re * f.im + a.im * f.re};
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < UD; u++) {
+            const uint32_t qq = base + u * st;
+            if (qq < n && (qq & cm)) vec[(qq >> dfr) | ((qq & cm) << m)] = y[u];
+          }
+        }
+        grp.sync();
+        dfr = 0;
+      }
+    };
     Noise ns{0, 0, 0xFFFFFFFFu, 0};
     if (P.nsites > 0) {
       if (DBG && A.forced_faults) ns.nf = 0xFFFFFFFFu;
@@ -508,6 +562,7 @@ struct Shot {
             break;
           }
           carry_valid = false;
+          materialize();
           // control slot s, targets tm: i -> i ^ tm for i with bit s set; each
           // pair is visited once from the member with target bit t0 clear
           const uint32_t tm = in.a, bs = 1u << s;
@@ -528,6 +583,7 @@ struct Shot {
             break;
           }
           carry_valid = false;
+          materialize();
           // -1 on i with bit s set and odd parity of i & sm: enumerate i with
           // bits s and c (lowest of sm) free, then fix bit c to make it odd
           const uint32_t sm = in.a, bs = 1u << s;
@@ -547,6 +603,7 @@ struct Shot {
           if constexpr (!VEC) break;
           else {
           carry_valid = false;
+          materialize();
           // flip bit s where parity(i & sm) is odd: pairs along s with odd parity
           const uint32_t sm = in.a, bs = 1u << s;
           const int c = __ffs(sm) - 1;
@@ -570,6 +627,7 @@ struct Shot {
             break;
           }
           carry_valid = false;
+          materialize();
           const uint32_t bs = 1u << s;
           pass1<G, R, U>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
                       [](cpx<R> a) { return cpx<R>{-a.im, a.re}; });
@@ -581,6 +639,7 @@ struct Shot {
           if constexpr (!VEC) break;
           else {
           carry_valid = false;
+          materialize();
           const R h = (R)0.70710678118654752440;
           const uint32_t bs = 1u << s;
           pass2<G, R, U>(grp, vec, 1u << (k - 1),
@@ -607,6 +666,26 @@ struct Shot {
           double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
           if (getbit<W>(T.x, v)) s2 = -s2;
           const R cr = (R)c2, ci = (R)s2;
+          if constexpr (OOP) {
+            // deferred: the new top slot's factor; when all are taken, the
+            // oldest (slot k - dfr) is applied first, as an expansion would
+            if (dfr == ND) {
+              const uint32_t n = 1u << (k - dfr);
+              const cpx<R> b0 = beta[0];
+              pass21<G, R, U>(grp, vec, n, [&](uint32_t p, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = r1 = p; w = p | n; },
+                              [b0](cpx<R> a, cpx<R>) { return cmul(a, b0.re, b0.im); });
+              grp.sync();
+#pragma unroll
+              for (int t = 0; t + 1 < ND; t++) beta[t] = beta[t + 1];
+              dfr--;
+            }
+#pragma unroll
+            for (int t = 0; t < ND; t++)
+              if (t == dfr) beta[t] = cpx<R>{cr, ci};
+            dfr++;
+            k++;
+            break;
+          }
           const uint32_t n = 1u << k;
           pass21<G, R, U>(grp, vec, n, [&](uint32_t p, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = r1 = p; w = p | n; },
                        [cr, ci](cpx<R> a, cpx<R>) { return cmul(a, cr, ci); });
@@ -619,6 +698,7 @@ struct Shot {
           if constexpr (!VEC) break;
           else {
           carry_valid = false;
+          materialize();
           double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
           if (getbit<W>(T.x, v)) s2 = -s2;
           const R cr = (R)c2, ci = (R)s2;
@@ -704,10 +784,65 @@ struct Shot {
             return fas ? cpx<R>{-y.im, y.re} : y;
           };
           double s0 = 0, s1 = 0;
+          // Deferred expansions (out of place): element lo | c << dm is
+          // stored[lo] times F(c), the product of beta over the set bits of c
+          // (|F| = 1), and its measured partner is (lo ^ dlo, c ^ dc).  Over
+          // the combinations c of one stored pair, the Z branch sums are nc
+          // times the stored ones, and the X cross term Re(conj(a) p) sums to
+          // Re(conj(va) pv Gam), Gam = sum over c of sigma_c F(c ^ dc) conj F(c)
+          // (sigma_c: the sign of the measured-slot phase from the bits of c).
+          const bool dfd = OOP && dfr > 0;
+          const int dm = k - dfr;
+          const uint32_t lmask = (1u << dm) - 1u, cmask = (1u << dfr) - 1u;
+          const uint32_t bsc = dfd && s >= dm ? (1u << (s - dm)) : 0u;
+          const uint32_t dlo = (bs ^ tm) & lmask, dc = dfd ? ((bs ^ tm) >> dm) & cmask : 0u;
+          const uint32_t bsl = bs & lmask, sml = sm & lmask, smc = dfd ? (sm >> dm) & cmask : 0u;
+          const uint32_t npairs = s < dm ? (1u << (dm - 1)) : (1u << dm);
+          // phase of a stored partner from the stored bits of its index
+          auto partner_lo = [&](cpx<R> x, uint32_t lo) {
+            cpx<R> y = (__popc((lo | bsl) & sml) & 1) ? cpx<R>{-x.re, -x.im} : x;
+            return fas ? cpx<R>{-y.im, y.re} : y;
+          };
           if (carry_valid) {
             // accumulated by the previous measurement's collapse pass
             s0 = carry0;
             s1 = carry1;
+          } else if (dfd) {
+            const double nc = (double)(s < dm ? (1u << dfr) : (1u << (dfr - 1)));
+            double gre = 0, gim = 0;
+            if (isx) {
+              for (uint32_t c = 0; c <= cmask; c++) {
+                if (c & bsc) continue;
+                const cpx<R> f = fac(c), g = fac(c ^ dc);
+                double re = (double)g.re * f.re + (double)g.im * f.im;
+                double im = (double)g.im * f.re - (double)g.re * f.im;
+                if (__popc((c | bsc) & smc) & 1) { re = -re; im = -im; }
+                gre += re;
+                gim += im;
+              }
+            }
+            reduce2<G, R, (U > 4 ? 4 : U)>(grp, vec, npairs,
+                             [&](uint32_t q, uint32_t& i0, uint32_t& i1) {
+                               i0 = s < dm ? ins0(q, s) : q;
+                               i1 = i0 ^ dlo;
+                             },
+                             [&](cpx<R> va, cpx<R> vc, uint32_t q, double& x0, double& x1) {
+                               const cpx<R> pv = partner_lo(vc, s < dm ? ins0(q, s) : q);
+                               if (isx) {
+                                 const double t = nc * (norm2(va) + norm2(pv));
+                                 const double wre = (double)va.re * pv.re + (double)va.im * pv.im;
+                                 const double wim = (double)va.re * pv.im - (double)va.im * pv.re;
+                                 const double cr = 2.0 * (wre * gre - wim * gim);
+                                 x0 += t + cr;
+                                 x1 += t - cr;
+                               } else {
+                                 x0 += nc * norm2(va);
+                                 x1 += nc * norm2(pv);
+                               }
+                             },
+                             s0, s1);
+            s0 = grp.sum(s0, red);
+            s1 = grp.sum(s1, red);
           } else {
             reduce2<G, R, U>(grp, vec, half,
                              [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = (i0 | bs) ^ tm; },
@@ -774,7 +909,45 @@ struct Shot {
               const uint32_t i1 = base | bs;
               return out1(vec[base], partner(vec[i1 ^ tm], i1));
             };
-            if (fuse) {
+            if (dfd) {
+              // each stored pair is read once; the outputs of its deferred
+              // combinations follow a Gray-code walk over c (one factor per
+              // step on each side); the next measurement reduces on its own
+              const cpx<R> g0 = fac(dc);
+              const R sg0 = (__popc(bsc & smc) & 1) ? (R)-1 : (R)1;
+              auto walk = [&](auto DT) {
+                constexpr int D = decltype(DT)::value;
+                for (uint32_t q = G == 1 ? 0u : (uint32_t)grp.tid; q < npairs; q += st) {
+                  const uint32_t lo = s < dm ? ins0(q, s) : q;
+                  cpx<R> av = vec[lo];
+                  cpx<R> pv = partner_lo(vec[lo ^ dlo], lo);
+                  pv = cmul(pv, sg0 * g0.re, sg0 * g0.im);
+                  auto put_out = [&](uint32_t c) {
+                    if (c & bsc) return;
+                    const uint32_t i0 = lo | (c << dm);
+                    dst[s == top ? i0 : ((i0 & ~tb) | (((i0 >> top) & 1u) << s))] = out1(av, pv);
+                  };
+                  put_out(0);
+#pragma unroll
+                  for (int j = 1; j < (1 << D); j++) {
+                    const int t = __builtin_ctz(j);
+                    const uint32_t c = (uint32_t)(j ^ (j >> 1));
+                    const bool nb = (c >> t) & 1u;  // bit t of c after the step
+                    const cpx<R> bt = beta[t];
+                    av = cmul(av, bt.re, nb ? bt.im : -bt.im);
+                    const bool pb = nb ^ ((dc >> t) & 1u);  // bit t of c ^ dc
+                    const R sg = ((smc >> t) & 1u) ? (R)-1 : (R)1;
+                    pv = cmul(pv, sg * bt.re, pb ? sg * bt.im : -sg * bt.im);
+                    put_out(c);
+                  }
+                }
+              };
+              if (dfr == 1) walk(IntC<1>{});
+              else if (dfr == 2) walk(IntC<2 <= ND ? 2 : 1>{});
+              else if (dfr == 3) walk(IntC<3 <= ND ? 3 : 1>{});
+              else walk(IntC<4 <= ND ? 4 : 1>{});
+              dfr = 0;
+            } else if (fuse) {
               // outputs (j0, j1): the next measurement's pair through its own
               // folded passes, summed as it is written
               constexpr int UP = U >= 2 ? U / 2 : 1;
@@ -985,6 +1158,7 @@ struct Shot {
           A.phi_out[local * 2 + 1] = 0.0;
         }
       } else if (VEC && A.phi_out && local < A.shots) {
+        if constexpr (OOP) materialize();
         // final active vector (its length 2^k is program-determined)
         FOR_GROUP(p, (1u << k)) {
           cpx<R> a = vec[p];

@@ -54,6 +54,12 @@ constexpr uint8_t F_FOLD_NEXT = 8;
 // again an active measurement: this measurement's collapse pass accumulates
 // that one's branch sums (F_FUSE_NEXT), and it skips its own reduction.
 constexpr uint8_t F_FUSE_NEXT = 2;
+// Kernels that collapse out of place keep up to this many trailing
+// expansions unapplied: the vector is then the stored 2^(k-d) amplitudes
+// times one phase factor per deferred top slot (an expansion only multiplies
+// its new upper half by a phase), and the next active measurement reads it
+// through them; any other vector instruction writes the deferred part first.
+constexpr int kDeferMax = 4;
 
 struct GInstr {
   uint8_t op;

@@ -229,7 +229,7 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
     const size_t rows_bytes = frames_lds_rows(tmp) * 64 * 4;
     const bool spec = c.specialize == 1;
     const bool bs_ok = H.kmax == 0 && !trace && (spec || rows_bytes <= kLdsLimit);
-    if (c.specialize != 0 && G != 0 && G != kBitSliced)
+    if (c.specialize == 1 && G != 0 && G != kBitSliced)
       return fail(CLIFFT_E_INVALID_ARG, "specialize applies to the bit-sliced tier only");
     if ((G == kBitSliced || spec) && !bs_ok)
       return fail(CLIFFT_E_CAPACITY, "bit-sliced frames need k_max = 0 and rows in LDS (not in trace mode)");

@@ -109,3 +109,4 @@ def test_specialize_host_only():
         pk.Program(circuits.surface_code_memory(3, 3, 2e-2)).specialize()
     with pytest.raises(pk.ClifftError):
         p.resolve_launch(10 ** 6, pk.make_launch("f32", 1, specialize=1))
+    assert p.resolve_launch(10 ** 6, pk.make_launch("f32", 1, specialize=-1))["specialize"] == 0  # not bit-sliced

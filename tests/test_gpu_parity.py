@@ -148,7 +148,12 @@ def _align(a, b):
 
 @pytest.mark.parametrize("case", range(12))
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
-def test_forced_probabilities_and_amplitudes(case, precision, tol):
+@pytest.mark.parametrize("tier", [None, (1, 1), (256, 1)], ids=["auto", "lane-hbm", "group-hbm"])
+def test_forced_probabilities_and_amplitudes(case, precision, tol, tier):
+    """Forced outcomes and faults of oracle shots: every measurement's
+    probability and the final vector.  The HBM tiers collapse out of place
+    through folded localization passes and deferred expansions (a Z or X
+    measurement on a stored or a deferred slot)."""
     rng = np.random.default_rng(700 + case)
     n = int(rng.integers(2, 6))
     text = random_small_circuit(rng, n, int(rng.integers(10, 45))).rsplit("M ", 1)[0]  # keep the final vector
@@ -170,7 +175,7 @@ def test_forced_probabilities_and_amplitudes(case, precision, tol):
         fm[s, : op.nevents] = t["m"]
         ff[s, : op.nsites] = faults
         traces.append(t)
-    L = pk.make_launch(precision)
+    L = pk.make_launch(precision) if tier is None else pk.make_launch(precision, tier[0], vector_in_hbm=tier[1])
     res = gp.sample_trace(shots, seed=case, launch=L, forced_m=torch.from_numpy(fm[:, : max(op.nevents, 0)]),
                           forced_faults=torch.from_numpy(ff[:, : max(op.nsites, 0)]))
     torch.cuda.synchronize()
@@ -406,3 +411,35 @@ def test_forced_amplitudes_k10(precision, tol, G, hbm):
         assert t["k"] == 10
         a, b = _align(_phi_in_oracle_order(phi[s, : 1 << 10], gslots, list(t["slots"])), t["phi"])
         assert np.linalg.norm(a - b) / np.linalg.norm(b) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
+@pytest.mark.parametrize("G", [1, 256])
+def test_forced_probabilities_d5_full(precision, tol, G):
+    """The whole d = 5 + 10 T workload on forced oracle shots with vectors in
+    HBM: its first active measurement reads ten expansions, four of them
+    deferred (the other six applied oldest first as the deferral fills), and
+    every later one collapses out of place; each forced outcome's branch
+    probability within the stated relative tolerance."""
+    text = circuits.workload("surface_d5_r5_t10")["texts"][0]
+    op = oracle.Program(text)
+    gp = pk.Program(text)
+    shots = 4
+    fm = np.zeros((shots, op.nevents), np.uint32)
+    ff = np.full((shots, op.nsites), -1, np.int32)
+    traces = []
+    for s in range(shots):
+        faults = op.faults(41, s)
+        t = op.trace(41, s, forced_faults=faults)
+        fm[s] = t["m"]
+        ff[s] = faults
+        traces.append(t)
+    res = gp.sample_trace(shots, seed=41, launch=pk.make_launch(precision, G, vector_in_hbm=1),
+                          forced_m=torch.from_numpy(fm), forced_faults=torch.from_numpy(ff))
+    torch.cuda.synchronize()
+    probs = res["probs"].cpu().numpy()
+    for s, t in enumerate(traces):
+        m = fm[s].astype(bool)
+        pg = np.where(m, probs[s], 1.0 - probs[s])
+        po = np.where(m, t["probs"], 1.0 - np.asarray(t["probs"]))
+        assert np.max(np.abs(pg - po) / po) <= tol
