@@ -190,15 +190,16 @@ clifft_status clifft_sample_trace(const clifft_program* p, uint64_t shots, uint6
                                   uint64_t* meas, uint64_t* det, uint64_t* obs, void* stream);
 
 /* ---- Batched launch: many programs of different width and active
- * dimension sampled by one persistent launch (work items: 64-shot tiles of
- * shot-per-lane programs and single shots of shot-per-workgroup programs,
+ * dimension sampled by one persistent launch per tier (work items: single
+ * shots of shot-per-workgroup programs, groups of four shots of
+ * shot-per-wave programs and 64-shot tiles of shot-per-lane programs,
  * ordered longest first by the cost model, claimed dynamically). */
 typedef struct clifft_batch clifft_batch; /* opaque, owned by the library */
 
 /* Prepare a batch of n programs (which must stay alive while the batch
  * exists), shots[i] shots of program i with Philox seed seeds[i] (host
  * arrays).  cfg: precision, optional threads_per_shot (0 automatic per
- * program, 1 or 256 for all) and grid.  Uploads the item table to the
+ * program, 1, 64 or 256 for all) and grid.  Uploads the item table to the
  * current device (allocates device memory, owned by the batch). */
 clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n, const uint64_t* shots,
                                   const uint64_t* seeds, const clifft_launch* cfg, clifft_batch** out);

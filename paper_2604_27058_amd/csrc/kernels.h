@@ -41,7 +41,7 @@ struct BatchProgram {
 struct BatchItem {
   uint32_t prog;   // index into the program table
   uint32_t kind;   // 1: four 64-shot tiles (one per wave); 256: one shot
-  uint64_t first;  // first tile (kind 1) or shot (kind 256)
+  uint64_t first;  // first tile (kind 1), first of four shots (kind 64) or the shot (kind 256)
 };
 // One queue of a batched launch (all items of one kind).
 struct BatchArgs {
@@ -54,11 +54,12 @@ struct BatchArgs {
   uint64_t slot_bytes;    // workspace bytes per workgroup
   uint32_t rec_words;     // max records + detectors + observables over programs
 };
-// The shot-per-workgroup queue, then the shot-per-lane queue, as two
-// persistent kernels on the stream (they share the workspace).  The two
-// counters are the 32-bit words at groups.counter and groups.counter + 2.
-hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArgs& lanes, int grid_lanes,
-                        size_t lds_bytes, bool fp64, hipStream_t stream);
+// The shot-per-workgroup queue, the shot-per-wave queue, then the
+// shot-per-lane queue, as three persistent kernels on the stream (they share
+// the workspace).  The counters are the 32-bit words at groups.counter,
+// groups.counter + 2 and groups.counter + 4.
+hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArgs& waves, int grid_waves,
+                        const BatchArgs& lanes, int grid_lanes, size_t lds_bytes, bool fp64, hipStream_t stream);
 
 hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t stream);
 // Bit-sliced Pauli-frame kernel (k_max = 0): 32 shots per lane, one 64-thread

@@ -1202,21 +1202,26 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
   const int tid = G == 256 ? (int)threadIdx.x : lane;
   const uint64_t ntiles = (A.shots + 63) / 64;
   const uint64_t words = ntiles;
-  if constexpr (G == 256) {
-    // One shot per workgroup: shots (not tiles) are spread over the
-    // workgroups so that small shot counts still fill the device; record bits
-    // are staged per shot (bit 0) and ORed into the zero-filled outputs.
+  if constexpr (G > 1) {
+    // One shot per workgroup (G = 256) or per wave (G = 64): shots (not
+    // tiles) are spread over the units so that small shot counts still fill
+    // the device; record bits are staged per shot (bit 0) and ORed into the
+    // zero-filled outputs.
+    auto unit_sync = [] {
+      if constexpr (G == 256) __syncthreads();
+      else { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+    };
     for (uint64_t sh_i = unit; sh_i < A.shots; sh_i += nunits) {
-      for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 256) rec[r] = 0;
-      __syncthreads();
+      for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += G) rec[r] = 0;
+      unit_sync();
       uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
       Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0,
                                                                   A.offset + g, g, alt};
       sh.run();
-      __syncthreads();
+      unit_sync();
       const uint64_t bit = 1ull << (g & 63);
       const size_t word = (size_t)(g >> 6);
-      for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 256) {
+      for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += G) {
         if (!(rec[r] & 1ull)) continue;
         uint64_t* dst;
         if (r < (uint32_t)P.nrec) dst = A.meas ? A.meas + (size_t)r * words + word : nullptr;
@@ -1224,7 +1229,7 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
         else dst = A.obs ? A.obs + (size_t)(r - P.nrec - P.ndet) * words + word : nullptr;
         if (dst) atomicOr((unsigned long long*)dst, (unsigned long long)bit);
       }
-      __syncthreads();
+      unit_sync();
     }
     return;
   }
@@ -1794,6 +1799,34 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
         }
       }
     }
+  } else if constexpr (KIND == 64) {
+    // up to four shots, one per wave, each with its own two buffers
+    const int wv = (int)rfl(threadIdx.x >> 6);
+    const uint64_t sh_i = it.first + (uint64_t)wv;
+    uint64_t* wrec = rec + (size_t)wv * B.rec_words;
+    if (sh_i < bp.shots) {
+      for (uint32_t r = (uint32_t)lane; r < nwords_rec; r += 64) wrec[r] = 0;
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      const uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
+      const size_t per = (size_t)1 << P.kmax;
+      cpx<R>* base = (cpx<R>*)slot + (size_t)wv * 2 * per;
+      Shot<W, 64, R, false, true, unroll_for<R, true>(), true> sh{P, A, Group<64>{lane}, Vec<64, R>{base, lane}, wrec,
+                                                               red, 0, A.offset + g, g, base + per};
+      sh.run();
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      const uint64_t bit = 1ull << (g & 63);
+      const size_t word = (size_t)(g >> 6);
+      for (uint32_t r = (uint32_t)lane; r < nwords_rec; r += 64) {
+        if (!(wrec[r] & 1ull)) continue;
+        uint64_t* dst;
+        if (r < (uint32_t)P.nrec) dst = A.meas ? A.meas + (size_t)r * words + word : nullptr;
+        else if (r < (uint32_t)(P.nrec + P.ndet)) dst = A.det ? A.det + (size_t)(r - P.nrec) * words + word : nullptr;
+        else dst = A.obs ? A.obs + (size_t)(r - P.nrec - P.ndet) * words + word : nullptr;
+        if (dst) atomicOr((unsigned long long*)dst, (unsigned long long)bit);
+      }
+    }
   } else {
     const uint64_t g = rfl((uint32_t)it.first) | (it.first & 0xFFFFFFFF00000000ull);
     for (uint32_t r = threadIdx.x; r < nwords_rec; r += 256) rec[r] = 0;
@@ -1817,8 +1850,9 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
   __syncthreads();
 }
 
-// KIND 256: the shot-per-workgroup queue; KIND 1: the shot-per-lane tiles.
-// Separate kernels, so that each path gets the registers it needs.
+// KIND 256: the shot-per-workgroup queue; KIND 64: four shots per
+// workgroup, one per wave; KIND 1: the shot-per-lane tiles.  Separate
+// kernels, so that each path gets the registers it needs.
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1856,14 +1890,17 @@ static hipError_t launch_batch_t(const BatchArgs& B, int grid, size_t lds_bytes,
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArgs& lanes, int grid_lanes,
-                        size_t lds_bytes, bool fp64, hipStream_t st) {
-  // both claim counters (32-bit words at the starts of two 64-bit slots)
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (uint64_t*)groups.counter, (size_t)2);
+hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArgs& waves, int grid_waves,
+                        const BatchArgs& lanes, int grid_lanes, size_t lds_bytes, bool fp64, hipStream_t st) {
+  // the three claim counters (32-bit words at the starts of three 64-bit slots)
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (uint64_t*)groups.counter, (size_t)3);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && groups.nitems)
     e = fp64 ? launch_batch_t<double, 256>(groups, grid_groups, lds_bytes, st)
              : launch_batch_t<float, 256>(groups, grid_groups, lds_bytes, st);
+  if (e == hipSuccess && waves.nitems)
+    e = fp64 ? launch_batch_t<double, 64>(waves, grid_waves, lds_bytes, st)
+             : launch_batch_t<float, 64>(waves, grid_waves, lds_bytes, st);
   if (e == hipSuccess && lanes.nitems)
     e = fp64 ? launch_batch_t<double, 1>(lanes, grid_lanes, lds_bytes, st)
              : launch_batch_t<float, 1>(lanes, grid_lanes, lds_bytes, st);
@@ -1910,7 +1947,10 @@ static hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShap
     if (L.global_vec) return launch_w<1, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
     return launch_w<1, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
   }
-  if (L.G == 64) return launch_w<64, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+  if (L.G == 64) {
+    if (L.global_vec) return launch_w<64, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
+    return launch_w<64, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+  }
   if (L.global_vec) return launch_w<256, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
   return launch_w<256, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
 }
@@ -1918,7 +1958,8 @@ static hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShap
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool debug,
                          hipStream_t st) {
   if (L.G < 0) return launch_frames(P, A, L.grid, st);
-  if (L.G == 256) {
+  if (L.G == 256 || L.G == 64) {
+    // shot-granular tiers OR their record bits into zero-filled rows
     const size_t words = (A.shots + 63) / 64;
     uint64_t* rows[3] = {A.meas, A.det, A.obs};
     const size_t counts[3] = {(size_t)P.nrec, (size_t)P.ndet, (size_t)P.nobs};

@@ -181,6 +181,7 @@ hipError_t launch_spec(hipFunction_t fn, const DevProgram& D, const KArgs& A, in
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kLaneMaxK = 12;                              // shot-per-lane tier up to this k_max
 constexpr int kBatchLaneMaxK = 10;                         // the same inside a batched launch
+constexpr int kWaveMaxK = 15;                              // shot-per-wave tier up to this k_max
 constexpr int kBitSliced = -32;                            // 32 shots per lane, bit-sliced frames
 constexpr size_t kWorkspaceBudget = (size_t)4 << 30;       // default global vector workspace
 
@@ -259,14 +260,13 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
   // vectors go to LDS when they fit.  A shot-per-workgroup vector stays in
   // LDS only while four workgroups per CU fit (32 KB); beyond that the HBM
   // workspace serves it faster, with more workgroups streaming per CU.
-  if (G == 0) G = (H.kmax <= kLaneMaxK) ? 1 : 256;
+  if (G == 0) G = H.kmax <= kLaneMaxK ? 1 : H.kmax <= kWaveMaxK ? 64 : 256;
   bool global_vec = false;
   if (H.kmax > 0) {
     size_t need = (G == 256 ? 1 : 4) * vec * amp * (G == 1 ? 64 : 1);
     if (c.vector_in_hbm == 1) global_vec = true;
     else if (c.vector_in_hbm == -1) global_vec = false;
     else global_vec = need > (G == 256 ? (size_t)32 * 1024 : kLdsLimit - 16 * 1024);
-    if (global_vec && G == 64) return fail(CLIFFT_E_CAPACITY, "shot-per-wave vectors must fit in LDS");
   }
   DevProgram tmp{};
   tmp.nrec = H.nrec;
@@ -275,8 +275,9 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
   tmp.kmax = H.kmax;
   size_t lds = lds_bytes_for(D ? *D : tmp, G, global_vec, *fp64);
   if (lds > kLdsLimit) return fail(CLIFFT_E_CAPACITY, "records and active vectors exceed LDS; use a larger tier");
-  // work items: 64-shot tiles per wave (G = 1, 64) or single shots per workgroup (G = 256)
-  uint64_t blocks_needed = G == 256 ? shots : ((shots + 63) / 64 + 3) / 4;
+  // work items: 64-shot tiles per wave (G = 1), single shots per wave (G = 64)
+  // or per workgroup (G = 256)
+  uint64_t blocks_needed = G == 256 ? shots : G == 64 ? (shots + 3) / 4 : ((shots + 63) / 64 + 3) / 4;
   int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, kLdsLimit / std::max<size_t>(lds, 1)));
   int grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
   if (global_vec && c.grid <= 0) {
@@ -370,22 +371,26 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
 struct clifft_batch {
   std::vector<const clifft_program*> progs;
   std::vector<BatchProgram> table;  // device pointers of each program's upload
-  // two queues: single shots of shot-per-workgroup programs, and 64-shot
-  // tile groups of shot-per-lane programs; each sorted longest first
-  std::vector<BatchItem> items_g, items_l;
+  // three queues: single shots of shot-per-workgroup programs, groups of
+  // four shots of shot-per-wave programs, and 64-shot tile groups of
+  // shot-per-lane programs; each sorted longest first
+  std::vector<BatchItem> items_g, items_w, items_l;
   bool fp64 = false;
   int device = 0;
-  int grid_g = 0, grid_l = 0;
+  int grid_g = 0, grid_w = 0, grid_l = 0;
   size_t lds = 0;
-  uint64_t slot_g = 0, slot_l = 0;  // workspace bytes per workgroup of each queue
+  uint64_t slot_g = 0, slot_w = 0, slot_l = 0;  // workspace bytes per workgroup of each queue
   uint32_t rec_words = 0;
   uint64_t meas_words = 0, det_words = 0, obs_words = 0;
   BatchProgram* d_table = nullptr;
   BatchItem* d_items_g = nullptr;
+  BatchItem* d_items_w = nullptr;
   BatchItem* d_items_l = nullptr;
   uint64_t* d_counter = nullptr;
 
-  size_t workspace_bytes() const { return std::max((size_t)grid_g * slot_g, (size_t)grid_l * slot_l); }
+  size_t workspace_bytes() const {
+    return std::max({(size_t)grid_g * slot_g, (size_t)grid_w * slot_w, (size_t)grid_l * slot_l});
+  }
 };
 
 extern "C" {
@@ -525,7 +530,7 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
   b->fp64 = c.precision == CLIFFT_FP64;
   (void)hipGetDevice(&b->device);
   const size_t amp = b->fp64 ? 16 : 8;
-  std::vector<double> cost_g, cost_l;
+  std::vector<double> cost_g, cost_w, cost_l;
   for (int i = 0; i < n; i++) {
     if (!progs[i]) { delete b; return fail(CLIFFT_E_INVALID_ARG, "null program in batch"); }
     const DevProgram* D = nullptr;
@@ -544,19 +549,23 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
     b->meas_words += (uint64_t)H.nrec * words;
     b->det_words += (uint64_t)H.ndet * words;
     b->obs_words += (uint64_t)H.nobs * words;
-    // tier: frames shot-per-lane while 64 vectors per wave stay small,
-    // else one shot per workgroup
-    int G = c.threads_per_shot == 256 ? 256 : c.threads_per_shot == 1 ? 1 : (H.kmax <= kBatchLaneMaxK ? 1 : 256);
+    // tier: frames shot-per-lane while 64 vectors per wave stay small, a
+    // shot per wave up to kWaveMaxK, else one shot per workgroup
+    int G = c.threads_per_shot == 256 || c.threads_per_shot == 64 || c.threads_per_shot == 1
+                ? c.threads_per_shot
+                : (H.kmax <= kBatchLaneMaxK ? 1 : H.kmax <= kWaveMaxK ? 64 : 256);
     if (c.threads_per_shot == 0) {
       // an autotuned program keeps its tier inside the batch
       auto it = progs[i]->tuned.find({b->device, c.precision});
-      if (it != progs[i]->tuned.end() && (H.kmax <= kLaneMaxK || it->second.threads_per_shot != 1))
-        G = it->second.threads_per_shot == 1 ? 1 : 256;
+      if (it != progs[i]->tuned.end() && it->second.threads_per_shot > 0 &&
+          (H.kmax <= kLaneMaxK || it->second.threads_per_shot != 1))
+        G = it->second.threads_per_shot;
     }
     bp.G = G;
     const uint64_t vec = (uint64_t)1 << H.kmax;
     // two buffers per shot vector (out-of-place collapses)
     if (G == 1) b->slot_l = std::max<uint64_t>(b->slot_l, 2 * 4 * 64 * vec * amp);
+    else if (G == 64) b->slot_w = std::max<uint64_t>(b->slot_w, 2 * 4 * vec * amp);
     else b->slot_g = std::max<uint64_t>(b->slot_g, 2 * vec * amp);
     b->rec_words = std::max<uint32_t>(b->rec_words, (uint32_t)(H.nrec + H.ndet + H.nobs));
     b->progs.push_back(progs[i]);
@@ -568,10 +577,16 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
     // threads
     const double lane_item = 20.0 * cm.instructions + cm.int_ops + cm.vector_bytes;
     const double block_item = 20.0 * cm.instructions + (cm.vector_bytes + cm.flops) / 64.0;
+    const double wave_item = 20.0 * cm.instructions + (cm.vector_bytes + cm.flops) / 16.0;
     if (G == 1) {
       for (uint64_t t = 0; t < words; t += 4) {
         b->items_l.push_back(BatchItem{(uint32_t)i, 1u, t});
         cost_l.push_back(lane_item);
+      }
+    } else if (G == 64) {
+      for (uint64_t s = 0; s < shots[i]; s += 4) {
+        b->items_w.push_back(BatchItem{(uint32_t)i, 64u, s});
+        cost_w.push_back(wave_item);
       }
     } else {
       for (uint64_t s = 0; s < shots[i]; s++) {
@@ -589,6 +604,7 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
     items.swap(sorted);
   };
   longest_first(b->items_g, cost_g);
+  longest_first(b->items_w, cost_w);
   longest_first(b->items_l, cost_l);
   b->rec_words = (b->rec_words + 1) & ~1u;
   b->lds = (size_t)4 * b->rec_words * 8 + 64 + 64;
@@ -604,15 +620,19 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
   // the workgroup queue is bounded by registers (about two workgroups per
   // CU resident), the lane queue by LDS
   b->grid_g = grid_for(4, b->slot_g, b->items_g.size());
+  b->grid_w = grid_for(4, b->slot_w, b->items_w.size());
   b->grid_l = grid_for((int)std::max<size_t>(1, std::min<size_t>(8, kLdsLimit / b->lds)), b->slot_l, b->items_l.size());
   hipError_t e = hipMalloc((void**)&b->d_table, sizeof(BatchProgram) * b->table.size());
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_items_g, sizeof(BatchItem) * std::max<size_t>(1, b->items_g.size()));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_items_w, sizeof(BatchItem) * std::max<size_t>(1, b->items_w.size()));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_items_l, sizeof(BatchItem) * std::max<size_t>(1, b->items_l.size()));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, 64);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_table, b->table.data(), sizeof(BatchProgram) * b->table.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !b->items_g.empty())
     e = hipMemcpy(b->d_items_g, b->items_g.data(), sizeof(BatchItem) * b->items_g.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !b->items_w.empty())
+    e = hipMemcpy(b->d_items_w, b->items_w.data(), sizeof(BatchItem) * b->items_w.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !b->items_l.empty())
     e = hipMemcpy(b->d_items_l, b->items_l.data(), sizeof(BatchItem) * b->items_l.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -671,12 +691,17 @@ clifft_status clifft_batch_sample(const clifft_batch* b, void* workspace, size_t
   G.workspace = workspace;
   G.slot_bytes = b->slot_g;
   G.rec_words = b->rec_words;
+  BatchArgs Wv = G;
+  Wv.items = b->d_items_w;
+  Wv.nitems = b->items_w.size();
+  Wv.counter = (uint32_t*)b->d_counter + 2;
+  Wv.slot_bytes = b->slot_w;
   BatchArgs L = G;
   L.items = b->d_items_l;
   L.nitems = b->items_l.size();
-  L.counter = (uint32_t*)b->d_counter + 2;
+  L.counter = (uint32_t*)b->d_counter + 4;
   L.slot_bytes = b->slot_l;
-  if (e == hipSuccess) e = launch_batch(G, b->grid_g, L, b->grid_l, b->lds, b->fp64, s);
+  if (e == hipSuccess) e = launch_batch(G, b->grid_g, Wv, b->grid_w, L, b->grid_l, b->lds, b->fp64, s);
   if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
   return CLIFFT_OK;
 }
@@ -688,6 +713,7 @@ void clifft_batch_free(clifft_batch* b) {
   (void)hipSetDevice(b->device);
   if (b->d_table) (void)hipFree(b->d_table);
   if (b->d_items_g) (void)hipFree(b->d_items_g);
+  if (b->d_items_w) (void)hipFree(b->d_items_w);
   if (b->d_items_l) (void)hipFree(b->d_items_l);
   if (b->d_counter) (void)hipFree(b->d_counter);
   (void)hipSetDevice(cur);
@@ -715,7 +741,6 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
     if (H.kmax == 0 && G != 1) continue;
     for (int hbm : {-1, 1}) {
       if (H.kmax == 0 && hbm == 1) continue;
-      if (G == 64 && hbm == 1) continue;
       if (G == 1 && H.kmax > kLaneMaxK) continue;
       for (int m : mult) cands.push_back(clifft_launch{precision, G, cus * m, H.kmax == 0 ? 0 : hbm});
     }

@@ -148,7 +148,7 @@ def _align(a, b):
 
 @pytest.mark.parametrize("case", range(12))
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
-@pytest.mark.parametrize("tier", [None, (1, 1), (256, 1)], ids=["auto", "lane-hbm", "group-hbm"])
+@pytest.mark.parametrize("tier", [None, (1, 1), (64, 1), (256, 1)], ids=["auto", "lane-hbm", "wave-hbm", "group-hbm"])
 def test_forced_probabilities_and_amplitudes(case, precision, tol, tier):
     """Forced outcomes and faults of oracle shots: every measurement's
     probability and the final vector.  The HBM tiers collapse out of place
@@ -199,7 +199,7 @@ def test_forced_probabilities_and_amplitudes(case, precision, tol, tier):
     assert worst_p <= tol and worst_v <= tol
 
 
-TIERS = [(1, -1), (1, 1), (64, -1), (256, -1), (256, 1)]  # (threads per shot, vector in HBM)
+TIERS = [(1, -1), (1, 1), (64, -1), (64, 1), (256, -1), (256, 1)]  # (threads per shot, vector in HBM)
 
 
 @pytest.mark.parametrize("G,hbm", TIERS)
@@ -248,15 +248,15 @@ def test_large_active_k20_sampled_shots():
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_batched_launch_matches_single_program_and_oracle(precision):
-    """A heterogeneous batch (both tiers, k_max 4..16, W = 1 and 2) in one
-    launch: every program's records equal its single-program call (FP64:
+    """A heterogeneous batch (all three tiers, k_max 4..16, W = 1 and 2) in
+    one launch: every program's records equal its single-program call (FP64:
     exactly; FP32: up to near-threshold shots) and, on a prefix, the oracle."""
     specs = circuits.batched_set(count=12, seed=4100)
     progs = [pk.Program(c["text"]) for c in specs]
     shots = [1000 + 37 * i for i in range(len(progs))]
     seeds = [11 + i for i in range(len(progs))]
     B = pk.Batch(progs, shots, seeds, precision=precision)
-    assert set(B.threads_per_shot) == {1, 256}
+    assert set(B.threads_per_shot) == {1, 64, 256}
     outs = B.sample()
     torch.cuda.synchronize()
     for i, (c, p) in enumerate(zip(specs, progs)):
@@ -377,7 +377,7 @@ def _surface_d5_through_t_layer():
 
 
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
-@pytest.mark.parametrize("G,hbm", [(1, 1), (256, -1), (256, 1)])  # 64 shot-per-lane vectors of 2^10 exceed LDS
+@pytest.mark.parametrize("G,hbm", [(1, 1), (64, 1), (256, -1), (256, 1)])  # 64 shot-per-lane vectors of 2^10 exceed LDS
 def test_forced_amplitudes_k10(precision, tol, G, hbm):
     """2^10 amplitudes after the T layer of the d = 5 workload, on forced
     shots (the oracle's own faults and outcomes), within the stated
@@ -414,7 +414,7 @@ def test_forced_amplitudes_k10(precision, tol, G, hbm):
 
 
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
-@pytest.mark.parametrize("G", [1, 256])
+@pytest.mark.parametrize("G", [1, 64, 256])
 def test_forced_probabilities_d5_full(precision, tol, G):
     """The whole d = 5 + 10 T workload on forced oracle shots with vectors in
     HBM: its first active measurement reads ten expansions, four of them
