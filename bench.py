@@ -135,7 +135,10 @@ def bench_batch(args, w, pk, torch):
                 diff |= np.bitwise_or.reduce(x ^ y, axis=0)
         differing += int(sum(bin(int(v)).count("1") for v in diff))
     cost = [p.cost_model(precision) for p in progs]
-    vec_bytes = sum(c["vector_bytes_fused"] * n for c, n in zip(cost, shots))  # every batched vector is in HBM
+    # every batched vector is in HBM; each program's bytes for the tier it runs on
+    tiers = B.threads_per_shot
+    vec_bytes = sum(c["vector_bytes_fused" if g == 1 else "vector_bytes_fused_group"] * n
+                    for c, n, g in zip(cost, shots, tiers))
     table_bytes = sum(c["vector_bytes"] * n for c, n in zip(cost, shots))
     achieved = vec_bytes / (kernel_ms * 1e-3)
     line = {
@@ -255,12 +258,14 @@ def main():
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT_OPS / 1e12, unit="Tops/s",
                     frac=achieved / PEAK_INT_OPS, work_model="per-shot table")
     elif shape["vector_in_hbm"] == 1:
-        # bytes the fused passes move (folded localization passes, carried
-        # branch sums); the unfused per-instruction table beside it
-        achieved = cost["vector_bytes_fused"] * shots / (kernel_ms * 1e-3)
+        # bytes the fused passes move (folded localization passes, deferred
+        # expansions, carried branch sums); the unfused per-instruction table
+        # beside it
+        fused_key = "vector_bytes_fused" if shape["threads_per_shot"] == 1 else "vector_bytes_fused_group"
+        achieved = cost[fused_key] * shots / (kernel_ms * 1e-3)
         table = cost["vector_bytes"] * shots / (kernel_ms * 1e-3)
         roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=achieved / PEAK_HBM,
-                    work_model="fused passes", bytes_per_shot=round(cost["vector_bytes_fused"], 1),
+                    work_model="fused passes", bytes_per_shot=round(cost[fused_key], 1),
                     unfused_table=dict(bytes_per_shot=round(cost["vector_bytes"], 1), achieved=table / 1e9,
                                        frac=table / PEAK_HBM))
     else:
@@ -270,7 +275,7 @@ def main():
     traffic = load_traffic(args.workload, precision, roof["kernel"])
     roof["traffic"] = traffic
     if traffic:
-        vb = cost["vector_bytes_fused"] if shape["vector_in_hbm"] == 1 else cost["vector_bytes"]
+        vb = cost[fused_key] if shape["vector_in_hbm"] == 1 else cost["vector_bytes"]
         roof["traffic_over_algorithmic"] = traffic / max(1.0, (vb + cost["record_bytes"]) * shots)
     roof["kernel_ms"] = kernel_ms
     roof["work_per_shot"] = {kk: round(v, 3) for kk, v in cost.items()}

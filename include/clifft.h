@@ -121,9 +121,12 @@ typedef struct clifft_cost {
   double instructions;    /* compiled instructions executed */
   double int_ops_bitsliced; /* integer lane-operations per shot of the bit-sliced form (32 shots per
                                frame word; per-shot random draws and outcome bits counted in full) */
-  double vector_bytes_fused; /* active-vector bytes of the fused passes of the HBM tiers (folded
-                               localization passes move nothing, a collapse reads the vector and
-                               writes half, carried branch sums skip the reduction) */
+  double vector_bytes_fused; /* active-vector bytes of the fused passes of the shot-per-lane tier
+                               with vectors in HBM (folded localization passes and deferred
+                               expansions move nothing, a collapse reads the vector and writes
+                               half, carried branch sums skip the reduction) */
+  double vector_bytes_fused_group; /* the same for a shot per wave or per workgroup (a collapse
+                               through deferred expansions carries no branch sums there) */
 } clifft_cost;
 clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clifft_cost* out);
 

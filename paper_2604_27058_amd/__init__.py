@@ -32,7 +32,7 @@ class clifft_info(ctypes.Structure):
 class clifft_cost(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "int_ops", "flops", "vector_bytes", "record_bytes", "expected_faults", "instructions",
-        "int_ops_bitsliced", "vector_bytes_fused")]
+        "int_ops_bitsliced", "vector_bytes_fused", "vector_bytes_fused_group")]
 
 
 class clifft_launch(ctypes.Structure):

@@ -606,12 +606,14 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
   // measurement move nothing; up to kDeferMax trailing expansions move
   // nothing until the next active measurement reads the stored 2^(k-d)
   // elements (once for its branch sums, once for its collapse, which writes
-  // all 2^(k-1) outputs and carries nothing), an expansion beyond them
+  // all 2^(k-1) outputs, and on the lane tier carries the next
+  // measurement's branch sums), an expansion beyond them
   // applies the oldest one (reads and writes 2^(k-d) elements), and any
   // other vector instruction first writes the deferred part; a collapse
   // reads the vector and writes half of it; its reduction pass is skipped
   // when the previous measurement's collapse carried its branch sums.
-  {
+  for (int lane_tier = 1; lane_tier >= 0; lane_tier--) {
+    double& bytes = lane_tier ? c.vector_bytes_fused : c.vector_bytes_fused_group;
     bool carried = false;
     int dfr = 0;
     for (size_t i = 0; i < P.code.size(); i++) {
@@ -620,31 +622,27 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
       const double A = std::ldexp(1.0, k);
       const double stored = std::ldexp(1.0, k - dfr);
       auto materialize = [&]() {
-        if (dfr) c.vector_bytes_fused += (stored + (A - stored)) * a;
+        if (dfr) bytes += (stored + (A - stored)) * a;
         dfr = 0;
       };
       switch (in.op) {
         case OP_APERM: case OP_ASIGN: case OP_AS:
-          if (!(in.flags & F_FOLD_NEXT)) { materialize(); c.vector_bytes_fused += A * a; carried = false; }
+          if (!(in.flags & F_FOLD_NEXT)) { materialize(); bytes += A * a; carried = false; }
           break;
-        case OP_APERM2: case OP_AROT: materialize(); c.vector_bytes_fused += A * a; carried = false; break;
-        case OP_AH: materialize(); c.vector_bytes_fused += 2 * A * a; carried = false; break;
+        case OP_APERM2: case OP_AROT: materialize(); bytes += A * a; carried = false; break;
+        case OP_AH: materialize(); bytes += 2 * A * a; carried = false; break;
         case OP_EXPAND:
           if (dfr == kDeferMax) {
-            c.vector_bytes_fused += 2 * stored * a;
+            bytes += 2 * stored * a;
             dfr--;
           }
           dfr++;
           carried = false;
           break;
         case OP_MACTZ: case OP_MACTX:
-          if (dfr) {
-            c.vector_bytes_fused += 2 * stored * a + 0.5 * A * a;
-            carried = false;
-          } else {
-            c.vector_bytes_fused += (carried ? 0.0 : A * a) + 1.5 * A * a;
-            carried = (in.flags & F_FUSE_NEXT) != 0;
-          }
+          if (dfr) bytes += 2 * stored * a + 0.5 * A * a;
+          else bytes += (carried ? 0.0 : A * a) + 1.5 * A * a;
+          carried = (in.flags & F_FUSE_NEXT) != 0 && (lane_tier || !dfr);
           dfr = 0;
           break;
         default: break;

@@ -40,7 +40,8 @@ struct CostModel {
   double expected_faults = 0;  // mean realized faults
   double instructions = 0;     // compiled instructions executed
   double int_ops_bitsliced = 0;  // integer lane-operations per shot when 32 shots share each frame word
-  double vector_bytes_fused = 0;  // active-vector bytes of the HBM tiers' fused passes
+  double vector_bytes_fused = 0;        // active-vector bytes of the fused passes, shot per lane in HBM
+  double vector_bytes_fused_group = 0;  // the same for a shot per wave or per workgroup
 };
 CostModel cost_model(const CompiledProgram& P, bool fp64);
 

@@ -912,40 +912,127 @@ struct Shot {
             if (dfd) {
               // each stored pair is read once; the outputs of its deferred
               // combinations follow a Gray-code walk over c (one factor per
-              // step on each side); the next measurement reduces on its own
+              // step on each side)
               const cpx<R> g0 = fac(dc);
               const R sg0 = (__popc(bsc & smc) & 1) ? (R)-1 : (R)1;
-              auto walk = [&](auto DT) {
-                constexpr int D = decltype(DT)::value;
-                for (uint32_t q = G == 1 ? 0u : (uint32_t)grp.tid; q < npairs; q += st) {
-                  const uint32_t lo = s < dm ? ins0(q, s) : q;
-                  cpx<R> av = vec[lo];
-                  cpx<R> pv = partner_lo(vec[lo ^ dlo], lo);
-                  pv = cmul(pv, sg0 * g0.re, sg0 * g0.im);
-                  auto put_out = [&](uint32_t c) {
-                    if (c & bsc) return;
-                    const uint32_t i0 = lo | (c << dm);
-                    dst[s == top ? i0 : ((i0 & ~tb) | (((i0 >> top) & 1u) << s))] = out1(av, pv);
-                  };
-                  put_out(0);
-#pragma unroll
-                  for (int j = 1; j < (1 << D); j++) {
-                    const int t = __builtin_ctz(j);
-                    const uint32_t c = (uint32_t)(j ^ (j >> 1));
-                    const bool nb = (c >> t) & 1u;  // bit t of c after the step
-                    const cpx<R> bt = beta[t];
-                    av = cmul(av, bt.re, nb ? bt.im : -bt.im);
-                    const bool pb = nb ^ ((dc >> t) & 1u);  // bit t of c ^ dc
-                    const R sg = ((smc >> t) & 1u) ? (R)-1 : (R)1;
-                    pv = cmul(pv, sg * bt.re, pb ? sg * bt.im : -sg * bt.im);
-                    put_out(c);
+              // output of input lo | c << dm (the top bit moves to slot s)
+              auto oidx = [&](uint32_t lo, uint32_t c) {
+                const uint32_t i0 = lo | (c << dm);
+                return s == top ? i0 : ((i0 & ~tb) | (((i0 >> top) & 1u) << s));
+              };
+              // one Gray-code step (bit t, to value nb) of a walk whose c is
+              // offset by off: its element factor and its partner factor
+              auto step = [&](cpx<R>& x, cpx<R>& y, int t, bool nb, uint32_t off) {
+                const cpx<R> bt = beta[t];
+                const bool xb = nb ^ ((off >> t) & 1u);
+                x = cmul(x, bt.re, xb ? bt.im : -bt.im);
+                const bool yb = xb ^ ((dc >> t) & 1u);  // bit t of (c ^ off) ^ dc
+                const R sg = ((smc >> t) & 1u) ? (R)-1 : (R)1;
+                y = cmul(y, sg * bt.re, yb ? sg * bt.im : -sg * bt.im);
+              };
+              // The next measurement (fused) pairs output o with o ^ d2 (the
+              // member with bit s2 clear first).  In stored and deferred bits
+              // d2 is (d2lo, d2c): the pair of the output of (lo, c) is the
+              // output of (lo ^ d2lo, c ^ d2c), from the same stored pair when
+              // d2lo = 0; piv is the bit that orders the two members.
+              const uint32_t cm1 = (1u << (dfr - 1)) - 1u;
+              auto to_c = [&](uint32_t M) {
+                return ((M >> dm) & cm1 & ~bsc) | (s != top ? ((M >> s) & 1u) << (dfr - 1) : 0u);
+              };
+              const uint32_t d2 = fuse ? b2 ^ tm2 : 0u;
+              const uint32_t d2lo = d2 & lmask & ~bsl, d2c = fuse ? to_c(d2) : 0u;
+              const bool same_row = d2lo == 0;
+              const uint32_t piv = same_row ? (d2c & (0u - d2c)) : (d2lo & (0u - d2lo));
+              const int pb = __ffs(piv) - 1;
+              const uint32_t nq = !fuse ? npairs : same_row ? npairs : npairs >> 1;
+              // stored index of row A of iteration q (pivot bit clear when the
+              // two rows differ)
+              auto row_a = [&](uint32_t q) {
+                if (!fuse || same_row) return s < dm ? ins0(q, s) : q;
+                if (s < dm) return ins0(ins0(q, min((int)s, pb)), max((int)s, pb));
+                return ins0(q, pb);
+              };
+              auto sigma = [&](uint32_t c) { return (__popc((c | bsc) & smc) & 1) ? (R)-1 : (R)1; };
+              if (G == 1 && fuse) {
+                // one lane walks c and c ^ d2c in step over the stored pairs
+                // at lo and lo ^ d2lo, writing both outputs and summing them
+                // (the cooperative tiers leave the sums to the next
+                // measurement's own streaming reduction, which they run faster)
+                const cpx<R> f2 = fac(d2c), g2 = fac(d2c ^ dc);
+                const R sg2 = sigma(d2c);
+                // a plain loop over the steps (unrolled, the two walks would
+                // cost the kernel its occupancy); beta[t] by selection
+                auto beta_at = [&](int t) {
+                  // constant indices only: a loop here would leave beta in memory
+                  static_assert(ND == 4, "four deferred factors");
+                  const cpx<R> b01 = t == 1 ? beta[1] : beta[0];
+                  const cpx<R> b23 = t == 3 ? beta[3] : beta[2];
+                  return t >= 2 ? b23 : b01;
+                };
+                auto step_d = [&](cpx<R>& x, cpx<R>& y, int t, bool nb, uint32_t off) {
+                  const cpx<R> bt = beta_at(t);
+                  const bool xb = nb ^ ((off >> t) & 1u);
+                  x = cmul(x, bt.re, xb ? bt.im : -bt.im);
+                  const bool yb = xb ^ ((dc >> t) & 1u);
+                  const R sg = ((smc >> t) & 1u) ? (R)-1 : (R)1;
+                  y = cmul(y, sg * bt.re, yb ? sg * bt.im : -sg * bt.im);
+                };
+                const uint32_t nc = 1u << dfr;
+                for (uint32_t q = G == 1 ? 0u : (uint32_t)grp.tid; q < nq; q += st) {
+                  const uint32_t la = row_a(q);
+                  const uint32_t lb = la ^ d2lo;
+                  cpx<R> xa = vec[la];
+                  cpx<R> ya = partner_lo(vec[la ^ dlo], la);
+                  cpx<R> xb = vec[lb];
+                  cpx<R> yb = partner_lo(vec[lb ^ dlo], lb);
+                  ya = cmul(ya, sg0 * g0.re, sg0 * g0.im);
+                  xb = cmul(xb, f2.re, f2.im);
+                  yb = cmul(yb, sg2 * g2.re, sg2 * g2.im);
+                  for (uint32_t j = 0; j < nc; j++) {
+                    const uint32_t c = j ^ (j >> 1);
+                    if (j) {
+                      const int t = __builtin_ctz(j);
+                      const bool nb = (c >> t) & 1u;
+                      step_d(xa, ya, t, nb, 0u);
+                      step_d(xb, yb, t, nb, d2c);
+                    }
+                    if ((c & bsc) || (same_row && (c & piv))) continue;  // a partner, or emitted from its pair
+                    const uint32_t oa = oidx(la, c), ob = oidx(lb, c ^ d2c);
+                    const cpx<R> va = out1(xa, ya), vb = out1(xb, yb);
+                    dst[oa] = va;
+                    dst[ob] = vb;
+                    const bool a0 = !(oa & b2);
+                    branch_sums(nx, a0 ? va : vb, partner2(a0 ? vb : va, (a0 ? oa : ob) | b2), n0, n1);
                   }
                 }
-              };
-              if (dfr == 1) walk(IntC<1>{});
-              else if (dfr == 2) walk(IntC<2 <= ND ? 2 : 1>{});
-              else if (dfr == 3) walk(IntC<3 <= ND ? 3 : 1>{});
-              else walk(IntC<4 <= ND ? 4 : 1>{});
+                fused_sums = true;
+              } else {
+                auto walk = [&](auto DT) {
+                  constexpr int D = decltype(DT)::value;
+                  for (uint32_t q = G == 1 ? 0u : (uint32_t)grp.tid; q < npairs; q += st) {
+                    const uint32_t lo = s < dm ? ins0(q, s) : q;
+                    cpx<R> av = vec[lo];
+                    cpx<R> pv = partner_lo(vec[lo ^ dlo], lo);
+                    pv = cmul(pv, sg0 * g0.re, sg0 * g0.im);
+                    auto put_out = [&](uint32_t c) {
+                      if (c & bsc) return;
+                      dst[oidx(lo, c)] = out1(av, pv);
+                    };
+                    put_out(0);
+#pragma unroll
+                    for (int j = 1; j < (1 << D); j++) {
+                      const int t = __builtin_ctz(j);
+                      const uint32_t c = (uint32_t)(j ^ (j >> 1));
+                      step(av, pv, t, (c >> t) & 1u, 0u);
+                      put_out(c);
+                    }
+                  }
+                };
+                if (dfr == 1) walk(IntC<1>{});
+                else if (dfr == 2) walk(IntC<2 <= ND ? 2 : 1>{});
+                else if (dfr == 3) walk(IntC<3 <= ND ? 3 : 1>{});
+                else walk(IntC<4 <= ND ? 4 : 1>{});
+              }
               dfr = 0;
             } else if (fuse) {
               // outputs (j0, j1): the next measurement's pair through its own
