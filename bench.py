@@ -21,11 +21,54 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "shots/sec at matched detector-rate accuracy, FP32-batched vs FP64-plain"
-PEAK_INT_OPS = 256 * 64 * 2.4e9      # 32-bit VALU lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# 32-bit VALU lane-ops/s at the rate the published FP32 vector figure implies
+# (157.3 TFLOP/s = 2 flops x 128 lanes x 256 CUs x 2.4 GHz).  The 16-lane SIMD
+# count (39.3 T) is not an upper bound here: the integer probe exceeds it.
+PEAK_INT_OPS = 256 * 128 * 2.4e9
 PEAK_FP32 = 157.3e12                 # FP32 vector FLOP/s
 PEAK_FP64 = 78.6e12                  # FP64 vector FLOP/s
 PEAK_HBM = 8.0e12                    # HBM3E bytes/s
 PEAK_LDS = 256 * 128 * 2.4e9         # LDS bytes/s: 128 B/clk/CU
+
+
+def measured_peak(bound, pk, torch):
+    """Achievable rate on this device for the bound, from the library's
+    probes timed with HIP events on the current stream: a 1 GiB device copy
+    (read + write bytes) for "hbm", 16 full-rate VALU instructions per
+    iteration for "alu".  None for other bounds."""
+    if bound not in ("hbm", "alu"):
+        return None
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if bound == "hbm":
+        n = 1 << 30
+        src = torch.empty(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        grid = 256 * 16
+        run = lambda: pk.probe(0, dst, src, n, grid, st)
+        work, unit = 2.0 * n, 1e9
+    else:
+        grid, iters = 256 * 16, 2048
+        dst = torch.empty(grid * 256, dtype=torch.int32, device="cuda")
+        run = lambda: pk.probe(1, dst, None, iters, grid, st)
+        work, unit = 16.0 * iters * grid * 256, 1e12
+    run()
+    torch.cuda.synchronize()
+    reps = 10
+    e0.record(st)
+    for _ in range(reps):
+        run()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return work * reps / (e0.elapsed_time(e1) * 1e-3) / unit
+
+
+def add_measured_peak(roof, pk, torch):
+    m = measured_peak(roof["bound"], pk, torch)
+    if m:
+        roof["peak_measured"] = m
+        roof["frac_measured"] = roof["achieved"] / m
 
 
 def load_traffic(workload, precision, kernel):
@@ -157,6 +200,7 @@ def bench_batch(args, w, pk, torch):
                                        "frac": table_bytes / (kernel_ms * 1e-3) / PEAK_HBM},
                      "traffic": None, "kernel_ms": kernel_ms},
     }
+    add_measured_peak(line["roofline"], pk, torch)
     print(json.dumps(line))
 
 
@@ -279,6 +323,7 @@ def main():
         roof["traffic_over_algorithmic"] = traffic / max(1.0, (vb + cost["record_bytes"]) * shots)
     roof["kernel_ms"] = kernel_ms
     roof["work_per_shot"] = {kk: round(v, 3) for kk, v in cost.items()}
+    add_measured_peak(roof, pk, torch)
 
     line = {
         "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,

@@ -229,6 +229,19 @@ void clifft_batch_free(clifft_batch* b);
 /* Release a program and its device copies. */
 void clifft_program_free(clifft_program* p);
 
+/* ---- Rate probes (measurement support, not part of sampling): kernels
+ * whose work is known exactly, for the caller to time on `stream` and so
+ * state achievable rates beside the published peaks.
+ *   kind 0: copy n bytes (a multiple of 16) from src to dst, both device
+ *           buffers of the caller (grid-stride, 16-byte elements);
+ *   kind 1: n iterations (< 2^32) of 16 full-rate 32-bit VALU instructions
+ *           per thread (eight independent xor/add chains); dst is a device
+ *           buffer of grid * 256 uint32 that receives one word per thread,
+ *           the XOR of the chains a <- (a ^ 0x9E3779B9) + 0x9E3779B9 started
+ *           at 8 * thread + j.
+ * grid: workgroups of 256 threads.  Asynchronous; errors as status codes. */
+clifft_status clifft_probe(int32_t kind, void* dst, const void* src, uint64_t n, int32_t grid, void* stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* clifft_last_error(void);
 

@@ -73,11 +73,13 @@ def lib():
         L.clifft_autotune.argtypes = [vp, u64, ctypes.c_int32, vp, ctypes.POINTER(clifft_launch)]
         L.clifft_specialize.argtypes = [vp, ctypes.c_char_p, sz]
         L.clifft_program_free.argtypes = [vp]
+        L.clifft_probe.argtypes = [ctypes.c_int32, vp, vp, u64, ctypes.c_int32, vp]
         L.clifft_last_error.restype = ctypes.c_char_p
         for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
                   "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_trace",
                   "clifft_cost_model", "clifft_resolve_launch", "clifft_batch_create", "clifft_batch_sizes",
-                  "clifft_batch_layout", "clifft_batch_sample", "clifft_autotune", "clifft_specialize"):
+                  "clifft_batch_layout", "clifft_batch_sample", "clifft_autotune", "clifft_specialize",
+                  "clifft_probe"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -86,6 +88,14 @@ def lib():
 def _check(st):
     if st != 0:
         raise ClifftError(st, lib().clifft_last_error().decode())
+
+
+def probe(kind, dst, src=None, n=0, grid=1, stream=None):
+    """clifft_probe on device tensors (kind 0: copy n bytes src -> dst;
+    kind 1: n iterations of 16 VALU instructions per thread into dst)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().clifft_probe(kind, dst.data_ptr(), None if src is None else src.data_ptr(), n, grid, s.cuda_stream))
 
 
 def make_launch(precision="f32", threads_per_shot=0, grid=0, vector_in_hbm=0, specialize=0):

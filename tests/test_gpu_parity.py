@@ -107,6 +107,21 @@ def test_shard_resume_bit_identical_gpu(G):
         assert np.array_equal(x, np.concatenate([y, z], axis=1))
 
 
+@pytest.mark.parametrize("G", [1, 64, 256])
+def test_shard_resume_active_hbm_fp64(G):
+    """Shards of an active-vector program on the HBM tiers (the cooperative
+    ones OR single shots' record bits into zero-filled rows) join into the
+    unsharded records bit for bit, and equal the oracle's."""
+    text = circuits.workload("random_clifford_t_n8")["texts"][0]
+    a = gpu_sample(text, 4096, seed=9, precision="f64", threads_per_shot=G, vector_in_hbm=1)
+    b = gpu_sample(text, 2048, seed=9, offset=0, precision="f64", threads_per_shot=G, vector_in_hbm=1)
+    c = gpu_sample(text, 2048, seed=9, offset=2048, precision="f64", threads_per_shot=G, vector_in_hbm=1)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, np.concatenate([y, z], axis=1))
+    om, _, _ = oracle.Program(text).sample(4096, seed=9, threads=8)
+    assert np.array_equal(a[0], om)
+
+
 @pytest.mark.parametrize("case", range(16))
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_random_circuits_records(case, precision):
