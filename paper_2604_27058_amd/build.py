@@ -14,7 +14,8 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unus
           "-I" + os.path.join(os.path.dirname(HERE), "include"), "-I" + os.path.join(HERE, "_build")]
 # Packed FP32 VALU ops stay disabled in device code on this target.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = [("kernels.hip", True), ("runtime.cpp", True), ("specialize.cpp", True), ("compiler.cpp", False)]
+SOURCES = [("kernels.hip", True), ("probe.hip", True), ("runtime.cpp", True), ("specialize.cpp", True),
+           ("compiler.cpp", False)]
 # device text compiled at run time by the specialized-kernel generator
 PRELUDE = ["philox.h", "spec_args.h", "spec_prelude.h"]
 

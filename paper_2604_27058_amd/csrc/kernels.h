@@ -62,10 +62,6 @@ hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArg
                         const BatchArgs& lanes, int grid_lanes, size_t lds_bytes, bool fp64, hipStream_t stream);
 
 hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t stream);
-// Rate probes: kind 0 copies n bytes (a multiple of 16) from src to dst;
-// kind 1 runs n iterations of 16 VALU instructions per thread and writes
-// one word per thread to dst.  Workgroups of 256 threads.
-hipError_t launch_probe(int kind, void* dst, const void* src, uint64_t n, int grid, hipStream_t stream);
 // Bit-sliced Pauli-frame kernel (k_max = 0): 32 shots per lane, one 64-thread
 // workgroup per 2048-shot tile.
 hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStream_t stream);

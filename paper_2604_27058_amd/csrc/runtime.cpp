@@ -16,6 +16,7 @@
 #include "kernels.h"
 #include "spec_args.h"
 #include "specialize.h"
+#include "probe.h"
 
 using namespace clifft;
 
