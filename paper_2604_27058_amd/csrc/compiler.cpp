@@ -603,7 +603,9 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
   c.record_bytes = (P.nrec + P.ndet + P.nobs) / 8.0;
 
   // Fused passes of the HBM tiers: localization passes folded into the next
-  // measurement move nothing; up to kDeferMax trailing expansions move
+  // measurement or H pass move nothing (that pass reads through them, the H
+  // pass out of place, and also applies a rotation on its slot that directly
+  // follows it); up to kDeferMax trailing expansions move
   // nothing until the next active measurement reads the stored 2^(k-d)
   // elements (once for its branch sums, once for its collapse, which writes
   // all 2^(k-1) outputs, and on the lane tier carries the next
@@ -629,7 +631,14 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
         case OP_APERM: case OP_ASIGN: case OP_AS:
           if (!(in.flags & F_FOLD_NEXT)) { materialize(); bytes += A * a; carried = false; }
           break;
-        case OP_APERM2: case OP_AROT: materialize(); bytes += A * a; carried = false; break;
+        case OP_AROT:
+          // directly after an H on its slot, the H pass applies it
+          if (i > 0 && P.code[i - 1].op == OP_AH && P.code[i - 1].s == in.s) break;
+          materialize();
+          bytes += A * a;
+          carried = false;
+          break;
+        case OP_APERM2: materialize(); bytes += A * a; carried = false; break;
         case OP_AH: materialize(); bytes += 2 * A * a; carried = false; break;
         case OP_EXPAND:
           if (dfr == kDeferMax) {
@@ -852,7 +861,7 @@ int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& 
       if (touches_vector(P.code[i].op)) vecops.push_back(i);
     for (size_t n = 0; n < vecops.size(); n++) {
       const GInstr& m = P.code[vecops[n]];
-      if (!is_meas(m.op)) continue;
+      if (!is_meas(m.op) && m.op != OP_AH) continue;  // an H pass on the slot reads through them too
       size_t j = n;
       const uint8_t order[3] = {OP_AS, OP_ASIGN, OP_APERM};  // backwards from the measurement
       for (uint8_t want : order) {

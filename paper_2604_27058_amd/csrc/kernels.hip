@@ -642,13 +642,62 @@ struct Shot {
           materialize();
           const R h = (R)0.70710678118654752440;
           const uint32_t bs = 1u << s;
-          pass2<G, R, U>(grp, vec, 1u << (k - 1),
-                      [&](uint32_t p, uint32_t& i0, uint32_t& i1) { i0 = ins0(p, s); i1 = i0 | bs; },
-                      [h](cpx<R>& a, cpx<R>& b) {
-                        cpx<R> x{h * (a.re + b.re), h * (a.im + b.im)};
-                        b = cpx<R>{h * (a.re - b.re), h * (a.im - b.im)};
-                        a = x;
-                      });
+          if constexpr (OOP) {
+            // out of place: a rotation on this slot that directly follows is
+            // applied to the written upper halves, and folded localization
+            // passes are read through (the element of i1 is that of i1 ^ tm,
+            // signed by parity(i1 & sm), times i for S)
+            const GInstr nx = load_instr(P.code, pc + 1);
+            const bool rot = nx.op == OP_AROT && nx.s == s;
+            R rr = (R)1, ri = (R)0;
+            if (rot) {
+              double c2 = P.consts[2 * nx.a], s2 = P.consts[2 * nx.a + 1];
+              if (getbit<W>(T.x, nx.v)) s2 = -s2;
+              rr = (R)c2;
+              ri = (R)s2;
+            }
+            const uint32_t tm = pend_tm, sm = pend_sm;
+            const bool fas = pend_as;
+            const Vec<G, R> dst{alt, vec.lane};
+            const uint32_t n = 1u << (k - 1), st = G == 1 ? 1u : (uint32_t)G;
+            constexpr int UH = G == 1 ? 1 : (U >= 4 ? U / 4 : 1);
+            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += UH * st) {
+              uint32_t ii[UH];
+              cpx<R> a[UH], c[UH];
+#pragma unroll
+              for (int u = 0; u < UH; u++) {
+                const uint32_t q = base + u * st;
+                ii[u] = ins0(q < n ? q : base, s);
+                if (q < n) {
+                  a[u] = vec[ii[u]];
+                  c[u] = vec[(ii[u] | bs) ^ tm];
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < UH; u++) {
+                if (base + u * st >= n) continue;
+                const uint32_t i1 = ii[u] | bs;
+                cpx<R> y = (__popc(i1 & sm) & 1) ? cpx<R>{-c[u].re, -c[u].im} : c[u];
+                if (fas) y = cpx<R>{-y.im, y.re};
+                dst[ii[u]] = cpx<R>{h * (a[u].re + y.re), h * (a[u].im + y.im)};
+                dst[i1] = cmul(cpx<R>{h * (a[u].re - y.re), h * (a[u].im - y.im)}, rr, ri);
+              }
+            }
+            cpx<R>* t = vec.base;
+            vec.base = alt;
+            alt = t;
+            pend_tm = pend_sm = 0;
+            pend_as = false;
+            if (rot) pc++;
+          } else {
+            pass2<G, R, U>(grp, vec, 1u << (k - 1),
+                        [&](uint32_t p, uint32_t& i0, uint32_t& i1) { i0 = ins0(p, s); i1 = i0 | bs; },
+                        [h](cpx<R>& a, cpx<R>& b) {
+                          cpx<R> x{h * (a.re + b.re), h * (a.im + b.im)};
+                          b = cpx<R>{h * (a.re - b.re), h * (a.im - b.im)};
+                          a = x;
+                        });
+          }
           grp.sync();
           }
           break;

@@ -43,12 +43,12 @@ enum Op : uint8_t {
 
 // flags
 constexpr uint8_t F_SIGN = 1;        // sign bit of the localized observable
-// Localization passes of an active measurement (Appendix A with an active
-// pivot): an OP_APERM, then an OP_ASIGN, then an OP_AS, each optional, on
-// the measured slot and directly before the measurement among the vector
-// instructions.  They permute and rephase only the elements whose measured
-// bit is set, so kernels that collapse out of place skip them
-// (F_FOLD_NEXT) and read the measurement through them.
+// Localization passes of an active measurement or H (Appendix A with an
+// active pivot): an OP_APERM, then an OP_ASIGN, then an OP_AS, each
+// optional, on the measured (or H) slot and directly before that
+// instruction among the vector instructions.  They permute and rephase only
+// the elements whose bit on that slot is set, so kernels that work out of
+// place skip them (F_FOLD_NEXT) and read the next pass through them.
 constexpr uint8_t F_FOLD_NEXT = 8;
 // Active measurement whose next vector instruction, after folded passes, is
 // again an active measurement: this measurement's collapse pass accumulates

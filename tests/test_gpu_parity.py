@@ -161,17 +161,9 @@ def _align(a, b):
     return a * (ov / abs(ov)), b
 
 
-@pytest.mark.parametrize("case", range(12))
-@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
-@pytest.mark.parametrize("tier", [None, (1, 1), (64, 1), (256, 1)], ids=["auto", "lane-hbm", "wave-hbm", "group-hbm"])
-def test_forced_probabilities_and_amplitudes(case, precision, tol, tier):
-    """Forced outcomes and faults of oracle shots: every measurement's
-    probability and the final vector.  The HBM tiers collapse out of place
-    through folded localization passes and deferred expansions (a Z or X
-    measurement on a stored or a deferred slot)."""
-    rng = np.random.default_rng(700 + case)
-    n = int(rng.integers(2, 6))
-    text = random_small_circuit(rng, n, int(rng.integers(10, 45))).rsplit("M ", 1)[0]  # keep the final vector
+def _forced_check(text, case, precision, tol, tier, rng):
+    """Forces the faults and outcomes of oracle shots (plus extra faults) and
+    compares every measurement's probability and the final vector."""
     op = oracle.Program(text)
     gp = pk.Program(text)
     shots = 8
@@ -212,6 +204,57 @@ def test_forced_probabilities_and_amplitudes(case, precision, tol, tier):
         worst_v = max(worst_v, float(np.linalg.norm(a - b) / np.linalg.norm(b)))
     print("%s case %d: worst relative probability error %.3g, vector error %.3g" % (precision, case, worst_p, worst_v))
     assert worst_p <= tol and worst_v <= tol
+
+
+@pytest.mark.parametrize("case", range(12))
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
+@pytest.mark.parametrize("tier", [None, (1, 1), (64, 1), (256, 1)], ids=["auto", "lane-hbm", "wave-hbm", "group-hbm"])
+def test_forced_probabilities_and_amplitudes(case, precision, tol, tier):
+    """Forced outcomes and faults of oracle shots: every measurement's
+    probability and the final vector.  The HBM tiers collapse out of place
+    through folded localization passes and deferred expansions (a Z or X
+    measurement on a stored or a deferred slot)."""
+    rng = np.random.default_rng(700 + case)
+    n = int(rng.integers(2, 6))
+    text = random_small_circuit(rng, n, int(rng.integers(10, 45))).rsplit("M ", 1)[0]  # keep the final vector
+    _forced_check(text, case, precision, tol, tier, rng)
+
+
+def active_rotation_circuit(rng, n, layers):
+    """Every qubit expanded first (H, T), then Cliffords, rotations, noise and
+    a few measurements on the active register: rotations whose generator has
+    X support only on active qubits become an H pass on their pivot slot, with
+    its localization passes before it and the diagonal rotation right after."""
+    lines = ["H %d" % q for q in range(n)] + ["T %d" % q for q in range(n)]
+    for _ in range(layers):
+        q = int(rng.integers(0, n))
+        r = rng.random()
+        if r < 0.3:
+            lines.append("%s %d" % (["H", "S", "S_DAG", "X"][int(rng.integers(0, 4))], q))
+        elif r < 0.55:
+            a, b = [int(v) for v in rng.choice(n, 2, replace=False)]
+            lines.append("%s %d %d" % (["CX", "CZ"][int(rng.integers(0, 2))], a, b))
+        elif r < 0.82:
+            lines.append(["T %d" % q, "T_DAG %d" % q, "R_Z(%r) %d" % (float(rng.uniform(-3, 3)), q)][int(rng.integers(0, 3))])
+        elif r < 0.9:
+            lines.append("%s %d" % (["MX", "M"][int(rng.integers(0, 2))], q))
+        else:
+            lines.append("%s(%r) %d" % (["X_ERROR", "Z_ERROR", "DEPOLARIZE1"][int(rng.integers(0, 3))],
+                                        float(rng.uniform(0.02, 0.1)), q))
+    return "\n".join(lines) + "\n"
+
+
+@pytest.mark.parametrize("case", range(8))
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
+@pytest.mark.parametrize("tier", [None, (1, 1), (64, 1), (256, 1)], ids=["auto", "lane-hbm", "wave-hbm", "group-hbm"])
+def test_forced_active_rotations(case, precision, tol, tier):
+    """H passes on active slots: on the HBM tiers they read their folded
+    localization passes and apply the rotation that follows them in the same
+    out-of-place pass (seeds 1300..1307 compile to several such passes)."""
+    rng = np.random.default_rng(1300 + case)
+    n = int(rng.integers(3, 6))
+    text = active_rotation_circuit(rng, n, int(rng.integers(20, 40)))
+    _forced_check(text, case, precision, tol, tier, rng)
 
 
 TIERS = [(1, -1), (1, 1), (64, -1), (64, 1), (256, -1), (256, 1)]  # (threads per shot, vector in HBM)
