@@ -604,8 +604,9 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
 
   // Fused passes of the HBM tiers: localization passes folded into the next
   // measurement or H pass move nothing (that pass reads through them, the H
-  // pass out of place, and also applies a rotation on its slot that directly
-  // follows it); up to kDeferMax trailing expansions move
+  // pass out of place and through deferred expansions, and also applies a
+  // rotation on its slot that directly follows it); up to kDeferMax
+  // trailing expansions move
   // nothing until the next active measurement reads the stored 2^(k-d)
   // elements (once for its branch sums, once for its collapse, which writes
   // all 2^(k-1) outputs, and on the lane tier carries the next
@@ -639,7 +640,7 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
           carried = false;
           break;
         case OP_APERM2: materialize(); bytes += A * a; carried = false; break;
-        case OP_AH: materialize(); bytes += 2 * A * a; carried = false; break;
+        case OP_AH: bytes += 2 * A * a; dfr = 0; carried = false; break;  // reads through deferred factors
         case OP_EXPAND:
           if (dfr == kDeferMax) {
             bytes += 2 * stored * a;

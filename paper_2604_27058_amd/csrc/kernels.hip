@@ -639,14 +639,21 @@ struct Shot {
           if constexpr (!VEC) break;
           else {
           carry_valid = false;
-          materialize();
+          if constexpr (!OOP) materialize();
           const R h = (R)0.70710678118654752440;
           const uint32_t bs = 1u << s;
           if constexpr (OOP) {
             // out of place: a rotation on this slot that directly follows is
             // applied to the written upper halves, and folded localization
             // passes are read through (the element of i1 is that of i1 ^ tm,
-            // signed by parity(i1 & sm), times i for S)
+            // signed by parity(i1 & sm), times i for S), as are deferred
+            // expansions (element x is stored[x mod 2^dm] times its factor)
+            const int dm = k - dfr;
+            const uint32_t lmask = (1u << dm) - 1u;
+            auto rdx = [&](uint32_t x) {
+              const cpx<R> e = vec[x & lmask], f = fac(x >> dm);
+              return cpx<R>{e.re * f.re - e.im * f.im, e.re * f.im + e.im * f.re};
+            };
             const GInstr nx = load_instr(P.code, pc + 1);
             const bool rot = nx.op == OP_AROT && nx.s == s;
             R rr = (R)1, ri = (R)0;
@@ -669,8 +676,8 @@ struct Shot {
                 const uint32_t q = base + u * st;
                 ii[u] = ins0(q < n ? q : base, s);
                 if (q < n) {
-                  a[u] = vec[ii[u]];
-                  c[u] = vec[(ii[u] | bs) ^ tm];
+                  a[u] = rdx(ii[u]);
+                  c[u] = rdx((ii[u] | bs) ^ tm);
                 }
               }
 #pragma unroll
@@ -688,6 +695,7 @@ struct Shot {
             alt = t;
             pend_tm = pend_sm = 0;
             pend_as = false;
+            dfr = 0;
             if (rot) pc++;
           } else {
             pass2<G, R, U>(grp, vec, 1u << (k - 1),
