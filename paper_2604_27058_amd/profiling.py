@@ -81,7 +81,9 @@ def traffic(fetch_dir, write_dir, copy_bytes, workload, prec):
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = _pmc(d, counter)
-        copy = [v for (k, _), v in per.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        # the calibration copy (the rate probes that bench also runs are not it)
+        copy = [v for (k, _), v in per.items()
+                if ("copy" in k.lower() or "elementwise" in k.lower()) and "probe" not in k.lower()]
         # the timed launch is the last sampling dispatch (earlier ones are the
         # launch-shape trials of the autotuner, if it ran)
         samp = sorted(((int(d), k, v) for (k, d), v in per.items() if any(n in k for n in SAMPLING_KERNELS)))
