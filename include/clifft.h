@@ -238,7 +238,10 @@ void clifft_program_free(clifft_program* p);
  *           per thread (eight independent xor/add chains); dst is a device
  *           buffer of grid * 256 uint32 that receives one word per thread,
  *           the XOR of the chains a <- (a ^ 0x9E3779B9) + 0x9E3779B9 started
- *           at 8 * thread + j.
+ *           at 8 * thread + j;
+ *   kind 2: read n bytes (a multiple of 16) of src; dst is a device buffer
+ *           of grid * 256 16-byte elements that receives, per thread, the
+ *           XOR of the elements it read (grid-stride). 
  * grid: workgroups of 256 threads.  Asynchronous; errors as status codes. */
 clifft_status clifft_probe(int32_t kind, void* dst, const void* src, uint64_t n, int32_t grid, void* stream);
 

@@ -10,6 +10,21 @@ __global__ __launch_bounds__(256) void k_probe_copy(uint4* __restrict__ dst, con
     dst[i] = src[i];
 }
 
+// A read-only sweep: every thread XORs the 16-byte elements it reads and
+// writes one element, so the reads cannot be dropped.
+__global__ __launch_bounds__(256) void k_probe_read(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n) {
+  uint4 acc = make_uint4(0, 0, 0, 0);
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (size_t i = g; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const uint4 v = src[i];
+    acc.x ^= v.x;
+    acc.y ^= v.y;
+    acc.z ^= v.z;
+    acc.w ^= v.w;
+  }
+  dst[g] = acc;
+}
+
 // Eight independent chains a = (a ^ c) + c: each iteration issues exactly
 // 16 VALU instructions per lane (written out so that none is fused away).
 __global__ __launch_bounds__(256) void k_probe_int(uint32_t* dst, uint32_t iters) {
@@ -35,7 +50,8 @@ __global__ __launch_bounds__(256) void k_probe_int(uint32_t* dst, uint32_t iters
 
 hipError_t launch_probe(int kind, void* dst, const void* src, uint64_t n, int grid, hipStream_t st) {
   if (kind == 0) hipLaunchKernelGGL(k_probe_copy, dim3(grid), dim3(256), 0, st, (uint4*)dst, (const uint4*)src, (size_t)(n / 16));
-  else hipLaunchKernelGGL(k_probe_int, dim3(grid), dim3(256), 0, st, (uint32_t*)dst, (uint32_t)n);
+  else if (kind == 1) hipLaunchKernelGGL(k_probe_int, dim3(grid), dim3(256), 0, st, (uint32_t*)dst, (uint32_t)n);
+  else hipLaunchKernelGGL(k_probe_read, dim3(grid), dim3(256), 0, st, (uint4*)dst, (const uint4*)src, (size_t)(n / 16));
   return hipGetLastError();
 }
 

@@ -828,8 +828,9 @@ void clifft_program_free(clifft_program* p) {
 }
 
 clifft_status clifft_probe(int32_t kind, void* dst, const void* src, uint64_t n, int32_t grid, void* stream) {
-  if (!dst || grid <= 0 || (kind != 0 && kind != 1)) return fail(CLIFFT_E_INVALID_ARG, "bad probe arguments");
-  if (kind == 0 && (!src || n % 16 != 0)) return fail(CLIFFT_E_INVALID_ARG, "copy probe needs src and a multiple of 16 bytes");
+  if (!dst || grid <= 0 || kind < 0 || kind > 2) return fail(CLIFFT_E_INVALID_ARG, "bad probe arguments");
+  if (kind != 1 && (!src || n % 16 != 0))
+    return fail(CLIFFT_E_INVALID_ARG, "copy and read probes need src and a multiple of 16 bytes");
   if (kind == 1 && n > 0xFFFFFFFFull) return fail(CLIFFT_E_INVALID_ARG, "too many probe iterations");
   hipError_t e = launch_probe(kind, dst, src, n, grid, (hipStream_t)stream);
   if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("probe launch failed: ") + hipGetErrorString(e));

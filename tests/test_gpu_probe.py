@@ -19,6 +19,20 @@ def test_copy_probe_copies():
     assert torch.equal(dst, src)
 
 
+def test_read_probe_reads():
+    grid, n = 5, (1 << 20) + 32
+    src = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(grid * 256 * 16, dtype=torch.uint8, device="cuda")
+    pk.probe(2, dst, src, n, grid)
+    torch.cuda.synchronize()
+    words = src.cpu().numpy().view(np.uint32).reshape(-1, 4)
+    out = dst.cpu().numpy().view(np.uint32).reshape(-1, 4)
+    T = grid * 256
+    for t in (0, 1, T - 1):
+        ref = np.bitwise_xor.reduce(words[t::T], axis=0)
+        assert np.array_equal(out[t], ref), t
+
+
 def test_valu_probe_chains():
     grid, iters = 3, 37
     dst = torch.zeros(grid * 256, dtype=torch.int32, device="cuda")
@@ -37,8 +51,12 @@ def test_valu_probe_chains():
 
 
 def test_probe_rejects_bad_arguments():
-    x = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    # sized for one workgroup's outputs, so that no call here could write
+    # beyond it even if it were accepted
+    x = torch.zeros(256 * 16, dtype=torch.uint8, device="cuda")
     with pytest.raises(pk.ClifftError):
         pk.probe(0, x, x, 63, 1)
     with pytest.raises(pk.ClifftError):
-        pk.probe(2, x, x, 16, 1)
+        pk.probe(2, x, x, 17, 1)
+    with pytest.raises(pk.ClifftError):
+        pk.probe(3, x, x, 16, 1)
