@@ -110,3 +110,32 @@ def test_specialize_host_only():
     with pytest.raises(pk.ClifftError):
         p.resolve_launch(10 ** 6, pk.make_launch("f32", 1, specialize=1))
     assert p.resolve_launch(10 ** 6, pk.make_launch("f32", 1, specialize=-1))["specialize"] == 0  # not bit-sliced
+
+
+def test_fused_byte_model_pins():
+    """The fused-pass byte model the HBM rooflines are priced on.  Six fresh
+    qubits expanded in a row with nothing reading the vector: four
+    expansions stay deferred, the fifth and sixth each apply the oldest
+    (reading and writing 2^0, then 2^1 stored amplitudes)."""
+    n = 6
+    text = "".join("H %d\n" % q for q in range(n)) + "".join("T %d\n" % q for q in range(n))
+    p = pk.Program(text)
+    assert p.k_max == n
+    for prec, amp in (("f32", 8), ("f64", 16)):
+        c = p.cost_model(prec)
+        assert c["vector_bytes_fused"] == c["vector_bytes_fused_group"] == (2 * 1 + 2 * 2) * amp
+        # the unfused table charges every expansion a read and a write of 2^k
+        assert c["vector_bytes"] == sum(2 * (1 << k) * amp for k in range(n))
+
+
+@pytest.mark.parametrize("name", ["random_clifford_t_n8", "surface_d5_r5_t10", "large_active_k20"])
+def test_fused_byte_model_orders(name):
+    """Fusing never adds bytes, and the lane tier (which also carries branch
+    sums through deferred expansions) moves no more than the cooperative
+    tiers."""
+    for text in circuits.workload(name)["texts"]:
+        c = pk.Program(text).cost_model("f32")
+        assert 0 < c["vector_bytes_fused"] <= c["vector_bytes_fused_group"] <= c["vector_bytes"]
+    for spec in circuits.batched_set()[:16]:
+        c = pk.Program(spec["text"]).cost_model("f32")
+        assert c["vector_bytes_fused"] <= c["vector_bytes_fused_group"] <= c["vector_bytes"]
