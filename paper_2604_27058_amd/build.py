@@ -14,8 +14,11 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unus
           "-I" + os.path.join(os.path.dirname(HERE), "include"), "-I" + os.path.join(HERE, "_build")]
 # Packed FP32 VALU ops stay disabled in device code on this target.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = [("kernels.hip", True), ("probe.hip", True), ("runtime.cpp", True), ("specialize.cpp", True),
-           ("compiler.cpp", False)]
+# The interpreter's instantiations are spread over several translation units
+# so that they compile in parallel; the slowest ones are listed first.
+SOURCES = [("sample_f32.hip", True), ("sample_f64.hip", True), ("trace_f32.hip", True), ("trace_f64.hip", True),
+           ("batch.hip", True), ("frames.hip", True), ("kernels.hip", True), ("probe.hip", True),
+           ("runtime.cpp", True), ("specialize.cpp", True), ("compiler.cpp", False)]
 # device text compiled at run time by the specialized-kernel generator
 PRELUDE = ["philox.h", "spec_args.h", "spec_prelude.h"]
 
@@ -55,7 +58,7 @@ def _compile(item):
 def build(verbose=False):
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     _write_prelude()
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
         logs = list(ex.map(_compile, SOURCES))
     if verbose:
         for l in logs:

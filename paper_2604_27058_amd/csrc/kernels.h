@@ -69,5 +69,10 @@ size_t frames_lds_rows(const DevProgram& P);
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool trace,
                          hipStream_t stream);
 size_t lds_bytes_for(const DevProgram& P, int G, bool global_vec, bool fp64);
+// Interpreter instantiations, one translation unit each (sample_*.hip, trace_*.hip).
+hipError_t launch_sample_f32(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
+hipError_t launch_sample_f64(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
+hipError_t launch_trace_f32(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
+hipError_t launch_trace_f64(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
 
 }  // namespace clifft

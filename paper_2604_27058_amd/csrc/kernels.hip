@@ -1,1418 +1,15 @@
-// HIP kernels for gfx950: persistent shot-parallel interpreter of the
-// compiled instruction stream (the paper's sample-time virtual machine,
-// Section 3.2), re-designed for CDNA4.
-//
-// Execution shapes (template G = threads per shot):
-//   G = 1    shot per lane: 64 shots per wave; Pauli frames live in VGPRs as
-//            W 64-bit words per lane; the active vector of each lane lives in
-//            LDS, interleaved so that amplitude i of the 64 lanes is one
-//            contiguous 512-byte row (conflict-free).
-//   G = 64   shot per wave: the frames are wave-uniform (SGPR/SALU); the 2^k
-//            amplitudes are spread over the lanes (LDS).
-//   G = 256  shot per workgroup: as G = 64 with workgroup barriers between
-//            array passes; the active vector is in LDS or in a global
-//            workspace slice (HBM) for large k.
-// Records are bit-packed 64 shots per word (record-major) and staged in LDS
-// per 64-shot tile.
-// Pauli-frame-only programs (k_max = 0) also have a bit-sliced kernel
-// (k_frames: 32 shots per lane, one LDS row per frame bit), and many programs
-// can share one persistent launch (k_batch).
-//
-// Paper passages: Definition 2 (frame-factored state), Appendix B.1
-// (rotations: phase / expansion / active), Appendix B.2 (measurements:
-// dormant deterministic, dormant random, active mask / interfere),
-// Appendix B.3 (conditional Paulis: noise and feed-forward), Section 3.2
-// (sparse noise sampling by jumping to the next fault).
+// Launch dispatch of the sampling kernels and the record zero-fill kernel.
+// The interpreter itself is in shot.h; its instantiations are spread over
+// sample_f32.hip, sample_f64.hip, trace_f32.hip and trace_f64.hip, the
+// bit-sliced kernel is in frames.hip and the batched launch in batch.hip.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <algorithm>
 
 #include "kernels.h"
-#include "philox.h"
-#include "program.h"
 
 namespace clifft {
-
-#define DEV static __device__ __forceinline__
-#define MDEV __device__ __forceinline__
-#define DEV_HOST_INLINE static __host__ __device__ __forceinline__
-
-// ------------------------------------------------------------------ RNG
-using clifft_rng::draw;
-using clifft_rng::U4;
-using clifft_rng::uniform53;
-
-// ------------------------------------------------------------------ helpers
-// Complex amplitude.  Copies are member-wise: a struct copy of two doubles
-// otherwise lowers to memcpy and keeps pass buffers in scratch memory.
-template <typename R>
-struct cpx {
-  R re, im;
-  cpx() = default;
-  __host__ __device__ constexpr cpx(R r, R i) : re(r), im(i) {}
-  __host__ __device__ constexpr cpx(const cpx& o) : re(o.re), im(o.im) {}
-  __host__ __device__ cpx& operator=(const cpx& o) {
-    re = o.re;
-    im = o.im;
-    return *this;
-  }
-};
-
-DEV uint32_t ins0(uint32_t p, int s) { return ((p >> s) << (s + 1)) | (p & ((1u << s) - 1u)); }
-
-// Frame words as a small vector value: a word chosen by a run-time qubit
-// index then lowers to register selects, where a plain array would be
-// turned into a variable offset into private (scratch) memory.
-template <int W>
-using Words = uint64_t __attribute__((ext_vector_type(W)));
-
-template <int W>
-struct Frame {
-  Words<W> x, z;
-};
-
-template <int W>
-DEV uint32_t getbit(const Words<W>& a, int q) {
-  uint64_t v = a[0];
-#pragma unroll
-  for (int w = 1; w < W; w++)
-    if ((q >> 6) == w) v = a[w];
-  return (uint32_t)(v >> (q & 63)) & 1u;
-}
-
-template <int W>
-DEV void xorbit(Words<W>& a, int q, uint32_t b) {
-#pragma unroll
-  for (int w = 0; w < W; w++)
-    if ((q >> 6) == w) a[w] ^= (uint64_t)b << (q & 63);
-}
-
-template <int W>
-DEV uint32_t parity_and(const Words<W>& a, const uint64_t* m) {
-  uint64_t acc = 0;
-#pragma unroll
-  for (int w = 0; w < W; w++) acc ^= a[w] & m[w];
-  return (uint32_t)__popcll(acc) & 1u;
-}
-
-// Fan of CNOT v->q (q in mask): x ^= x_v * mask, z_v ^= parity(z & mask).
-template <int W>
-DEV void fan_cx(Frame<W>& f, int v, const uint64_t* m) {
-  uint64_t sel = 0ull - (uint64_t)getbit<W>(f.x, v);
-  uint32_t pz = parity_and<W>(f.z, m);
-#pragma unroll
-  for (int w = 0; w < W; w++) f.x[w] ^= sel & m[w];
-  xorbit<W>(f.z, v, pz);
-}
-// Fan of CZ v,q: z ^= x_v * mask, z_v ^= parity(x & mask).
-template <int W>
-DEV void fan_cz(Frame<W>& f, int v, const uint64_t* m) {
-  uint64_t sel = 0ull - (uint64_t)getbit<W>(f.x, v);
-  uint32_t px = parity_and<W>(f.x, m);
-#pragma unroll
-  for (int w = 0; w < W; w++) f.z[w] ^= sel & m[w];
-  xorbit<W>(f.z, v, px);
-}
-// Fan of CNOT q->v: x_v ^= parity(x & mask), z ^= z_v * mask.
-template <int W>
-DEV void fan_2(Frame<W>& f, int v, const uint64_t* m) {
-  uint64_t sel = 0ull - (uint64_t)getbit<W>(f.z, v);
-  uint32_t px = parity_and<W>(f.x, m);
-#pragma unroll
-  for (int w = 0; w < W; w++) f.z[w] ^= sel & m[w];
-  xorbit<W>(f.x, v, px);
-}
-template <int W>
-DEV void frame_s(Frame<W>& f, int v) { xorbit<W>(f.z, v, getbit<W>(f.x, v)); }
-template <int W>
-DEV void frame_h(Frame<W>& f, int v) {
-  uint32_t d = getbit<W>(f.x, v) ^ getbit<W>(f.z, v);
-  xorbit<W>(f.x, v, d);
-  xorbit<W>(f.z, v, d);
-}
-template <int W>
-DEV void frame_xor(Frame<W>& f, const uint64_t* px, const uint64_t* pz) {
-#pragma unroll
-  for (int w = 0; w < W; w++) { f.x[w] ^= px[w]; f.z[w] ^= pz[w]; }
-}
-
-// Scalar (SMEM) view of program data: uniform addresses read through the
-// constant address space so that the compiler issues s_load.
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T*;
-template <typename T>
-DEV cptr<T> as_const(const T* p) { return (cptr<T>)(p); }
-
-DEV uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// One 16-byte instruction through the scalar cache.
-DEV GInstr load_instr(const GInstr* code, int pc) {
-  cptr<uint32_t> w = (cptr<uint32_t>)(as_const(code) + pc);
-  uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
-  GInstr in;
-  in.op = (uint8_t)(w0 & 0xFF);
-  in.flags = (uint8_t)((w0 >> 8) & 0xFF);
-  in.v = (uint16_t)(w0 >> 16);
-  in.s = (uint16_t)(w1 & 0xFFFF);
-  in.u = (uint16_t)(w1 >> 16);
-  in.a = w2;
-  in.b = w3;
-  return in;
-}
-DEV double rfl(double v) {
-  uint64_t b = __double_as_longlong(v);
-  uint32_t lo = rfl((uint32_t)b), hi = rfl((uint32_t)(b >> 32));
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-// ------------------------------------------------------------------ group context
-template <int G>
-struct Group {
-  int tid;  // thread index inside the shot group
-  __device__ void sync() const {
-    if constexpr (G == 256) __syncthreads();
-    else if constexpr (G == 64) { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
-  }
-  __device__ double sum(double v, double* red) const {
-    if constexpr (G == 1) {
-      return v;
-    } else {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      if constexpr (G == 64) {
-        return rfl(v);
-      } else {
-        int wv = threadIdx.x >> 6;
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) red[wv] = v;
-        __syncthreads();
-        double t = red[0] + red[1] + red[2] + red[3];
-        return rfl(t);
-      }
-    }
-  }
-};
-
-// Amplitude storage: G == 1 lane-interleaved (element i of lane l at i*64+l),
-// otherwise element i of the group's vector at i.
-template <int G, typename R>
-struct Vec {
-  cpx<R>* base;
-  int lane;
-  __device__ cpx<R>& operator[](uint32_t i) const {
-    if constexpr (G == 1) return base[(size_t)i * 64 + lane];
-    else return base[i];
-  }
-};
-
-template <int N>
-struct IntC {
-  static constexpr int value = N;
-};
-
-// Iterate p over [0, n) split among the threads of a group.
-#define FOR_GROUP(p, n) for (uint32_t p = (G == 1 ? 0u : (uint32_t)grp.tid); p < (n); p += (G == 1 ? 1u : (uint32_t)G))
-
-// Unrolled passes over the active vector.  Iteration p touches an element
-// set disjoint from every other iteration's, so a batch of U iterations
-// issues all its loads before its stores (U independent loads in flight per
-// lane) without any hazard.
-constexpr int kUnroll = 4;        // iterations in flight per lane, vectors on chip
-constexpr int kUnrollGlobal = 8;  // FP32 vectors in HBM: more bytes in flight per wave
-template <typename R, bool GLOBAL>
-constexpr int unroll_for() { return GLOBAL && sizeof(R) == 4 ? kUnrollGlobal : kUnroll; }
-
-// Read-modify-write of one element per iteration: i = idx(p).
-template <int G, typename R, int U, typename IdxF, typename BodyF>
-DEV void pass1(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body) {
-  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
-    uint32_t ii[U];
-    cpx<R> a[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      uint32_t p = base + u * st;
-      ii[u] = idx(p < n ? p : base);
-      if (p < n) a[u] = vec[ii[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if (base + u * st < n) vec[ii[u]] = body(a[u]);
-  }
-}
-
-// Read-modify-write of a pair per iteration: (i0, i1) = idx(p).
-template <int G, typename R, int U, typename IdxF, typename BodyF>
-DEV void pass2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body) {
-  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
-    uint32_t i0[U], i1[U];
-    cpx<R> a[U], b[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      uint32_t p = base + u * st;
-      idx(p < n ? p : base, i0[u], i1[u]);
-      if (p < n) { a[u] = vec[i0[u]]; b[u] = vec[i1[u]]; }
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if (base + u * st < n) {
-        body(a[u], b[u]);
-        vec[i0[u]] = a[u];
-        vec[i1[u]] = b[u];
-      }
-  }
-}
-
-// Two reads, one write per iteration: out[wi(p)] = body(in[r0(p)], in[r1(p)])
-// (r1 may equal r0).  Used where a pass writes fewer elements than it reads.
-template <int G, typename R, int U, typename IdxF, typename BodyF>
-DEV void pass21(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body) {
-  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
-    uint32_t r0[U], r1[U], wi[U];
-    cpx<R> a[U], b[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      uint32_t p = base + u * st;
-      idx(p < n ? p : base, r0[u], r1[u], wi[u]);
-      if (p < n) { a[u] = vec[r0[u]]; b[u] = vec[r1[u]]; }
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if (base + u * st < n) vec[wi[u]] = body(a[u], b[u]);
-  }
-}
-
-// Read-only pairs accumulated into two FP64 sums (the body also gets the
-// iteration index).
-template <int G, typename R, int U, typename IdxF, typename BodyF>
-DEV void reduce2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx, BodyF body, double& s0,
-                 double& s1) {
-  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
-    cpx<R> a[U], b[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      uint32_t p = base + u * st;
-      uint32_t i0, i1;
-      idx(p < n ? p : base, i0, i1);
-      if (p < n) { a[u] = vec[i0]; b[u] = vec[i1]; }
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if (base + u * st < n) body(a[u], b[u], base + u * st, s0, s1);
-  }
-}
-
-// Gather pass into another buffer: dst[p] = gen(p) for p in [0, n) (gen
-// reads the source); all U values of a batch are formed before the stores.
-template <int G, typename R, int U, typename GenF>
-DEV void pass1_to(const Group<G>& grp, const Vec<G, R>& dst, uint32_t n, GenF gen) {
-  const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-  for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
-    cpx<R> v[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const uint32_t p = base + u * st;
-      if (p < n) v[u] = gen(p);
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const uint32_t p = base + u * st;
-      if (p < n) dst[p] = v[u];
-    }
-  }
-}
-
-template <typename R>
-DEV cpx<R> cmul(cpx<R> a, R cr, R ci) { return cpx<R>{a.re * cr - a.im * ci, a.re * ci + a.im * cr}; }
-template <typename R>
-DEV double norm2(cpx<R> a) { return (double)a.re * (double)a.re + (double)a.im * (double)a.im; }
-
-// ------------------------------------------------------------------ noise state
-struct Noise {
-  uint32_t chunk, ord, nf, nf_out;
-};
-
-DEV uint32_t nout_of(uint32_t t) { return t == S_DEP1 ? 3u : t == S_DEP2 ? 15u : 1u; }
-
-// Next fault at or after local index cur of the current chunk (Section 3.2,
-// jump to the next realized fault).  tau = u * S[cur]; the fault is the
-// smallest j with S[j+1] <= tau, j == len meaning none left in the chunk.
-DEV void next_fault(const DevProgram& P, Noise& ns, uint32_t cur, uint64_t shot, uint64_t seed) {
-  U4 w = draw(ns.ord++, kPurposeNoise | ns.chunk, shot, seed);
-  const double* S = P.surv + (size_t)ns.chunk * (kChunk + 1);
-  uint32_t len = min((uint32_t)kChunk, (uint32_t)P.nsites - ns.chunk * (uint32_t)kChunk);
-  double tau = uniform53(w) * S[cur];
-  uint32_t lo = cur, hi = len;
-  if (S[len] > tau) lo = len;  // no fault in the rest of the chunk (same answer as the search)
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (S[mid + 1] <= tau) hi = mid;
-    else lo = mid + 1;
-  }
-  ns.nf = ns.chunk * (uint32_t)kChunk + lo;
-  if (lo < len) {
-    uint64_t w64 = ((uint64_t)w.w3 << 32) | w.w2;
-    ns.nf_out = (uint32_t)__umul64hi(w64, (uint64_t)nout_of(P.site_type[ns.nf]));
-  }
-}
-
-template <int W>
-DEV void apply_fault(const DevProgram& P, Frame<W>& T, Frame<W>& N, uint32_t site, uint32_t o) {
-  uint32_t t = P.site_type[site];
-  const uint64_t* img = P.masks + P.site_img[site];
-  uint32_t la, lb = 0;
-  if (t == S_DEP1) la = o + 1;
-  else if (t == S_DEP2) { la = (o + 1) >> 2; lb = (o + 1) & 3; }
-  else la = t - 1;  // X_ERROR 1, Y_ERROR 2, Z_ERROR 3
-  uint64_t ex[W], ez[W];
-#pragma unroll
-  for (int w = 0; w < W; w++) { ex[w] = 0; ez[w] = 0; }
-  // image layout per qubit: X~ (x words, z words) then Z~ (x words, z words)
-  const uint32_t L[2] = {la, lb};
-#pragma unroll
-  for (int qi = 0; qi < 2; qi++) {
-    uint32_t l = L[qi];
-    const uint64_t* ix = img + (size_t)qi * 4 * W;
-    const uint64_t* iz = ix + 2 * W;
-    uint64_t ux = (l == 1 || l == 2) ? ~0ull : 0ull;
-    uint64_t uz = (l == 2 || l == 3) ? ~0ull : 0ull;
-    if (qi == 1 && t != S_DEP2) break;
-#pragma unroll
-    for (int w = 0; w < W; w++) {
-      ex[w] ^= (ix[w] & ux) ^ (iz[w] & uz);
-      ez[w] ^= (ix[W + w] & ux) ^ (iz[W + w] & uz);
-    }
-  }
-  frame_xor<W>(T, ex, ez);
-  frame_xor<W>(N, ex, ez);
-}
-
-// ------------------------------------------------------------------ one shot
-// OOP: active vectors in HBM with a second buffer of the same size; active
-// measurements collapse out of place (alternating buffers) and read through
-// their folded localization passes.
-template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OOP = false>
-struct Shot {
-  const DevProgram& P;
-  const KArgs& A;
-  Group<G> grp;
-  Vec<G, R> vec;
-  uint64_t* rec;  // LDS record words of the tile (R + D + O)
-  double* red;    // LDS reduction scratch (G == 256)
-  int slane;      // shot index inside the 64-shot tile
-  uint64_t shot;  // global shot index (G == 1: per lane)
-  uint64_t local; // shot index relative to the call (debug buffers)
-  cpx<R>* alt = nullptr;  // OOP: the other buffer
-
-  // The next active measurement after instruction pc (whose collapse fuses
-  // it): its slot and type and the localization passes folded into it.
-  MDEV void peek_next_measurement(int pc, uint32_t& s2, bool& x2, uint32_t& tm2, uint32_t& sm2, bool& as2) const {
-    tm2 = sm2 = 0;
-    as2 = false;
-    for (int q = pc + 1;; q++) {
-      const GInstr g = load_instr(P.code, q);
-      if (g.op == OP_APERM) tm2 = g.a;
-      else if (g.op == OP_ASIGN) sm2 = g.a;
-      else if (g.op == OP_AS) as2 = true;
-      else if (g.op == OP_MACTZ || g.op == OP_MACTX || g.op == OP_END) {
-        s2 = g.s;
-        x2 = g.op == OP_MACTX;
-        return;
-      }
-    }
-  }
-
-  MDEV bool writer() const { return (G == 1 || grp.tid == 0) && local < A.shots; }
-
-  MDEV void put(uint32_t r, uint32_t m) {
-    if constexpr (G == 1) {
-      uint64_t word = __ballot(m);
-      if ((threadIdx.x & 63) == 0) rec[r] = word;
-    } else {
-      if (grp.tid == 0) rec[r] |= (uint64_t)m << slane;
-    }
-  }
-  MDEV uint32_t xor_refs(uint32_t a, uint32_t u) {
-    // G == 1: whole 64-shot words; otherwise this shot's bit
-    uint64_t acc = 0;
-    cptr<uint32_t> refs = as_const(P.refs);
-    for (uint32_t i = 0; i < u; i++) acc ^= rec[refs[a + i]];
-    if constexpr (G == 1) {
-      uint32_t lane = threadIdx.x & 63;
-      return (uint32_t)(acc >> lane) & 1u;
-    } else {
-      return (uint32_t)(acc >> slane) & 1u;
-    }
-  }
-
-  __device__ void run() {
-    Frame<W> T, N;
-#pragma unroll
-    for (int w = 0; w < W; w++) { T.x[w] = T.z[w] = N.x[w] = N.z[w] = 0; }
-    const uint64_t seed = A.seed;
-    int k = 0;
-    uint32_t last_m = 0, last_pn = 0;
-    uint32_t rb_blk = 0xFFFFFFFFu;
-    U4 rb{0, 0, 0, 0};
-    double carry0 = 0, carry1 = 0;  // branch sums of the next active measurement (fused)
-    bool carry_valid = false;
-    uint32_t pend_tm = 0, pend_sm = 0;  // folded localization passes of the next measurement
-    bool pend_as = false;
-    // Out of place: the last dfr expansions are not applied yet; element x
-    // is vec[x mod 2^(k-dfr)] times beta[t] for every set bit t of
-    // x >> (k-dfr) (an expansion multiplies its new upper half by a phase).
-    constexpr int ND = OOP ? kDeferMax : 1;
-    // passes through the factors run one iteration at a time: their reads
-    // mostly hit the cache (each stored element serves up to 2^dfr outputs)
-    // and a deeper unroll would cost the whole kernel occupancy
-    constexpr int UD = 1;
-    int dfr = 0;
-    cpx<R> beta[ND];
-#pragma unroll
-    for (int t = 0; t < ND; t++) beta[t] = cpx<R>{(R)1, (R)0};
-    auto fac = [&](uint32_t c) {
-      cpx<R> f = (c & 1u) ? beta[0] : cpx<R>{(R)1, (R)0};
-#pragma unroll
-      for (int t = 1; t < ND; t++) {
-        const cpx<R> b = ((c >> t) & 1u) ? beta[t] : cpx<R>{(R)1, (R)0};
-        f = cpx<R>{f.re * b.re - f.im * b.im, f.re * b.im + f.im * b.re};
-      }
-      return f;
-    };
-    // writes the deferred part: x = lo | c << (k-dfr) for c != 0, with c the
-    // fastest index so that each stored element is read once per group of c
-    auto materialize = [&]() {
-      if constexpr (OOP) {
-        if (dfr == 0) return;
-        const int m = k - dfr;
-        const uint32_t n = 1u << k, cm = (1u << dfr) - 1u;
-        const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-        for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += UD * st) {
-          cpx<R> y[UD];
-#pragma unroll
-          for (int u = 0; u < UD; u++) {
-            const uint32_t qq = base + u * st;
-            if (qq < n && (qq & cm)) {
-              const cpx<R> a = vec[qq >> dfr], f = fac(qq & cm);
-              y[u] = cpx<R>{a.re * f.re - a.im * f.im, a.re * f.im + a.im * f.re};
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < UD; u++) {
-            const uint32_t qq = base + u * st;
-            if (qq < n && (qq & cm)) vec[(qq >> dfr) | ((qq & cm) << m)] = y[u];
-          }
-        }
-        grp.sync();
-        dfr = 0;
-      }
-    };
-    Noise ns{0, 0, 0xFFFFFFFFu, 0};
-    if (P.nsites > 0) {
-      if (DBG && A.forced_faults) ns.nf = 0xFFFFFFFFu;
-      else next_fault(P, ns, 0, shot, seed);
-    }
-    if (VEC && P.kmax > 0) {
-      FOR_GROUP(p, 1u) vec[p] = cpx<R>{(R)1, (R)0};
-      grp.sync();
-    }
-    cptr<uint64_t> masks = as_const(P.masks);
-    for (int pc = 0;; pc++) {
-      const GInstr in = load_instr(P.code, pc);
-      const int v = in.v;
-      const int s = in.s;
-      switch (in.op) {
-        case OP_END:
-          goto done;
-        case OP_FANCX: {
-          uint64_t m[W];
-#pragma unroll
-          for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
-          fan_cx<W>(T, v, m);
-          fan_cx<W>(N, v, m);
-          break;
-        }
-        case OP_FANCZ: {
-          uint64_t m[W];
-#pragma unroll
-          for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
-          fan_cz<W>(T, v, m);
-          fan_cz<W>(N, v, m);
-          break;
-        }
-        case OP_FAN2: {
-          uint64_t m[W];
-#pragma unroll
-          for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
-          fan_2<W>(T, v, m);
-          fan_2<W>(N, v, m);
-          break;
-        }
-        case OP_FS: frame_s<W>(T, v); frame_s<W>(N, v); break;
-        case OP_FH: frame_h<W>(T, v); frame_h<W>(N, v); break;
-        case OP_APERM: {
-          if constexpr (!VEC) break;
-          else {
-          if (OOP && (in.flags & F_FOLD_NEXT)) {  // read through by the next measurement
-            pend_tm = in.a;
-            break;
-          }
-          carry_valid = false;
-          materialize();
-          // control slot s, targets tm: i -> i ^ tm for i with bit s set; each
-          // pair is visited once from the member with target bit t0 clear
-          const uint32_t tm = in.a, bs = 1u << s;
-          const int t0 = __ffs(tm) - 1;
-          const int lo = min(s, t0), hi = max(s, t0);
-          pass2<G, R, U>(grp, vec, 1u << (k - 2),
-                      [&](uint32_t p, uint32_t& i0, uint32_t& i1) { i0 = ins0(ins0(p, lo), hi) | bs; i1 = i0 ^ tm; },
-                      [](cpx<R>& a, cpx<R>& b) { cpx<R> t = a; a = b; b = t; });
-          grp.sync();
-          }
-          break;
-        }
-        case OP_ASIGN: {
-          if constexpr (!VEC) break;
-          else {
-          if (OOP && (in.flags & F_FOLD_NEXT)) {
-            pend_sm = in.a;
-            break;
-          }
-          carry_valid = false;
-          materialize();
-          // -1 on i with bit s set and odd parity of i & sm: enumerate i with
-          // bits s and c (lowest of sm) free, then fix bit c to make it odd
-          const uint32_t sm = in.a, bs = 1u << s;
-          const int c = __ffs(sm) - 1;
-          const int lo = min(s, c), hi = max(s, c);
-          pass1<G, R, U>(grp, vec, 1u << (k - 2),
-                      [&](uint32_t p) {
-                        uint32_t i = ins0(ins0(p, lo), hi) | bs;
-                        return i | ((uint32_t)((__popc(i & sm) & 1) ^ 1) << c);
-                      },
-                      [](cpx<R> a) { return cpx<R>{-a.re, -a.im}; });
-          grp.sync();
-          }
-          break;
-        }
-        case OP_APERM2: {
-          if constexpr (!VEC) break;
-          else {
-          carry_valid = false;
-          materialize();
-          // flip bit s where parity(i & sm) is odd: pairs along s with odd parity
-          const uint32_t sm = in.a, bs = 1u << s;
-          const int c = __ffs(sm) - 1;
-          const int lo = min(s, c), hi = max(s, c);
-          pass2<G, R, U>(grp, vec, 1u << (k - 2),
-                      [&](uint32_t p, uint32_t& i0, uint32_t& i1) {
-                        uint32_t i = ins0(ins0(p, lo), hi);
-                        i0 = i | ((uint32_t)((__popc(i & sm) & 1) ^ 1) << c);
-                        i1 = i0 | bs;
-                      },
-                      [](cpx<R>& a, cpx<R>& b) { cpx<R> t = a; a = b; b = t; });
-          grp.sync();
-          }
-          break;
-        }
-        case OP_AS: {
-          if constexpr (!VEC) break;
-          else {
-          if (OOP && (in.flags & F_FOLD_NEXT)) {
-            pend_as = true;
-            break;
-          }
-          carry_valid = false;
-          materialize();
-          const uint32_t bs = 1u << s;
-          pass1<G, R, U>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
-                      [](cpx<R> a) { return cpx<R>{-a.im, a.re}; });
-          grp.sync();
-          }
-          break;
-        }
-        case OP_AH: {
-          if constexpr (!VEC) break;
-          else {
-          carry_valid = false;
-          if constexpr (!OOP) materialize();
-          const R h = (R)0.70710678118654752440;
-          const uint32_t bs = 1u << s;
-          if constexpr (OOP) {
-            // out of place: a rotation on this slot that directly follows is
-            // applied to the written upper halves, and folded localization
-            // passes are read through (the element of i1 is that of i1 ^ tm,
-            // signed by parity(i1 & sm), times i for S), as are deferred
-            // expansions (element x is stored[x mod 2^dm] times its factor)
-            const int dm = k - dfr;
-            const uint32_t lmask = (1u << dm) - 1u;
-            auto rdx = [&](uint32_t x) {
-              const cpx<R> e = vec[x & lmask], f = fac(x >> dm);
-              return cpx<R>{e.re * f.re - e.im * f.im, e.re * f.im + e.im * f.re};
-            };
-            const GInstr nx = load_instr(P.code, pc + 1);
-            const bool rot = nx.op == OP_AROT && nx.s == s;
-            R rr = (R)1, ri = (R)0;
-            if (rot) {
-              double c2 = P.consts[2 * nx.a], s2 = P.consts[2 * nx.a + 1];
-              if (getbit<W>(T.x, nx.v)) s2 = -s2;
-              rr = (R)c2;
-              ri = (R)s2;
-            }
-            const uint32_t tm = pend_tm, sm = pend_sm;
-            const bool fas = pend_as;
-            const Vec<G, R> dst{alt, vec.lane};
-            const uint32_t n = 1u << (k - 1), st = G == 1 ? 1u : (uint32_t)G;
-            constexpr int UH = G == 1 ? 1 : (U >= 4 ? U / 4 : 1);
-            for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += UH * st) {
-              uint32_t ii[UH];
-              cpx<R> a[UH], c[UH];
-#pragma unroll
-              for (int u = 0; u < UH; u++) {
-                const uint32_t q = base + u * st;
-                ii[u] = ins0(q < n ? q : base, s);
-                if (q < n) {
-                  a[u] = rdx(ii[u]);
-                  c[u] = rdx((ii[u] | bs) ^ tm);
-                }
-              }
-#pragma unroll
-              for (int u = 0; u < UH; u++) {
-                if (base + u * st >= n) continue;
-                const uint32_t i1 = ii[u] | bs;
-                cpx<R> y = (__popc(i1 & sm) & 1) ? cpx<R>{-c[u].re, -c[u].im} : c[u];
-                if (fas) y = cpx<R>{-y.im, y.re};
-                dst[ii[u]] = cpx<R>{h * (a[u].re + y.re), h * (a[u].im + y.im)};
-                dst[i1] = cmul(cpx<R>{h * (a[u].re - y.re), h * (a[u].im - y.im)}, rr, ri);
-              }
-            }
-            cpx<R>* t = vec.base;
-            vec.base = alt;
-            alt = t;
-            pend_tm = pend_sm = 0;
-            pend_as = false;
-            dfr = 0;
-            if (rot) pc++;
-          } else {
-            pass2<G, R, U>(grp, vec, 1u << (k - 1),
-                        [&](uint32_t p, uint32_t& i0, uint32_t& i1) { i0 = ins0(p, s); i1 = i0 | bs; },
-                        [h](cpx<R>& a, cpx<R>& b) {
-                          cpx<R> x{h * (a.re + b.re), h * (a.im + b.im)};
-                          b = cpx<R>{h * (a.re - b.re), h * (a.im - b.im)};
-                          a = x;
-                        });
-          }
-          grp.sync();
-          }
-          break;
-        }
-        case OP_EXPAND: {
-          if constexpr (!VEC) break;
-          else {
-          carry_valid = false;
-          // Appendix B.1 case 2: H_v takes |0>_v to |+>_v (frames conjugated);
-          // then exp(-i theta' Z_v) on the new axis, theta' sign-flipped by
-          // x_v of the frame.  The common phase e^{-i theta'} is global, so
-          // the new half is the old one times e^{2 i theta'}.
-          frame_h<W>(T, v);
-          frame_h<W>(N, v);
-          double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
-          if (getbit<W>(T.x, v)) s2 = -s2;
-          const R cr = (R)c2, ci = (R)s2;
-          if constexpr (OOP) {
-            // deferred: the new top slot's factor; when all are taken, the
-            // oldest (slot k - dfr) is applied first, as an expansion would
-            if (dfr == ND) {
-              const uint32_t n = 1u << (k - dfr);
-              const cpx<R> b0 = beta[0];
-              pass21<G, R, U>(grp, vec, n, [&](uint32_t p, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = r1 = p; w = p | n; },
-                              [b0](cpx<R> a, cpx<R>) { return cmul(a, b0.re, b0.im); });
-              grp.sync();
-#pragma unroll
-              for (int t = 0; t + 1 < ND; t++) beta[t] = beta[t + 1];
-              dfr--;
-            }
-#pragma unroll
-            for (int t = 0; t < ND; t++)
-              if (t == dfr) beta[t] = cpx<R>{cr, ci};
-            dfr++;
-            k++;
-            break;
-          }
-          const uint32_t n = 1u << k;
-          pass21<G, R, U>(grp, vec, n, [&](uint32_t p, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = r1 = p; w = p | n; },
-                       [cr, ci](cpx<R> a, cpx<R>) { return cmul(a, cr, ci); });
-          k++;
-          grp.sync();
-          }
-          break;
-        }
-        case OP_AROT: {
-          if constexpr (!VEC) break;
-          else {
-          carry_valid = false;
-          materialize();
-          double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
-          if (getbit<W>(T.x, v)) s2 = -s2;
-          const R cr = (R)c2, ci = (R)s2;
-          const uint32_t bs = 1u << s;
-          pass1<G, R, U>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
-                      [cr, ci](cpx<R> a) { return cmul(a, cr, ci); });
-          grp.sync();
-          }
-          break;
-        }
-        case OP_MSTATIC: {
-          uint64_t m[W];
-#pragma unroll
-          for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
-          uint32_t mm = parity_and<W>(T.x, m) ^ (uint32_t)(in.flags & F_SIGN);
-          last_pn = parity_and<W>(N.x, m);
-          if constexpr (DBG) {
-            if (A.probs && writer()) A.probs[local * P.nevents + in.b] = (double)mm;
-            if (A.forced_m && writer() && A.forced_m[local * P.nevents + in.b] != mm) atomicOr(A.error, 2);
-          }
-          last_m = mm;
-          int r = as_const(P.ev_rec)[in.b];
-          if (r >= 0) put((uint32_t)r, mm);
-          break;
-        }
-        case OP_MRANDOM: {
-          uint32_t j = in.b;
-          uint32_t p = getbit<W>(T.z, v), pn = getbit<W>(N.z, v);
-          uint32_t mm;
-          if constexpr (DBG) {
-            if (A.probs && writer()) A.probs[local * P.nevents + j] = 0.5;
-          }
-          if (DBG && A.forced_m) {
-            mm = local < A.shots ? A.forced_m[local * P.nevents + j] : 0u;
-            if constexpr (G > 1) mm = rfl(mm);
-          } else {
-            if ((j >> 7) != rb_blk) {
-              rb_blk = j >> 7;
-              rb = draw(rb_blk, kPurposeRbit, shot, seed);
-            }
-            uint32_t bi = j & 127, word = bi >> 5;
-            uint32_t wv = word == 0 ? rb.w0 : word == 1 ? rb.w1 : word == 2 ? rb.w2 : rb.w3;
-            mm = ((wv >> (bi & 31)) & 1u) ^ pn;
-          }
-          uint32_t b = mm ^ (uint32_t)(in.flags & F_SIGN) ^ p;
-          frame_h<W>(T, v);
-          frame_h<W>(N, v);
-          xorbit<W>(T.x, v, b);
-          last_m = mm;
-          last_pn = pn;
-          int r = as_const(P.ev_rec)[j];
-          if (r >= 0) put((uint32_t)r, mm);
-          break;
-        }
-        case OP_MACTZ:
-        case OP_MACTX: {
-          if constexpr (!VEC) break;
-          else {
-          const bool isx = in.op == OP_MACTX;
-          uint32_t j = in.b;
-          uint32_t sign = in.flags & F_SIGN;
-          uint32_t p = isx ? getbit<W>(T.z, v) : getbit<W>(T.x, v);
-          uint32_t pn = isx ? getbit<W>(N.z, v) : getbit<W>(N.x, v);
-          const uint32_t bs = 1u << s;
-          const uint32_t half = 1u << (k - 1);
-          // branch sums (Appendix B.2): |a|^2 per half along the axis, or
-          // |a +- b|^2 of the fold for an X-type measurement
-          auto branch_sums = [](bool x, cpx<R> a, cpx<R> b, double& x0, double& x1) {
-            if (x) {
-              x0 += norm2(cpx<R>{a.re + b.re, a.im + b.im});
-              x1 += norm2(cpx<R>{a.re - b.re, a.im - b.im});
-            } else {
-              x0 += norm2(a);
-              x1 += norm2(b);
-            }
-          };
-          // the partner (measured bit set) of a pair, read through the folded
-          // localization passes: element (i1 ^ tm) times the phase at i1
-          const uint32_t tm = pend_tm, sm = pend_sm;
-          const bool fas = pend_as;
-          auto partner = [&](cpx<R> x, uint32_t i1) {
-            cpx<R> y = (__popc(i1 & sm) & 1) ? cpx<R>{-x.re, -x.im} : x;
-            return fas ? cpx<R>{-y.im, y.re} : y;
-          };
-          double s0 = 0, s1 = 0;
-          // Deferred expansions (out of place): element lo | c << dm is
-          // stored[lo] times F(c), the product of beta over the set bits of c
-          // (|F| = 1), and its measured partner is (lo ^ dlo, c ^ dc).  Over
-          // the combinations c of one stored pair, the Z branch sums are nc
-          // times the stored ones, and the X cross term Re(conj(a) p) sums to
-          // Re(conj(va) pv Gam), Gam = sum over c of sigma_c F(c ^ dc) conj F(c)
-          // (sigma_c: the sign of the measured-slot phase from the bits of c).
-          const bool dfd = OOP && dfr > 0;
-          const int dm = k - dfr;
-          const uint32_t lmask = (1u << dm) - 1u, cmask = (1u << dfr) - 1u;
-          const uint32_t bsc = dfd && s >= dm ? (1u << (s - dm)) : 0u;
-          const uint32_t dlo = (bs ^ tm) & lmask, dc = dfd ? ((bs ^ tm) >> dm) & cmask : 0u;
-          const uint32_t bsl = bs & lmask, sml = sm & lmask, smc = dfd ? (sm >> dm) & cmask : 0u;
-          const uint32_t npairs = s < dm ? (1u << (dm - 1)) : (1u << dm);
-          // phase of a stored partner from the stored bits of its index
-          auto partner_lo = [&](cpx<R> x, uint32_t lo) {
-            cpx<R> y = (__popc((lo | bsl) & sml) & 1) ? cpx<R>{-x.re, -x.im} : x;
-            return fas ? cpx<R>{-y.im, y.re} : y;
-          };
-          if (carry_valid) {
-            // accumulated by the previous measurement's collapse pass
-            s0 = carry0;
-            s1 = carry1;
-          } else if (dfd) {
-            const double nc = (double)(s < dm ? (1u << dfr) : (1u << (dfr - 1)));
-            double gre = 0, gim = 0;
-            if (isx) {
-              for (uint32_t c = 0; c <= cmask; c++) {
-                if (c & bsc) continue;
-                const cpx<R> f = fac(c), g = fac(c ^ dc);
-                double re = (double)g.re * f.re + (double)g.im * f.im;
-                double im = (double)g.im * f.re - (double)g.re * f.im;
-                if (__popc((c | bsc) & smc) & 1) { re = -re; im = -im; }
-                gre += re;
-                gim += im;
-              }
-            }
-            reduce2<G, R, (U > 4 ? 4 : U)>(grp, vec, npairs,
-                             [&](uint32_t q, uint32_t& i0, uint32_t& i1) {
-                               i0 = s < dm ? ins0(q, s) : q;
-                               i1 = i0 ^ dlo;
-                             },
-                             [&](cpx<R> va, cpx<R> vc, uint32_t q, double& x0, double& x1) {
-                               const cpx<R> pv = partner_lo(vc, s < dm ? ins0(q, s) : q);
-                               if (isx) {
-                                 const double t = nc * (norm2(va) + norm2(pv));
-                                 const double wre = (double)va.re * pv.re + (double)va.im * pv.im;
-                                 const double wim = (double)va.re * pv.im - (double)va.im * pv.re;
-                                 const double cr = 2.0 * (wre * gre - wim * gim);
-                                 x0 += t + cr;
-                                 x1 += t - cr;
-                               } else {
-                                 x0 += nc * norm2(va);
-                                 x1 += nc * norm2(pv);
-                               }
-                             },
-                             s0, s1);
-            s0 = grp.sum(s0, red);
-            s1 = grp.sum(s1, red);
-          } else {
-            reduce2<G, R, U>(grp, vec, half,
-                             [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = (i0 | bs) ^ tm; },
-                             [&](cpx<R> a, cpx<R> c, uint32_t q, double& x0, double& x1) {
-                               branch_sums(isx, a, partner(c, ins0(q, s) | bs), x0, x1);
-                             },
-                             s0, s1);
-            s0 = grp.sum(s0, red);
-            s1 = grp.sum(s1, red);
-          }
-          if (isx) { s0 *= 0.5; s1 *= 0.5; }
-          double tot = s0 + s1;
-          uint32_t bm1 = 1u ^ sign ^ p;  // virtual branch of m = 1
-          double sb1 = bm1 ? s1 : s0;
-          uint32_t mm;
-          if constexpr (DBG) {
-            if (A.probs && writer()) A.probs[local * P.nevents + j] = sb1 / tot;
-          }
-          if (DBG && A.forced_m) {
-            mm = local < A.shots ? A.forced_m[local * P.nevents + j] : 0u;
-            if constexpr (G > 1) mm = rfl(mm);
-          } else {
-            U4 w = draw(j, kPurposeAmeas, shot, seed);
-            double pref1 = ((bm1 ^ pn) ? s1 : s0) / tot;  // P(m_ref = 1)
-            mm = (uniform53(w) < pref1 ? 1u : 0u) ^ pn;
-          }
-          uint32_t b = mm ^ sign ^ p;
-          double sb = b ? s1 : s0;
-          if (!(sb > 1e-300 * tot)) {
-            if constexpr (DBG) {
-              if (writer()) atomicOr(A.error, 2);
-            }
-            sb = tot > 0 ? tot : 1.0;
-          }
-          const R scale = (R)(1.0 / sqrt(sb));
-          const R fs = isx ? (R)0.70710678118654752440 : (R)1;
-          const R sgn = b ? (R)-1 : (R)1;
-          const int top = k - 1;
-          const uint32_t tb = 1u << top;
-          auto out1 = [&](cpx<R> a, cpx<R> c) -> cpx<R> {
-            if (isx) return cpx<R>{fs * scale * (a.re + sgn * c.re), fs * scale * (a.im + sgn * c.im)};
-            return b ? cpx<R>{scale * c.re, scale * c.im} : cpx<R>{scale * a.re, scale * a.im};
-          };
-          // the next measurement (after this demotion), when fused: its slot,
-          // type and folded localization passes
-          const bool fuse = (in.flags & F_FUSE_NEXT) && k >= 2;
-          uint32_t s2 = 0, tm2 = 0, sm2 = 0;
-          bool nx = false, as2 = false;
-          if (fuse) peek_next_measurement(pc, s2, nx, tm2, sm2, as2);
-          const uint32_t b2 = 1u << s2;
-          auto partner2 = [&](cpx<R> x, uint32_t i1) {
-            cpx<R> y = (__popc(i1 & sm2) & 1) ? cpx<R>{-x.re, -x.im} : x;
-            return as2 ? cpx<R>{-y.im, y.re} : y;
-          };
-          const uint32_t st = G == 1 ? 1u : (uint32_t)G;
-          double n0 = 0, n1 = 0;
-          bool fused_sums = false;
-          if constexpr (OOP) {
-            // out of place into the other buffer: output o (new slot s holds
-            // the former top bit) reads its pair through the folded passes
-            const Vec<G, R> dst{alt, vec.lane};
-            auto one = [&](uint32_t o) {
-              const uint32_t base = s == top ? o : ((o & ~bs) | (((o >> s) & 1u) << top));
-              const uint32_t i1 = base | bs;
-              return out1(vec[base], partner(vec[i1 ^ tm], i1));
-            };
-            if (dfd) {
-              // each stored pair is read once; the outputs of its deferred
-              // combinations follow a Gray-code walk over c (one factor per
-              // step on each side)
-              const cpx<R> g0 = fac(dc);
-              const R sg0 = (__popc(bsc & smc) & 1) ? (R)-1 : (R)1;
-              // output of input lo | c << dm (the top bit moves to slot s)
-              auto oidx = [&](uint32_t lo, uint32_t c) {
-                const uint32_t i0 = lo | (c << dm);
-                return s == top ? i0 : ((i0 & ~tb) | (((i0 >> top) & 1u) << s));
-              };
-              // one Gray-code step (bit t, to value nb) of a walk whose c is
-              // offset by off: its element factor and its partner factor
-              auto step = [&](cpx<R>& x, cpx<R>& y, int t, bool nb, uint32_t off) {
-                const cpx<R> bt = beta[t];
-                const bool xb = nb ^ ((off >> t) & 1u);
-                x = cmul(x, bt.re, xb ? bt.im : -bt.im);
-                const bool yb = xb ^ ((dc >> t) & 1u);  // bit t of (c ^ off) ^ dc
-                const R sg = ((smc >> t) & 1u) ? (R)-1 : (R)1;
-                y = cmul(y, sg * bt.re, yb ? sg * bt.im : -sg * bt.im);
-              };
-              // The next measurement (fused) pairs output o with o ^ d2 (the
-              // member with bit s2 clear first).  In stored and deferred bits
-              // d2 is (d2lo, d2c): the pair of the output of (lo, c) is the
-              // output of (lo ^ d2lo, c ^ d2c), from the same stored pair when
-              // d2lo = 0; piv is the bit that orders the two members.
-              const uint32_t cm1 = (1u << (dfr - 1)) - 1u;
-              auto to_c = [&](uint32_t M) {
-                return ((M >> dm) & cm1 & ~bsc) | (s != top ? ((M >> s) & 1u) << (dfr - 1) : 0u);
-              };
-              const uint32_t d2 = fuse ? b2 ^ tm2 : 0u;
-              const uint32_t d2lo = d2 & lmask & ~bsl, d2c = fuse ? to_c(d2) : 0u;
-              const bool same_row = d2lo == 0;
-              const uint32_t piv = same_row ? (d2c & (0u - d2c)) : (d2lo & (0u - d2lo));
-              const int pb = __ffs(piv) - 1;
-              const uint32_t nq = !fuse ? npairs : same_row ? npairs : npairs >> 1;
-              // stored index of row A of iteration q (pivot bit clear when the
-              // two rows differ)
-              auto row_a = [&](uint32_t q) {
-                if (!fuse || same_row) return s < dm ? ins0(q, s) : q;
-                if (s < dm) return ins0(ins0(q, min((int)s, pb)), max((int)s, pb));
-                return ins0(q, pb);
-              };
-              auto sigma = [&](uint32_t c) { return (__popc((c | bsc) & smc) & 1) ? (R)-1 : (R)1; };
-              if (G == 1 && fuse) {
-                // one lane walks c and c ^ d2c in step over the stored pairs
-                // at lo and lo ^ d2lo, writing both outputs and summing them
-                // (the cooperative tiers leave the sums to the next
-                // measurement's own streaming reduction, which they run faster)
-                const cpx<R> f2 = fac(d2c), g2 = fac(d2c ^ dc);
-                const R sg2 = sigma(d2c);
-                // a plain loop over the steps (unrolled, the two walks would
-                // cost the kernel its occupancy); beta[t] by selection
-                auto beta_at = [&](int t) {
-                  // constant indices only: a loop here would leave beta in memory
-                  static_assert(ND == 4, "four deferred factors");
-                  const cpx<R> b01 = t == 1 ? beta[1] : beta[0];
-                  const cpx<R> b23 = t == 3 ? beta[3] : beta[2];
-                  return t >= 2 ? b23 : b01;
-                };
-                auto step_d = [&](cpx<R>& x, cpx<R>& y, int t, bool nb, uint32_t off) {
-                  const cpx<R> bt = beta_at(t);
-                  const bool xb = nb ^ ((off >> t) & 1u);
-                  x = cmul(x, bt.re, xb ? bt.im : -bt.im);
-                  const bool yb = xb ^ ((dc >> t) & 1u);
-                  const R sg = ((smc >> t) & 1u) ? (R)-1 : (R)1;
-                  y = cmul(y, sg * bt.re, yb ? sg * bt.im : -sg * bt.im);
-                };
-                const uint32_t nc = 1u << dfr;
-                for (uint32_t q = G == 1 ? 0u : (uint32_t)grp.tid; q < nq; q += st) {
-                  const uint32_t la = row_a(q);
-                  const uint32_t lb = la ^ d2lo;
-                  cpx<R> xa = vec[la];
-                  cpx<R> ya = partner_lo(vec[la ^ dlo], la);
-                  cpx<R> xb = vec[lb];
-                  cpx<R> yb = partner_lo(vec[lb ^ dlo], lb);
-                  ya = cmul(ya, sg0 * g0.re, sg0 * g0.im);
-                  xb = cmul(xb, f2.re, f2.im);
-                  yb = cmul(yb, sg2 * g2.re, sg2 * g2.im);
-                  for (uint32_t j = 0; j < nc; j++) {
-                    const uint32_t c = j ^ (j >> 1);
-                    if (j) {
-                      const int t = __builtin_ctz(j);
-                      const bool nb = (c >> t) & 1u;
-                      step_d(xa, ya, t, nb, 0u);
-                      step_d(xb, yb, t, nb, d2c);
-                    }
-                    if ((c & bsc) || (same_row && (c & piv))) continue;  // a partner, or emitted from its pair
-                    const uint32_t oa = oidx(la, c), ob = oidx(lb, c ^ d2c);
-                    const cpx<R> va = out1(xa, ya), vb = out1(xb, yb);
-                    dst[oa] = va;
-                    dst[ob] = vb;
-                    const bool a0 = !(oa & b2);
-                    branch_sums(nx, a0 ? va : vb, partner2(a0 ? vb : va, (a0 ? oa : ob) | b2), n0, n1);
-                  }
-                }
-                fused_sums = true;
-              } else {
-                auto walk = [&](auto DT) {
-                  constexpr int D = decltype(DT)::value;
-                  for (uint32_t q = G == 1 ? 0u : (uint32_t)grp.tid; q < npairs; q += st) {
-                    const uint32_t lo = s < dm ? ins0(q, s) : q;
-                    cpx<R> av = vec[lo];
-                    cpx<R> pv = partner_lo(vec[lo ^ dlo], lo);
-                    pv = cmul(pv, sg0 * g0.re, sg0 * g0.im);
-                    auto put_out = [&](uint32_t c) {
-                      if (c & bsc) return;
-                      dst[oidx(lo, c)] = out1(av, pv);
-                    };
-                    put_out(0);
-#pragma unroll
-                    for (int j = 1; j < (1 << D); j++) {
-                      const int t = __builtin_ctz(j);
-                      const uint32_t c = (uint32_t)(j ^ (j >> 1));
-                      step(av, pv, t, (c >> t) & 1u, 0u);
-                      put_out(c);
-                    }
-                  }
-                };
-                if (dfr == 1) walk(IntC<1>{});
-                else if (dfr == 2) walk(IntC<2 <= ND ? 2 : 1>{});
-                else if (dfr == 3) walk(IntC<3 <= ND ? 3 : 1>{});
-                else walk(IntC<4 <= ND ? 4 : 1>{});
-              }
-              dfr = 0;
-            } else if (fuse) {
-              // outputs (j0, j1): the next measurement's pair through its own
-              // folded passes, summed as it is written
-              constexpr int UP = U >= 2 ? U / 2 : 1;
-              const uint32_t n2 = half >> 1;
-              for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n2; base += UP * st) {
-                uint32_t j0[UP];
-                cpx<R> y0[UP], y1[UP];
-#pragma unroll
-                for (int u = 0; u < UP; u++) {
-                  const uint32_t q = base + u * st;
-                  j0[u] = ins0(q < n2 ? q : base, s2);
-                  if (q < n2) {
-                    y0[u] = one(j0[u]);
-                    y1[u] = one((j0[u] | b2) ^ tm2);
-                  }
-                }
-#pragma unroll
-                for (int u = 0; u < UP; u++)
-                  if (base + u * st < n2) {
-                    dst[j0[u]] = y0[u];
-                    dst[(j0[u] | b2) ^ tm2] = y1[u];
-                    branch_sums(nx, y0[u], partner2(y1[u], j0[u] | b2), n0, n1);
-                  }
-              }
-              fused_sums = true;
-            } else {
-              pass1_to<G, R, U>(grp, dst, half, one);
-            }
-            cpx<R>* t = vec.base;
-            vec.base = alt;
-            alt = t;
-          } else {
-            // in place (on-chip vectors; folded passes are never skipped here,
-            // so only a directly following measurement is fused): the kept
-            // half (or fold) is written in place; the top slot k-1 takes the
-            // place of slot s (no hazard: every thread owns its outputs and
-            // reads only them and the elements above them)
-            const bool fuse_here = fuse && tm2 == 0 && sm2 == 0 && !as2;
-            if (fuse_here && s == top) {
-              constexpr int UP = U >= 4 ? U / 4 : 1;
-              const uint32_t n2 = half >> 1;
-              for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n2; base += UP * st) {
-                uint32_t oo[UP];
-                cpx<R> x0[UP], x1[UP], y0[UP], y1[UP];
-#pragma unroll
-                for (int u = 0; u < UP; u++) {
-                  const uint32_t q = base + u * st;
-                  oo[u] = ins0(q < n2 ? q : base, s2);
-                  if (q < n2) {
-                    x0[u] = vec[oo[u]];
-                    x1[u] = vec[oo[u] | tb];
-                    y0[u] = vec[oo[u] | b2];
-                    y1[u] = vec[oo[u] | b2 | tb];
-                  }
-                }
-#pragma unroll
-                for (int u = 0; u < UP; u++)
-                  if (base + u * st < n2) {
-                    const cpx<R> lo = out1(x0[u], x1[u]), hi = out1(y0[u], y1[u]);
-                    vec[oo[u]] = lo;
-                    vec[oo[u] | b2] = hi;
-                    branch_sums(nx, lo, hi, n0, n1);
-                  }
-              }
-              fused_sums = true;
-            } else if (fuse_here && s2 != s) {
-              // four outputs {o, o|bs, o|b2, o|bs|b2} from eight inputs (new
-              // bit s of an output is the former top bit of its inputs); the
-              // next axis pairs (o, o|b2) and (o|bs, o|bs|b2)
-              const uint32_t n4 = half >> 2;
-              const int lo_b = min((int)s, (int)s2), hi_b = max((int)s, (int)s2);
-              for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += st) {
-                const uint32_t o = ins0(ins0(base, lo_b), hi_b);
-                const cpx<R> i0 = vec[o], i1 = vec[o | bs], i2 = vec[o | tb], i3 = vec[o | tb | bs];
-                const cpx<R> i4 = vec[o | b2], i5 = vec[o | b2 | bs], i6 = vec[o | b2 | tb], i7 = vec[o | b2 | tb | bs];
-                const cpx<R> r0 = out1(i0, i1), r1 = out1(i2, i3), r2 = out1(i4, i5), r3 = out1(i6, i7);
-                vec[o] = r0;
-                vec[o | bs] = r1;
-                vec[o | b2] = r2;
-                vec[o | bs | b2] = r3;
-                branch_sums(nx, r0, r2, n0, n1);
-                branch_sums(nx, r1, r3, n0, n1);
-              }
-              fused_sums = true;
-            } else if (s == top) {
-              pass21<G, R, U>(grp, vec, half,
-                              [&](uint32_t q, uint32_t& r0, uint32_t& r1, uint32_t& w) { r0 = w = q; r1 = q | bs; },
-                              [&](cpx<R> a, cpx<R> c) { return out1(a, c); });
-            } else {
-              // pair (j0, j1 = j0 | bs) of outputs reads its own two elements
-              // and the two above them in the top slot
-              const uint32_t n4 = half >> 1;
-              for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n4; base += U * st) {
-                uint32_t jj[U];
-                cpx<R> a0[U], a1[U], c0[U], c1[U];
-#pragma unroll
-                for (int u = 0; u < U; u++) {
-                  uint32_t q = base + u * st;
-                  jj[u] = ins0(q < n4 ? q : base, s);
-                  if (q < n4) {
-                    a0[u] = vec[jj[u]];
-                    a1[u] = vec[jj[u] | bs];
-                    c0[u] = vec[jj[u] | tb];
-                    c1[u] = vec[jj[u] | bs | tb];
-                  }
-                }
-#pragma unroll
-                for (int u = 0; u < U; u++)
-                  if (base + u * st < n4) {
-                    const cpx<R> lo = out1(a0[u], a1[u]), hi = out1(c0[u], c1[u]);
-                    vec[jj[u]] = lo;
-                    vec[jj[u] | bs] = hi;
-                    // next axis == s: the two outputs are its pair
-                    if (fuse_here) branch_sums(nx, lo, hi, n0, n1);
-                  }
-              }
-              fused_sums = fuse_here;
-            }
-          }
-          pend_tm = pend_sm = 0;
-          pend_as = false;
-          carry_valid = fused_sums;
-          if (fused_sums) {
-            carry0 = grp.sum(n0, red);
-            carry1 = grp.sum(n1, red);
-          }
-          k--;
-          grp.sync();
-          if (isx) { frame_h<W>(T, v); frame_h<W>(N, v); }
-          xorbit<W>(T.x, v, b);
-          last_m = mm;
-          last_pn = pn;
-          int r = as_const(P.ev_rec)[j];
-          if (r >= 0) put((uint32_t)r, mm);
-          }
-          break;
-        }
-        case OP_CPAULI: {
-          uint64_t px[W], pz[W], zero[W];
-#pragma unroll
-          for (int w = 0; w < W; w++) {
-            px[w] = masks[in.a + w];
-            pz[w] = masks[in.a + W + w];
-            zero[w] = 0;
-          }
-          uint64_t mm = 0ull - (uint64_t)last_m, mp = 0ull - (uint64_t)last_pn;
-          uint64_t ax[W], az[W], bx[W], bz[W];
-#pragma unroll
-          for (int w = 0; w < W; w++) {
-            ax[w] = px[w] & mm; az[w] = pz[w] & mm;
-            bx[w] = px[w] & mp; bz[w] = pz[w] & mp;
-          }
-          (void)zero;
-          frame_xor<W>(T, ax, az);
-          frame_xor<W>(N, bx, bz);
-          break;
-        }
-        case OP_NOISE: {
-          if constexpr (DBG) {
-            if (A.forced_faults) {
-              for (uint32_t st = in.a; st < in.b; st++) {
-                int o = local < A.shots ? A.forced_faults[local * P.nsites + st] : -1;
-                if (o >= 0) apply_fault<W>(P, T, N, st, (uint32_t)o);
-              }
-              break;
-            }
-          }
-          const uint32_t hi = in.b;
-          while (ns.nf < hi) {
-            uint32_t cend = min((ns.chunk + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
-            if (ns.nf >= cend) {
-              ns.chunk++;
-              ns.ord = 0;
-              next_fault(P, ns, 0, shot, seed);
-              continue;
-            }
-            apply_fault<W>(P, T, N, ns.nf, ns.nf_out);
-            next_fault(P, ns, ns.nf - ns.chunk * (uint32_t)kChunk + 1, shot, seed);
-          }
-          break;
-        }
-        case OP_DET: {
-          uint32_t d = xor_refs(in.a, in.u);
-          put((uint32_t)P.nrec + in.b, d);
-          break;
-        }
-        case OP_OBS: {
-          uint32_t d = xor_refs(in.a, in.u);
-          uint32_t r = (uint32_t)P.nrec + (uint32_t)P.ndet + in.b;
-          if constexpr (G == 1) {
-            uint64_t word = __ballot(d);
-            if ((threadIdx.x & 63) == 0) rec[r] ^= word;
-          } else {
-            if (grp.tid == 0) rec[r] ^= (uint64_t)d << slane;
-          }
-          break;
-        }
-        default:
-          break;
-      }
-    }
-  done:
-    if constexpr (DBG) {
-      if (A.phi_out && local < A.shots && P.kmax == 0) {
-        // no active vector exists: the state is the trivial [1]
-        if (G == 1 || grp.tid == 0) {
-          A.phi_out[local * 2] = 1.0;
-          A.phi_out[local * 2 + 1] = 0.0;
-        }
-      } else if (VEC && A.phi_out && local < A.shots) {
-        if constexpr (OOP) materialize();
-        // final active vector (its length 2^k is program-determined)
-        FOR_GROUP(p, (1u << k)) {
-          cpx<R> a = vec[p];
-          A.phi_out[(local << P.kmax) * 2 + 2 * p] = (double)a.re;
-          A.phi_out[(local << P.kmax) * 2 + 2 * p + 1] = (double)a.im;
-        }
-      }
-    }
-    grp.sync();
-  }
-};
-
-// ------------------------------------------------------------------ kernel
-// One persistent launch: units (lanes-of-a-wave for G = 1, waves for G = 64,
-// workgroups for G = 256) take 64-shot tiles round-robin.
-template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC>
-__global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int units_per_block = G == 256 ? 1 : 4;
-  const int unit_in_block = G == 256 ? 0 : (int)rfl(threadIdx.x >> 6);
-  const uint64_t unit = (uint64_t)blockIdx.x * units_per_block + unit_in_block;
-  const uint64_t nunits = (uint64_t)gridDim.x * units_per_block;
-  const uint32_t nwords_rec = (uint32_t)(P.nrec + P.ndet + P.nobs);
-  const uint32_t rec_stride = (nwords_rec + 1) & ~1u;  // keep 16-byte alignment
-  uint64_t* rec = (uint64_t*)smem + (size_t)unit_in_block * rec_stride;
-  unsigned char* after_rec = smem + (size_t)units_per_block * rec_stride * 8;
-  double* red = (double*)after_rec;
-  cpx<R>* arr_lds = (cpx<R>*)(after_rec + 64);
-  const size_t vec_elems = (size_t)1 << P.kmax;
-  cpx<R>* base;
-  cpx<R>* alt = nullptr;
-  if constexpr (GLOBAL) {
-    // two buffers per unit (active measurements collapse from one into the other)
-    const size_t per = vec_elems * (G == 1 ? 64 : 1);
-    base = (cpx<R>*)A.workspace + unit * per * 2;
-    alt = base + per;
-  } else {
-    base = arr_lds + (size_t)unit_in_block * vec_elems * (G == 1 ? 64 : 1);
-  }
-  const int lane = threadIdx.x & 63;
-  const int tid = G == 256 ? (int)threadIdx.x : lane;
-  const uint64_t ntiles = (A.shots + 63) / 64;
-  const uint64_t words = ntiles;
-  if constexpr (G > 1) {
-    // One shot per workgroup (G = 256) or per wave (G = 64): shots (not
-    // tiles) are spread over the units so that small shot counts still fill
-    // the device; record bits are staged per shot (bit 0) and ORed into the
-    // zero-filled outputs.
-    auto unit_sync = [] {
-      if constexpr (G == 256) __syncthreads();
-      else { __builtin_amdgcn_wave_barrier(); __atomic_signal_fence(__ATOMIC_SEQ_CST); }
-    };
-    for (uint64_t sh_i = unit; sh_i < A.shots; sh_i += nunits) {
-      for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += G) rec[r] = 0;
-      unit_sync();
-      uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0,
-                                                                  A.offset + g, g, alt};
-      sh.run();
-      unit_sync();
-      const uint64_t bit = 1ull << (g & 63);
-      const size_t word = (size_t)(g >> 6);
-      for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += G) {
-        if (!(rec[r] & 1ull)) continue;
-        uint64_t* dst;
-        if (r < (uint32_t)P.nrec) dst = A.meas ? A.meas + (size_t)r * words + word : nullptr;
-        else if (r < (uint32_t)(P.nrec + P.ndet)) dst = A.det ? A.det + (size_t)(r - P.nrec) * words + word : nullptr;
-        else dst = A.obs ? A.obs + (size_t)(r - P.nrec - P.ndet) * words + word : nullptr;
-        if (dst) atomicOr((unsigned long long*)dst, (unsigned long long)bit);
-      }
-      unit_sync();
-    }
-    return;
-  }
-  for (uint64_t tile = unit; tile < ntiles; tile += nunits) {
-    for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 64) rec[r] = 0;
-    __builtin_amdgcn_wave_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    if constexpr (G == 1) {
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
-                                                                  A.offset + tile * 64 + lane, tile * 64 + lane, alt};
-      sh.run();
-    } else {
-      uint32_t nsh = (uint32_t)min((uint64_t)64, A.shots - tile * 64);
-      for (uint32_t sl = 0; sl < nsh; sl++) {
-        uint64_t g = rfl((uint32_t)(tile * 64 + sl)) | ((tile * 64 + sl) & 0xFFFFFFFF00000000ull);
-        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red,
-                                                                    (int)sl, A.offset + g, g, alt};
-        sh.run();
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    // flush the tile's record words (bits of shots beyond the end cleared)
-    const uint64_t nvalid = min((uint64_t)64, A.shots - tile * 64);
-    const uint64_t vmask = nvalid == 64 ? ~0ull : ((1ull << nvalid) - 1ull);
-    for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += 64) {
-      uint64_t v = rec[r] & vmask;
-      if (r < (uint32_t)P.nrec) {
-        if (A.meas) A.meas[(size_t)r * words + tile] = v;
-      } else if (r < (uint32_t)(P.nrec + P.ndet)) {
-        if (A.det) A.det[(size_t)(r - P.nrec) * words + tile] = v;
-      } else {
-        if (A.obs) A.obs[(size_t)(r - P.nrec - P.ndet) * words + tile] = v;
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  }
-}
 
 // Zero-fill of record rows (a plain kernel rather than a memset node, so the
 // whole call can be captured in a graph).
@@ -1420,686 +17,11 @@ __global__ void k_zero(uint64_t* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
-// ------------------------------------------------------------------ bit-sliced frames
-// Pauli-frame-only programs (k_max = 0): every lane carries 32 shots, one bit
-// per shot, so a frame bit of one virtual qubit for the 64 x 32 shots of a
-// wave is one 256-byte LDS row (lane l owns word l: conflict free).  Frame
-// instructions become a few word operations per touched qubit for 2048
-// shots; dispatch is paid once per 2048 shots.  The stochastic contract is
-// the per-shot one of the other kernels (each shot keeps its own gap-sampler
-// cursor), so records are identical.
-constexpr int kShotsPerLane = 32;
-
-struct FrameRows {
-  uint32_t* base;  // LDS rows of 64 words
-  int lane;
-  __device__ uint32_t& operator()(uint32_t row) const { return base[row * 64u + (uint32_t)lane]; }
-};
-
-// first fault at or after local index cur of `chunk` for one shot; returns
-// the absolute site (chunk end when none) and advances *ord
-template <bool LDS_SURV>
-DEV uint32_t bs_next_fault(const DevProgram& P, const double* surv_lds, uint32_t chunk, uint32_t cur, uint32_t* ord,
-                           uint64_t shot, uint64_t seed, uint32_t* outcome = nullptr) {
-  U4 w = draw((*ord)++, kPurposeNoise | chunk, shot, seed);
-  const double* S = LDS_SURV ? surv_lds : P.surv + (size_t)chunk * (kChunk + 1);
-  uint32_t len = min((uint32_t)kChunk, (uint32_t)P.nsites - chunk * (uint32_t)kChunk);
-  double tau = uniform53(w) * S[cur];
-  uint32_t lo = cur, hi = len;
-  if (S[len] > tau) lo = len;  // no fault in the rest of the chunk (same answer as the search)
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (S[mid + 1] <= tau) hi = mid;
-    else lo = mid + 1;
-  }
-  const uint32_t nf = chunk * (uint32_t)kChunk + lo;
-  if (outcome && lo < len) {
-    const uint64_t w64 = ((uint64_t)w.w3 << 32) | w.w2;
-    *outcome = (uint32_t)__umul64hi(w64, (uint64_t)nout_of(P.site_type[nf]));
-  }
-  return nf;
-}
-
-template <int W>
-DEV void bs_apply_fault(const DevProgram& P, const FrameRows& F, uint32_t N, uint32_t site, uint32_t o, uint32_t bit) {
-  uint32_t t = P.site_type[site];
-  const uint64_t* img = P.masks + P.site_img[site];
-  uint32_t la, lb = 0;
-  if (t == S_DEP1) la = o + 1;
-  else if (t == S_DEP2) { la = (o + 1) >> 2; lb = (o + 1) & 3; }
-  else la = t - 1;
-  for (int qi = 0; qi < (t == S_DEP2 ? 2 : 1); qi++) {
-    const uint32_t l = qi ? lb : la;
-    const uint64_t ux = (l == 1 || l == 2) ? ~0ull : 0ull, uz = (l == 2 || l == 3) ? ~0ull : 0ull;
-    const uint64_t* ix = img + (size_t)qi * 4 * W;
-    const uint64_t* iz = ix + 2 * W;
-    for (int w = 0; w < W; w++) {
-      uint64_t ex = (ix[w] & ux) ^ (iz[w] & uz);
-      uint64_t ez = (ix[W + w] & ux) ^ (iz[W + w] & uz);
-      while (ex) {
-        uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)ex) - 1);
-        ex &= ex - 1;
-        F(q) ^= bit;          // full x
-        F(2 * N + q) ^= bit;  // noise x
-      }
-      while (ez) {
-        uint32_t q = (uint32_t)(w * 64 + __ffsll((unsigned long long)ez) - 1);
-        ez &= ez - 1;
-        F(N + q) ^= bit;      // full z
-        F(3 * N + q) ^= bit;  // noise z
-      }
-    }
-  }
-}
-
-// LDS rows: [0,4N) frames (full x, full z, noise x, noise z), then one row
-// per detector and observable accumulator, then the dormant-random bit rows
-// of the current 128-event block, then the lane's fault list (or per-shot
-// noise cursors: site; draw ordinal | chunk << 16), then a row that stays
-// zero and a row that absorbs stores of unused slots (so batched accesses
-// need no branches), then the survival products when they fit.
-constexpr int kSurvLdsMax = 2048;  // survival products staged in LDS (single chunk, up to this many sites)
-constexpr int kListCap = 24;       // faults per lane kept in the precomputed list
-DEV_HOST_INLINE bool frames_surv_in_lds(const DevProgram& P) { return P.nchunks == 1 && P.nsites < kSurvLdsMax; }
-// Low-noise programs precompute each lane's faults into a site-sorted list
-// (expected faults per lane at most a quarter of the list); others keep one
-// sampler cursor per shot.
-DEV_HOST_INLINE bool frames_fault_list(const DevProgram& P) {
-  return P.nsites < (1 << 23) && (double)P.exp_faults * kShotsPerLane <= kListCap / 4;
-}
-size_t frames_lds_rows(const DevProgram& P) {
-  size_t rows = (size_t)4 * P.nq + P.ndet_rows + P.nobs + (P.rblk_max > 0 ? P.rblk_max : 1);
-  rows += frames_fault_list(P) ? kListCap : 2 * kShotsPerLane;
-  rows += 2;  // zero row, dump row
-  if (frames_surv_in_lds(P)) rows += ((size_t)(P.nsites + 1) * 8 + 255) / 256;  // doubles, in 256-byte rows
-  return rows;
-}
-
-// Up to four set bits of a wave-uniform mask word (qubit wbase + bit),
-// removed from m; returns how many.
-MDEV int take4(uint64_t& m, uint32_t wbase, uint32_t (&q)[4]) {
-  int n = 0;
-#pragma unroll
-  for (int i = 0; i < 4; i++) {
-    q[i] = m ? wbase + (uint32_t)__ffsll((unsigned long long)m) - 1 : 0u;
-    n += m ? 1 : 0;
-    m &= m - 1;
-  }
-  return n;
-}
-
-template <int W, bool LDS_SURV, bool LIST>
-__global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
-  extern __shared__ __align__(16) uint32_t sm[];
-  const int lane = threadIdx.x;
-  const uint32_t N = (uint32_t)P.nq;
-  const FrameRows F{sm, lane};
-  const uint32_t ACC = 4 * N, RB = ACC + (uint32_t)(P.ndet_rows + P.nobs);
-  // LIST: rows [NF, NF + kListCap) hold the fault list; otherwise per-shot
-  // cursors: next fault site at NF + s, draw ordinal | chunk << 16 at OC + s
-  const uint32_t NF = RB + (uint32_t)(P.rblk_max > 0 ? P.rblk_max : 1), OC = NF + kShotsPerLane;
-  const uint32_t ZR = NF + (LIST ? kListCap : 2 * kShotsPerLane), DR = ZR + 1;
-  double* surv = (double*)(sm + (size_t)(DR + 1) * 64);
-  F(ZR) = 0;
-  if (LDS_SURV)
-    for (int i = lane; i <= P.nsites; i += 64) surv[i] = P.surv[i];
-  __syncthreads();
-  const uint64_t seed = A.seed;
-  const uint64_t words64 = (A.shots + 63) / 64;
-  const uint64_t tiles = (A.shots + 64 * kShotsPerLane - 1) / (64 * kShotsPerLane);
-  uint32_t* meas32 = (uint32_t*)A.meas;
-  uint32_t* det32 = (uint32_t*)A.det;
-  uint32_t* obs32 = (uint32_t*)A.obs;
-  cptr<uint64_t> masks = as_const(P.masks);
-  cptr<uint32_t> rec_tgt_off = as_const(P.rec_tgt_off), rec_tgt = as_const(P.rec_tgt);
-  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const uint64_t s0 = tile * (64 * kShotsPerLane) + (uint64_t)lane * kShotsPerLane;  // first shot of the lane
-    const uint32_t valid = s0 >= A.shots ? 0u : (A.shots - s0 >= 32 ? ~0u : ((1u << (A.shots - s0)) - 1u));
-    const size_t col = (size_t)(s0 >> 5);  // 32-bit column of this lane in the record rows
-    const bool store = col < 2 * words64;  // inside the buffer (bits past the last shot are written as 0)
-    for (uint32_t r = 0; r < RB; r++) F(r) = 0;
-    uint32_t min_nf = 0xFFFFFFFFu;
-    uint32_t lcnt = 0, lhead = 0;
-    const uint32_t lcap = min((uint32_t)kListCap, A.list_cap);
-    bool lovf = false;
-    if (LIST && P.nsites > 0) {
-      // every fault of the lane's 32 shots, as (site << 9 | shot << 4 | outcome)
-      for (int j = 0; j < kShotsPerLane; j++) {
-        const uint64_t shot = A.offset + s0 + j;
-        for (uint32_t c = 0; c < (uint32_t)P.nchunks; c++) {
-          const uint32_t cend = min((c + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
-          uint32_t ord = 0, cur = 0;
-          for (;;) {
-            uint32_t o = 0;
-            const uint32_t nf = bs_next_fault<LDS_SURV>(P, surv, c, cur, &ord, shot, seed, &o);
-            if (nf >= cend) break;
-            if (lcnt < lcap) F(NF + lcnt) = (nf << 9) | ((uint32_t)j << 4) | o;
-            else lovf = true;
-            lcnt++;
-            cur = nf - c * (uint32_t)kChunk + 1;
-          }
-        }
-      }
-      const uint32_t n = min(lcnt, lcap);
-      for (uint32_t i = 1; i < n; i++) {  // insertion sort by site
-        const uint32_t e = F(NF + i);
-        uint32_t kk = i;
-        while (kk > 0 && F(NF + kk - 1) > e) {
-          F(NF + kk) = F(NF + kk - 1);
-          kk--;
-        }
-        F(NF + kk) = e;
-      }
-    }
-    // per-shot noise cursors
-    if (!LIST && P.nsites > 0) {
-      for (int j = 0; j < kShotsPerLane; j++) {
-        uint32_t ord = 0;
-        uint32_t nf = bs_next_fault<LDS_SURV>(P, surv, 0, 0, &ord, A.offset + s0 + j, seed);
-        F(NF + j) = nf;
-        F(OC + j) = ord;
-        min_nf = min(min_nf, nf);
-      }
-    }
-    uint32_t last_m = 0, last_pn = 0;
-    uint32_t rblk = 0xFFFFFFFFu;
-    for (int pc = 0;; pc++) {
-      const GInstr in = load_instr(P.code, pc);
-      const uint32_t v = in.v;
-      if (in.op == OP_END) break;
-      switch (in.op) {
-        case OP_FANCX:
-        case OP_FANCZ:
-        case OP_FAN2: {
-          // target rows T ^= the pivot word, parity of rows Q into the pivot;
-          // four targets (both frames) per round trip
-          const uint32_t xv = F(v), zv = F(N + v), nxv = F(2 * N + v), nzv = F(3 * N + v);
-          const bool cx = in.op == OP_FANCX;
-          const uint32_t tf = cx ? 0u : N, qf = cx ? N : 0u;  // row offsets of T and Q in the full frame
-          const uint32_t sf = in.op == OP_FAN2 ? zv : xv, sn = in.op == OP_FAN2 ? nzv : nxv;
-          uint32_t par = 0, npar = 0;
-          for (int w = 0; w < W; w++) {
-            uint64_t m = masks[in.a + w];
-            while (m) {
-              uint32_t q[4];
-              const int n = take4(m, (uint32_t)w * 64, q);
-              uint32_t rt[4], rq[4], a[4], b[4], c[4], d[4];
-#pragma unroll
-              for (int i = 0; i < 4; i++) {
-                rt[i] = i < n ? tf + q[i] : DR;
-                rq[i] = i < n ? qf + q[i] : ZR;
-              }
-#pragma unroll
-              for (int i = 0; i < 4; i++) {
-                a[i] = F(rt[i]);
-                b[i] = F(rt[i] == DR ? DR : rt[i] + 2 * N);
-                c[i] = F(rq[i]);
-                d[i] = F(rq[i] == ZR ? ZR : rq[i] + 2 * N);
-              }
-#pragma unroll
-              for (int i = 0; i < 4; i++) {
-                F(rt[i]) = a[i] ^ sf;
-                F(rt[i] == DR ? DR : rt[i] + 2 * N) = b[i] ^ sn;
-                par ^= c[i];
-                npar ^= d[i];
-              }
-            }
-          }
-          if (in.op == OP_FAN2) {
-            F(v) = xv ^ par;
-            F(2 * N + v) = nxv ^ npar;
-          } else {
-            F(N + v) = zv ^ par;
-            F(3 * N + v) = nzv ^ npar;
-          }
-          break;
-        }
-        case OP_FS: {
-          const uint32_t x = F(v), z = F(N + v), nx = F(2 * N + v), nz = F(3 * N + v);
-          F(N + v) = z ^ x;
-          F(3 * N + v) = nz ^ nx;
-          break;
-        }
-        case OP_FH: {
-          const uint32_t x = F(v), z = F(N + v), nx = F(2 * N + v), nz = F(3 * N + v);
-          F(v) = z;
-          F(N + v) = x;
-          F(2 * N + v) = nz;
-          F(3 * N + v) = nx;
-          break;
-        }
-        case OP_MSTATIC:
-        case OP_MRANDOM: {
-          uint32_t mm, pn;
-          if (in.op == OP_MSTATIC) {
-            // parity of the x rows over the measured Z-string, both frames
-            mm = (in.flags & F_SIGN) ? ~0u : 0u;
-            pn = 0;
-            for (int w = 0; w < W; w++) {
-              uint64_t m = masks[in.a + w];
-              while (m) {
-                uint32_t q[4];
-                const int n = take4(m, (uint32_t)w * 64, q);
-                uint32_t a[4], b[4];
-#pragma unroll
-                for (int i = 0; i < 4; i++) {
-                  a[i] = F(i < n ? q[i] : ZR);
-                  b[i] = F(i < n ? 2 * N + q[i] : ZR);
-                }
-                mm ^= a[0] ^ a[1] ^ a[2] ^ a[3];
-                pn ^= b[0] ^ b[1] ^ b[2] ^ b[3];
-              }
-            }
-          } else {
-            const uint32_t j = in.b, blk = j >> 7;
-            if (blk != rblk) {
-              // bits of this block's dormant random events for the lane's 32
-              // shots, eight events per pass, gathered in registers
-              const uint32_t o0 = P.rblk_off[blk], o1 = P.rblk_off[blk + 1];
-              for (uint32_t g = o0; g < o1; g += 8) {
-                uint32_t e[8], bits[8];
-#pragma unroll
-                for (int i = 0; i < 8; i++) {
-                  e[i] = g + i < o1 ? (uint32_t)P.rblk_ev[g + i] : 0u;
-                  bits[i] = 0;
-                }
-                for (int s = 0; s < kShotsPerLane; s++) {
-                  const U4 w = draw(blk, kPurposeRbit, A.offset + s0 + s, seed);
-#pragma unroll
-                  for (int i = 0; i < 8; i++) {
-                    const uint32_t h = e[i] >> 5;
-                    const uint32_t wv = h == 0 ? w.w0 : h == 1 ? w.w1 : h == 2 ? w.w2 : w.w3;
-                    bits[i] |= ((wv >> (e[i] & 31)) & 1u) << s;
-                  }
-                }
-#pragma unroll
-                for (int i = 0; i < 8; i++)
-                  if (g + i < o1) F(RB + (g - o0) + i) = bits[i];
-              }
-              rblk = blk;
-            }
-            const uint32_t x = F(v), z = F(N + v), nx = F(2 * N + v), nz = F(3 * N + v), rb = F(RB + in.u);
-            pn = nz;
-            mm = rb ^ pn;
-            const uint32_t b = mm ^ z ^ ((in.flags & F_SIGN) ? ~0u : 0u);
-            // H absorbed after the outcome, then the correction X^b
-            F(v) = z ^ b;
-            F(N + v) = x;
-            F(2 * N + v) = nz;
-            F(3 * N + v) = nx;
-          }
-          last_m = mm;
-          last_pn = pn;
-          const int r = as_const(P.ev_rec)[in.b];
-          if (r >= 0) {
-            if (meas32 && store) meas32[(size_t)r * 2 * words64 + col] = mm & valid;
-            // accumulators fed by this record, four per round trip
-            const uint32_t t1 = rec_tgt_off[r + 1];
-            for (uint32_t t = rec_tgt_off[r]; t < t1; t += 4) {
-              uint32_t rr[4], a[4];
-#pragma unroll
-              for (int i = 0; i < 4; i++) rr[i] = t + i < t1 ? ACC + rec_tgt[t + i] : DR;
-#pragma unroll
-              for (int i = 0; i < 4; i++) a[i] = F(rr[i]);
-#pragma unroll
-              for (int i = 0; i < 4; i++) F(rr[i]) = a[i] ^ mm;
-            }
-          }
-          break;
-        }
-        case OP_CPAULI: {
-          // X^m on the x rows (full frame), X^pn (noise frame); same for Z
-          for (int zpart = 0; zpart < 2; zpart++) {
-            const uint32_t off = zpart ? N : 0u;
-            for (int w = 0; w < W; w++) {
-              uint64_t m = masks[in.a + zpart * W + w];
-              while (m) {
-                uint32_t q[4], rf[4], rn[4], a[4], b[4];
-                const int n = take4(m, (uint32_t)w * 64, q);
-#pragma unroll
-                for (int i = 0; i < 4; i++) {
-                  rf[i] = i < n ? off + q[i] : DR;
-                  rn[i] = i < n ? 2 * N + off + q[i] : DR;
-                }
-#pragma unroll
-                for (int i = 0; i < 4; i++) {
-                  a[i] = F(rf[i]);
-                  b[i] = F(rn[i]);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; i++) {
-                  F(rf[i]) = a[i] ^ last_m;
-                  F(rn[i]) = b[i] ^ last_pn;
-                }
-              }
-            }
-          }
-          break;
-        }
-        case OP_NOISE: {
-          const uint32_t hi = in.b;
-          if (LIST) {
-            if (!lovf) {
-              while (lhead < lcnt) {
-                const uint32_t e = F(NF + lhead);
-                if ((e >> 9) >= hi) break;
-                bs_apply_fault<W>(P, F, N, e >> 9, e & 15u, 1u << ((e >> 4) & 31u));
-                lhead++;
-              }
-            } else {
-              // list overflow (rare): re-draw this block's faults per shot from
-              // the start of each chunk it touches (stateless, same faults)
-              const uint32_t lo = in.a;
-              for (int j = 0; j < kShotsPerLane; j++) {
-                const uint64_t shot = A.offset + s0 + j;
-                for (uint32_t c = lo / (uint32_t)kChunk; c * (uint32_t)kChunk < hi; c++) {
-                  const uint32_t cend = min(min((c + 1) * (uint32_t)kChunk, (uint32_t)P.nsites), hi);
-                  uint32_t ord = 0, cur = 0;
-                  for (;;) {
-                    uint32_t o = 0;
-                    const uint32_t nf = bs_next_fault<LDS_SURV>(P, surv, c, cur, &ord, shot, seed, &o);
-                    if (nf >= cend) break;
-                    if (nf >= lo) bs_apply_fault<W>(P, F, N, nf, o, 1u << j);
-                    cur = nf - c * (uint32_t)kChunk + 1;
-                  }
-                }
-              }
-            }
-            break;
-          }
-          if (min_nf < hi) {
-            // which of the lane's shots have a fault before hi: 32 independent
-            // LDS loads, then a mask
-            uint32_t due = 0;
-#pragma unroll
-            for (int s = 0; s < kShotsPerLane; s++) due |= (uint32_t)(F(NF + s) < hi) << s;
-            while (due) {
-              const int s = __ffs(due) - 1;
-              due &= due - 1;
-              uint32_t nf = F(NF + s);
-              {
-                uint32_t oc = F(OC + s);
-                uint32_t chunk = oc >> 16, ord = oc & 0xFFFFu;
-                const uint64_t shot = A.offset + s0 + s;
-                while (nf < hi) {
-                  const uint32_t cend = min((chunk + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
-                  if (nf >= cend) {
-                    chunk++;
-                    ord = 0;
-                    nf = bs_next_fault<LDS_SURV>(P, surv, chunk, 0, &ord, shot, seed);
-                    continue;
-                  }
-                  // the outcome comes from the draw that placed this fault
-                  U4 w = draw(ord - 1, kPurposeNoise | chunk, shot, seed);
-                  const uint64_t w64 = ((uint64_t)w.w3 << 32) | w.w2;
-                  const uint32_t o = (uint32_t)__umul64hi(w64, (uint64_t)nout_of(P.site_type[nf]));
-                  bs_apply_fault<W>(P, F, N, nf, o, 1u << s);
-                  nf = bs_next_fault<LDS_SURV>(P, surv, chunk, nf - chunk * (uint32_t)kChunk + 1, &ord, shot, seed);
-                }
-                F(NF + s) = nf;
-                F(OC + s) = ord | (chunk << 16);
-              }
-            }
-            uint32_t nmin = 0xFFFFFFFFu;
-#pragma unroll
-            for (int s = 0; s < kShotsPerLane; s++) nmin = min(nmin, F(NF + s));
-            min_nf = nmin;
-          }
-          break;
-        }
-        case OP_DET:
-          if (det32 && store) det32[(size_t)in.b * 2 * words64 + col] = F(ACC + in.s) & valid;
-          F(ACC + in.s) = 0;  // the row is reused by a later detector
-          break;
-        default:  // OP_OBS: accumulated from its records; no active-vector ops exist here
-          break;
-      }
-    }
-    if (obs32 && store)
-      for (int o = 0; o < P.nobs; o++) obs32[(size_t)o * 2 * words64 + col] = F(ACC + P.ndet_rows + o) & valid;
-  }
-}
-
-template <bool LS, bool LI>
-static hipError_t launch_frames_t(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
-  static bool attr[5] = {false, false, false, false, false};
-  const void* fn = P.W == 1 ? (const void*)k_frames<1, LS, LI> : P.W == 2 ? (const void*)k_frames<2, LS, LI>
-                   : P.W == 3 ? (const void*)k_frames<3, LS, LI> : (const void*)k_frames<4, LS, LI>;
-  if (!attr[P.W]) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr[P.W] = true;
-  }
-  switch (P.W) {
-    case 1: hipLaunchKernelGGL((k_frames<1, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
-    case 2: hipLaunchKernelGGL((k_frames<2, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
-    case 3: hipLaunchKernelGGL((k_frames<3, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
-    default: hipLaunchKernelGGL((k_frames<4, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStream_t st) {
-  const size_t lds = frames_lds_rows(P) * 64 * 4;
-  const bool ls = frames_surv_in_lds(P), li = frames_fault_list(P);
-  if (ls && li) return launch_frames_t<true, true>(P, A, grid, lds, st);
-  if (ls) return launch_frames_t<true, false>(P, A, grid, lds, st);
-  if (li) return launch_frames_t<false, true>(P, A, grid, lds, st);
-  return launch_frames_t<false, false>(P, A, grid, lds, st);
-}
-
-// ------------------------------------------------------------------ batched launch
-// One persistent launch over many programs of different width and active
-// dimension.  Workgroups claim items in the order the host sorted them
-// (longest first) from an atomic counter; an item is either four 64-shot
-// tiles of a shot-per-lane program (one tile per wave) or one shot of a
-// shot-per-workgroup program.  Every active vector lives in the workgroup's
-// slice of the global workspace.
-template <int W, typename R, int KIND>
-__device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgram& bp, const BatchItem& it, uint64_t* rec,
-                           double* red, unsigned char* slot) {
-  const DevProgram& P = bp.P;
-  KArgs A{};
-  A.shots = bp.shots;
-  A.seed = bp.seed;
-  A.offset = bp.offset;
-  A.meas = B.meas ? B.meas + bp.meas_off : nullptr;
-  A.det = B.det ? B.det + bp.det_off : nullptr;
-  A.obs = B.obs ? B.obs + bp.obs_off : nullptr;
-  const uint32_t nwords_rec = (uint32_t)(P.nrec + P.ndet + P.nobs);
-  const uint64_t words = (bp.shots + 63) / 64;
-  const int lane = threadIdx.x & 63;
-  if constexpr (KIND == 1) {
-    const int wv = (int)rfl(threadIdx.x >> 6);
-    const uint64_t tile = it.first + (uint64_t)wv;
-    uint64_t* wrec = rec + (size_t)wv * B.rec_words;
-    if (tile < words) {
-      for (uint32_t r = (uint32_t)lane; r < nwords_rec; r += 64) wrec[r] = 0;
-      __builtin_amdgcn_wave_barrier();
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      const size_t per = 64 * ((size_t)1 << P.kmax);  // each wave: two buffers
-      cpx<R>* base = (cpx<R>*)slot + (size_t)wv * 2 * per;
-      if (P.kmax == 0) {
-        Shot<W, 1, R, false, false> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
-                                       A.offset + tile * 64 + lane, tile * 64 + lane};
-        sh.run();
-      } else {
-        Shot<W, 1, R, false, true, kUnroll, true> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
-                                                      A.offset + tile * 64 + lane, tile * 64 + lane, base + per};
-        sh.run();
-      }
-      __builtin_amdgcn_wave_barrier();
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      const uint64_t nvalid = min((uint64_t)64, A.shots - tile * 64);
-      const uint64_t vmask = nvalid == 64 ? ~0ull : ((1ull << nvalid) - 1ull);
-      for (uint32_t r = (uint32_t)lane; r < nwords_rec; r += 64) {
-        uint64_t v = wrec[r] & vmask;
-        if (r < (uint32_t)P.nrec) {
-          if (A.meas) A.meas[(size_t)r * words + tile] = v;
-        } else if (r < (uint32_t)(P.nrec + P.ndet)) {
-          if (A.det) A.det[(size_t)(r - P.nrec) * words + tile] = v;
-        } else {
-          if (A.obs) A.obs[(size_t)(r - P.nrec - P.ndet) * words + tile] = v;
-        }
-      }
-    }
-  } else if constexpr (KIND == 64) {
-    // up to four shots, one per wave, each with its own two buffers
-    const int wv = (int)rfl(threadIdx.x >> 6);
-    const uint64_t sh_i = it.first + (uint64_t)wv;
-    uint64_t* wrec = rec + (size_t)wv * B.rec_words;
-    if (sh_i < bp.shots) {
-      for (uint32_t r = (uint32_t)lane; r < nwords_rec; r += 64) wrec[r] = 0;
-      __builtin_amdgcn_wave_barrier();
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      const uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
-      const size_t per = (size_t)1 << P.kmax;
-      cpx<R>* base = (cpx<R>*)slot + (size_t)wv * 2 * per;
-      Shot<W, 64, R, false, true, unroll_for<R, true>(), true> sh{P, A, Group<64>{lane}, Vec<64, R>{base, lane}, wrec,
-                                                               red, 0, A.offset + g, g, base + per};
-      sh.run();
-      __builtin_amdgcn_wave_barrier();
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      const uint64_t bit = 1ull << (g & 63);
-      const size_t word = (size_t)(g >> 6);
-      for (uint32_t r = (uint32_t)lane; r < nwords_rec; r += 64) {
-        if (!(wrec[r] & 1ull)) continue;
-        uint64_t* dst;
-        if (r < (uint32_t)P.nrec) dst = A.meas ? A.meas + (size_t)r * words + word : nullptr;
-        else if (r < (uint32_t)(P.nrec + P.ndet)) dst = A.det ? A.det + (size_t)(r - P.nrec) * words + word : nullptr;
-        else dst = A.obs ? A.obs + (size_t)(r - P.nrec - P.ndet) * words + word : nullptr;
-        if (dst) atomicOr((unsigned long long*)dst, (unsigned long long)bit);
-      }
-    }
-  } else {
-    const uint64_t g = rfl((uint32_t)it.first) | (it.first & 0xFFFFFFFF00000000ull);
-    for (uint32_t r = threadIdx.x; r < nwords_rec; r += 256) rec[r] = 0;
-    __syncthreads();
-    Shot<W, 256, R, false, true, unroll_for<R, true>(), true> sh{P, A, Group<256>{(int)threadIdx.x},
-                                                              Vec<256, R>{(cpx<R>*)slot, lane}, rec, red, 0, A.offset + g,
-                                                              g, (cpx<R>*)slot + ((size_t)1 << P.kmax)};
-    sh.run();
-    __syncthreads();
-    const uint64_t bit = 1ull << (g & 63);
-    const size_t word = (size_t)(g >> 6);
-    for (uint32_t r = threadIdx.x; r < nwords_rec; r += 256) {
-      if (!(rec[r] & 1ull)) continue;
-      uint64_t* dst;
-      if (r < (uint32_t)P.nrec) dst = A.meas ? A.meas + (size_t)r * words + word : nullptr;
-      else if (r < (uint32_t)(P.nrec + P.ndet)) dst = A.det ? A.det + (size_t)(r - P.nrec) * words + word : nullptr;
-      else dst = A.obs ? A.obs + (size_t)(r - P.nrec - P.ndet) * words + word : nullptr;
-      if (dst) atomicOr((unsigned long long*)dst, (unsigned long long)bit);
-    }
-  }
-  __syncthreads();
-}
-
-// KIND 256: the shot-per-workgroup queue; KIND 64: four shots per
-// workgroup, one per wave; KIND 1: the shot-per-lane tiles.  Separate
-// kernels, so that each path gets the registers it needs.  The cooperative
-// kinds inline the interpreter for every frame width and would need about
-// 200 VGPRs (two waves per SIMD); they are held to four waves per SIMD,
-// which spills a few values to scratch and runs the batched set 1.2x faster.
-template <typename R, int KIND>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == 1 ? 1 : 4))) void k_batch(BatchArgs B) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint64_t* rec = (uint64_t*)smem;  // 4 * rec_words
-  double* red = (double*)(smem + (size_t)4 * B.rec_words * 8);
-  uint32_t* claim = (uint32_t*)(smem + (size_t)4 * B.rec_words * 8 + 64);
-  unsigned char* slot = (unsigned char*)B.workspace + (size_t)blockIdx.x * B.slot_bytes;
-  for (;;) {
-    if (threadIdx.x == 0) *claim = atomicAdd(B.counter, 1u);
-    __syncthreads();
-    const uint32_t item = rfl(*claim);
-    __syncthreads();
-    if ((uint64_t)item >= B.nitems) break;
-    const BatchItem it = B.items[item];
-    const BatchProgram& bp = B.progs[it.prog];
-    switch (bp.P.W) {
-      case 1: batch_item<1, R, KIND>(B, bp, it, rec, red, slot); break;
-      case 2: batch_item<2, R, KIND>(B, bp, it, rec, red, slot); break;
-      case 3: batch_item<3, R, KIND>(B, bp, it, rec, red, slot); break;
-      default: batch_item<4, R, KIND>(B, bp, it, rec, red, slot); break;
-    }
-  }
-}
-
-template <typename R, int KIND>
-static hipError_t launch_batch_t(const BatchArgs& B, int grid, size_t lds_bytes, hipStream_t st) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e =
-        hipFuncSetAttribute((const void*)k_batch<R, KIND>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL((k_batch<R, KIND>), dim3(grid), dim3(256), lds_bytes, st, B);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArgs& waves, int grid_waves,
-                        const BatchArgs& lanes, int grid_lanes, size_t lds_bytes, bool fp64, hipStream_t st) {
-  // the three claim counters (32-bit words at the starts of three 64-bit slots)
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (uint64_t*)groups.counter, (size_t)3);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess && groups.nitems)
-    e = fp64 ? launch_batch_t<double, 256>(groups, grid_groups, lds_bytes, st)
-             : launch_batch_t<float, 256>(groups, grid_groups, lds_bytes, st);
-  if (e == hipSuccess && waves.nitems)
-    e = fp64 ? launch_batch_t<double, 64>(waves, grid_waves, lds_bytes, st)
-             : launch_batch_t<float, 64>(waves, grid_waves, lds_bytes, st);
-  if (e == hipSuccess && lanes.nitems)
-    e = fp64 ? launch_batch_t<double, 1>(lanes, grid_lanes, lds_bytes, st)
-             : launch_batch_t<float, 1>(lanes, grid_lanes, lds_bytes, st);
-  return e;
-}
-
 hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t st) {
   if (!p || n == 0) return hipSuccess;
   int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
   hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, p, n);
   return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ dispatch table
-template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC>
-static hipError_t launch_one(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
-  static bool attr = false;  // allow the whole 160 KB of LDS for dynamic use
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG, VEC>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG, VEC>), dim3(grid), dim3(256), lds, st, P, A);
-  return hipGetLastError();
-}
-
-template <int G, typename R, bool GLOBAL, bool DBG, bool VEC = true>
-static hipError_t launch_w(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
-  switch (P.W) {
-    case 1: return launch_one<1, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
-    case 2: return launch_one<2, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
-    case 3: return launch_one<3, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
-    case 4: return launch_one<4, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <typename R, bool DBG>
-static hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t st) {
-  if (L.G == 1) {
-    // Pauli-frame-only programs get an instantiation without any active-vector code
-    if (P.kmax == 0) return launch_w<1, R, false, DBG, false>(P, A, L.grid, L.lds_bytes, st);
-    if (L.global_vec) return launch_w<1, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
-    return launch_w<1, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
-  }
-  if (L.G == 64) {
-    if (L.global_vec) return launch_w<64, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
-    return launch_w<64, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
-  }
-  if (L.global_vec) return launch_w<256, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
-  return launch_w<256, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
 }
 
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool debug,
@@ -2117,8 +39,8 @@ hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape&
       hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, rows[i], n);
     }
   }
-  if (fp64) return debug ? launch_g<double, true>(P, A, L, st) : launch_g<double, false>(P, A, L, st);
-  return debug ? launch_g<float, true>(P, A, L, st) : launch_g<float, false>(P, A, L, st);
+  if (fp64) return debug ? launch_trace_f64(P, A, L, st) : launch_sample_f64(P, A, L, st);
+  return debug ? launch_trace_f32(P, A, L, st) : launch_sample_f32(P, A, L, st);
 }
 
 size_t lds_bytes_for(const DevProgram& P, int G, bool global_vec, bool fp64) {
