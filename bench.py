@@ -1,15 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the sample-many path on one MI355X.
 
-A step is one clifft_sample call over the whole workload (every shot of the
-batch through the compiled stream: frames, noise, active vector, records),
-with the program resident on the device and the outputs preallocated,
-replayed from a captured HIP graph (--no-graph: launched eagerly).
-Prints one JSON line (driver contract).
+Default workload (the headline): 64 seeded heterogeneous near-Clifford
+circuits (20-100 qubits, peak active dimension 4-16, 1e5 shots each).  A
+step samples every shot of every circuit with the FP32 batched launch
+(amplitudes FP32, reductions and renormalisation FP64); the plain form, one
+FP64 clifft_sample call per circuit, is timed the same way beside it, and
+both are checked against the FP64 oracle rate by rate (matched accuracy).
+Programs are resident and outputs preallocated; steps replay a captured HIP
+graph (--no-graph: launched eagerly).  Prints one JSON line.
 
-Default workload: rotated surface-code memory d = 3, 3 rounds,
-circuit-level depolarizing p = 1e-3, 1e7 shots (the Pauli-frame
-configuration of the benchmark table).  Other workloads: --workload.
+Single-program workloads (--workload): one clifft_sample call over the
+workload's shots per step, reported under their own metric name.
 """
 import argparse
 import json
@@ -21,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "shots/sec at matched detector-rate accuracy, FP32-batched vs FP64-plain"
+# single-program workloads are reported under their own name
+METRIC_SINGLE = "shots/sec, one program per call (%s, %s)"
 # 32-bit VALU lane-ops/s at the rate the published FP32 vector figure implies
 # (157.3 TFLOP/s = 2 flops x 128 lanes x 256 CUs x 2.4 GHz).  The 16-lane SIMD
 # count (39.3 T) is not an upper bound here: the integer probe exceeds it.
@@ -116,9 +120,19 @@ def cpu_baseline(text, shots_hint, seed):
     t0 = time.perf_counter()
     meas, det, obs = prog.sample(target, seed=seed, threads=threads)
     dt = time.perf_counter() - t0
-    return dict(value=target / dt, unit="shots/s", cores=threads, kind="oracle",
+    return dict(value=target / dt, unit="shots/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
                 sample="first %d shots of the workload (seed %d), FP64 oracle, %d threads, %.1f s"
                        % (target, seed, threads, dt)), (target, meas, det, obs)
+
+
+def calibration_copy(nbytes, torch):
+    """One plain device copy of nbytes (the HBM counters' calibration)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def captured(fn, torch):
@@ -136,93 +150,254 @@ def captured(fn, torch):
     return g.replay, g
 
 
-def bench_batch(args, w, pk, torch):
-    """Batched workload: all circuits in one persistent FP32 launch, against
-    the plain FP64 form (one clifft_sample call per circuit) on the same GPU."""
-    import numpy as np
-    texts = w["texts"]
-    shots = [w["shots"]] * len(texts)
-    seeds = list(range(len(texts)))
-    progs = [pk.Program(t) for t in texts]
-    precision = args.precision or "f32"
-    if not args.no_autotune and not args.threads_per_shot:
-        for p in progs:
-            p.autotune(shots[0], precision)
-            p.autotune(shots[0], "f64")  # the plain FP64 form below uses its own tuned shapes
-    B = pk.Batch(progs, shots, seeds, precision=precision, threads_per_shot=args.threads_per_shot, grid=args.grid)
-    outs, ws = B.alloc()
-    stream = torch.cuda.current_stream()
-    step = lambda: B.sample(outs, ws)
-    if not args.no_graph:
-        step, graph = captured(step, torch)
-    for _ in range(args.warmup):
-        step()
+def time_steps(fn, steps, warmup, torch, graph=True):
+    """The driver's timing contract for one form: `warmup` untimed calls,
+    then exactly `steps` calls bracketed by device synchronisations, each also
+    bracketed by HIP events on the launch stream.  Returns (wall seconds of
+    the timed calls, per-step event times in ms, graph handle)."""
+    g = None
+    if graph:
+        fn, g = captured(fn, torch)
+    for _ in range(warmup):
+        fn()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for a, b in evs:
         a.record(stream)
-        step()
+        fn()
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
+    return wall, [a.elapsed_time(b) for a, b in evs], g
+
+
+def progress(msg):
+    """One progress line on stderr (the JSON result alone goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def median(xs):
+    s = sorted(xs)
+    n = len(s)
+    return s[n // 2] if n % 2 else 0.5 * (s[n // 2 - 1] + s[n // 2])
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def row_counts(words, shots):
+    """Set bits per row of a record-major bit-packed array (first `shots` shots)."""
+    import numpy as np
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size == 0:
+        return np.zeros(w.shape[0], np.int64)
+    nw = (shots + 63) // 64
+    w = w[:, :nw].copy()
+    rem = shots % 64
+    if rem:
+        w[:, -1] &= np.uint64((1 << rem) - 1)
+    return np.unpackbits(w.view(np.uint8), axis=1).sum(axis=1).astype(np.int64)
+
+
+def two_sample_5sigma(k1, n1, k2, n2, nsig=5.0):
+    """Two-sample binomial test with pooled variance: per-row booleans."""
+    import numpy as np
+    k1, k2 = np.asarray(k1, float), np.asarray(k2, float)
+    p = (k1 + k2) / (n1 + n2)
+    sd = np.sqrt(np.maximum(p * (1 - p), 1e-300) * (1.0 / n1 + 1.0 / n2))
+    return np.abs(k1 / n1 - k2 / n2) <= nsig * sd + 1.0 / min(n1, n2)
+
+
+def differing_shots(a, b, shots):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    if a.size == 0:
+        return 0
+    nw = (shots + 63) // 64
+    d = np.bitwise_or.reduce(a[:, :nw] ^ b[:, :nw], axis=0)
+    rem = shots % 64
+    if rem:
+        d[-1] &= np.uint64((1 << rem) - 1)
+    return int(np.unpackbits(d.view(np.uint8)).sum())
+
+
+def bench_batch(args, w, pk, torch):
+    """The headline comparison: every circuit of the set sampled by the
+    batched launch in FP32 (amplitudes FP32; branch sums, renormalisation
+    factors and rotation constants FP64) against the plain form, one FP64
+    clifft_sample call per circuit, on the same GPU.  Both forms are timed
+    the same way (captured graph, warm-up, `steps` timed replays).  Matched
+    accuracy: every measurement, detector and observable rate of both forms
+    passes a two-sample 5-sigma binomial test against the oracle on a prefix
+    of each circuit's shots, and against each other at full size."""
+    import numpy as np
+    texts = w["texts"]
+    n = len(texts)
+    shots = [w["shots"]] * n
+    seeds = list(range(n))
+    progs = [pk.Program(t) for t in texts]
     total = sum(shots)
-    value = total * args.steps / wall
-    # plain FP64 form: one call per circuit, sequential, same shots and seeds
+    if args.calibrate_copy:
+        calibration_copy(args.calibrate_copy, torch)
+    tuned = False
+    t_tune = time.perf_counter()
+    if not args.no_autotune and not args.threads_per_shot:
+        for i, (p, s) in enumerate(zip(progs, shots)):
+            p.autotune(s, "f32")
+            p.autotune(s, "f64")  # the plain FP64 form uses its own tuned shapes
+            if i % 16 == 15:
+                progress("autotuned %d of %d circuits (%.0f s)" % (i + 1, n, time.perf_counter() - t_tune))
+        tuned = True
+    tune_s = time.perf_counter() - t_tune
+    graph = not args.no_graph
+
+    # FP32, all circuits in one batched launch
+    B = pk.Batch(progs, shots, seeds, precision="f32", threads_per_shot=args.threads_per_shot, grid=args.grid)
+    outs, ws = B.alloc()
+    wall32, ev32, g32 = time_steps(lambda: B.sample(outs, ws), args.steps, args.warmup, torch, graph)
+    med32 = median(ev32)
+    value = total * args.steps / wall32
+    progress("FP32 batched: %.1f ms per step (median)" % med32)
+
+    # FP64 plain: one call per circuit, in order, sharing one workspace
     L64 = pk.make_launch("f64")
-    plain = [(p, p.alloc_outputs(n), p.alloc_workspace(L64)) for p, n in zip(progs, shots)]
-    for p, o, wsp in plain:
-        p.sample(shots[0], seed=0, launch=L64, outputs=o, workspace=wsp)
+    plain_outs = [p.alloc_outputs(s) for p, s in zip(progs, shots)]
+    ws64_bytes = max(p.workspace_size(L64) for p in progs)
+    ws64 = torch.empty(max(ws64_bytes, 1), dtype=torch.uint8, device="cuda") if ws64_bytes else None
+
+    def plain_step():
+        for i, p in enumerate(progs):
+            p.sample(shots[i], seed=seeds[i], launch=L64, outputs=plain_outs[i], workspace=ws64)
+
+    wall64, ev64, g64 = time_steps(plain_step, args.steps, args.warmup, torch, graph)
+    med64 = median(ev64)
+    value64 = total * args.steps / wall64
+    progress("FP64 plain: %.1f ms per step (median)" % med64)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i, (p, o, wsp) in enumerate(plain):
-        p.sample(shots[i], seed=seeds[i], launch=L64, outputs=o, workspace=wsp)
-    torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t0
-    # matched accuracy: the FP32 batched records agree with the FP64 plain ones
-    differing = 0
-    for i, (p, o, _) in enumerate(plain):
-        bm = [x.cpu().numpy().view(np.uint64) for x in B.records(outs, i)]
-        pm = [x.cpu().numpy().view(np.uint64) for x in o]
-        diff = np.zeros(bm[0].shape[1], np.uint64)
-        for x, y in zip(bm, pm):
-            if x.size:
-                diff |= np.bitwise_or.reduce(x ^ y, axis=0)
-        differing += int(sum(bin(int(v)).count("1") for v in diff))
-    cost = [p.cost_model(precision) for p in progs]
-    # every batched vector is in HBM; each program's bytes for the tier it runs on
+
+    rec32 = [[x.cpu().numpy().view(np.uint64) for x in B.records(outs, i)] for i in range(n)]
+    rec64 = [[x.cpu().numpy().view(np.uint64) for x in o] for o in plain_outs]
+
+    cost = [p.cost_model("f32") for p in progs]
     tiers = B.threads_per_shot
-    vec_bytes = sum(c["vector_bytes_fused" if g == 1 else "vector_bytes_fused_group"] * n
-                    for c, n, g in zip(cost, shots, tiers))
-    table_bytes = sum(c["vector_bytes"] * n for c, n in zip(cost, shots))
-    achieved = vec_bytes / (kernel_ms * 1e-3)
+    vec_bytes = sum(c["vector_bytes_fused" if g == 1 else "vector_bytes_fused_group"] * s
+                    for c, s, g in zip(cost, shots, tiers))
+    rec_bytes = sum(c["record_bytes"] * s for c, s in zip(cost, shots))
+    table_bytes = sum(c["vector_bytes"] * s for c, s in zip(cost, shots))
+    achieved = vec_bytes / (med32 * 1e-3)
+    roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM, "kernel": "k_batch (the batched step: its queue kernels in order)",
+            "work_model": "fused passes", "bytes_per_step": vec_bytes,
+            "unfused_table": {"bytes_per_step": table_bytes, "achieved": table_bytes / (med32 * 1e-3) / 1e9,
+                              "frac": table_bytes / (med32 * 1e-3) / PEAK_HBM},
+            "kernel_ms": med32}
+    traffic = load_traffic(args.workload, "f32", "k_batch")
+    roof["traffic"] = traffic
+    if traffic:
+        roof["traffic_over_algorithmic"] = traffic / max(1.0, vec_bytes + rec_bytes)
+    add_measured_peak(roof, pk, torch)
+
     line = {
         "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": precision, "data": "synthetic",
-        "config": {"workload": args.workload, "circuits": len(texts), "shots_per_circuit": shots[0],
-                   "k_max": [p.k_max for p in progs], "threads_per_shot": B.threads_per_shot,
-                   "graph": not args.no_graph, "parallelism": "all circuits in one persistent launch"},
-        "fp64_plain": {"value": total / plain_s, "unit": "shots/s", "ms": plain_s * 1e3,
-                       "speedup_of_fp32_batched": value / (total / plain_s),
-                       "records_differing_shots": differing, "records_total_shots": total},
-        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM, "work_model": "fused passes",
-                     "unfused_table": {"achieved": table_bytes / (kernel_ms * 1e-3) / 1e9,
-                                       "frac": table_bytes / (kernel_ms * 1e-3) / PEAK_HBM},
-                     "traffic": None, "kernel_ms": kernel_ms},
+        "warmup": args.warmup, "ms_per_step": wall32 * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "circuits": n, "shots_per_circuit": shots[0],
+                   "qubits": [p.num_qubits for p in progs], "k_max": [p.k_max for p in progs],
+                   "threads_per_shot": tiers, "graph": graph, "autotuned": tuned,
+                   "autotune_s": round(tune_s, 2),
+                   "parallelism": "all circuits in one batched launch (shot-parallel on one GPU)"},
+        "ms_median": med32,
+        "fp64_plain": {"value": value64, "unit": "shots/s", "ms_per_step": wall64 * 1e3 / args.steps,
+                       "ms_median": med64, "timing": "same as the FP32 form (graph replay, warm-up, steps)",
+                       "speedup_of_fp32_batched": value / value64},
+        "roofline": roof,
     }
-    add_measured_peak(line["roofline"], pk, torch)
+    # agreement of the two GPU forms at full size
+    rows_3264 = fails_3264 = diff_3264 = 0
+    for i in range(n):
+        for a, b in zip(rec32[i], rec64[i]):
+            if a.size == 0:
+                continue
+            ok = two_sample_5sigma(row_counts(a, shots[i]), shots[i], row_counts(b, shots[i]), shots[i])
+            rows_3264 += len(ok)
+            fails_3264 += int((~ok).sum())
+        diff_3264 += differing_shots(np.vstack([x for x in rec32[i] if x.size]),
+                                     np.vstack([x for x in rec64[i] if x.size]), shots[i])
+    line["fp64_plain"]["rates_5sigma_vs_fp32"] = {"rows": rows_3264, "failing": fails_3264}
+    line["fp64_plain"]["records_differing_shots"] = diff_3264
+    line["fp64_plain"]["records_total_shots"] = total
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline_batch(texts, shots, seeds, rec32, rec64)
+        line["cpu_baseline"] = cb
+        line["matched_accuracy"] = (cb["rates_5sigma"]["fp32_batched"]["failing"] == 0
+                                    and cb["rates_5sigma"]["fp64_plain"]["failing"] == 0 and fails_3264 == 0)
     print(json.dumps(line))
+
+
+def cpu_baseline_batch(texts, shots, seeds, rec32, rec64, budget_s=15.0):
+    """The FP64 oracle on the host cores, on the same prefix of every
+    circuit's shots (sized from a short calibration run to about `budget_s`
+    seconds); its rates test both GPU forms (two-sample 5 sigma per row), and
+    its records equal the FP64 plain form's on the prefix."""
+    import numpy as np
+    import oracle
+    threads = host_threads()
+    oprogs = [oracle.Program(t) for t in texts]
+    t0 = time.perf_counter()
+    for p, sd in zip(oprogs, seeds):
+        p.sample(64, seed=sd, threads=threads)
+    cal = time.perf_counter() - t0  # one 64-shot range per circuit, one thread each
+    per = int(64 * budget_s * threads / max(cal, 1e-6))
+    per = max(64, min(min(shots), per // 64 * 64))
+    progress("oracle prefix: %d shots per circuit" % per)
+    t0 = time.perf_counter()
+    orec = []
+    for p, sd in zip(oprogs, seeds):
+        orec.append(p.sample(per, seed=sd, threads=threads))
+    dt = time.perf_counter() - t0
+    res = {}
+    for name, recs in (("fp32_batched", rec32), ("fp64_plain", rec64)):
+        rows = fails = 0
+        for i, (o, g) in enumerate(zip(orec, recs)):
+            for a, b in zip(o, g):
+                if a.size == 0:
+                    continue
+                ok = two_sample_5sigma(row_counts(b, shots[i]), shots[i], row_counts(a, per), per)
+                rows += len(ok)
+                fails += int((~ok).sum())
+        res[name] = {"rows": rows, "failing": fails}
+    diff64 = sum(differing_shots(np.vstack([x for x in o if x.size]), np.vstack([x for x in g if x.size]), per)
+                 for o, g in zip(orec, rec64))
+    diff32 = sum(differing_shots(np.vstack([x for x in o if x.size]), np.vstack([x for x in g if x.size]), per)
+                 for o, g in zip(orec, rec32))
+    return dict(value=per * len(texts) / dt, unit="shots/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
+                sample="first %d shots of each of the %d circuits (seed = circuit index), FP64 oracle, %d threads, "
+                       "%.1f s" % (per, len(texts), threads, dt),
+                rates_5sigma=res, prefix_shots_per_circuit=per,
+                records_differing_on_prefix={"fp64_plain": diff64, "fp32_batched": diff32})
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="surface_d3_r3")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batched64")
     ap.add_argument("--precision", default=None, help="f32 or f64 (default: the workload's)")
     ap.add_argument("--threads-per-shot", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
@@ -270,12 +445,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     if args.calibrate_copy:
-        src = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(args.calibrate_copy, torch)
     step = lambda: prog.sample(shots, seed=seed, launch=launch, outputs=outs, workspace=ws)
     if not args.no_graph:
         step, graph = captured(step, torch)
@@ -339,7 +509,8 @@ def main():
     add_measured_peak(roof, pk, torch)
 
     line = {
-        "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC_SINGLE % (args.workload, "u64 frames" if k == 0 else precision), "value": value,
+        "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64" if k == 0 else precision, "data": "synthetic",
         "config": {"workload": args.workload, "shots": shots, "qubits": prog.num_qubits, "k_max": k,

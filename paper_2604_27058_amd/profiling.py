@@ -30,8 +30,8 @@ def code_tokens(text):
 # Sources that decide what a kernel family executes: the device code and the
 # host compiler that produces the instruction stream it runs.
 FAMILY_SOURCES = {
-    "interpreter": ("shot.h", "kernels.hip", "frames.hip", "batch.hip", "kernels.h", "program.h", "philox.h",
-                    "compiler.cpp", "compiler.h"),
+    "interpreter": ("shot.h", "kernels.hip", "frames.hip", "batch.hip", "sample_f32.hip", "sample_f64.hip",
+                    "kernels.h", "program.h", "philox.h", "compiler.cpp", "compiler.h"),
     "specialized": ("specialize.cpp", "spec_prelude.h", "spec_args.h", "program.h", "philox.h", "compiler.cpp",
                     "compiler.h"),
 }
@@ -79,6 +79,7 @@ def _pmc(d, counter):
 
 
 def traffic(fetch_dir, write_dir, copy_bytes, workload, prec):
+    batched = workload == "batched64"
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = _pmc(d, counter)
@@ -86,13 +87,22 @@ def traffic(fetch_dir, write_dir, copy_bytes, workload, prec):
         copy = [v for (k, _), v in per.items()
                 if ("copy" in k.lower() or "elementwise" in k.lower()) and "probe" not in k.lower()]
         # the timed launch is the last sampling dispatch (earlier ones are the
-        # launch-shape trials of the autotuner, if it ran)
+        # launch-shape trials of the autotuner, if it ran); a batched step is
+        # the last dispatch of each of its queue kernels
         samp = sorted(((int(d), k, v) for (k, d), v in per.items() if any(n in k for n in SAMPLING_KERNELS)))
+        if batched:
+            samp = [x for x in samp if "k_batch" in x[1]]
         if not copy or not samp:
             raise RuntimeError("missing copy or sampling dispatches for " + counter)
         kib_copy = max(copy)
         factor = kib_copy * 1024.0 / copy_bytes
-        _, name, kib = samp[-1]
+        if batched:
+            last = {}
+            for _, k, v in samp:
+                last[k] = v
+            name, kib = " + ".join(sorted(last)), sum(last.values())
+        else:
+            _, name, kib = samp[-1]
         res[counter] = dict(kernel=name, kib_per_dispatch=kib, copy_kib=kib_copy, factor=factor,
                             bytes_per_launch=kib * 1024.0 / factor)
     family = kernel_family(res["FETCH_SIZE"]["kernel"])

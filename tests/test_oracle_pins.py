@@ -273,6 +273,41 @@ def test_oracle_matches_dense_structured(name):
         _compare_shot(text, seed=1, shot=shot, check_state=(shot == 0))
 
 
+@pytest.mark.parametrize("name", ["surface_d2_t1", "register_n10_k4", "register_n9_k6"])
+def test_oracle_matches_dense_workload_recipes(name):
+    """Small-N versions of the benchmark recipes through the dense brute
+    force: the surface code with a T layer between rounds (the d = 5 + 10 T
+    recipe at d = 2) and the magic-register recipe of the batched and
+    large-k workloads (register expanded by H + T / R_Z, Clifford layers,
+    mid-circuit MR of register qubits and re-expansion, final measurement),
+    at noise high enough that most shots carry faults."""
+    if name == "surface_d2_t1":
+        text = circuits.surface_code_memory(d=2, rounds=3, p=0.02, t_rotations=1, t_after_round=1)
+        kmax = 1
+    elif name == "register_n10_k4":
+        text = circuits.register_circuit(10, 12, 4, 6, 0.02, seed=7, mid_measure_every=8, mid_measure_count=2)
+        kmax = 4
+    else:
+        text = circuits.register_circuit(9, 10, 6, 9, 0.03, seed=8, mid_measure_every=4, mid_measure_count=3)
+        kmax = 6
+    assert oracle.Program(text).kmax == kmax
+    for shot in range(6):
+        _compare_shot(text, seed=2, shot=shot, check_state=(shot == 0))
+
+
+@pytest.mark.parametrize("name", ["register_n9_k6", "surface_d2_t1"])
+def test_oracle_matches_dense_workload_recipes_forced(name):
+    """The same recipes on forced faults and outcomes (every branch
+    probability and the final state along the forced trajectory)."""
+    if name == "surface_d2_t1":
+        text = circuits.surface_code_memory(d=2, rounds=3, p=0.02, t_rotations=1, t_after_round=1)
+    else:
+        text = circuits.register_circuit(9, 10, 6, 9, 0.03, seed=8, mid_measure_every=4, mid_measure_count=3)
+    rng = np.random.default_rng(31)
+    for shot in range(3):
+        _compare_shot(text, seed=4, shot=shot, forced=True, rng=rng, check_state=(shot == 0))
+
+
 def test_impossible_forced_outcome_flagged():
     p = oracle.Program("H 0\nT 0\nH 0\nT 0\nM 0\nM 0\n")
     t = p.trace(0, 0, forced_m=np.array([1, 0], np.uint8))
