@@ -202,13 +202,14 @@ class Program:
                                    ptr(det), ptr(obs), s.cuda_stream))
         return meas, det, obs
 
-    def sample_trace(self, shots, seed=0, offset=0, launch=None, forced_m=None, forced_faults=None):
+    def sample_trace(self, shots, seed=0, offset=0, launch=None, forced_m=None, forced_faults=None, want_phi=True):
         """Trace mode (testing).  Returns dict of device tensors: meas, det,
-        obs, probs [shots, events], phi [shots, 2^k_max] complex128."""
+        obs, probs [shots, events], phi [shots, 2^k_max] complex128 (None
+        when want_phi is false)."""
         import torch
         meas, det, obs = self.alloc_outputs(shots)
         probs = torch.zeros((shots, max(self.num_events, 1)), dtype=torch.float64, device="cuda")
-        phi = torch.zeros((shots, 1 << self.k_max, 2), dtype=torch.float64, device="cuda")
+        phi = torch.zeros((shots, 1 << self.k_max, 2), dtype=torch.float64, device="cuda") if want_phi else None
         ws = self.alloc_workspace(launch)
         fm = None if forced_m is None else forced_m.to(device="cuda", dtype=torch.int32).contiguous()
         ff = None if forced_faults is None else forced_faults.to(device="cuda", dtype=torch.int32).contiguous()
@@ -219,7 +220,7 @@ class Program:
                                          ptr(probs), ptr(phi), ptr(ws), 0 if ws is None else ws.numel(),
                                          ptr(meas), ptr(det), ptr(obs), s.cuda_stream))
         return dict(meas=meas, det=det, obs=obs, probs=probs[:, : self.num_events],
-                    phi=torch.view_as_complex(phi))
+                    phi=None if phi is None else torch.view_as_complex(phi))
 
 
 class Batch:

@@ -54,6 +54,38 @@ def mismatched_shots(a, b, shots):
     return int(sum(bin(int(w)).count("1") for w in diff))
 
 
+def fp32_mismatch_bound(text, shots, seed=0, sample_shots=64, tail=1e-6, safety=4.0, forms=1):
+    """Upper bound on the number of shots, out of `shots`, whose FP32
+    records may differ from the FP64 (oracle) ones.  A record differs only
+    when a measurement's uniform falls between its FP32 and FP64
+    probabilities, so the expected count is the sum over shots and events of
+    |P32 - P64| along a common trajectory.  That gap is measured on oracle
+    trajectories forced onto the FP32 path (`sample_shots` of them), scaled
+    to `shots` with a safety factor (and by `forms` when two FP32 forms are
+    compared with each other), and the bound is the Poisson quantile of that
+    mean at tail probability `tail`."""
+    from scipy.stats import poisson
+    op = oracle.Program(text)
+    if op.nevents == 0:
+        return 0
+    gp = pk.Program(text)
+    fm = np.zeros((sample_shots, op.nevents), np.uint32)
+    ff = np.full((sample_shots, max(op.nsites, 1)), -1, np.int32)
+    po = np.zeros((sample_shots, op.nevents))
+    for s in range(sample_shots):
+        faults = op.faults(seed, s)
+        t = op.trace(seed, s, forced_faults=faults)
+        fm[s] = t["m"]
+        ff[s, : op.nsites] = faults
+        po[s] = t["probs"]
+    res = gp.sample_trace(sample_shots, seed=seed, launch=pk.make_launch("f32"), forced_m=torch.from_numpy(fm),
+                          forced_faults=torch.from_numpy(ff[:, : op.nsites]), want_phi=False)
+    torch.cuda.synchronize()
+    gap = float(np.abs(res["probs"].cpu().numpy() - po).sum(axis=1).mean())
+    mu = safety * forms * shots * gap
+    return int(poisson.isf(tail, mu)) + 1 if mu > 0 else 0
+
+
 def test_in_tree_library_is_the_one_loaded():
     gpu_sample(circuits.surface_code_memory(3, 1, 1e-3), 64)
     maps = open("/proc/self/maps").read()
@@ -136,20 +168,19 @@ def test_random_circuits_records(case, precision):
     if precision == "f64":
         assert bad == 0
     else:
-        assert bad <= 2
+        assert bad <= fp32_mismatch_bound(text, shots, seed=case)
 
 
 def _phi_in_oracle_order(phi_g, gslots, oslots):
     """Permute a GPU active vector (slot s holds virtual qubit gslots[s]) to
     the oracle's slot order."""
     pos = {q: t for t, q in enumerate(oslots)}
+    i = np.arange(len(phi_g), dtype=np.int64)
+    j = np.zeros_like(i)
+    for s, q in enumerate(gslots):
+        j |= ((i >> s) & 1) << pos[q]
     out = np.zeros_like(phi_g)
-    for i in range(len(phi_g)):
-        j = 0
-        for s, q in enumerate(gslots):
-            if (i >> s) & 1:
-                j |= 1 << pos[q]
-        out[j] = phi_g[i]
+    out[j] = phi_g
     return out
 
 
@@ -292,7 +323,9 @@ def test_surface_d5_t10_records(precision, G):
     if precision == "f64":
         assert bad == 0
     else:
-        assert bad <= 3
+        bound = fp32_mismatch_bound(text, shots, seed=3)
+        print("FP32 shots differing: %d (bound %d)" % (bad, bound))
+        assert bad <= bound
 
 
 def test_large_active_k20_sampled_shots():
@@ -321,11 +354,14 @@ def test_batched_launch_matches_single_program_and_oracle(precision):
         bm = [u64(x) for x in B.records(outs, i)]
         sm = gpu_sample(p, shots[i], seed=seeds[i], precision=precision)
         bad = mismatched_shots(np.vstack([x for x in bm if x.size]), np.vstack([x for x in sm if x.size]), shots[i])
-        assert bad == 0 if precision == "f64" else bad <= 2, (i, bad)
+        # two FP32 forms may each differ from FP64 near a threshold
+        bound = 0 if precision == "f64" else fp32_mismatch_bound(c["text"], shots[i], seed=seeds[i], forms=2)
+        assert bad <= bound, (i, bad, bound)
         n = 64 if p.k_max <= 12 else 16
         om, _, _ = oracle.Program(c["text"]).sample(n, seed=seeds[i], threads=8)
         bad = mismatched_shots(om[:, :1], bm[0][:, :1] & np.uint64((1 << n) - 1 if n < 64 else ~np.uint64(0)), n)
-        assert bad == 0 if precision == "f64" else bad <= 1, (i, bad)
+        bound = 0 if precision == "f64" else fp32_mismatch_bound(c["text"], n, seed=seeds[i])
+        assert bad <= bound, (i, bad, bound)
 
 
 @pytest.mark.parametrize("cap", ["0", "1", "3"])
