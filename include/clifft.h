@@ -179,6 +179,28 @@ clifft_status clifft_sample(const clifft_program* p, uint64_t shots, uint64_t se
                             const clifft_launch* cfg, void* workspace, size_t workspace_bytes, uint64_t* meas,
                             uint64_t* det, uint64_t* obs, void* stream);
 
+/* Allocation-free sampling, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, records and launch choices as clifft_sample,
+ * without the workspace: the active-vector workspace of the HBM tiers is a
+ * fixed device array of 64 MiB inside the library (each device that loads
+ * the library holds one until the process ends).  When the chosen launch
+ * needs more than that, the call uses fewer persistent workgroups (records
+ * do not depend on the grid); it returns E_CAPACITY when one workgroup's
+ * vectors alone exceed 64 MiB or when cfg fixes a grid whose workspace does
+ * not fit.  The call allocates nothing: the program must already be
+ * resident on the current device (E_INVALID_ARG otherwise; any clifft_sample
+ * call on the device uploads it), and a program-specialized kernel not yet
+ * loaded on the device is replaced by the bit-sliced interpreter, which
+ * writes the same records (E_INVALID_ARG if cfg demands it).  Nothing in
+ * the array needs to start at zero (every shot initializes its vectors).
+ * Calls that overlap in time on one device share the array and race: the
+ * caller orders them (one stream, or events).  Queues work on `stream` and
+ * returns. */
+clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                                    const clifft_launch* cfg, uint64_t* meas, uint64_t* det, uint64_t* obs,
+                                    void* stream);
+
 /* Trace mode (testing): like clifft_sample, and in addition
  *   forced_m       device [shots][num_events] uint32 outcomes to force, or NULL
  *   forced_faults  device [shots][num_noise_sites] int32 fault outcome index

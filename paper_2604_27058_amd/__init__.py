@@ -58,6 +58,7 @@ def lib():
         L.clifft_final_slots.argtypes = [vp, i32p, i32p]
         L.clifft_workspace_size.argtypes = [vp, ctypes.POINTER(clifft_launch), ctypes.POINTER(sz)]
         L.clifft_sample.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, sz, vp, vp, vp, vp]
+        L.clifft_sample_noalloc.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp]
         L.clifft_sample_trace.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp, vp, sz,
                                           vp, vp, vp, vp]
         L.clifft_cost_model.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(clifft_cost)]
@@ -76,7 +77,8 @@ def lib():
         L.clifft_probe.argtypes = [ctypes.c_int32, vp, vp, u64, ctypes.c_int32, vp]
         L.clifft_last_error.restype = ctypes.c_char_p
         for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
-                  "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_trace",
+                  "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_noalloc",
+                  "clifft_sample_trace",
                   "clifft_cost_model", "clifft_resolve_launch", "clifft_batch_create", "clifft_batch_sizes",
                   "clifft_batch_layout", "clifft_batch_sample", "clifft_autotune", "clifft_specialize",
                   "clifft_probe"):
@@ -200,6 +202,19 @@ class Program:
         _check(lib().clifft_sample(self._h, shots, seed, offset, None if launch is None else ctypes.byref(launch),
                                    ptr(workspace), 0 if workspace is None else workspace.numel(), ptr(meas),
                                    ptr(det), ptr(obs), s.cuda_stream))
+        return meas, det, obs
+
+    def sample_noalloc(self, shots, seed=0, offset=0, launch=None, outputs=None, stream=None):
+        """Queue clifft_sample_noalloc (no workspace argument; the library's
+        fixed device scratch serves the HBM tiers) into `outputs` on the
+        current stream; returns (meas, det, obs)."""
+        import torch
+        meas, det, obs = outputs if outputs is not None else self.alloc_outputs(shots)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        ptr = lambda t: t.data_ptr() if (t is not None and t.numel()) else None
+        _check(lib().clifft_sample_noalloc(self._h, shots, seed, offset,
+                                           None if launch is None else ctypes.byref(launch), ptr(meas), ptr(det),
+                                           ptr(obs), s.cuda_stream))
         return meas, det, obs
 
     def sample_trace(self, shots, seed=0, offset=0, launch=None, forced_m=None, forced_faults=None, want_phi=True):

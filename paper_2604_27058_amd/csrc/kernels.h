@@ -62,6 +62,11 @@ hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArg
                         const BatchArgs& lanes, int grid_lanes, size_t lds_bytes, bool fp64, hipStream_t stream);
 
 hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t stream);
+// The allocation-free entry point's fixed device workspace: kScratchBytes at
+// the address *ptr on the current device (looked up on the first call per
+// device).  Calls that overlap on one device share it.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+hipError_t scratch_region(void** ptr);
 // Bit-sliced Pauli-frame kernel (k_max = 0): 32 shots per lane, one 64-thread
 // workgroup per 2048-shot tile.
 hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStream_t stream);

@@ -6,10 +6,37 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.h"
 
 namespace clifft {
+
+// Fixed device scratch of the allocation-free sampling entry point: it holds
+// the active-vector workspace of the HBM tiers.  Each device that loads the
+// library keeps its own copy until the process ends.  In host code the
+// array's name is not a device address; scratch_region() returns the address
+// of the current device's copy (looked up once per device).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_region(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 // Zero-fill of record rows (a plain kernel rather than a memset node, so the
 // whole call can be captured in a graph).

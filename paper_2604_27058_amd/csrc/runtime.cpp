@@ -513,6 +513,77 @@ clifft_status clifft_sample(const clifft_program* p, uint64_t shots, uint64_t se
                    nullptr, nullptr, nullptr, false);
 }
 
+clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                                    const clifft_launch* cfg, uint64_t* meas, uint64_t* det, uint64_t* obs,
+                                    void* stream) {
+  if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
+  if (shots == 0) return CLIFFT_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(CLIFFT_E_DEVICE, "no HIP device");
+  const DevProgram* D = nullptr;
+  hipFunction_t spec_fn = nullptr;
+  {
+    // the program must already be resident: uploading it would allocate
+    clifft_program* mp = const_cast<clifft_program*>(p);
+    std::lock_guard<std::mutex> lock(mp->mu);
+    auto it = mp->dev.find(dev);
+    if (it == mp->dev.end())
+      return fail(CLIFFT_E_INVALID_ARG,
+                  "program is not resident on this device (a clifft_sample call on the device uploads it)");
+    D = &it->second.view;
+    spec_fn = it->second.spec_fn;
+  }
+  LaunchShape L{};
+  bool fp64 = false;
+  clifft_status st = choose_shape(p->host, D, cfg, shots, &L, &fp64, &p->tuned, false);
+  if (st != CLIFFT_OK) return st;
+  if (L.spec && !spec_fn) {
+    // loading the specialized code object would allocate: the bit-sliced
+    // interpreter writes the same records
+    if (cfg && cfg->specialize == 1)
+      return fail(CLIFFT_E_INVALID_ARG, "the specialized kernel is not loaded on this device yet");
+    clifft_launch c = cfg ? *cfg : clifft_launch{};
+    c.precision = fp64 ? CLIFFT_FP64 : CLIFFT_FP32;
+    c.threads_per_shot = kBitSliced;
+    c.grid = L.grid;
+    c.specialize = -1;
+    st = choose_shape(p->host, D, &c, shots, &L, &fp64, nullptr, false);
+    if (st != CLIFFT_OK) return st;
+  }
+  void* ws = nullptr;
+  size_t need = workspace_bytes(p->host, L, fp64);
+  if (need > 0) {
+    if (need > kScratchBytes) {
+      // keep the workspace inside the fixed scratch: fewer persistent
+      // workgroups (records do not depend on the grid)
+      const size_t per_block = need / (size_t)L.grid;
+      const size_t fit = kScratchBytes / per_block;
+      if ((cfg && cfg->grid > 0) || fit == 0) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "workspace of %zu bytes exceeds the %zu-byte scratch of the allocation-free call",
+                 cfg && cfg->grid > 0 ? need : per_block, kScratchBytes);
+        return fail(CLIFFT_E_CAPACITY, buf);
+      }
+      L.grid = (int)fit;
+    }
+    hipError_t e = scratch_region(&ws);
+    if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("scratch lookup failed: ") + hipGetErrorString(e));
+  }
+  KArgs A{};
+  A.shots = shots;
+  A.seed = seed;
+  A.offset = shot_offset;
+  A.meas = meas;
+  A.det = det;
+  A.obs = obs;
+  A.workspace = ws;
+  A.list_cap = 0xFFFFFFFFu;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = L.spec ? launch_spec(spec_fn, *D, A, L.grid, s) : launch_sample(*D, A, L, fp64, false, s);
+  if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return CLIFFT_OK;
+}
+
 clifft_status clifft_sample_trace(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
                                   const clifft_launch* cfg, const uint32_t* forced_m, const int32_t* forced_faults,
                                   double* probs, double* phi, void* workspace, size_t workspace_bytes,
