@@ -87,11 +87,33 @@ typedef struct clifft_launch {
                                the autotuner chose the specialized kernel) */
 } clifft_launch;
 
+/* Compile options; zero-initialize (or pass NULL) for the defaults. */
+typedef struct clifft_compile_opts {
+  int32_t hir_passes;  /* optimisation passes on the Heisenberg representation
+                          before localization (Section 3.1, middle end), a bit
+                          mask: 1 peephole (fuse adjacent rotations about one
+                          generator, cancel inverse pairs, absorb a resulting
+                          Clifford rotation into the frame), 2 commuting
+                          reorder (measurements earlier, non-Clifford
+                          rotations later, across operations they commute
+                          with).  0: none, so that k(t) is that of the
+                          operations as written */
+  int32_t k_limit;     /* E_CAPACITY if the peak active dimension exceeds this
+                          (0: the format limit, 30) */
+  int32_t drop_phases; /* 1: leave out the instructions whose only effect is a
+                          phase of the global scalar (rotations about dormant
+                          Z strings, Appendix B.1 case 1); the trace call's
+                          global scalar then misses those phases.  0: keep */
+} clifft_compile_opts;
+
 /* Compile circuit text (len bytes, need not be NUL-terminated) into a
- * program.  Host only; no device work.  *out receives a handle that the
- * caller releases with clifft_program_free.  Errors: E_PARSE,
- * E_UNSUPPORTED, E_CAPACITY, E_INVALID_ARG (null text or out). */
-clifft_status clifft_compile(const char* text, size_t len, clifft_program** out);
+ * program (Section 3.1: Heisenberg mapping of the physical operations into
+ * the virtual basis, Definition 1 / Eq. 1; Pauli localization, Lemma 1 and
+ * Appendix A; lowering to a flat instruction stream).  opts may be NULL.
+ * Host only; no device work.  *out receives a handle that the caller
+ * releases with clifft_program_free.  Errors: E_PARSE, E_UNSUPPORTED,
+ * E_CAPACITY, E_INVALID_ARG (null text or out, bad option). */
+clifft_status clifft_compile(const char* text, size_t len, const clifft_compile_opts* opts, clifft_program** out);
 
 /* Static properties of a compiled program (Theorem 1: fixed before sampling). */
 clifft_status clifft_program_info(const clifft_program* p, clifft_info* out);
@@ -108,7 +130,7 @@ clifft_status clifft_final_slots(const clifft_program* p, int32_t* slots, int32_
 
 /* Algorithmic work of one shot, summed over the compiled stream with the
  * active dimension in force at each instruction (the per-shot cost of
- * Section 2.5, Eq. for the per-shot cost, made concrete).  Integer work
+ * Section 2.6, asymptotic complexity, made concrete).  Integer work
  * counts 32-bit lane operations (a 64-bit word operation is two); noise work
  * uses the expected number of realized faults; vector traffic is the bytes
  * an unfused pass per instruction reads and writes at `precision`. */
@@ -168,7 +190,11 @@ clifft_status clifft_specialize(clifft_program* p, char* log, size_t cap);
 clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes);
 
 /* Sample `shots` shots with global indices shot_offset .. shot_offset+shots-1
- * and Philox seed `seed`.  meas / det / obs are device buffers of
+ * and Philox seed `seed` (Section 3.2: every shot resets the frames and the
+ * active vector, runs the compiled stream -- Pauli-frame updates, sparse
+ * noise sampling by jumping to the next realized fault, expansion, rotation
+ * and measurement of the active vector, Appendix B -- and writes its
+ * measurement, detector and observable records).  meas / det / obs are device buffers of
  * num_measurements / num_detectors / num_observables rows of
  * ceil(shots / 64) uint64 words (any may be NULL to skip it).  workspace is
  * a device buffer of at least clifft_workspace_size bytes (may be NULL when
@@ -201,21 +227,33 @@ clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uin
                                     const clifft_launch* cfg, uint64_t* meas, uint64_t* det, uint64_t* obs,
                                     void* stream);
 
-/* Trace mode (testing): like clifft_sample, and in addition
+/* Trace mode (testing; the forced-outcome call of the frame-factored state,
+ * Definition 2 / Eq. 2: psi = gamma U_C P~ (phi_A (x) |0>_D)): like
+ * clifft_sample, and in addition
  *   forced_m       device [shots][num_events] uint32 outcomes to force, or NULL
  *   forced_faults  device [shots][num_noise_sites] int32 fault outcome index
  *                  (-1 none) replacing the noise sampler, or NULL
  *   probs          device [shots][num_events] double, P(m = 1) of each event
- *   phi            device [shots][2^k_max][2] double, final active vector
- * Synchronizes `stream`; returns E_IMPOSSIBLE_OUTCOME if a forced outcome
- * had zero probability. */
+ *                  (Appendix B.2), or NULL
+ *   phi            device [shots][2^k_max][2] double, final active vector in
+ *                  the program's final slot order (clifft_final_slots), or NULL
+ *   gamma          device [shots][2] double, the final global scalar, or NULL:
+ *                  phases of frame conjugations and products (Appendix B.3),
+ *                  of rotations (Appendix B.1) and the normalisation of phi,
+ *                  so that gamma * phi is the physical amplitude vector
+ *                  relative to U_C P~ with no further phase or scale
+ * Not available on the bit-sliced tier.  Synchronizes `stream`; returns
+ * E_IMPOSSIBLE_OUTCOME if a forced outcome had zero probability. */
 clifft_status clifft_sample_trace(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
                                   const clifft_launch* cfg, const uint32_t* forced_m, const int32_t* forced_faults,
-                                  double* probs, double* phi, void* workspace, size_t workspace_bytes,
-                                  uint64_t* meas, uint64_t* det, uint64_t* obs, void* stream);
+                                  double* probs, double* phi, double* gamma, void* workspace,
+                                  size_t workspace_bytes, uint64_t* meas, uint64_t* det, uint64_t* obs,
+                                  void* stream);
 
-/* ---- Batched launch: many programs of different width and active
- * dimension sampled by one persistent launch per tier (work items: single
+/* ---- Batched launch (Section 3.2: shots, and here whole programs, are
+ * independent, so many compiled programs share one launch): many programs
+ * of different width and active dimension sampled by one persistent launch
+ * per tier (work items: single
  * shots of shot-per-workgroup programs, groups of four shots of
  * shot-per-wave programs and 64-shot tiles of shot-per-lane programs,
  * ordered longest first by the cost model, claimed dynamically). */

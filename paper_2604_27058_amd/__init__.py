@@ -35,6 +35,10 @@ class clifft_cost(ctypes.Structure):
         "int_ops_bitsliced", "vector_bytes_fused", "vector_bytes_fused_group")]
 
 
+class clifft_compile_opts(ctypes.Structure):
+    _fields_ = [("hir_passes", ctypes.c_int32), ("k_limit", ctypes.c_int32), ("drop_phases", ctypes.c_int32)]
+
+
 class clifft_launch(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("threads_per_shot", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("vector_in_hbm", ctypes.c_int32), ("specialize", ctypes.c_int32)]
@@ -51,7 +55,7 @@ def lib():
             raise ImportError("libclifft.so is not built (run paper_2604_27058_amd/build.py)")
         L = ctypes.CDLL(LIB_PATH)
         vp, u64, sz, i32p = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32)
-        L.clifft_compile.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(vp)]
+        L.clifft_compile.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(clifft_compile_opts), ctypes.POINTER(vp)]
         L.clifft_program_info.argtypes = [vp, ctypes.POINTER(clifft_info)]
         L.clifft_k_profile.argtypes = [vp, i32p, sz, ctypes.POINTER(sz)]
         L.clifft_event_classes.argtypes = [vp, i32p, sz, ctypes.POINTER(sz)]
@@ -59,8 +63,8 @@ def lib():
         L.clifft_workspace_size.argtypes = [vp, ctypes.POINTER(clifft_launch), ctypes.POINTER(sz)]
         L.clifft_sample.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, sz, vp, vp, vp, vp]
         L.clifft_sample_noalloc.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp]
-        L.clifft_sample_trace.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp, vp, sz,
-                                          vp, vp, vp, vp]
+        L.clifft_sample_trace.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp, vp, vp,
+                                          sz, vp, vp, vp, vp]
         L.clifft_cost_model.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(clifft_cost)]
         L.clifft_resolve_launch.argtypes = [vp, ctypes.POINTER(clifft_launch), u64, ctypes.POINTER(clifft_launch)]
         L.clifft_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(u64), ctypes.POINTER(u64),
@@ -106,12 +110,14 @@ def make_launch(precision="f32", threads_per_shot=0, grid=0, vector_in_hbm=0, sp
 
 
 class Program:
-    """A compiled circuit (clifft_compile)."""
+    """A compiled circuit (clifft_compile; keyword options as in
+    clifft_compile_opts)."""
 
-    def __init__(self, text):
+    def __init__(self, text, hir_passes=0, k_limit=0, drop_phases=0):
         h = ctypes.c_void_p()
         b = text.encode()
-        _check(lib().clifft_compile(b, len(b), ctypes.byref(h)))
+        opts = clifft_compile_opts(hir_passes, k_limit, drop_phases)
+        _check(lib().clifft_compile(b, len(b), ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
         inf = clifft_info()
         _check(lib().clifft_program_info(h, ctypes.byref(inf)))
@@ -220,11 +226,12 @@ class Program:
     def sample_trace(self, shots, seed=0, offset=0, launch=None, forced_m=None, forced_faults=None, want_phi=True):
         """Trace mode (testing).  Returns dict of device tensors: meas, det,
         obs, probs [shots, events], phi [shots, 2^k_max] complex128 (None
-        when want_phi is false)."""
+        when want_phi is false), gamma [shots] complex128."""
         import torch
         meas, det, obs = self.alloc_outputs(shots)
         probs = torch.zeros((shots, max(self.num_events, 1)), dtype=torch.float64, device="cuda")
         phi = torch.zeros((shots, 1 << self.k_max, 2), dtype=torch.float64, device="cuda") if want_phi else None
+        gamma = torch.zeros((shots, 2), dtype=torch.float64, device="cuda")
         ws = self.alloc_workspace(launch)
         fm = None if forced_m is None else forced_m.to(device="cuda", dtype=torch.int32).contiguous()
         ff = None if forced_faults is None else forced_faults.to(device="cuda", dtype=torch.int32).contiguous()
@@ -232,10 +239,10 @@ class Program:
         s = torch.cuda.current_stream()
         _check(lib().clifft_sample_trace(self._h, shots, seed, offset,
                                          None if launch is None else ctypes.byref(launch), ptr(fm), ptr(ff),
-                                         ptr(probs), ptr(phi), ptr(ws), 0 if ws is None else ws.numel(),
+                                         ptr(probs), ptr(phi), ptr(gamma), ptr(ws), 0 if ws is None else ws.numel(),
                                          ptr(meas), ptr(det), ptr(obs), s.cuda_stream))
         return dict(meas=meas, det=det, obs=obs, probs=probs[:, : self.num_events],
-                    phi=None if phi is None else torch.view_as_complex(phi))
+                    phi=None if phi is None else torch.view_as_complex(phi), gamma=torch.view_as_complex(gamma))
 
 
 class Batch:

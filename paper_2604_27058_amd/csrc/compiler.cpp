@@ -290,6 +290,7 @@ struct Compiler {
   std::vector<int> q_at;      // slot -> virtual qubit
   int k = 0;
   CompiledProgram* out;
+  bool drop_phases = false;
 
   Compiler(int n_, CompiledProgram* o) : n(n_), W((n_ + 63) / 64), out(o) {
     ix.assign(n, Pauli(W));
@@ -346,10 +347,15 @@ struct Compiler {
     push_mask(p.z);
     return off;
   }
+  // A rotation exp(-i theta Z) on an axis acts as diag(e^{-i theta},
+  // e^{i theta}); the kernels apply e^{2 i theta} to the upper half and put
+  // the common factor e^{-i theta} into the global scalar.
   uint32_t push_angle(double theta) {
-    uint32_t idx = (uint32_t)(out->consts.size() / 2);
+    uint32_t idx = (uint32_t)(out->consts.size() / 4);
     out->consts.push_back(cos(2 * theta));
     out->consts.push_back(sin(2 * theta));
+    out->consts.push_back(cos(theta));
+    out->consts.push_back(sin(theta));
     return idx;
   }
   void emit(uint8_t op, uint8_t flags, int v, int s, uint32_t a, uint32_t b, int u = 0) {
@@ -453,7 +459,8 @@ struct Compiler {
         localize_case2(g, vz);
         emit(OP_AROT, 0, vz, slot_of[vz], push_angle(g.r ? -theta : theta), 0);
       }
-      // otherwise: a scalar phase on gamma only (global phase, not tracked on the GPU)
+      else if (!drop_phases)  // a Z string on dormant qubits: a phase of the global scalar only
+        emit(OP_PHASE, 0, 0, 0, push_mask(g.z), push_angle(g.r ? -theta : theta));
     }
   }
 
@@ -508,7 +515,7 @@ struct Compiler {
 
   void reset_fix(int q, int j) {
     Pauli xq = image(q, 'X');
-    emit(OP_CPAULI, 0, 0, 0, push_pauli(xq), (uint32_t)j);
+    emit(OP_CPAULI, xq.r ? F_SIGN : 0, 0, 0, push_pauli(xq), (uint32_t)j);
   }
 
   void noise(const PhysOp& o) {
@@ -518,10 +525,13 @@ struct Compiler {
     out->site_img.push_back((uint32_t)out->masks.size());
     push_pauli(ix[o.a]);
     push_pauli(iz[o.a]);
+    uint8_t sg = (uint8_t)(ix[o.a].r | (iz[o.a].r << 1));
     if (o.ntype == S_DEP2) {
       push_pauli(ix[o.b]);
       push_pauli(iz[o.b]);
+      sg |= (uint8_t)((ix[o.b].r << 2) | (iz[o.b].r << 3));
     }
+    out->site_sign.push_back(sg);
     if (!out->code.empty() && out->code.back().op == OP_NOISE && out->code.back().b == site) {
       out->code.back().b = site + 1;  // extend the current block
     } else {
@@ -708,7 +718,7 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
   return c;
 }
 
-int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& err) {
+int compile_text(const char* text, size_t len, const CompileOptions& opts, CompiledProgram& P, std::string& err) {
   Lines L;
   {
     std::string all(text, len);
@@ -743,6 +753,8 @@ int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& 
   P.nq = n;
   P.W = (n + 63) / 64;
   Compiler C(n, &P);
+  C.drop_phases = opts.drop_phases;
+  const int k_limit = opts.k_limit > 0 && opts.k_limit < kMaxK ? opts.k_limit : kMaxK;
   int rec = 0;
   for (const PhysOp& o : ps.ops) {
     switch (o.kind) {
@@ -765,8 +777,8 @@ int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& 
         break;
       }
     }
-    if (P.kmax > kMaxK) {
-      err = "active dimension exceeds the format limit";
+    if (P.kmax > k_limit) {
+      err = k_limit == kMaxK ? "active dimension exceeds the format limit" : "active dimension exceeds k_limit";
       return 3;
     }
   }
@@ -884,10 +896,10 @@ int compile_text(const char* text, size_t len, CompiledProgram& P, std::string& 
   }
   survival_tables(P);
   if (P.masks.empty()) P.masks.push_back(0);
-  if (P.consts.empty()) { P.consts.push_back(1.0); P.consts.push_back(0.0); }
+  if (P.consts.empty()) P.consts = {1.0, 0.0, 1.0, 0.0};
   if (P.refs.empty()) P.refs.push_back(0);
   if (P.ev_rec.empty()) P.ev_rec.push_back(-1);
-  if (P.site_type.empty()) { P.site_type.push_back(0); P.site_img.push_back(0); }
+  if (P.site_type.empty()) { P.site_type.push_back(0); P.site_img.push_back(0); P.site_sign.push_back(0); }
   if (P.surv.empty()) P.surv.assign(kChunk + 1, 0.0);
   return 0;
 }

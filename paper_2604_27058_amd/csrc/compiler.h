@@ -15,13 +15,14 @@ struct CompiledProgram {
   std::vector<GInstr> code;
   std::vector<int> k_after;        // active dimension after each instruction
   std::vector<uint64_t> masks;     // W-word masks and 2W-word Pauli images
-  std::vector<double> consts;      // (cos 2theta, sin 2theta) pairs
+  std::vector<double> consts;      // (cos 2theta, sin 2theta, cos theta, sin theta) per angle
   std::vector<uint32_t> refs;      // detector / observable record references
   std::vector<int32_t> ev_rec;     // event -> record index or -1
   std::vector<int> ev_class;       // event -> 0 deterministic, 1 dormant random, 2 active
   std::vector<uint8_t> site_type;  // per noise site
   std::vector<double> site_p;      // per noise site probability
   std::vector<uint32_t> site_img;  // per site offset of its images in masks
+  std::vector<uint8_t> site_sign;  // per site sign bits of its images (bit 2i X, 2i+1 Z of qubit i)
   std::vector<double> surv;        // nchunks x (kChunk + 1) survival products
   std::vector<int> final_slots;    // virtual qubit held by each slot at the end
   std::vector<uint32_t> rec_tgt_off, rec_tgt;  // record -> detector/observable accumulator rows
@@ -45,7 +46,14 @@ struct CostModel {
 };
 CostModel cost_model(const CompiledProgram& P, bool fp64);
 
+// Compile options (see clifft_compile_opts in include/clifft.h).
+struct CompileOptions {
+  int hir_passes = 0;     // bit 1 peephole, bit 2 commuting reorder
+  int k_limit = 0;        // reject k_max above this (0: kMaxK)
+  bool drop_phases = false;  // omit OP_PHASE instructions
+};
+
 // Returns 0 on success, 1 parse error, 2 unsupported instruction, 3 capacity.
-int compile_text(const char* text, size_t len, CompiledProgram& out, std::string& err);
+int compile_text(const char* text, size_t len, const CompileOptions& opts, CompiledProgram& out, std::string& err);
 
 }  // namespace clifft

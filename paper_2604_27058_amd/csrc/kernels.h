@@ -18,6 +18,7 @@ struct KArgs {
   const int32_t* forced_faults;  // [shots][nsites] outcome or -1, or null
   double* probs;                 // [shots][nevents] P(m = 1) or null
   double* phi_out;               // [shots][2^kmax][2] or null
+  double* gamma_out;             // [shots][2] global scalar (re, im) or null
   int* error;                    // device flag word (trace mode)
   uint32_t list_cap = 0xFFFFFFFFu;  // bit-sliced fault-list capacity (tests may lower it)
 };

@@ -38,11 +38,13 @@ enum Op : uint8_t {
   OP_NOISE,    // noise sites [a, b)
   OP_DET,      // detector b = XOR of records refs[a .. a+u); s = its accumulator row
   OP_OBS,      // observable b ^= XOR of records refs[a .. a+u)
+  OP_PHASE,    // rotation whose generator is a Z string on dormant qubits   a=mask(z), b=const
+               //   (Appendix B.1 case 1): only the global scalar changes
   OP_COUNT
 };
 
 // flags
-constexpr uint8_t F_SIGN = 1;        // sign bit of the localized observable
+constexpr uint8_t F_SIGN = 1;        // sign bit of the localized observable (of the image, for OP_CPAULI)
 // Localization passes of an active measurement or H (Appendix A with an
 // active pivot): an OP_APERM, then an OP_ASIGN, then an OP_AS, each
 // optional, on the measured (or H) slot and directly before that
@@ -84,11 +86,12 @@ constexpr uint32_t kPurposeAmeas = 0x41000000u;
 struct DevProgram {
   const GInstr* code;
   const uint64_t* masks;     // W-word Pauli masks
-  const double* consts;      // (cos 2theta, sin 2theta) pairs
+  const double* consts;      // (cos 2theta, sin 2theta, cos theta, sin theta) per rotation angle
   const uint32_t* refs;      // record references of detectors / observables
   const int32_t* ev_rec;     // event -> record index or -1
   const uint8_t* site_type;  // per noise site
   const uint32_t* site_img;  // per site: offset of its images in masks (2 or 4 images x 2W words)
+  const uint8_t* site_sign;  // per site: sign bits of those images (bit 2i: X image of its qubit i, 2i+1: Z)
   const double* surv;        // per chunk: kChunk + 1 survival products
   const uint32_t* rec_tgt_off;  // per record: first entry in rec_tgt (nrec + 1 entries)
   const uint32_t* rec_tgt;      // accumulators (detector d, or ndet + observable o) a record feeds

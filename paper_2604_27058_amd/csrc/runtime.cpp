@@ -86,6 +86,7 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
   if (e == hipSuccess) e = upload_vec(H.ev_rec, &v.ev_rec, dc.allocs);
   if (e == hipSuccess) e = upload_vec(H.site_type, &v.site_type, dc.allocs);
   if (e == hipSuccess) e = upload_vec(H.site_img, &v.site_img, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.site_sign, &v.site_sign, dc.allocs);
   if (e == hipSuccess) e = upload_vec(H.surv, &v.surv, dc.allocs);
   if (e == hipSuccess) e = upload_vec(H.rec_tgt_off, &v.rec_tgt_off, dc.allocs);
   if (e == hipSuccess) e = upload_vec(H.rec_tgt, &v.rec_tgt, dc.allocs);
@@ -306,7 +307,7 @@ size_t workspace_bytes(const CompiledProgram& H, const LaunchShape& L, bool fp64
 clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t offset,
                         const clifft_launch* cfg, void* ws, size_t ws_bytes, uint64_t* meas, uint64_t* det,
                         uint64_t* obs, void* stream, const uint32_t* forced_m, const int32_t* forced_faults,
-                        double* probs, double* phi, bool trace) {
+                        double* probs, double* phi, double* gamma, bool trace) {
   if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
   if (shots == 0) return CLIFFT_OK;
   const DevProgram* D = nullptr;
@@ -339,6 +340,7 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
     A.forced_faults = forced_faults;
     A.probs = probs;
     A.phi_out = phi;
+    A.gamma_out = gamma;
     if (hipMalloc(&dflag, sizeof(int)) != hipSuccess) return fail(CLIFFT_E_DEVICE, "flag allocation failed");
     (void)hipMemsetAsync(dflag, 0, sizeof(int), s);
     A.error = dflag;
@@ -396,12 +398,21 @@ struct clifft_batch {
 
 extern "C" {
 
-clifft_status clifft_compile(const char* text, size_t len, clifft_program** out) {
+clifft_status clifft_compile(const char* text, size_t len, const clifft_compile_opts* opts, clifft_program** out) {
   if (!text || !out) return fail(CLIFFT_E_INVALID_ARG, "null argument");
   *out = nullptr;
+  CompileOptions co;
+  if (opts) {
+    if (opts->hir_passes & ~3) return fail(CLIFFT_E_INVALID_ARG, "hir_passes: unknown pass bits");
+    if (opts->k_limit < 0) return fail(CLIFFT_E_INVALID_ARG, "k_limit must be >= 0");
+    if (opts->drop_phases != 0 && opts->drop_phases != 1) return fail(CLIFFT_E_INVALID_ARG, "drop_phases must be 0 or 1");
+    co.hir_passes = opts->hir_passes;
+    co.k_limit = opts->k_limit;
+    co.drop_phases = opts->drop_phases == 1;
+  }
   clifft_program* p = new clifft_program();
   std::string err;
-  int rc = compile_text(text, len, p->host, err);
+  int rc = compile_text(text, len, co, p->host, err);
   if (rc != 0) {
     delete p;
     return fail(rc == 1 ? CLIFFT_E_PARSE : rc == 2 ? CLIFFT_E_UNSUPPORTED : CLIFFT_E_CAPACITY, err);
@@ -510,7 +521,7 @@ clifft_status clifft_sample(const clifft_program* p, uint64_t shots, uint64_t se
                             const clifft_launch* cfg, void* workspace, size_t workspace_bytes, uint64_t* meas,
                             uint64_t* det, uint64_t* obs, void* stream) {
   return do_sample(p, shots, seed, shot_offset, cfg, workspace, workspace_bytes, meas, det, obs, stream, nullptr,
-                   nullptr, nullptr, nullptr, false);
+                   nullptr, nullptr, nullptr, nullptr, false);
 }
 
 clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
@@ -586,10 +597,10 @@ clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uin
 
 clifft_status clifft_sample_trace(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
                                   const clifft_launch* cfg, const uint32_t* forced_m, const int32_t* forced_faults,
-                                  double* probs, double* phi, void* workspace, size_t workspace_bytes,
+                                  double* probs, double* phi, double* gamma, void* workspace, size_t workspace_bytes,
                                   uint64_t* meas, uint64_t* det, uint64_t* obs, void* stream) {
   return do_sample(p, shots, seed, shot_offset, cfg, workspace, workspace_bytes, meas, det, obs, stream, forced_m,
-                   forced_faults, probs, phi, true);
+                   forced_faults, probs, phi, gamma, true);
 }
 
 clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n, const uint64_t* shots,

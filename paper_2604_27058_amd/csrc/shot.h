@@ -392,6 +392,57 @@ DEV void apply_fault(const DevProgram& P, Frame<W>& T, Frame<W>& N, uint32_t sit
   frame_xor<W>(N, ex, ez);
 }
 
+// Power of i that a fired fault contributes to the global scalar (trace
+// mode; Appendix B.3): the fired Pauli is the product of its qubits'
+// letters' signed images (Y = i X Z), written E = i^e X^ex Z^ez, and
+// E X^x Z^z = i^(e + 2|ez & x|) X^(ex ^ x) Z^(ez ^ z) for the frame X^x Z^z.
+template <int W>
+DEV int fault_phase(const DevProgram& P, const Words<W>& fx, uint32_t site, uint32_t o) {
+  const uint32_t t = P.site_type[site];
+  const uint64_t* img = P.masks + P.site_img[site];
+  const uint32_t sg = P.site_sign[site];
+  uint32_t la, lb = 0;
+  if (t == S_DEP1) la = o + 1;
+  else if (t == S_DEP2) { la = (o + 1) >> 2; lb = (o + 1) & 3; }
+  else la = t - 1;
+  int e = 0;
+  uint64_t px[W], pz[W];
+#pragma unroll
+  for (int w = 0; w < W; w++) { px[w] = 0; pz[w] = 0; }
+  const uint32_t L[2] = {la, lb};
+  for (int qi = 0; qi < 2; qi++) {
+    if (qi == 1 && t != S_DEP2) break;
+    const uint32_t l = L[qi];
+    if (l == 0) continue;
+    const uint64_t* ax = img + (size_t)qi * 4 * W;  // X image: x words, z words
+    const uint64_t* bx = ax + 2 * W;                // Z image: x words, z words
+    const int rx = (sg >> (2 * qi)) & 1, rz = (sg >> (2 * qi + 1)) & 1;
+    uint64_t qx[W], qz[W];
+    int eq = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+      if (l == 1) { qx[w] = ax[w]; qz[w] = ax[W + w]; eq += __popcll(ax[w] & ax[W + w]); }
+      else if (l == 3) { qx[w] = bx[w]; qz[w] = bx[W + w]; eq += __popcll(bx[w] & bx[W + w]); }
+      else {
+        qx[w] = ax[w] ^ bx[w];
+        qz[w] = ax[W + w] ^ bx[W + w];
+        eq += __popcll(ax[w] & ax[W + w]) + __popcll(bx[w] & bx[W + w]) + 2 * __popcll(ax[W + w] & bx[w]);
+      }
+    }
+    eq += l == 1 ? 2 * rx : l == 3 ? 2 * rz : 1 + 2 * rx + 2 * rz;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+      eq += 2 * __popcll(pz[w] & qx[w]);
+      px[w] ^= qx[w];
+      pz[w] ^= qz[w];
+    }
+    e += eq;
+  }
+#pragma unroll
+  for (int w = 0; w < W; w++) e += 2 * __popcll(pz[w] & fx[w]);
+  return e & 3;
+}
+
 // ------------------------------------------------------------------ one shot
 // OOP: active vectors in HBM with a second buffer of the same size; active
 // measurements collapse out of place (alternating buffers) and read through
@@ -512,6 +563,25 @@ struct Shot {
         dfr = 0;
       }
     };
+    // Trace mode tracks the global scalar of the frame-factored state
+    // (Definition 2): an exact power of i from frame conjugations and
+    // products (Appendix B.3), rotation phases (the factor e^{-i theta} that
+    // the kernels leave out of the vector, and dormant-Z phases), and
+    // 2^{-1/2} per expansion since the last collapse (the vector is left
+    // unnormalised by expansions and renormalised by a collapse).
+    int g_ipow = 0, g_nexp = 0;
+    double g_re = 1.0, g_im = 0.0;
+    auto g_rot = [&](uint32_t ci, bool flip) {  // gamma *= e^{-i theta}, theta sign-flipped by the frame
+      if constexpr (DBG) {
+        const double c = P.consts[4 * ci + 2], sn = flip ? -P.consts[4 * ci + 3] : P.consts[4 * ci + 3];
+        const double re = g_re * c + g_im * sn;
+        g_im = g_im * c - g_re * sn;
+        g_re = re;
+      }
+    };
+    auto g_h = [&](int q) {  // frame conjugation by H_q: (-1)^(x_q z_q)
+      if constexpr (DBG) g_ipow += 2 * (int)(getbit<W>(T.x, q) & getbit<W>(T.z, q));
+    };
     Noise ns{0, 0, 0xFFFFFFFFu, 0};
     if (P.nsites > 0) {
       if (DBG && A.forced_faults) ns.nf = 0xFFFFFFFFu;
@@ -541,6 +611,7 @@ struct Shot {
           uint64_t m[W];
 #pragma unroll
           for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
+          if constexpr (DBG) g_ipow += 2 * (int)(getbit<W>(T.x, v) & parity_and<W>(T.x, m));
           fan_cz<W>(T, v, m);
           fan_cz<W>(N, v, m);
           break;
@@ -553,8 +624,25 @@ struct Shot {
           fan_2<W>(N, v, m);
           break;
         }
-        case OP_FS: frame_s<W>(T, v); frame_s<W>(N, v); break;
-        case OP_FH: frame_h<W>(T, v); frame_h<W>(N, v); break;
+        case OP_FS:
+          if constexpr (DBG) g_ipow += (int)getbit<W>(T.x, v);  // S X S^dag = Y = i X Z
+          frame_s<W>(T, v);
+          frame_s<W>(N, v);
+          break;
+        case OP_FH:
+          g_h(v);
+          frame_h<W>(T, v);
+          frame_h<W>(N, v);
+          break;
+        case OP_PHASE: {
+          if constexpr (DBG) {
+            uint64_t m[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) m[w] = masks[in.a + w];
+            g_rot(in.b, parity_and<W>(T.x, m) != 0);
+          }
+          break;
+        }
         case OP_APERM: {
           if constexpr (!VEC) break;
           else {
@@ -659,10 +747,11 @@ struct Shot {
             const bool rot = nx.op == OP_AROT && nx.s == s;
             R rr = (R)1, ri = (R)0;
             if (rot) {
-              double c2 = P.consts[2 * nx.a], s2 = P.consts[2 * nx.a + 1];
+              double c2 = P.consts[4 * nx.a], s2 = P.consts[4 * nx.a + 1];
               if (getbit<W>(T.x, nx.v)) s2 = -s2;
               rr = (R)c2;
               ri = (R)s2;
+              g_rot(nx.a, getbit<W>(T.x, nx.v) != 0);
             }
             const uint32_t tm = pend_tm, sm = pend_sm;
             const bool fas = pend_as;
@@ -719,10 +808,13 @@ struct Shot {
           // then exp(-i theta' Z_v) on the new axis, theta' sign-flipped by
           // x_v of the frame.  The common phase e^{-i theta'} is global, so
           // the new half is the old one times e^{2 i theta'}.
+          g_h(v);
           frame_h<W>(T, v);
           frame_h<W>(N, v);
-          double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
+          double c2 = P.consts[4 * in.a], s2 = P.consts[4 * in.a + 1];
           if (getbit<W>(T.x, v)) s2 = -s2;
+          g_rot(in.a, getbit<W>(T.x, v) != 0);
+          g_nexp++;
           const R cr = (R)c2, ci = (R)s2;
           if constexpr (OOP) {
             // deferred: the new top slot's factor; when all are taken, the
@@ -757,8 +849,9 @@ struct Shot {
           else {
           carry_valid = false;
           materialize();
-          double c2 = P.consts[2 * in.a], s2 = P.consts[2 * in.a + 1];
+          double c2 = P.consts[4 * in.a], s2 = P.consts[4 * in.a + 1];
           if (getbit<W>(T.x, v)) s2 = -s2;
+          g_rot(in.a, getbit<W>(T.x, v) != 0);
           const R cr = (R)c2, ci = (R)s2;
           const uint32_t bs = 1u << s;
           pass1<G, R, U>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
@@ -802,8 +895,10 @@ struct Shot {
             mm = ((wv >> (bi & 31)) & 1u) ^ pn;
           }
           uint32_t b = mm ^ (uint32_t)(in.flags & F_SIGN) ^ p;
+          g_h(v);  // H_v absorbed into the frames
           frame_h<W>(T, v);
           frame_h<W>(N, v);
+          if constexpr (DBG) g_ipow += 2 * (int)(b & getbit<W>(T.z, v));  // X^x Z^z X_v = (-1)^{z_v} X^(x^v) Z^z
           xorbit<W>(T.x, v, b);
           last_m = mm;
           last_pn = pn;
@@ -1221,7 +1316,9 @@ struct Shot {
           }
           k--;
           grp.sync();
-          if (isx) { frame_h<W>(T, v); frame_h<W>(N, v); }
+          g_nexp = 0;  // the kept branch is normalised
+          if (isx) { g_h(v); frame_h<W>(T, v); frame_h<W>(N, v); }
+          if constexpr (DBG) g_ipow += 2 * (int)(b & getbit<W>(T.z, v));
           xorbit<W>(T.x, v, b);
           last_m = mm;
           last_pn = pn;
@@ -1246,6 +1343,15 @@ struct Shot {
             bx[w] = px[w] & mp; bz[w] = pz[w] & mp;
           }
           (void)zero;
+          if constexpr (DBG) {
+            // X^m of the reset: the signed image E = (-1)^r i^|ex & ez| X^ex Z^ez
+            if (last_m) {
+              int e = 2 * (int)(in.flags & F_SIGN);
+#pragma unroll
+              for (int w = 0; w < W; w++) e += __popcll(px[w] & pz[w]) + 2 * __popcll(pz[w] & T.x[w]);
+              g_ipow += e;
+            }
+          }
           frame_xor<W>(T, ax, az);
           frame_xor<W>(N, bx, bz);
           break;
@@ -1255,7 +1361,10 @@ struct Shot {
             if (A.forced_faults) {
               for (uint32_t st = in.a; st < in.b; st++) {
                 int o = local < A.shots ? A.forced_faults[local * P.nsites + st] : -1;
-                if (o >= 0) apply_fault<W>(P, T, N, st, (uint32_t)o);
+                if (o >= 0) {
+                  g_ipow += fault_phase<W>(P, T.x, st, (uint32_t)o);
+                  apply_fault<W>(P, T, N, st, (uint32_t)o);
+                }
               }
               break;
             }
@@ -1269,6 +1378,7 @@ struct Shot {
               next_fault(P, ns, 0, shot, seed);
               continue;
             }
+            if constexpr (DBG) g_ipow += fault_phase<W>(P, T.x, ns.nf, ns.nf_out);
             apply_fault<W>(P, T, N, ns.nf, ns.nf_out);
             next_fault(P, ns, ns.nf - ns.chunk * (uint32_t)kChunk + 1, shot, seed);
           }
@@ -1296,6 +1406,15 @@ struct Shot {
     }
   done:
     if constexpr (DBG) {
+      if (A.gamma_out && local < A.shots && (G == 1 || grp.tid == 0)) {
+        const double sc = exp2(-0.5 * (double)g_nexp);
+        const int e = g_ipow & 3;
+        // i^e (g_re + i g_im) 2^{-n/2}
+        const double re = e == 0 ? g_re : e == 1 ? -g_im : e == 2 ? -g_re : g_im;
+        const double im = e == 0 ? g_im : e == 1 ? g_re : e == 2 ? -g_im : -g_re;
+        A.gamma_out[local * 2] = re * sc;
+        A.gamma_out[local * 2 + 1] = im * sc;
+      }
       if (A.phi_out && local < A.shots && P.kmax == 0) {
         // no active vector exists: the state is the trivial [1]
         if (G == 1 || grp.tid == 0) {

@@ -139,3 +139,23 @@ def test_fused_byte_model_orders(name):
     for spec in circuits.batched_set()[:16]:
         c = pk.Program(spec["text"]).cost_model("f32")
         assert c["vector_bytes_fused"] <= c["vector_bytes_fused_group"] <= c["vector_bytes"]
+
+
+def test_compile_options():
+    text = circuits.workload("random_clifford_t_n8")["texts"][0]
+    assert pk.Program(text, k_limit=4).k_max == 4
+    with pytest.raises(pk.ClifftError) as e:
+        pk.Program(text, k_limit=3)
+    assert e.value.status == 3
+    with pytest.raises(pk.ClifftError) as e:
+        pk.Program(text, hir_passes=8)
+    assert e.value.status == 4
+    with pytest.raises(pk.ClifftError) as e:
+        pk.Program(text, drop_phases=2)
+    assert e.value.status == 4
+    # a rotation about a dormant Z string only changes the global scalar:
+    # kept as one instruction, or left out on request
+    ph = "T 0\nH 1\nT 1\nM 0 1\n"
+    a, b = pk.Program(ph), pk.Program(ph, drop_phases=1)
+    assert a.k_max == b.k_max == 1
+    assert a.num_instructions == b.num_instructions + 1

@@ -5,10 +5,11 @@ Bar: records bit-exact for Pauli-frame-only circuits; with FP64 amplitudes
 records bit-exact on every circuit (the only possible difference is a
 uniform draw falling between two probabilities that differ by rounding);
 with FP32 amplitudes records identical except for such near-threshold
-shots, bounded here.  On forced-outcome shots the probability of every
-forced outcome is within 1e-12 (FP64) or 2e-5 (FP32) relative, and the
-final active vector, after slot permutation and global-phase alignment,
-within the same tolerance relative to its norm.
+shots, bounded from the measured FP32-FP64 probability gap.  On
+forced-outcome shots the probability of every forced outcome is within
+1e-12 (FP64) or 2e-5 (FP32) relative, and gamma * phi (the global scalar
+times the final active vector, after slot permutation only) within the same
+tolerance relative to its norm.
 """
 import os
 
@@ -184,12 +185,13 @@ def _phi_in_oracle_order(phi_g, gslots, oslots):
     return out
 
 
-def _align(a, b):
-    """Normalise both and remove the global phase of a relative to b."""
-    a = a / np.linalg.norm(a)
-    b = b / np.linalg.norm(b)
-    ov = np.vdot(a, b)
-    return a * (ov / abs(ov)), b
+def _state_error(phi_g, gamma_g, gslots, t):
+    """Relative distance between gamma * phi of the GPU (slots permuted to
+    the oracle's order) and of the oracle: the same vector of the
+    frame-factored state with no phase alignment and no rescaling."""
+    a = gamma_g * _phi_in_oracle_order(phi_g, gslots, list(t["slots"]))
+    b = t["gamma"] * np.asarray(t["phi"])
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def _forced_check(text, case, precision, tol, tier, rng):
@@ -219,6 +221,7 @@ def _forced_check(text, case, precision, tol, tier, rng):
     torch.cuda.synchronize()
     probs = res["probs"].cpu().numpy()
     phi = res["phi"].cpu().numpy()
+    gam = res["gamma"].cpu().numpy()
     gslots = gp.final_slots()
     worst_p = worst_v = 0.0
     for s, t in enumerate(traces):
@@ -231,8 +234,7 @@ def _forced_check(text, case, precision, tol, tier, rng):
             worst_p = max(worst_p, float(np.max(np.abs(pg - po) / po)))
         k = t["k"]
         assert len(gslots) == k
-        a, b = _align(_phi_in_oracle_order(phi[s, : 1 << k], gslots, list(t["slots"])), t["phi"])
-        worst_v = max(worst_v, float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+        worst_v = max(worst_v, _state_error(phi[s, : 1 << k], gam[s], gslots, t))
     print("%s case %d: worst relative probability error %.3g, vector error %.3g" % (precision, case, worst_p, worst_v))
     assert worst_p <= tol and worst_v <= tol
 
@@ -496,6 +498,7 @@ def test_forced_amplitudes_k10(precision, tol, G, hbm):
     torch.cuda.synchronize()
     probs = res["probs"].cpu().numpy()
     phi = res["phi"].cpu().numpy()
+    gam = res["gamma"].cpu().numpy()
     gslots = gp.final_slots()
     for s, t in enumerate(traces):
         m = fm[s].astype(bool)
@@ -503,8 +506,7 @@ def test_forced_amplitudes_k10(precision, tol, G, hbm):
         po = np.where(m, t["probs"], 1.0 - np.asarray(t["probs"]))
         assert np.max(np.abs(pg - po) / po) <= tol
         assert t["k"] == 10
-        a, b = _align(_phi_in_oracle_order(phi[s, : 1 << 10], gslots, list(t["slots"])), t["phi"])
-        assert np.linalg.norm(a - b) / np.linalg.norm(b) <= tol
+        assert _state_error(phi[s, : 1 << 10], gam[s], gslots, t) <= tol
 
 
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
