@@ -277,7 +277,7 @@ def bench_batch(args, w, pk, torch):
     # FP64 plain: one call per circuit, in order, sharing one workspace
     L64 = pk.make_launch("f64")
     plain_outs = [p.alloc_outputs(s) for p, s in zip(progs, shots)]
-    ws64_bytes = max(p.workspace_size(L64) for p in progs)
+    ws64_bytes = max(p.workspace_size(L64, s) for p, s in zip(progs, shots))
     ws64 = torch.empty(max(ws64_bytes, 1), dtype=torch.uint8, device="cuda") if ws64_bytes else None
 
     def plain_step():
@@ -441,7 +441,7 @@ def main():
     launch = pk.make_launch(precision, threads_per_shot=args.threads_per_shot, grid=args.grid,
                             vector_in_hbm=args.vector_in_hbm, specialize=args.specialize)
     outs = prog.alloc_outputs(shots)
-    ws = prog.alloc_workspace(launch)
+    ws = prog.alloc_workspace(launch, shots=shots)
     stream = torch.cuda.current_stream()
 
     if args.calibrate_copy:

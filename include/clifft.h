@@ -85,6 +85,21 @@ typedef struct clifft_launch {
                                clifft_specialize; an error on any other tier),
                                -1 never, 0 automatic (the interpreter unless
                                the autotuner chose the specialized kernel) */
+  int32_t split;            /* 1, 2, 3 the split form (programs with an active
+                               vector and at most 256 active measurements):
+                               the Pauli frames of every shot run bit-sliced
+                               with the active outcomes taken as 0 (records
+                               and the frame bits the vector reads are affine
+                               over GF(2) in those outcomes), then the vector
+                               instructions alone at threads_per_shot /
+                               vector_in_hbm / grid, then a fix-up XORs the
+                               outcomes into the records they feed; same
+                               records as the whole-program interpreter.
+                               The frame pass runs bit-sliced (2), shot per
+                               lane with frames in VGPRs (3), or (1) bit-sliced
+                               when its rows fit in LDS and there are at least
+                               two 2048-shot tiles per CU.
+                               -1 never, 0 automatic (the autotuner's choice) */
 } clifft_launch;
 
 /* Compile options; zero-initialize (or pass NULL) for the defaults. */
@@ -183,11 +198,13 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
  * bytes, NUL-terminated) receives the reason or the compiler log. */
 clifft_status clifft_specialize(clifft_program* p, char* log, size_t cap);
 
-/* Bytes of caller-provided device workspace a sample call needs with this
- * configuration (0 when the active vectors fit in LDS).  Vectors in HBM take
- * two buffers of 2^k_max amplitudes per shot in flight: active measurements
- * collapse from one into the other. */
-clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes);
+/* Bytes of caller-provided device workspace a sample call of `shots` shots
+ * needs with this configuration (0 when the active vectors fit in LDS and
+ * the split form is not used).  Vectors in HBM take two buffers of
+ * 2^k_max amplitudes per shot in flight: active measurements collapse from
+ * one into the other.  The split form adds its needed-bit and outcome rows
+ * (bit-packed, one row per needed bit and per active measurement). */
+clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, uint64_t shots, size_t* bytes);
 
 /* Sample `shots` shots with global indices shot_offset .. shot_offset+shots-1
  * and Philox seed `seed` (Section 3.2: every shot resets the frames and the

@@ -41,7 +41,7 @@ class clifft_compile_opts(ctypes.Structure):
 
 class clifft_launch(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("threads_per_shot", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("vector_in_hbm", ctypes.c_int32), ("specialize", ctypes.c_int32)]
+                ("vector_in_hbm", ctypes.c_int32), ("specialize", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 _lib = None
@@ -60,7 +60,7 @@ def lib():
         L.clifft_k_profile.argtypes = [vp, i32p, sz, ctypes.POINTER(sz)]
         L.clifft_event_classes.argtypes = [vp, i32p, sz, ctypes.POINTER(sz)]
         L.clifft_final_slots.argtypes = [vp, i32p, i32p]
-        L.clifft_workspace_size.argtypes = [vp, ctypes.POINTER(clifft_launch), ctypes.POINTER(sz)]
+        L.clifft_workspace_size.argtypes = [vp, ctypes.POINTER(clifft_launch), u64, ctypes.POINTER(sz)]
         L.clifft_sample.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, sz, vp, vp, vp, vp]
         L.clifft_sample_noalloc.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp]
         L.clifft_sample_trace.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp, vp, vp,
@@ -104,9 +104,9 @@ def probe(kind, dst, src=None, n=0, grid=1, stream=None):
     _check(lib().clifft_probe(kind, dst.data_ptr(), None if src is None else src.data_ptr(), n, grid, s.cuda_stream))
 
 
-def make_launch(precision="f32", threads_per_shot=0, grid=0, vector_in_hbm=0, specialize=0):
+def make_launch(precision="f32", threads_per_shot=0, grid=0, vector_in_hbm=0, specialize=0, split=0):
     p = CLIFFT_FP64 if precision in ("f64", CLIFFT_FP64) else CLIFFT_FP32
-    return clifft_launch(p, threads_per_shot, grid, vector_in_hbm, specialize)
+    return clifft_launch(p, threads_per_shot, grid, vector_in_hbm, specialize, split)
 
 
 class Program:
@@ -178,9 +178,9 @@ class Program:
                                      torch.cuda.current_stream().cuda_stream, ctypes.byref(out)))
         return {f: getattr(out, f) for f, _ in clifft_launch._fields_}
 
-    def workspace_size(self, launch=None):
+    def workspace_size(self, launch=None, shots=1 << 20):
         n = ctypes.c_size_t()
-        _check(lib().clifft_workspace_size(self._h, None if launch is None else ctypes.byref(launch),
+        _check(lib().clifft_workspace_size(self._h, None if launch is None else ctypes.byref(launch), shots,
                                            ctypes.byref(n)))
         return n.value
 
@@ -191,9 +191,9 @@ class Program:
         mk = lambda rows: torch.empty((rows, words), dtype=torch.int64, device=device)
         return mk(self.num_measurements), mk(self.num_detectors), mk(self.num_observables)
 
-    def alloc_workspace(self, launch=None, device="cuda"):
+    def alloc_workspace(self, launch=None, device="cuda", shots=1 << 20):
         import torch
-        n = self.workspace_size(launch)
+        n = self.workspace_size(launch, shots)
         return torch.empty(max(n, 1), dtype=torch.uint8, device=device) if n else None
 
     def sample(self, shots, seed=0, offset=0, launch=None, outputs=None, workspace=None, stream=None):
@@ -202,7 +202,7 @@ class Program:
         import torch
         meas, det, obs = outputs if outputs is not None else self.alloc_outputs(shots)
         if workspace is None:
-            workspace = self.alloc_workspace(launch)
+            workspace = self.alloc_workspace(launch, shots=shots)
         s = stream if stream is not None else torch.cuda.current_stream()
         ptr = lambda t: t.data_ptr() if (t is not None and t.numel()) else None
         _check(lib().clifft_sample(self._h, shots, seed, offset, None if launch is None else ctypes.byref(launch),
@@ -232,7 +232,7 @@ class Program:
         probs = torch.zeros((shots, max(self.num_events, 1)), dtype=torch.float64, device="cuda")
         phi = torch.zeros((shots, 1 << self.k_max, 2), dtype=torch.float64, device="cuda") if want_phi else None
         gamma = torch.zeros((shots, 2), dtype=torch.float64, device="cuda")
-        ws = self.alloc_workspace(launch)
+        ws = self.alloc_workspace(launch, shots=shots)
         fm = None if forced_m is None else forced_m.to(device="cuda", dtype=torch.int32).contiguous()
         ff = None if forced_faults is None else forced_faults.to(device="cuda", dtype=torch.int32).contiguous()
         ptr = lambda t: t.data_ptr() if (t is not None and t.numel()) else None

@@ -718,6 +718,184 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
   return c;
 }
 
+// Split form (program.h): the frame-only and vector-only streams, and the
+// GF(2) dependency of the needed bits and of every output row on the active
+// measurement outcomes, found by running the frame instructions on masks:
+// each full-frame bit carries the set of active outcomes it depends on
+// (the frames' other inputs, faults and dormant random bits, are sampled by
+// the frame stream itself).  An active measurement leaves x_v = m ^ sign; a
+// reset's correction X^m adds the dependency of m to the bits it flips; a
+// dormant random measurement leaves x_v = m ^ sign with m independent of
+// the active outcomes.
+static void build_split(CompiledProgram& P) {
+  const int n = P.nq, W = P.W;
+  int nact = 0;
+  for (int cl : P.ev_class) nact += cl == 2;
+  P.nactive = nact;
+  P.split_ok = P.kmax > 0 && nact <= kSplitMaxActive;
+  if (!P.split_ok) return;
+  const int DW = std::max(1, (nact + 63) / 64);
+  P.dep_words = DW;
+  using Dep = std::vector<uint64_t>;
+  const Dep zero(DW, 0);
+  auto xr = [&](Dep& a, const Dep& b) {
+    for (int w = 0; w < DW; w++) a[w] ^= b[w];
+  };
+  auto each_bit = [&](uint32_t off, auto fn) {
+    for (int w = 0; w < W; w++) {
+      uint64_t m = P.masks[off + w];
+      while (m) {
+        fn(w * 64 + __builtin_ctzll(m));
+        m &= m - 1;
+      }
+    }
+  };
+  std::vector<Dep> dx(n, zero), dz(n, zero), ev_dep(std::max(P.nevents, 1), zero);
+  std::vector<Dep> rows(P.nrec + P.ndet + P.nobs, zero);  // meas, det, obs rows
+  P.vev_rec.assign(std::max(P.nevents, 1), -1);
+  int nb = 0, act = 0;
+  auto need = [&](const Dep& d) {
+    P.vdep.insert(P.vdep.end(), d.begin(), d.end());
+    return nb++;
+  };
+  auto vpush = [&](GInstr g, size_t i) {
+    P.vcode.push_back(g);
+    P.vk_after.push_back(P.k_after[i]);
+  };
+  for (size_t i = 0; i < P.code.size(); i++) {
+    GInstr in = P.code[i];
+    const int v = in.v;
+    switch (in.op) {
+      case OP_FANCX: {
+        Dep par = zero;
+        each_bit(in.a, [&](int q) { xr(dx[q], dx[v]); xr(par, dz[q]); });
+        xr(dz[v], par);
+        P.fcode.push_back(in);
+        break;
+      }
+      case OP_FANCZ: {
+        Dep par = zero;
+        each_bit(in.a, [&](int q) { xr(dz[q], dx[v]); xr(par, dx[q]); });
+        xr(dz[v], par);
+        P.fcode.push_back(in);
+        break;
+      }
+      case OP_FAN2: {
+        Dep par = zero;
+        each_bit(in.a, [&](int q) { xr(dz[q], dz[v]); xr(par, dx[q]); });
+        xr(dx[v], par);
+        P.fcode.push_back(in);
+        break;
+      }
+      case OP_FS: xr(dz[v], dx[v]); P.fcode.push_back(in); break;
+      case OP_FH: std::swap(dx[v], dz[v]); P.fcode.push_back(in); break;
+      case OP_EXPAND: {
+        std::swap(dx[v], dz[v]);
+        GInstr h{};
+        h.op = OP_FH;
+        h.v = (uint16_t)v;
+        P.fcode.push_back(h);
+        GInstr e{};
+        e.op = OP_EMIT;
+        e.v = (uint16_t)v;
+        e.u = (uint16_t)nb;
+        P.fcode.push_back(e);
+        in.v = (uint16_t)need(dx[v]);
+        vpush(in, i);
+        break;
+      }
+      case OP_AROT: {
+        GInstr e{};
+        e.op = OP_EMIT;
+        e.v = (uint16_t)v;
+        e.u = (uint16_t)nb;
+        P.fcode.push_back(e);
+        in.v = (uint16_t)need(dx[v]);
+        vpush(in, i);
+        break;
+      }
+      case OP_APERM: case OP_ASIGN: case OP_APERM2: case OP_AS: case OP_AH:
+        vpush(in, i);
+        break;
+      case OP_MSTATIC: {
+        Dep d = zero;
+        each_bit(in.a, [&](int q) { xr(d, dx[q]); });
+        ev_dep[in.b] = d;
+        if (P.ev_rec[in.b] >= 0) rows[P.ev_rec[in.b]] = d;
+        P.fcode.push_back(in);
+        break;
+      }
+      case OP_MRANDOM: {
+        // the outcome is independent of the active outcomes; x_v = m ^ sign
+        const Dep ox = dx[v];
+        dx[v] = zero;
+        dz[v] = ox;
+        ev_dep[in.b] = zero;
+        P.fcode.push_back(in);
+        break;
+      }
+      case OP_MACTZ: case OP_MACTX: {
+        const bool isx = in.op == OP_MACTX;
+        GInstr f{};
+        f.op = OP_MACTF;
+        f.flags = (uint8_t)((in.flags & F_SIGN) | (isx ? F_XMEAS : 0));
+        f.v = (uint16_t)v;
+        f.u = (uint16_t)nb;
+        f.b = in.b;
+        P.fcode.push_back(f);
+        const int row = need(isx ? dz[v] : dx[v]);  // p
+        need(zero);                                 // pn: noise frame only
+        in.v = (uint16_t)row;
+        in.a = (uint32_t)act;
+        vpush(in, i);
+        if (isx) std::swap(dx[v], dz[v]);
+        Dep e = zero;
+        e[act >> 6] |= 1ull << (act & 63);
+        dx[v] = e;
+        ev_dep[in.b] = e;
+        if (P.ev_rec[in.b] >= 0) rows[P.ev_rec[in.b]] = e;
+        P.vev_rec[in.b] = act++;
+        break;
+      }
+      case OP_CPAULI: {
+        const Dep d = ev_dep[in.b];
+        each_bit(in.a, [&](int q) { xr(dx[q], d); });
+        each_bit(in.a + W, [&](int q) { xr(dz[q], d); });
+        P.fcode.push_back(in);
+        break;
+      }
+      case OP_DET: {
+        Dep d = zero;
+        for (uint32_t k = 0; k < in.u; k++) xr(d, rows[P.refs[in.a + k]]);
+        rows[P.nrec + in.b] = d;
+        P.fcode.push_back(in);
+        break;
+      }
+      case OP_OBS: {
+        for (uint32_t k = 0; k < in.u; k++) xr(rows[P.nrec + P.ndet + in.b], rows[P.refs[in.a + k]]);
+        P.fcode.push_back(in);
+        break;
+      }
+      case OP_END:
+        P.fcode.push_back(in);
+        vpush(in, i);
+        break;
+      default:  // noise blocks, phase-only instructions
+        P.fcode.push_back(in);
+        break;
+    }
+  }
+  P.nbits = nb;
+  if (P.vdep.empty()) P.vdep.assign(DW, 0);
+  P.xdep_off.assign(1, 0);
+  for (const Dep& d : rows) {
+    for (int a = 0; a < nact; a++)
+      if ((d[a >> 6] >> (a & 63)) & 1) P.xdep.push_back((uint32_t)a);
+    P.xdep_off.push_back((uint32_t)P.xdep.size());
+  }
+  if (P.xdep.empty()) P.xdep.push_back(0);
+}
+
 int compile_text(const char* text, size_t len, const CompileOptions& opts, CompiledProgram& P, std::string& err) {
   Lines L;
   {
@@ -896,6 +1074,7 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
   }
   survival_tables(P);
   if (P.masks.empty()) P.masks.push_back(0);
+  build_split(P);
   if (P.consts.empty()) P.consts = {1.0, 0.0, 1.0, 0.0};
   if (P.refs.empty()) P.refs.push_back(0);
   if (P.ev_rec.empty()) P.ev_rec.push_back(-1);

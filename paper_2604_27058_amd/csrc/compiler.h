@@ -30,6 +30,18 @@ struct CompiledProgram {
   std::vector<uint32_t> rblk_off;              // 128-event block -> its dormant random events
   std::vector<uint8_t> rblk_ev;
   int rblk_max = 0;
+  // split form (program.h): valid when split_ok
+  bool split_ok = false;
+  int nactive = 0;                 // active measurement events
+  int nbits = 0;                   // needed-bit rows (a rotation: one; an active measurement: two)
+  int dep_words = 1;               // 64-bit words per dependency mask
+  std::vector<GInstr> fcode;       // frame-only stream (k_max 0 for the bit-sliced kernel)
+  std::vector<GInstr> vcode;       // vector-only stream (v: needed-bit row; MACT: a = active index)
+  std::vector<int> vk_after;       // active dimension after each vector instruction
+  std::vector<uint64_t> vdep;      // [nbits][dep_words] dependency masks of the needed bits
+  std::vector<int32_t> vev_rec;    // event -> active index or -1 (the vector stream's records)
+  std::vector<uint32_t> xdep_off;  // per output row (meas, det, obs): first entry in xdep
+  std::vector<uint32_t> xdep;      // active outcome rows XORed into each output row
 };
 
 // Algorithmic work of one shot (see cost_model in compiler.cpp).

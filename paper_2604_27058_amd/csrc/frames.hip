@@ -134,6 +134,7 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   uint32_t* meas32 = (uint32_t*)A.meas;
   uint32_t* det32 = (uint32_t*)A.det;
   uint32_t* obs32 = (uint32_t*)A.obs;
+  uint32_t* bits32 = (uint32_t*)A.nbits;  // split form: needed-bit rows
   cptr<uint64_t> masks = as_const(P.masks);
   cptr<uint32_t> rec_tgt_off = as_const(P.rec_tgt_off), rec_tgt = as_const(P.rec_tgt);
   for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -435,6 +436,33 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
           if (det32 && store) det32[(size_t)in.b * 2 * words64 + col] = F(ACC + in.s) & valid;
           F(ACC + in.s) = 0;  // the row is reused by a later detector
           break;
+        case OP_EMIT:
+          // frame-only stream of the split form: a rotation's sign bit
+          if (bits32 && store) bits32[(size_t)in.u * 2 * words64 + col] = F(v) & valid;
+          break;
+        case OP_MACTF: {
+          // frame side of an active measurement taken with outcome 0: its
+          // frame and noise parities for the vector stream, H_v (X-type),
+          // x_v = sign; the record row stays 0 until the fix-up
+          const bool isx = (in.flags & F_XMEAS) != 0;
+          const uint32_t x = F(v), z = F(N + v), nx = F(2 * N + v), nz = F(3 * N + v);
+          const uint32_t pn = isx ? nz : nx;
+          if (bits32 && store) {
+            bits32[(size_t)in.u * 2 * words64 + col] = (isx ? z : x) & valid;
+            bits32[(size_t)(in.u + 1) * 2 * words64 + col] = pn & valid;
+          }
+          if (isx) {
+            F(N + v) = x;
+            F(2 * N + v) = nz;
+            F(3 * N + v) = nx;
+          }
+          F(v) = (in.flags & F_SIGN) ? ~0u : 0u;
+          last_m = 0;
+          last_pn = pn;
+          const int r = as_const(P.ev_rec)[in.b];
+          if (r >= 0 && meas32 && store) meas32[(size_t)r * 2 * words64 + col] = 0;
+          break;
+        }
         default:  // OP_OBS: accumulated from its records; no active-vector ops exist here
           break;
       }

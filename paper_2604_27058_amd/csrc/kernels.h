@@ -20,6 +20,9 @@ struct KArgs {
   double* phi_out;               // [shots][2^kmax][2] or null
   double* gamma_out;             // [shots][2] global scalar (re, im) or null
   int* error;                    // device flag word (trace mode)
+  // split form: needed-bit rows [nbits][ceil(shots/64)], written by the frame
+  // stream and read by the vector stream
+  uint64_t* nbits;
   uint32_t list_cap = 0xFFFFFFFFu;  // bit-sliced fault-list capacity (tests may lower it)
 };
 
@@ -29,6 +32,13 @@ struct LaunchShape {
   size_t lds_bytes; // dynamic LDS per workgroup
   bool global_vec;  // active vectors in the global workspace
   bool spec;        // bit-sliced: the program-specialized kernel
+  // split form: the frame-only stream on the bit-sliced kernel (fgrid
+  // workgroups of 64 threads), then the vector-only stream with the shape
+  // above, then the record fix-up
+  bool split;
+  int fgrid;
+  bool flane;       // split: frames too wide for LDS rows, so the frame pass
+                    // runs shot per lane (fgrid workgroups of 256 threads)
 };
 
 // Batched launch: many programs, one persistent kernel.
@@ -80,5 +90,25 @@ hipError_t launch_sample_f32(const DevProgram& P, const KArgs& A, const LaunchSh
 hipError_t launch_sample_f64(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
 hipError_t launch_trace_f32(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
 hipError_t launch_trace_f64(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
+// Split form: the vector-only stream (vsample_*.hip) and the record fix-up:
+// rows[i] (an output row: meas, then det, then obs) ^= XOR of the outcome
+// rows mrows[xdep[xdep_off[rows[i]] ..]] over every word.
+hipError_t launch_vsample_f32(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
+hipError_t launch_vsample_f64(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
+struct FixupArgs {
+  uint64_t *meas, *det, *obs;
+  int32_t nrec, ndet, nobs;
+  const uint32_t* rows;      // output rows with a nonempty dependency
+  uint32_t nrows;
+  const uint32_t* xdep_off;  // per output row
+  const uint32_t* xdep;
+  const uint64_t* mrows;     // [nactive][words] active outcomes
+  uint64_t words;
+};
+hipError_t launch_fixup(const FixupArgs& F, hipStream_t stream);
+// The split form's vector pass (record rows zero-filled first where the
+// shot-granular tiers OR their bits into them).
+hipError_t launch_vector_pass(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64,
+                              hipStream_t stream);
 
 }  // namespace clifft

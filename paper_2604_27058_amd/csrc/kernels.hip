@@ -51,6 +51,24 @@ hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+static void zero_records(const DevProgram& P, const KArgs& A, hipStream_t st) {
+  const size_t words = (A.shots + 63) / 64;
+  uint64_t* rows[3] = {A.meas, A.det, A.obs};
+  const size_t counts[3] = {(size_t)P.nrec, (size_t)P.ndet, (size_t)P.nobs};
+  for (int i = 0; i < 3; i++) {
+    size_t n = counts[i] * words;
+    if (!rows[i] || n == 0) continue;
+    int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, rows[i], n);
+  }
+}
+
+hipError_t launch_vector_pass(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64,
+                              hipStream_t st) {
+  if (L.G == 256 || L.G == 64) zero_records(P, A, st);
+  return fp64 ? launch_vsample_f64(P, A, L, st) : launch_vsample_f32(P, A, L, st);
+}
+
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool debug,
                          hipStream_t st) {
   if (L.G < 0) return launch_frames(P, A, L.grid, st);
@@ -68,6 +86,30 @@ hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape&
   }
   if (fp64) return debug ? launch_trace_f64(P, A, L, st) : launch_sample_f64(P, A, L, st);
   return debug ? launch_trace_f32(P, A, L, st) : launch_sample_f32(P, A, L, st);
+}
+
+// Record fix-up of the split form: one thread per word of a dependent row.
+__global__ void k_fixup(FixupArgs F) {
+  const uint64_t n = (uint64_t)F.nrows * F.words;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = F.rows[i / F.words];
+    const uint64_t w = i % F.words;
+    uint64_t acc = 0;
+    for (uint32_t e = F.xdep_off[r]; e < F.xdep_off[r + 1]; e++) acc ^= F.mrows[(size_t)F.xdep[e] * F.words + w];
+    uint64_t* dst;
+    if (r < (uint32_t)F.nrec) dst = F.meas ? F.meas + (size_t)r * F.words : nullptr;
+    else if (r < (uint32_t)(F.nrec + F.ndet)) dst = F.det ? F.det + (size_t)(r - F.nrec) * F.words : nullptr;
+    else dst = F.obs ? F.obs + (size_t)(r - F.nrec - F.ndet) * F.words : nullptr;
+    if (dst) dst[w] ^= acc;
+  }
+}
+
+hipError_t launch_fixup(const FixupArgs& F, hipStream_t st) {
+  const uint64_t n = (uint64_t)F.nrows * F.words;
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)std::min<uint64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(k_fixup, dim3(blocks), dim3(256), 0, st, F);
+  return hipGetLastError();
 }
 
 size_t lds_bytes_for(const DevProgram& P, int G, bool global_vec, bool fp64) {

@@ -40,6 +40,12 @@ enum Op : uint8_t {
   OP_OBS,      // observable b ^= XOR of records refs[a .. a+u)
   OP_PHASE,    // rotation whose generator is a Z string on dormant qubits   a=mask(z), b=const
                //   (Appendix B.1 case 1): only the global scalar changes
+  // Frame-only stream of the split form (below): the frame side of the
+  // vector instructions, for the bit-sliced frame kernel.
+  OP_EMIT,     // write bit x_v of the full frame to needed-bit row u
+  OP_MACTF,    // frame side of an active measurement with outcome 0: write p
+               //   (x_v, or z_v for F_XMEAS) to row u and the noise frame's to
+               //   row u + 1; H_v for F_XMEAS; then x_v = sign; record 0  v, u, b=event
   OP_COUNT
 };
 
@@ -56,6 +62,7 @@ constexpr uint8_t F_FOLD_NEXT = 8;
 // again an active measurement: this measurement's collapse pass accumulates
 // that one's branch sums (F_FUSE_NEXT), and it skips its own reduction.
 constexpr uint8_t F_FUSE_NEXT = 2;
+constexpr uint8_t F_XMEAS = 4;  // OP_MACTF: the measurement is X-type (interfere)
 // Kernels that collapse out of place keep up to this many trailing
 // expansions unapplied: the vector is then the stored 2^(k-d) amplitudes
 // times one phase factor per deferred top slot (an expansion only multiplies
@@ -82,6 +89,23 @@ constexpr uint32_t kPurposeNoise = 0x4E000000u;  // | chunk
 constexpr uint32_t kPurposeRbit = 0x52000000u;
 constexpr uint32_t kPurposeAmeas = 0x41000000u;
 
+// Split form.  Every frame bit and every record of a shot is an affine
+// function over GF(2) of the shot's faults, dormant random bits and active
+// measurement outcomes, and the active vector reads the frames only through a
+// few bits (a rotation's sign, an active measurement's frame and noise
+// parities).  So a program can run as
+//   1. the frame-only stream (bit-sliced, 32 shots per lane) with every active
+//      outcome taken as 0, writing records and the needed bits;
+//   2. the vector-only stream, one shot per lane, wave or workgroup, each
+//      needed bit corrected by the parity of its dependency mask with the
+//      shot's active outcomes so far, writing the active outcomes;
+//   3. a fix-up XORing into each record row the outcome rows its dependency
+//      lists.
+// At most kSplitMaxActive active measurements (dependency masks of
+// kSplitWords 64-bit words).
+constexpr int kSplitMaxActive = 256;
+constexpr int kSplitWords = kSplitMaxActive / 64;
+
 // Device-side view of one program (all pointers are device addresses).
 struct DevProgram {
   const GInstr* code;
@@ -103,6 +127,12 @@ struct DevProgram {
   int32_t rblk_max;             // most dormant random events in one 128-event block
   int32_t ndet_rows;            // detector accumulator rows (observables follow them)
   float exp_faults;             // expected realized faults per shot (sum of site probabilities)
+  // split form, vector-only view: needed bits of the shot ([rows][words],
+  // bit-packed like records) and each row's dependency mask over the active
+  // outcomes (kSplitWords words per row); null elsewhere
+  const uint64_t* vdep;
+  int32_t nbits;                // needed-bit rows
+  int32_t dep_words;            // words per dependency mask actually used (<= kSplitWords)
 };
 
 }  // namespace clifft

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -31,6 +32,14 @@ clifft_status fail(clifft_status st, const std::string& msg) {
 
 struct DeviceCopy {
   DevProgram view{};
+  // split form: the frame-only view (bit-sliced kernel), the vector-only view,
+  // and the fix-up tables (output rows with a dependency, their entries)
+  bool has_split = false;
+  DevProgram fview{}, vview{};
+  const uint32_t* xrows = nullptr;
+  uint32_t nxrows = 0;
+  const uint32_t* xdep_off = nullptr;
+  const uint32_t* xdep = nullptr;
   std::vector<void*> allocs;
   hipModule_t spec_mod = nullptr;  // specialized kernel, loaded at its first launch
   hipFunction_t spec_fn = nullptr;
@@ -65,7 +74,7 @@ hipError_t upload_vec(const std::vector<T>& v, const T** dst, std::vector<void*>
   return hipSuccess;
 }
 
-clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
+clifft_status ensure_device(const clifft_program* cp, const DevProgram** out, const DeviceCopy** copy = nullptr) {
   clifft_program* p = const_cast<clifft_program*>(cp);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(CLIFFT_E_DEVICE, "no HIP device");
@@ -73,6 +82,7 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
   auto it = p->dev.find(dev);
   if (it != p->dev.end()) {
     *out = &it->second.view;
+    if (copy) *copy = &it->second;
     return CLIFFT_OK;
   }
   DeviceCopy dc;
@@ -113,8 +123,43 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out) {
     for (double q : H.site_p) f += q;
     v.exp_faults = (float)f;
   }
+  if (H.split_ok) {
+    DevProgram f = v, g = v;
+    std::vector<uint32_t> xrows;
+    for (size_t i = 0; i + 1 < H.xdep_off.size(); i++)
+      if (H.xdep_off[i + 1] > H.xdep_off[i]) xrows.push_back((uint32_t)i);
+    if (xrows.empty()) xrows.push_back(0);
+    if (e == hipSuccess) e = upload_vec(H.fcode, &f.code, dc.allocs);
+    if (e == hipSuccess) e = upload_vec(H.vcode, &g.code, dc.allocs);
+    if (e == hipSuccess) e = upload_vec(H.vdep, &g.vdep, dc.allocs);
+    if (e == hipSuccess) e = upload_vec(H.vev_rec, &g.ev_rec, dc.allocs);
+    if (e == hipSuccess) e = upload_vec(xrows, &dc.xrows, dc.allocs);
+    if (e == hipSuccess) e = upload_vec(H.xdep_off, &dc.xdep_off, dc.allocs);
+    if (e == hipSuccess) e = upload_vec(H.xdep, &dc.xdep, dc.allocs);
+    if (e != hipSuccess) {
+      for (void* a : dc.allocs) (void)hipFree(a);
+      return fail(CLIFFT_E_DEVICE, std::string("program upload failed: ") + hipGetErrorString(e));
+    }
+    f.ncode = (int)H.fcode.size();
+    f.kmax = 0;
+    g.ncode = (int)H.vcode.size();
+    g.W = 1;
+    g.nrec = H.nactive;
+    g.ndet = g.nobs = 0;
+    g.nsites = g.nchunks = 0;
+    g.rblk_max = 0;
+    g.ndet_rows = 0;
+    g.exp_faults = 0;
+    g.nbits = H.nbits;
+    g.dep_words = H.dep_words;
+    dc.fview = f;
+    dc.vview = g;
+    dc.nxrows = H.xdep_off.back() > 0 ? (uint32_t)(xrows.size()) : 0u;
+    dc.has_split = true;
+  }
   auto res = p->dev.emplace(dev, std::move(dc));
   *out = &res.first->second.view;
+  if (copy) *copy = &res.first->second;
   return CLIFFT_OK;
 }
 
@@ -203,14 +248,87 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
   if (cfg) c = *cfg;
   if (c.precision != CLIFFT_FP32 && c.precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
   *fp64 = c.precision == CLIFFT_FP64;
-  if (tuned && c.threads_per_shot == 0 && c.grid == 0 && c.vector_in_hbm == 0 && c.specialize == 0) {
+  if (tuned && c.threads_per_shot == 0 && c.grid == 0 && c.vector_in_hbm == 0 && c.specialize == 0 && c.split == 0) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     auto it = tuned->find({dev, c.precision});
-    if (it != tuned->end() && !(trace && it->second.threads_per_shot == kBitSliced)) c = it->second;
+    if (it != tuned->end() && !(trace && (it->second.threads_per_shot == kBitSliced || it->second.split >= 1)))
+      c = it->second;
   }
   const size_t amp = *fp64 ? 16 : 8;
   const size_t vec = (size_t)1 << H.kmax;
+  if (c.split < -1 || c.split > 3) return fail(CLIFFT_E_INVALID_ARG, "split must be -1, 0, 1, 2 or 3");
+  if (c.split >= 1) {
+    if (trace) return fail(CLIFFT_E_INVALID_ARG, "the split form has no trace mode");
+    if (!H.split_ok)
+      return fail(CLIFFT_E_UNSUPPORTED, "the split form needs an active vector and at most 256 active measurements");
+    if (c.specialize == 1) return fail(CLIFFT_E_INVALID_ARG, "specialize applies to the bit-sliced tier only");
+    // frame pass: the bit-sliced kernel over the frame-only stream
+    DevProgram tmp{};
+    tmp.nq = H.nq;
+    tmp.ndet = H.ndet;
+    tmp.nobs = H.nobs;
+    tmp.rblk_max = H.rblk_max;
+    tmp.ndet_rows = H.ndet_rows;
+    tmp.nsites = (int)H.site_p.size();
+    tmp.nchunks = H.nchunks;
+    {
+      double f = 0;
+      for (double q : H.site_p) f += q;
+      tmp.exp_faults = (float)f;
+    }
+    const size_t rows_bytes = frames_lds_rows(tmp) * 64 * 4;
+    // frame pass: bit-sliced (2), shot per lane with frames in VGPRs (3), or
+    // (1) bit-sliced when its rows fit in LDS and its 2048-shot tiles fill
+    // the device twice over
+    const bool fits = rows_bytes <= kLdsLimit;
+    if (c.split == 2 && !fits) return fail(CLIFFT_E_CAPACITY, "frame rows of the split form exceed LDS");
+    const bool flane = c.split == 3 || !fits || (c.split == 1 && (shots + 2047) / 2048 < 2 * (uint64_t)device_cus());
+    int fgrid;
+    if (!flane) {
+      const uint64_t tiles = (shots + 2047) / 2048;
+      fgrid = device_cus() * (int)std::max<size_t>(1, std::min<size_t>(16, kLdsLimit / rows_bytes));
+      if ((uint64_t)fgrid > tiles) fgrid = (int)std::max<uint64_t>(1, tiles);
+    } else {
+      const uint64_t blocks = ((shots + 63) / 64 + 3) / 4;
+      fgrid = device_cus() * 8;
+      if ((uint64_t)fgrid > blocks) fgrid = (int)std::max<uint64_t>(1, blocks);
+    }
+    // vector pass: the vector-only stream, no frames
+    int G = c.threads_per_shot;
+    if (G == 0) G = H.kmax <= 6 ? 1 : H.kmax <= 13 ? 64 : 256;
+    if (G != 1 && G != 64 && G != 256) return fail(CLIFFT_E_INVALID_ARG, "the split form's threads_per_shot is 1, 64 or 256");
+    const size_t need = (G == 256 ? 1 : 4) * vec * amp * (G == 1 ? 64 : 1);
+    bool global_vec = c.vector_in_hbm == 1 ||
+                      (c.vector_in_hbm == 0 && need > (G == 256 ? (size_t)32 * 1024 : kLdsLimit - 16 * 1024));
+    DevProgram tv{};
+    tv.nrec = H.nactive;
+    tv.kmax = H.kmax;
+    const size_t lds = lds_bytes_for(tv, G, global_vec, *fp64);
+    if (lds > kLdsLimit) return fail(CLIFFT_E_CAPACITY, "active vectors exceed LDS; use the HBM workspace");
+    const uint64_t blocks_needed = G == 256 ? shots : G == 64 ? (shots + 3) / 4 : ((shots + 63) / 64 + 3) / 4;
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, kLdsLimit / std::max<size_t>(lds, 1)));
+    int grid = c.grid > 0 ? c.grid : device_cus() * per_cu;
+    if (global_vec && c.grid <= 0) {
+      const size_t per_block = 2 * (size_t)(G == 256 ? 1 : 4) * vec * amp * (G == 1 ? 64 : 1);
+      const size_t cap = std::max<size_t>(1, kWorkspaceBudget / per_block);
+      if ((size_t)grid > cap) grid = (int)cap;
+    }
+    if ((uint64_t)grid > blocks_needed) grid = (int)std::max<uint64_t>(1, blocks_needed);
+    L->G = G;
+    L->grid = grid;
+    L->lds_bytes = lds;
+    L->global_vec = global_vec;
+    L->spec = false;
+    L->split = true;
+    L->fgrid = fgrid;
+    L->flane = flane;
+    L->G = G;
+    return CLIFFT_OK;
+  }
+  L->split = false;
+  L->fgrid = 0;
+  L->flane = false;
   int G = c.threads_per_shot;
   if (G != 0 && G != 1 && G != 64 && G != 256 && G != kBitSliced)
     return fail(CLIFFT_E_INVALID_ARG, "threads_per_shot must be 0, 1, 64, 256 or -32");
@@ -296,12 +414,72 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
   return CLIFFT_OK;
 }
 
-size_t workspace_bytes(const CompiledProgram& H, const LaunchShape& L, bool fp64) {
-  if (!L.global_vec) return 0;
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Split form: needed-bit rows, then active-outcome rows (bit-packed).
+size_t split_rows_bytes(const CompiledProgram& H, uint64_t shots) {
+  const size_t words = (shots + 63) / 64;
+  return align256((size_t)H.nbits * words * 8) + align256((size_t)H.nactive * words * 8);
+}
+
+// Workspace layout: [split rows][active vectors in HBM]
+size_t workspace_bytes(const CompiledProgram& H, const LaunchShape& L, bool fp64, uint64_t shots) {
+  size_t bytes = L.split ? split_rows_bytes(H, shots) : 0;
+  if (!L.global_vec) return bytes;
   size_t amp = fp64 ? 16 : 8;
   size_t units = (size_t)L.grid * (L.G == 256 ? 1 : 4);
   // two buffers per unit: active measurements collapse from one into the other
-  return 2 * units * ((size_t)1 << H.kmax) * amp * (L.G == 1 ? 64 : 1);
+  return bytes + 2 * units * ((size_t)1 << H.kmax) * amp * (L.G == 1 ? 64 : 1);
+}
+
+// One sampling launch sequence on `s`: the whole-program kernel, or the
+// split form's frame pass, vector pass and record fix-up.
+hipError_t launch_plan(const CompiledProgram& H, const DeviceCopy& dc, const LaunchShape& L, const KArgs& A,
+                       bool fp64, bool trace, hipStream_t s) {
+  if (!L.split) return launch_sample(dc.view, A, L, fp64, trace, s);
+  const uint64_t words = (A.shots + 63) / 64;
+  unsigned char* ws = (unsigned char*)A.workspace;
+  uint64_t* bits = (uint64_t*)ws;
+  uint64_t* mrows = (uint64_t*)(ws + align256((size_t)H.nbits * words * 8));
+  void* vws = ws + split_rows_bytes(H, A.shots);
+  KArgs AF = A;
+  AF.nbits = bits;
+  AF.workspace = nullptr;
+  hipError_t e;
+  if (L.flane) {
+    LaunchShape LF{};
+    LF.G = 1;
+    LF.grid = L.fgrid;
+    LF.lds_bytes = lds_bytes_for(dc.fview, 1, false, fp64);
+    e = launch_sample(dc.fview, AF, LF, fp64, false, s);
+  } else {
+    e = launch_frames(dc.fview, AF, L.fgrid, s);
+  }
+  if (e != hipSuccess) return e;
+  KArgs AV{};
+  AV.shots = A.shots;
+  AV.seed = A.seed;
+  AV.offset = A.offset;
+  AV.meas = H.nactive ? mrows : nullptr;
+  AV.workspace = L.global_vec ? vws : nullptr;
+  AV.nbits = bits;
+  AV.list_cap = A.list_cap;
+  e = launch_vector_pass(dc.vview, AV, L, fp64, s);
+  if (e != hipSuccess) return e;
+  FixupArgs X{};
+  X.meas = A.meas;
+  X.det = A.det;
+  X.obs = A.obs;
+  X.nrec = H.nrec;
+  X.ndet = H.ndet;
+  X.nobs = H.nobs;
+  X.rows = dc.xrows;
+  X.nrows = dc.nxrows;
+  X.xdep_off = dc.xdep_off;
+  X.xdep = dc.xdep;
+  X.mrows = mrows;
+  X.words = words;
+  return launch_fixup(X, s);
 }
 
 clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t offset,
@@ -311,13 +489,14 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
   if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
   if (shots == 0) return CLIFFT_OK;
   const DevProgram* D = nullptr;
-  clifft_status st = ensure_device(p, &D);
+  const DeviceCopy* DC = nullptr;
+  clifft_status st = ensure_device(p, &D, &DC);
   if (st != CLIFFT_OK) return st;
   LaunchShape L{};
   bool fp64 = false;
   st = choose_shape(p->host, D, cfg, shots, &L, &fp64, &p->tuned, trace);
   if (st != CLIFFT_OK) return st;
-  size_t need = workspace_bytes(p->host, L, fp64);
+  size_t need = workspace_bytes(p->host, L, fp64, shots);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) {
     char buf[128];
     snprintf(buf, sizeof buf, "workspace of %zu bytes needed", need);
@@ -352,7 +531,7 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
     if (st != CLIFFT_OK) return st;
     e = launch_spec(fn, *D, A, L.grid, s);
   } else {
-    e = launch_sample(*D, A, L, fp64, trace, s);
+    e = launch_plan(p->host, *DC, L, A, fp64, trace, s);
   }
   if (e != hipSuccess) {
     if (dflag) (void)hipFree(dflag);
@@ -492,6 +671,7 @@ clifft_status clifft_resolve_launch(const clifft_program* p, const clifft_launch
   out->grid = L.grid;
   out->vector_in_hbm = L.global_vec ? 1 : -1;
   out->specialize = L.G == kBitSliced ? (L.spec ? 1 : -1) : 0;
+  out->split = L.split ? (L.flane ? 3 : 2) : (p->host.split_ok ? -1 : 0);
   return CLIFFT_OK;
 }
 
@@ -507,13 +687,14 @@ clifft_status clifft_specialize(clifft_program* p, char* log, size_t cap) {
   return st;
 }
 
-clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, size_t* bytes) {
+clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch* cfg, uint64_t shots, size_t* bytes) {
   if (!p || !bytes) return fail(CLIFFT_E_INVALID_ARG, "null argument");
   LaunchShape L{};
   bool fp64 = false;
+  // the grid is sized for the largest shot count (so the workspace covers any call)
   clifft_status st = choose_shape(p->host, nullptr, cfg, ~0ull >> 8, &L, &fp64, &p->tuned);
   if (st != CLIFFT_OK) return st;
-  *bytes = workspace_bytes(p->host, L, fp64);
+  *bytes = workspace_bytes(p->host, L, fp64, shots);
   return CLIFFT_OK;
 }
 
@@ -532,6 +713,7 @@ clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uin
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(CLIFFT_E_DEVICE, "no HIP device");
   const DevProgram* D = nullptr;
+  const DeviceCopy* DC = nullptr;
   hipFunction_t spec_fn = nullptr;
   {
     // the program must already be resident: uploading it would allocate
@@ -542,6 +724,7 @@ clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uin
       return fail(CLIFFT_E_INVALID_ARG,
                   "program is not resident on this device (a clifft_sample call on the device uploads it)");
     D = &it->second.view;
+    DC = &it->second;
     spec_fn = it->second.spec_fn;
   }
   LaunchShape L{};
@@ -562,17 +745,19 @@ clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uin
     if (st != CLIFFT_OK) return st;
   }
   void* ws = nullptr;
-  size_t need = workspace_bytes(p->host, L, fp64);
+  size_t need = workspace_bytes(p->host, L, fp64, shots);
   if (need > 0) {
     if (need > kScratchBytes) {
       // keep the workspace inside the fixed scratch: fewer persistent
-      // workgroups (records do not depend on the grid)
-      const size_t per_block = need / (size_t)L.grid;
-      const size_t fit = kScratchBytes / per_block;
+      // workgroups (records do not depend on the grid); the split form's
+      // rows do not shrink with the grid
+      const size_t fixed = L.split ? split_rows_bytes(p->host, shots) : 0;
+      const size_t per_block = L.global_vec ? (need - fixed) / (size_t)L.grid : 0;
+      const size_t fit = per_block && fixed < kScratchBytes ? (kScratchBytes - fixed) / per_block : 0;
       if ((cfg && cfg->grid > 0) || fit == 0) {
         char buf[160];
         snprintf(buf, sizeof buf, "workspace of %zu bytes exceeds the %zu-byte scratch of the allocation-free call",
-                 cfg && cfg->grid > 0 ? need : per_block, kScratchBytes);
+                 need, kScratchBytes);
         return fail(CLIFFT_E_CAPACITY, buf);
       }
       L.grid = (int)fit;
@@ -590,7 +775,7 @@ clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uin
   A.workspace = ws;
   A.list_cap = 0xFFFFFFFFu;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = L.spec ? launch_spec(spec_fn, *D, A, L.grid, s) : launch_sample(*D, A, L, fp64, false, s);
+  hipError_t e = L.spec ? launch_spec(spec_fn, *D, A, L.grid, s) : launch_plan(p->host, *DC, L, A, fp64, false, s);
   if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return CLIFFT_OK;
 }
@@ -641,7 +826,7 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
     if (c.threads_per_shot == 0) {
       // an autotuned program keeps its tier inside the batch
       auto it = progs[i]->tuned.find({b->device, c.precision});
-      if (it != progs[i]->tuned.end() && it->second.threads_per_shot > 0 &&
+      if (it != progs[i]->tuned.end() && it->second.threads_per_shot > 0 && it->second.split < 1 &&
           (H.kmax <= kLaneMaxK || it->second.threads_per_shot != 1))
         G = it->second.threads_per_shot;
     }
@@ -804,6 +989,44 @@ void clifft_batch_free(clifft_batch* b) {
   delete b;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Autotuner results by program signature (the compiled stream and side
+// tables, the precision, the trial size and the device), so that a program
+// compiled again in the same process is not timed again.
+struct TuneKey {
+  uint64_t sig;
+  int precision;
+  uint64_t trial;
+  int device;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(sig, precision, trial, device) < std::tie(o.sig, o.precision, o.trial, o.device);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, clifft_launch> g_tune_cache;
+
+uint64_t program_signature(const CompiledProgram& H) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a, 64 bit
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; i++) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(&H.nq, sizeof H.nq);
+  mix(H.code.data(), H.code.size() * sizeof(GInstr));
+  mix(H.masks.data(), H.masks.size() * sizeof(uint64_t));
+  mix(H.consts.data(), H.consts.size() * sizeof(double));
+  mix(H.site_p.data(), H.site_p.size() * sizeof(double));
+  mix(H.site_type.data(), H.site_type.size());
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
 clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precision, void* stream, clifft_launch* out) {
   if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
   if (precision != CLIFFT_FP32 && precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
@@ -814,23 +1037,44 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
   // best grid depends on the number of 2048-shot tiles)
   uint64_t trial = H.kmax == 0 ? ((uint64_t)1 << 24) : H.kmax <= 12 ? ((uint64_t)1 << 18) : (uint64_t)cus * 8;
   if (shots > 0 && shots < trial) trial = shots;
-  std::vector<clifft_launch> cands;
-  const int mult[4] = {1, 2, 4, 8};
-  if (H.kmax == 0) {
-    for (int m : {1, 2, 4, 5, 8, 16}) cands.push_back(clifft_launch{precision, kBitSliced, cus * m, 0, -1});
-    if (spec_supported(H, nullptr) && ensure_spec(p) == CLIFFT_OK)
-      for (int m : {4, 8, 12, 16, 24, 32}) cands.push_back(clifft_launch{precision, kBitSliced, cus * m, 0, 1});
-  }
-  for (int G : {1, 64, 256}) {
-    if (H.kmax == 0 && G != 1) continue;
-    for (int hbm : {-1, 1}) {
-      if (H.kmax == 0 && hbm == 1) continue;
-      if (G == 1 && H.kmax > kLaneMaxK) continue;
-      for (int m : mult) cands.push_back(clifft_launch{precision, G, cus * m, H.kmax == 0 ? 0 : hbm});
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const TuneKey key{program_signature(H), precision, trial, dev};
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      std::lock_guard<std::mutex> lock2(p->mu);
+      p->tuned[{dev, precision}] = it->second;
+      if (out) *out = it->second;
+      return CLIFFT_OK;
     }
   }
+  // Stage 1: every tier at its default grid.  Stage 2: grids from one to
+  // eight workgroups per CU for the two fastest tiers.
+  std::vector<clifft_launch> tiers;
+  if (H.kmax == 0) {
+    tiers.push_back(clifft_launch{precision, kBitSliced, 0, 0, -1, 0});
+    if (spec_supported(H, nullptr) && ensure_spec(p) == CLIFFT_OK)
+      tiers.push_back(clifft_launch{precision, kBitSliced, 0, 0, 1, 0});
+    tiers.push_back(clifft_launch{precision, 1, 0, 0, 0, -1});
+  } else {
+    for (int G : {1, 64, 256}) {
+      if (G == 1 && H.kmax > kLaneMaxK) continue;
+      if (G == 64 && H.kmax < 7) continue;
+      if (G == 256 && H.kmax < 11) continue;
+      for (int hbm : {-1, 1}) tiers.push_back(clifft_launch{precision, G, 0, hbm, 0, -1});
+    }
+    // split form: frame pass bit-sliced (2) or shot per lane (3), vector
+    // pass shot per lane (the shot-granular vector passes are latency bound
+    // without frame work to hide it)
+    if (H.split_ok && H.kmax <= kLaneMaxK)
+      for (int fp : {2, 3})
+        for (int hbm : {-1, 1}) tiers.push_back(clifft_launch{precision, 1, 0, hbm, 0, fp});
+  }
   const DevProgram* D = nullptr;
-  clifft_status st = ensure_device(p, &D);
+  const DeviceCopy* DC = nullptr;
+  clifft_status st = ensure_device(p, &D, &DC);
   if (st != CLIFFT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const uint64_t words = (trial + 63) / 64;
@@ -841,17 +1085,17 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
   if (e == hipSuccess) e = hipMalloc((void**)&obs, (H.nobs + 1) * words * 8);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  float best_ms = 1e30f;
-  clifft_launch best{};
-  bool found = false;
-  for (const clifft_launch& c : cands) {
-    if (e != hipSuccess) break;
+  // time one candidate (the faster of two launches); < 0 when it does not fit
+  auto time_one = [&](const clifft_launch& c, clifft_launch* resolved) -> float {
     LaunchShape L{};
     bool fp64 = false;
-    if (choose_shape(H, D, &c, trial, &L, &fp64) != CLIFFT_OK) continue;
-    size_t wsb = workspace_bytes(H, L, fp64);
+    if (e != hipSuccess || choose_shape(H, D, &c, trial, &L, &fp64) != CLIFFT_OK) return -1.0f;
+    size_t wsb = workspace_bytes(H, L, fp64, trial);
     void* ws = nullptr;
-    if (wsb && hipMalloc(&ws, wsb) != hipSuccess) { (void)hipGetLastError(); continue; }
+    if (wsb && hipMalloc(&ws, wsb) != hipSuccess) {
+      (void)hipGetLastError();
+      return -1.0f;
+    }
     KArgs A{};
     A.shots = trial;
     A.seed = 0;
@@ -859,26 +1103,49 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
     A.det = det;
     A.obs = obs;
     A.workspace = ws;
+    A.list_cap = 0xFFFFFFFFu;
     hipFunction_t fn = nullptr;
     if (L.spec && spec_function(p, &fn) != CLIFFT_OK) {
       if (ws) (void)hipFree(ws);
-      continue;
+      return -1.0f;
     }
-    float ms = 0;
+    float best = 1e30f;
     for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
+      float ms = 0;
       e = hipEventRecord(e0, s);
-      if (e == hipSuccess) e = L.spec ? launch_spec(fn, *D, A, L.grid, s) : launch_sample(*D, A, L, fp64, false, s);
+      if (e == hipSuccess) e = L.spec ? launch_spec(fn, *D, A, L.grid, s) : launch_plan(H, *DC, L, A, fp64, false, s);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, ms);
     }
     if (ws) (void)hipFree(ws);
-    if (e == hipSuccess && ms < best_ms) {
-      best_ms = ms;
-      best = clifft_launch{precision, L.G, L.grid, L.global_vec ? 1 : -1, L.G == kBitSliced ? (L.spec ? 1 : -1) : 0};
-      found = true;
-    }
+    *resolved = clifft_launch{precision, L.G, L.grid, L.global_vec ? 1 : -1,
+                              L.G == kBitSliced ? (L.spec ? 1 : -1) : 0,
+                              L.split ? (L.flane ? 3 : 2) : (H.split_ok ? -1 : 0)};
+    return e == hipSuccess ? best : -1.0f;
+  };
+  std::vector<std::pair<float, clifft_launch>> ranked;  // (ms, tier as requested)
+  float best_ms = 1e30f;
+  clifft_launch best{};
+  bool found = false;
+  for (const clifft_launch& c : tiers) {
+    clifft_launch r{};
+    const float ms = time_one(c, &r);
+    if (ms < 0) continue;
+    ranked.push_back({ms, c});
+    if (ms < best_ms) { best_ms = ms; best = r; found = true; }
   }
+  std::sort(ranked.begin(), ranked.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  const std::vector<int> mults = H.kmax == 0 ? std::vector<int>{1, 2, 4, 5, 8, 16} : std::vector<int>{1, 2, 4, 8};
+  for (size_t t = 0; t < ranked.size() && t < 2 && e == hipSuccess; t++)
+    for (int m : mults) {
+      clifft_launch c = ranked[t].second;
+      c.grid = cus * (c.specialize == 1 ? 2 * m : m);
+      clifft_launch r{};
+      const float ms = time_one(c, &r);
+      if (ms >= 0 && ms < best_ms) { best_ms = ms; best = r; found = true; }
+    }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (meas) (void)hipFree(meas);
@@ -886,11 +1153,13 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
   if (obs) (void)hipFree(obs);
   if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("autotune failed: ") + hipGetErrorString(e));
   if (!found) return fail(CLIFFT_E_CAPACITY, "no launch shape fits this program");
-  int dev = 0;
-  (void)hipGetDevice(&dev);
   {
     std::lock_guard<std::mutex> lock(p->mu);
     p->tuned[{dev, precision}] = best;
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = best;
   }
   if (out) *out = best;
   return CLIFFT_OK;

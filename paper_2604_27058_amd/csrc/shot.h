@@ -447,7 +447,7 @@ DEV int fault_phase(const DevProgram& P, const Words<W>& fx, uint32_t site, uint
 // OOP: active vectors in HBM with a second buffer of the same size; active
 // measurements collapse out of place (alternating buffers) and read through
 // their folded localization passes.
-template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OOP = false>
+template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OOP = false, bool VONLY = false>
 struct Shot {
   const DevProgram& P;
   const KArgs& A;
@@ -501,8 +501,56 @@ struct Shot {
     }
   }
 
+  // Vector-only stream of the split form: needed bit `row` of this shot
+  // (written by the frame stream with every active outcome 0), corrected by
+  // the parity of its dependency mask with the active outcomes so far.
+  // Shot-granular tiers fetch the first kNbitPre rows of the shot once, one
+  // row per lane, into wave-uniform masks.
+  static constexpr int kNbitPre = 256;
+  uint64_t nbm[kNbitPre / 64];
+  MDEV void fetch_nbits() {
+    if constexpr (G > 1 && VONLY) {
+      const uint64_t words = (A.shots + 63) / 64;
+      const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+      for (int q = 0; q < kNbitPre / 64; q++) {
+        const uint32_t row = (uint32_t)q * 64 + lane;
+        uint32_t b = 0;
+        if (q * 64 < P.nbits && row < (uint32_t)P.nbits && local < A.shots)
+          b = (uint32_t)(A.nbits[(size_t)row * words + (local >> 6)] >> (local & 63)) & 1u;
+        nbm[q] = __ballot(b);
+      }
+    }
+  }
+  MDEV uint32_t raw_nbit(uint32_t row) const {
+    if constexpr (G > 1) {
+      if (row < (uint32_t)kNbitPre) {
+        uint64_t w = nbm[0];
+#pragma unroll
+        for (int q = 1; q < kNbitPre / 64; q++)
+          if ((row >> 6) == (uint32_t)q) w = nbm[q];
+        return (uint32_t)(w >> (row & 63)) & 1u;
+      }
+    }
+    const uint64_t words = (A.shots + 63) / 64;
+    return (uint32_t)(A.nbits[(size_t)row * words + (local >> 6)] >> (local & 63)) & 1u;
+  }
+  MDEV uint32_t nbit(uint32_t row, const uint64_t (&mb)[kSplitWords]) const {
+    uint32_t b = raw_nbit(row);
+    cptr<uint64_t> dep = as_const(P.vdep) + (size_t)row * P.dep_words;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < kSplitWords; q++)
+      if (q < P.dep_words) acc ^= dep[q] & mb[q];
+    return b ^ ((uint32_t)__popcll(acc) & 1u);
+  }
+
   __device__ void run() {
     Frame<W> T, N;
+    uint64_t mb[kSplitWords];  // vector-only stream: active outcomes so far (bit = active index)
+#pragma unroll
+    for (int q = 0; q < kSplitWords; q++) mb[q] = 0;
+    if constexpr (VONLY) fetch_nbits();
 #pragma unroll
     for (int w = 0; w < W; w++) { T.x[w] = T.z[w] = N.x[w] = N.z[w] = 0; }
     const uint64_t seed = A.seed;
@@ -748,10 +796,11 @@ struct Shot {
             R rr = (R)1, ri = (R)0;
             if (rot) {
               double c2 = P.consts[4 * nx.a], s2 = P.consts[4 * nx.a + 1];
-              if (getbit<W>(T.x, nx.v)) s2 = -s2;
+              const bool flip = VONLY ? nbit(nx.v, mb) != 0 : getbit<W>(T.x, nx.v) != 0;
+              if (flip) s2 = -s2;
               rr = (R)c2;
               ri = (R)s2;
-              g_rot(nx.a, getbit<W>(T.x, nx.v) != 0);
+              g_rot(nx.a, flip);
             }
             const uint32_t tm = pend_tm, sm = pend_sm;
             const bool fas = pend_as;
@@ -808,12 +857,18 @@ struct Shot {
           // then exp(-i theta' Z_v) on the new axis, theta' sign-flipped by
           // x_v of the frame.  The common phase e^{-i theta'} is global, so
           // the new half is the old one times e^{2 i theta'}.
-          g_h(v);
-          frame_h<W>(T, v);
-          frame_h<W>(N, v);
+          bool flip;
+          if constexpr (VONLY) {
+            flip = nbit(v, mb) != 0;
+          } else {
+            g_h(v);
+            frame_h<W>(T, v);
+            frame_h<W>(N, v);
+            flip = getbit<W>(T.x, v) != 0;
+          }
           double c2 = P.consts[4 * in.a], s2 = P.consts[4 * in.a + 1];
-          if (getbit<W>(T.x, v)) s2 = -s2;
-          g_rot(in.a, getbit<W>(T.x, v) != 0);
+          if (flip) s2 = -s2;
+          g_rot(in.a, flip);
           g_nexp++;
           const R cr = (R)c2, ci = (R)s2;
           if constexpr (OOP) {
@@ -850,8 +905,9 @@ struct Shot {
           carry_valid = false;
           materialize();
           double c2 = P.consts[4 * in.a], s2 = P.consts[4 * in.a + 1];
-          if (getbit<W>(T.x, v)) s2 = -s2;
-          g_rot(in.a, getbit<W>(T.x, v) != 0);
+          const bool flip = VONLY ? nbit(v, mb) != 0 : getbit<W>(T.x, v) != 0;
+          if (flip) s2 = -s2;
+          g_rot(in.a, flip);
           const R cr = (R)c2, ci = (R)s2;
           const uint32_t bs = 1u << s;
           pass1<G, R, U>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
@@ -913,8 +969,14 @@ struct Shot {
           const bool isx = in.op == OP_MACTX;
           uint32_t j = in.b;
           uint32_t sign = in.flags & F_SIGN;
-          uint32_t p = isx ? getbit<W>(T.z, v) : getbit<W>(T.x, v);
-          uint32_t pn = isx ? getbit<W>(N.z, v) : getbit<W>(N.x, v);
+          uint32_t p, pn;
+          if constexpr (VONLY) {
+            p = nbit(v, mb);
+            pn = raw_nbit(v + 1);
+          } else {
+            p = isx ? getbit<W>(T.z, v) : getbit<W>(T.x, v);
+            pn = isx ? getbit<W>(N.z, v) : getbit<W>(N.x, v);
+          }
           const uint32_t bs = 1u << s;
           const uint32_t half = 1u << (k - 1);
           // branch sums (Appendix B.2): |a|^2 per half along the axis, or
@@ -1317,9 +1379,13 @@ struct Shot {
           k--;
           grp.sync();
           g_nexp = 0;  // the kept branch is normalised
-          if (isx) { g_h(v); frame_h<W>(T, v); frame_h<W>(N, v); }
-          if constexpr (DBG) g_ipow += 2 * (int)(b & getbit<W>(T.z, v));
-          xorbit<W>(T.x, v, b);
+          if constexpr (VONLY) {
+            mb[in.a >> 6] |= (uint64_t)mm << (in.a & 63);
+          } else {
+            if (isx) { g_h(v); frame_h<W>(T, v); frame_h<W>(N, v); }
+            if constexpr (DBG) g_ipow += 2 * (int)(b & getbit<W>(T.z, v));
+            xorbit<W>(T.x, v, b);
+          }
           last_m = mm;
           last_pn = pn;
           int r = as_const(P.ev_rec)[j];
@@ -1389,6 +1455,39 @@ struct Shot {
           put((uint32_t)P.nrec + in.b, d);
           break;
         }
+        case OP_EMIT:
+        case OP_MACTF: {
+          // frame-only stream of the split form on the shot-per-lane tier
+          // (frames too wide for the bit-sliced kernel's LDS rows)
+          if constexpr (G == 1 && !VEC) {
+            const uint64_t words = (A.shots + 63) / 64;
+            const uint32_t lane = threadIdx.x & 63;
+            uint64_t* row = A.nbits + (size_t)in.u * words + (local >> 6);
+            if (in.op == OP_EMIT) {
+              const uint64_t wb = __ballot(getbit<W>(T.x, v));
+              if (lane == 0) row[0] = wb;
+              break;
+            }
+            const bool isx = (in.flags & F_XMEAS) != 0;
+            const uint32_t p = isx ? getbit<W>(T.z, v) : getbit<W>(T.x, v);
+            const uint32_t pn = isx ? getbit<W>(N.z, v) : getbit<W>(N.x, v);
+            const uint64_t wp = __ballot(p), wn = __ballot(pn);
+            if (lane == 0) {
+              row[0] = wp;
+              row[words] = wn;
+            }
+            if (isx) {
+              frame_h<W>(T, v);
+              frame_h<W>(N, v);
+            }
+            xorbit<W>(T.x, v, getbit<W>(T.x, v) ^ (uint32_t)(in.flags & F_SIGN));  // x_v = sign
+            last_m = 0;
+            last_pn = pn;
+            const int r = as_const(P.ev_rec)[in.b];
+            if (r >= 0) put((uint32_t)r, 0u);
+          }
+          break;
+        }
         case OP_OBS: {
           uint32_t d = xor_refs(in.a, in.u);
           uint32_t r = (uint32_t)P.nrec + (uint32_t)P.ndet + in.b;
@@ -1438,7 +1537,7 @@ struct Shot {
 // ------------------------------------------------------------------ kernel
 // One persistent launch: units (lanes-of-a-wave for G = 1, waves for G = 64,
 // workgroups for G = 256) take 64-shot tiles round-robin.
-template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC>
+template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false>
 __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int units_per_block = G == 256 ? 1 : 4;
@@ -1479,7 +1578,7 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
       for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += G) rec[r] = 0;
       unit_sync();
       uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0,
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0,
                                                                   A.offset + g, g, alt};
       sh.run();
       unit_sync();
@@ -1502,14 +1601,14 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if constexpr (G == 1) {
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
                                                                   A.offset + tile * 64 + lane, tile * 64 + lane, alt};
       sh.run();
     } else {
       uint32_t nsh = (uint32_t)min((uint64_t)64, A.shots - tile * 64);
       for (uint32_t sl = 0; sl < nsh; sl++) {
         uint64_t g = rfl((uint32_t)(tile * 64 + sl)) | ((tile * 64 + sl) & 0xFFFFFFFF00000000ull);
-        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red,
+        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red,
                                                                     (int)sl, A.offset + g, g, alt};
         sh.run();
       }
@@ -1535,17 +1634,32 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
 }
 
 // ------------------------------------------------------------------ dispatch table
-template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC>
+template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false>
 inline hipError_t launch_one(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
   static bool attr = false;  // allow the whole 160 KB of LDS for dynamic use
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG, VEC>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG, VEC>), dim3(grid), dim3(256), lds, st, P, A);
+  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY>), dim3(grid), dim3(256), lds, st, P, A);
   return hipGetLastError();
+}
+
+// The vector-only stream of the split form (no frames: W = 1).
+template <typename R>
+inline hipError_t launch_vonly(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t st) {
+  if (L.G == 1) {
+    if (L.global_vec) return launch_one<1, 1, R, true, false, true, true>(P, A, L.grid, L.lds_bytes, st);
+    return launch_one<1, 1, R, false, false, true, true>(P, A, L.grid, L.lds_bytes, st);
+  }
+  if (L.G == 64) {
+    if (L.global_vec) return launch_one<1, 64, R, true, false, true, true>(P, A, L.grid, L.lds_bytes, st);
+    return launch_one<1, 64, R, false, false, true, true>(P, A, L.grid, L.lds_bytes, st);
+  }
+  if (L.global_vec) return launch_one<1, 256, R, true, false, true, true>(P, A, L.grid, L.lds_bytes, st);
+  return launch_one<1, 256, R, false, false, true, true>(P, A, L.grid, L.lds_bytes, st);
 }
 
 template <int G, typename R, bool GLOBAL, bool DBG, bool VEC = true>

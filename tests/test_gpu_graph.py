@@ -73,7 +73,7 @@ def test_sample_graph_replay(name, make, launch, shots):
     p = pk.Program(make())
     L = pk.make_launch(**launch)
     outs = tuple(o.fill_(-1) for o in p.alloc_outputs(shots))
-    ws = p.alloc_workspace(L)
+    ws = p.alloc_workspace(L, shots=shots)
     p.sample(shots, seed=9, launch=L, outputs=outs, workspace=ws)
     torch.cuda.synchronize()
     ref = snapshot(outs)
