@@ -112,7 +112,9 @@ typedef struct clifft_compile_opts {
                           reorder (measurements earlier, non-Clifford
                           rotations later, across operations they commute
                           with).  0: none, so that k(t) is that of the
-                          operations as written */
+                          operations as written.  4: lower through the
+                          Heisenberg representation without optimizing it
+                          (the same program as 0; for testing) */
   int32_t k_limit;     /* E_CAPACITY if the peak active dimension exceeds this
                           (0: the format limit, 30) */
   int32_t drop_phases; /* 1: leave out the instructions whose only effect is a

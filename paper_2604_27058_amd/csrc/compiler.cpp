@@ -432,9 +432,20 @@ struct Compiler {
     return false;
   }
 
-  // Appendix B.1: rotation exp(-i theta Z_q).
-  void rotation(int q, double theta) {
-    Pauli g = iz[q];
+  // U_C^dagger P U_C for a Pauli P given in the basis the images refer to
+  // (the product of its letters' images; letters of different qubits commute).
+  Pauli map(const Pauli& p) const {
+    Pauli r(W);
+    r.r = p.r;
+    for (int q = 0; q < n; q++) {
+      const bool x = p.getx(q), z = p.getz(q);
+      if (x || z) mul_into(r, image(q, x && z ? 'Y' : x ? 'X' : 'Z'), 0);
+    }
+    return r;
+  }
+
+  // Appendix B.1: rotation exp(-i theta g) about the virtual generator g.
+  void rotation(Pauli g, double theta) {
     int vd = lowest(g.x, false);
     int va = lowest(g.x, true);
     if (vd >= 0) {
@@ -477,20 +488,25 @@ struct Compiler {
     k--;
   }
 
-  // Appendix B.2: measurement of `letter` on physical qubit q.
-  int measure(int q, char letter, int rec) {
-    Pauli g = image(q, letter);
-    int j = out->nevents++;
-    out->ev_rec.push_back(rec);
+  // Appendix B.2: measurement of the virtual observable g as event j (the
+  // next ordinal when j < 0), recorded as record `rec` (-1: not recorded).
+  int measure(Pauli g, int rec, int j = -1) {
+    if (j < 0) j = out->nevents;
+    out->nevents = std::max(out->nevents, j + 1);
+    if ((int)out->ev_rec.size() <= j) {
+      out->ev_rec.resize(j + 1, -1);
+      out->ev_class.resize(j + 1, 0);
+    }
+    out->ev_rec[j] = rec;
     bool anyx = nonzero(g.x);
     int xd = lowest(g.x, false);
     if (!anyx && lowest(g.z, true) < 0) {
-      out->ev_class.push_back(0);
+      out->ev_class[j] = 0;
       emit(OP_MSTATIC, g.r ? F_SIGN : 0, 0, 0, push_mask(g.z), (uint32_t)j);
     } else if (xd >= 0) {
       localize_case1(g, xd);
       virt(V_H, xd, -1);  // H_v absorbed after the outcome
-      out->ev_class.push_back(1);
+      out->ev_class[j] = 1;
       emit(OP_MRANDOM, g.r ? F_SIGN : 0, xd, 0, 0, (uint32_t)j);
     } else {
       int v;
@@ -506,30 +522,32 @@ struct Compiler {
         op = OP_MACTZ;
       }
       int s = slot_of[v];
-      out->ev_class.push_back(2);
+      out->ev_class[j] = 2;
       demote(v);
       emit(op, g.r ? F_SIGN : 0, v, s, 0, (uint32_t)j);
     }
     return j;
   }
 
-  void reset_fix(int q, int j) {
-    Pauli xq = image(q, 'X');
+  // reset correction X^m of event j; xq is the virtual image of X on the qubit
+  void reset_fix(const Pauli& xq, int j) {
     emit(OP_CPAULI, xq.r ? F_SIGN : 0, 0, 0, push_pauli(xq), (uint32_t)j);
   }
 
-  void noise(const PhysOp& o) {
+  // noise site: img holds the virtual images of X and Z on its qubit (and
+  // on its second qubit for DEPOLARIZE2)
+  void noise(const PhysOp& o, const Pauli* img) {
     uint32_t site = (uint32_t)out->site_type.size();
     out->site_type.push_back((uint8_t)o.ntype);
     out->site_p.push_back(o.arg);
     out->site_img.push_back((uint32_t)out->masks.size());
-    push_pauli(ix[o.a]);
-    push_pauli(iz[o.a]);
-    uint8_t sg = (uint8_t)(ix[o.a].r | (iz[o.a].r << 1));
+    push_pauli(img[0]);
+    push_pauli(img[1]);
+    uint8_t sg = (uint8_t)(img[0].r | (img[1].r << 1));
     if (o.ntype == S_DEP2) {
-      push_pauli(ix[o.b]);
-      push_pauli(iz[o.b]);
-      sg |= (uint8_t)((ix[o.b].r << 2) | (iz[o.b].r << 3));
+      push_pauli(img[2]);
+      push_pauli(img[3]);
+      sg |= (uint8_t)((img[2].r << 2) | (img[3].r << 3));
     }
     out->site_sign.push_back(sg);
     if (!out->code.empty() && out->code.back().op == OP_NOISE && out->code.back().b == site) {
@@ -539,6 +557,139 @@ struct Compiler {
     }
   }
 };
+
+// ---------------------------------------------------------------- Heisenberg representation
+// A node of the Heisenberg intermediate representation (Section 3.1): an
+// active operation whose generator is mapped through the physical Cliffords
+// only (the virtual basis before any localization), in program order.
+struct HNode {
+  enum Kind { ROT, MEAS, NOISE, CPAULI, DET, OBS } kind;
+  Pauli g;          // ROT: exp(-i theta g); MEAS: the measured observable;
+                    // CPAULI: image of X on the reset qubit
+  double theta = 0;
+  int event = -1;   // MEAS, CPAULI: measurement event ordinal
+  int rec = -1;     // MEAS: record index or -1
+  const PhysOp* op = nullptr;  // NOISE, DET, OBS: the parsed operation
+  Pauli img[4];     // NOISE: images of X, Z on its qubits
+};
+
+static bool commutes(const Pauli& a, const Pauli& b) {
+  int par = 0;
+  for (size_t w = 0; w < a.x.size(); w++)
+    par ^= __builtin_popcountll((a.x[w] & b.z[w]) ^ (a.z[w] & b.x[w])) & 1;
+  return par == 0;
+}
+
+static bool same_axis(const Pauli& a, const Pauli& b) { return a.x == b.x && a.z == b.z; }
+
+// every fault outcome of a noise node commutes with g
+static bool noise_commutes(const HNode& n, const Pauli& g) {
+  const int t = n.op->ntype, nq = t == S_DEP2 ? 2 : 1;
+  for (int q = 0; q < nq; q++) {
+    const bool cx = commutes(n.img[2 * q], g), cz = commutes(n.img[2 * q + 1], g);
+    if (t == S_XERR && !cx) return false;
+    if (t == S_ZERR && !cz) return false;
+    if (t == S_YERR && cx != cz) return false;
+    if ((t == S_DEP1 || t == S_DEP2) && !(cx && cz)) return false;
+  }
+  return true;
+}
+
+// whether node n commutes with the operator exp(-i theta g) or a measurement of g
+static bool node_commutes(const HNode& n, const Pauli& g) {
+  switch (n.kind) {
+    case HNode::ROT: case HNode::MEAS: case HNode::CPAULI: return commutes(n.g, g);
+    case HNode::NOISE: return noise_commutes(n, g);
+    default: return true;  // detectors and observables are classical
+  }
+}
+
+// q <- C^dagger q C for the Clifford C = exp(-i c pi/4 g)
+static void conj_clifford(Pauli& q, const Pauli& g, int c) {
+  c &= 3;
+  if (c == 0 || commutes(q, g)) return;
+  if (c == 2) { q.r ^= 1; return; }  // exp(-i pi/2 g) = -i g
+  Pauli t = g;
+  mul_into(t, q, c == 1 ? 1 : 3);    // +i g q (c = 1), -i g q (c = 3)
+  q = t;
+}
+
+// Middle end (Section 3.1), peephole pass: rotations about one generator
+// that meet through operations commuting with it are fused into one; the
+// Clifford part of every rotation (the multiple of pi/4 nearest its angle,
+// so that the rest lies in (-pi/8, pi/8]) is absorbed into the frame, that
+// is, conjugated into every later generator, and a rotation left with angle
+// 0 disappears (inverse pairs cancel).
+static void hir_peephole(std::vector<HNode>& h) {
+  const double q4 = M_PI / 4;
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (size_t i = 0; i < h.size(); i++) {
+      if (h[i].kind != HNode::ROT) continue;
+      for (size_t j = i + 1; j < h.size();) {
+        if (h[j].kind == HNode::ROT && same_axis(h[j].g, h[i].g)) {
+          h[i].theta += h[j].g.r == h[i].g.r ? h[j].theta : -h[j].theta;
+          h.erase(h.begin() + (long)j);
+          changed = true;
+          continue;
+        }
+        if (!node_commutes(h[j], h[i].g)) break;
+        j++;
+      }
+    }
+    for (size_t i = 0; i < h.size();) {
+      if (h[i].kind != HNode::ROT) { i++; continue; }
+      // the multiple of pi/4 nearest the angle, ties towards 0 (|rest| <= pi/8)
+      const double th = h[i].theta;
+      const long cl = (th >= 0 ? 1 : -1) * (long)std::ceil((std::fabs(th) - M_PI / 8) / q4 - 1e-9);
+      const double rest = th - (double)cl * q4;
+      const int c = (int)(((cl % 4) + 4) % 4);
+      const Pauli g = h[i].g;
+      const bool drop = std::fabs(rest) < 1e-12;
+      if (c != 0) {
+        for (size_t j = i + 1; j < h.size(); j++) {
+          conj_clifford(h[j].g, g, c);
+          if (h[j].kind == HNode::NOISE)
+            for (int k = 0; k < (h[j].op->ntype == S_DEP2 ? 4 : 2); k++) conj_clifford(h[j].img[k], g, c);
+        }
+        changed = true;
+      }
+      if (drop) {
+        h.erase(h.begin() + (long)i);
+        changed = true;
+        continue;
+      }
+      h[i].theta = rest;
+      i++;
+    }
+  }
+}
+
+// Middle end, commuting reorder: each measurement (with its reset
+// correction, if it has one), taken once in program order, moves earlier past
+// every rotation, noise site, measurement and detector that commutes with it
+// (with both, for a reset), so that measurements come before the
+// non-Clifford rotations they commute with.  A measurement keeps its event
+// ordinal (its random draws) and its record index wherever it lands.
+static void hir_reorder(std::vector<HNode>& h) {
+  std::vector<int> order;  // events in program order
+  for (const HNode& n : h)
+    if (n.kind == HNode::MEAS) order.push_back(n.event);
+  for (int ev : order) {
+    size_t j = 0;
+    while (!(h[j].kind == HNode::MEAS && h[j].event == ev)) j++;
+    const bool reset = j + 1 < h.size() && h[j + 1].kind == HNode::CPAULI && h[j + 1].event == ev;
+    const size_t len = reset ? 2 : 1;
+    while (j > 0) {
+      const HNode& p = h[j - 1];
+      if (p.kind == HNode::CPAULI) break;  // a reset's correction stays with its measurement
+      if (!node_commutes(p, h[j].g) || (reset && !node_commutes(p, h[j + 1].g))) break;
+      // a measurement passed over must not be separated from its correction
+      std::rotate(h.begin() + (long)(j - 1), h.begin() + (long)j, h.begin() + (long)(j + len));
+      j--;
+    }
+  }
+}
 
 }  // namespace
 
@@ -934,31 +1085,111 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
   C.drop_phases = opts.drop_phases;
   const int k_limit = opts.k_limit > 0 && opts.k_limit < kMaxK ? opts.k_limit : kMaxK;
   int rec = 0;
-  for (const PhysOp& o : ps.ops) {
-    switch (o.kind) {
-      case K_H: case K_S: case K_SDAG: case K_X: case K_Y: case K_Z: case K_CX: case K_CZ: case K_SWAP:
-        C.phys(o.kind, o.a, o.b);
-        break;
-      case K_ROTZ: C.rotation(o.a, o.arg); break;
-      case K_M: C.measure(o.a, 'Z', rec++); break;
-      case K_MX: C.measure(o.a, 'X', rec++); break;
-      case K_MR: { int j = C.measure(o.a, 'Z', rec++); C.reset_fix(o.a, j); break; }
-      case K_R: { int j = C.measure(o.a, 'Z', -1); C.reset_fix(o.a, j); break; }
-      case K_NOISE: C.noise(o); break;
-      case K_DET:
-      case K_OBS: {
-        uint32_t off = (uint32_t)P.refs.size();
-        for (int r : o.refs) P.refs.push_back((uint32_t)r);
-        if (o.refs.size() > 65535) { err = "too many detector references"; return 3; }
-        uint32_t idx = o.kind == K_DET ? (uint32_t)P.ndet++ : (uint32_t)o.obs;
-        C.emit(o.kind == K_DET ? OP_DET : OP_OBS, 0, 0, 0, off, idx, (int)o.refs.size());
-        break;
+  auto classical = [&](const PhysOp& o) {
+    uint32_t off = (uint32_t)P.refs.size();
+    for (int r : o.refs) P.refs.push_back((uint32_t)r);
+    if (o.refs.size() > 65535) { err = "too many detector references"; return false; }
+    uint32_t idx = o.kind == K_DET ? (uint32_t)P.ndet++ : (uint32_t)o.obs;
+    C.emit(o.kind == K_DET ? OP_DET : OP_OBS, 0, 0, 0, off, idx, (int)o.refs.size());
+    return true;
+  };
+  auto over_limit = [&]() {
+    if (P.kmax <= k_limit) return false;
+    err = k_limit == kMaxK ? "active dimension exceeds the format limit" : "active dimension exceeds k_limit";
+    return true;
+  };
+  if (opts.hir_passes == 0) {
+    // operations as written: Heisenberg mapping and localization in one sweep
+    for (const PhysOp& o : ps.ops) {
+      switch (o.kind) {
+        case K_H: case K_S: case K_SDAG: case K_X: case K_Y: case K_Z: case K_CX: case K_CZ: case K_SWAP:
+          C.phys(o.kind, o.a, o.b);
+          break;
+        case K_ROTZ: C.rotation(C.iz[o.a], o.arg); break;
+        case K_M: C.measure(C.image(o.a, 'Z'), rec++); break;
+        case K_MX: C.measure(C.image(o.a, 'X'), rec++); break;
+        case K_MR: { int j = C.measure(C.image(o.a, 'Z'), rec++); C.reset_fix(C.ix[o.a], j); break; }
+        case K_R: { int j = C.measure(C.image(o.a, 'Z'), -1); C.reset_fix(C.ix[o.a], j); break; }
+        case K_NOISE: {
+          const Pauli img[4] = {C.ix[o.a], C.iz[o.a], o.ntype == S_DEP2 ? C.ix[o.b] : Pauli(), o.ntype == S_DEP2 ? C.iz[o.b] : Pauli()};
+          C.noise(o, img);
+          break;
+        }
+        case K_DET:
+        case K_OBS:
+          if (!classical(o)) return 3;
+          break;
       }
+      if (over_limit()) return 3;
     }
-    if (P.kmax > k_limit) {
-      err = k_limit == kMaxK ? "active dimension exceeds the format limit" : "active dimension exceeds k_limit";
-      return 3;
+  } else {
+    // front end: the Heisenberg representation (physical Cliffords only)
+    Compiler F(n, &P);
+    std::vector<HNode> h;
+    int nev = 0;
+    for (const PhysOp& o : ps.ops) {
+      HNode nd{};
+      switch (o.kind) {
+        case K_H: case K_S: case K_SDAG: case K_X: case K_Y: case K_Z: case K_CX: case K_CZ: case K_SWAP:
+          F.phys(o.kind, o.a, o.b);
+          continue;
+        case K_ROTZ: nd.kind = HNode::ROT; nd.g = F.iz[o.a]; nd.theta = o.arg; break;
+        case K_M: case K_MX: case K_MR: case K_R:
+          nd.kind = HNode::MEAS;
+          nd.g = F.image(o.a, o.kind == K_MX ? 'X' : 'Z');
+          nd.event = nev++;
+          nd.rec = o.kind == K_R ? -1 : rec++;
+          h.push_back(nd);
+          if (o.kind == K_MR || o.kind == K_R) {
+            HNode cp{};
+            cp.kind = HNode::CPAULI;
+            cp.g = F.ix[o.a];
+            cp.event = nd.event;
+            h.push_back(cp);
+          }
+          continue;
+        case K_NOISE:
+          nd.kind = HNode::NOISE;
+          nd.op = &o;
+          nd.g = Pauli(P.W);
+          nd.img[0] = F.ix[o.a];
+          nd.img[1] = F.iz[o.a];
+          if (o.ntype == S_DEP2) { nd.img[2] = F.ix[o.b]; nd.img[3] = F.iz[o.b]; }
+          break;
+        case K_DET: case K_OBS:
+          nd.kind = o.kind == K_DET ? HNode::DET : HNode::OBS;
+          nd.op = &o;
+          nd.g = Pauli(P.W);
+          break;
+      }
+      h.push_back(nd);
     }
+    P.ev_rec.assign(nev, -1);
+    P.ev_class.assign(nev, 0);
+    // middle end
+    if (opts.hir_passes & 1) hir_peephole(h);
+    if (opts.hir_passes & 2) hir_reorder(h);
+    if (opts.hir_passes & 1) hir_peephole(h);
+    // back end: localization of the optimized representation
+    for (const HNode& nd : h) {
+      switch (nd.kind) {
+        case HNode::ROT: C.rotation(C.map(nd.g), nd.theta); break;
+        case HNode::MEAS: C.measure(C.map(nd.g), nd.rec, nd.event); break;
+        case HNode::CPAULI: C.reset_fix(C.map(nd.g), nd.event); break;
+        case HNode::NOISE: {
+          const int m = nd.op->ntype == S_DEP2 ? 4 : 2;
+          Pauli img[4];
+          for (int k = 0; k < m; k++) img[k] = C.map(nd.img[k]);
+          C.noise(*nd.op, img);
+          break;
+        }
+        case HNode::DET: case HNode::OBS:
+          if (!classical(*nd.op)) return 3;
+          break;
+      }
+      if (over_limit()) return 3;
+    }
+    P.nevents = nev;
   }
   C.emit(OP_END, 0, 0, 0, 0, 0);
   P.nrec = rec;

@@ -582,7 +582,7 @@ clifft_status clifft_compile(const char* text, size_t len, const clifft_compile_
   *out = nullptr;
   CompileOptions co;
   if (opts) {
-    if (opts->hir_passes & ~3) return fail(CLIFFT_E_INVALID_ARG, "hir_passes: unknown pass bits");
+    if (opts->hir_passes & ~7) return fail(CLIFFT_E_INVALID_ARG, "hir_passes: unknown pass bits");
     if (opts->k_limit < 0) return fail(CLIFFT_E_INVALID_ARG, "k_limit must be >= 0");
     if (opts->drop_phases != 0 && opts->drop_phases != 1) return fail(CLIFFT_E_INVALID_ARG, "drop_phases must be 0 or 1");
     co.hir_passes = opts->hir_passes;
