@@ -9,10 +9,17 @@
  * sampling, active-vector expansion / rotation / measurement, Appendix B).
  *
  * Conventions used by every entry point:
- *   - Circuit text: a Stim-style subset.  Gates H S S_DAG X Y Z CX (CNOT)
+ *   - Circuit text: a Stim-style subset, extended with non-Clifford
+ *     rotations (Section 3.1, front end).  Gates H S S_DAG X Y Z CX (CNOT)
  *     CZ SWAP; rotations T = exp(-i pi/8 Z), T_DAG = exp(+i pi/8 Z),
- *     R_Z(phi) = exp(-i phi Z / 2); M MX MR R; noise DEPOLARIZE1(p)
- *     DEPOLARIZE2(p) X_ERROR(p) Y_ERROR(p) Z_ERROR(p); DETECTOR rec[-k]...;
+ *     R_Z(phi) = exp(-i phi Z / 2), R_X(phi), R_Y(phi) likewise about X and
+ *     Y, R_PAULI(phi) P... = exp(-i phi P / 2) for Pauli products P written
+ *     X0*Y3*Z5, U3(theta, phi, lambda) (the matrix [[c, -e^{i l} s],
+ *     [e^{i p} s, e^{i (p + l)} c]], c = cos(theta/2), s = sin(theta/2));
+ *     M MX MR R, MPP P... (one record per product, eigenvalue (-1)^m);
+ *     record-controlled Paulis CX / CY / CZ rec[-k] q (a Pauli on q when the
+ *     record is 1; Appendix B.3); noise DEPOLARIZE1(p) DEPOLARIZE2(p)
+ *     X_ERROR(p) Y_ERROR(p) Z_ERROR(p); DETECTOR rec[-k]...;
  *     OBSERVABLE_INCLUDE(i) rec[-k]...; REPEAT n { ... }; TICK and
  *     coordinates are ignored.  At most 256 qubits, k_max <= 30.
  *   - Records are bit-packed and record-major: for a call with `shots`

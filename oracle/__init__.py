@@ -68,7 +68,7 @@ def gap_next(S, cur, u):
 
 
 OP_NAMES = ["VCX", "VCZ", "VS", "VH", "EXPAND", "ROT", "PHASE", "MSTATIC", "MRANDOM", "MACTIVE_Z",
-            "MACTIVE_X", "CPAULI", "NOISE", "DET", "OBS"]
+            "MACTIVE_X", "CPAULI", "NOISE", "DET", "OBS", "CFEED"]
 
 
 class OracleError(RuntimeError):

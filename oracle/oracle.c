@@ -166,7 +166,11 @@ enum {
     P_ROTZ,          /* exp(-i theta Z_q) */
     P_M, P_MX, P_MR, P_R,
     P_NOISE,
-    P_DET, P_OBS
+    P_DET, P_OBS,
+    P_PROT,          /* exp(-i theta P) for a Pauli product P (pq, pl) */
+    P_MPP,           /* measurement of a Pauli product P (pq, pl) */
+    P_CFEED,         /* Pauli pl[0] on qubit a if record refs[0] is 1 */
+    P_GPHASE         /* global phase exp(-i theta) */
 };
 enum { N_DEP1, N_DEP2, N_XERR, N_YERR, N_ZERR };
 
@@ -176,8 +180,11 @@ typedef struct {
     double arg;     /* rotation angle theta, or noise probability */
     int ntype;      /* noise type */
     int nref;
-    int *refs;      /* absolute record indices (DET / OBS) */
+    int *refs;      /* absolute record indices (DET / OBS / CFEED) */
     int obs;
+    int np;         /* Pauli product: qubits pq[i] with letters pl[i] ('X', 'Y', 'Z') */
+    int *pq;
+    char *pl;
 } pop;
 
 typedef struct {
@@ -241,15 +248,25 @@ static int parse_instruction(circuit *c, char *line, lexer *L, int depth)
     name[ni] = 0;
     for (int i = 0; name[i]; i++)
         if (name[i] >= 'a' && name[i] <= 'z') name[i] = (char)(name[i] - 'a' + 'A');
-    double arg = 0;
-    int has_arg = 0;
+    double arg = 0, args[3] = {0, 0, 0};
+    int has_arg = 0, nargs = 0;
     while (*p == ' ' || *p == '\t') p++;
     if (*p == '(') {
         char *e = strchr(p, ')');
         if (!e) { snprintf(c->err, sizeof c->err, "line %d: missing ')'", L->line); return -1; }
         *e = 0;
-        arg = strtod(p + 1, NULL);
-        has_arg = 1;
+        char *a = p + 1;
+        while (nargs < 3) {
+            char *end;
+            args[nargs] = strtod(a, &end);
+            if (end == a) break;
+            nargs++;
+            while (*end == ' ' || *end == '\t') end++;
+            if (*end != ',') break;
+            a = end + 1;
+        }
+        arg = args[0];
+        has_arg = nargs > 0;
         p = e + 1;
     }
     if (!strcmp(name, "REPEAT")) {
@@ -273,13 +290,22 @@ static int parse_instruction(circuit *c, char *line, lexer *L, int depth)
     }
     if (!strcmp(name, "TICK") || !strcmp(name, "QUBIT_COORDS") || !strcmp(name, "SHIFT_COORDS")) return 0;
 
-    /* targets */
+    /* targets; a Pauli product target (MPP, R_PAULI) is letters and qubits
+     * joined by '*', as X0*Y3*Z5 */
     int tg[8192];
     int nt = 0;
     int isrec[8192];
+    char *prods[1024];
+    int nprod = 0;
     char *tok = strtok(p, " \t");
     while (tok) {
         if (nt >= 8192) { snprintf(c->err, sizeof c->err, "line %d: too many targets", L->line); return -1; }
+        if ((tok[0] == 'X' || tok[0] == 'Y' || tok[0] == 'Z' || tok[0] == 'x' || tok[0] == 'y' || tok[0] == 'z')) {
+            if (nprod >= 1024) { snprintf(c->err, sizeof c->err, "line %d: too many products", L->line); return -1; }
+            prods[nprod++] = tok;
+            tok = strtok(NULL, " \t");
+            continue;
+        }
         if (!strncmp(tok, "rec[", 4)) {
             tg[nt] = (int)strtol(tok + 4, NULL, 10);
             isrec[nt++] = 1;
@@ -295,6 +321,72 @@ static int parse_instruction(circuit *c, char *line, lexer *L, int depth)
     }
     pop o;
     memset(&o, 0, sizeof o);
+    int is_prod_gate = !strcmp(name, "MPP") || !strcmp(name, "R_PAULI");
+    if (nprod && !is_prod_gate) { snprintf(c->err, sizeof c->err, "line %d: Pauli product target on %s", L->line, name); return -1; }
+    if (is_prod_gate) {
+        /* MPP P...: one measurement per product; R_PAULI(phi) P...:
+         * exp(-i phi P / 2) per product */
+        if (nt) { snprintf(c->err, sizeof c->err, "line %d: %s takes Pauli products", L->line, name); return -1; }
+        if (!strcmp(name, "R_PAULI") && !has_arg) { snprintf(c->err, sizeof c->err, "line %d: R_PAULI needs an angle", L->line); return -1; }
+        for (int k = 0; k < nprod; k++) {
+            pop q;
+            memset(&q, 0, sizeof q);
+            q.kind = !strcmp(name, "MPP") ? P_MPP : P_PROT;
+            q.arg = arg / 2;
+            q.pq = (int *)malloc(sizeof(int) * 256);
+            q.pl = (char *)malloc(256);
+            char *s = prods[k];
+            while (*s) {
+                char letter = (char)(*s >= 'a' ? *s - 'a' + 'A' : *s);
+                if (letter != 'X' && letter != 'Y' && letter != 'Z') { snprintf(c->err, sizeof c->err, "line %d: bad Pauli product", L->line); free(q.pq); free(q.pl); return -1; }
+                char *end;
+                long v = strtol(s + 1, &end, 10);
+                if (end == s + 1 || v < 0 || v >= MAXQ || (*end && *end != '*') || q.np >= 256) { snprintf(c->err, sizeof c->err, "line %d: bad Pauli product", L->line); free(q.pq); free(q.pl); return -1; }
+                for (int i = 0; i < q.np; i++)
+                    if (q.pq[i] == (int)v) { snprintf(c->err, sizeof c->err, "line %d: repeated qubit in a product", L->line); free(q.pq); free(q.pl); return -1; }
+                q.pq[q.np] = (int)v;
+                q.pl[q.np++] = letter;
+                if (v + 1 > c->nq) c->nq = (int)v + 1;
+                s = *end ? end + 1 : end;
+            }
+            if (!q.np) { snprintf(c->err, sizeof c->err, "line %d: empty Pauli product", L->line); free(q.pq); free(q.pl); return -1; }
+            circ_push(c, q);
+            if (q.kind == P_MPP) c->nrec++;
+        }
+        return 0;
+    }
+    /* Pauli X, Y or Z on a qubit controlled by a measurement record
+     * (feed-forward, Appendix B.3): CX rec[-k] q, CY rec[-k] q, CZ rec[-k] q
+     * (CZ also q rec[-k]) */
+    if ((!strcmp(name, "CX") || !strcmp(name, "CNOT") || !strcmp(name, "ZCX") || !strcmp(name, "CY") ||
+         !strcmp(name, "ZCY") || !strcmp(name, "CZ") || !strcmp(name, "ZCZ"))) {
+        int anyrec = 0;
+        for (int i = 0; i < nt; i++) anyrec |= isrec[i];
+        if (anyrec) {
+            char letter = name[strlen(name) - 1] == 'Y' ? 'Y' : (!strcmp(name, "CZ") || !strcmp(name, "ZCZ")) ? 'Z' : 'X';
+            if (nt % 2) { snprintf(c->err, sizeof c->err, "line %d: %s needs target pairs", L->line, name); return -1; }
+            for (int i = 0; i < nt; i += 2) {
+                int r = i, q = i + 1;
+                if (letter == 'Z' && !isrec[i] && isrec[i + 1]) { r = i + 1; q = i; }
+                if (!isrec[r] || isrec[q]) { snprintf(c->err, sizeof c->err, "line %d: feed-forward needs rec[-k] then a qubit", L->line); return -1; }
+                if (tg[r] >= 0 || c->nrec + tg[r] < 0) { snprintf(c->err, sizeof c->err, "line %d: bad rec target", L->line); return -1; }
+                pop q2;
+                memset(&q2, 0, sizeof q2);
+                q2.kind = P_CFEED;
+                q2.a = tg[q];
+                q2.nref = 1;
+                q2.refs = (int *)malloc(sizeof(int));
+                q2.refs[0] = c->nrec + tg[r];
+                q2.np = 1;
+                q2.pq = (int *)malloc(sizeof(int));
+                q2.pl = (char *)malloc(1);
+                q2.pq[0] = tg[q];
+                q2.pl[0] = letter;
+                circ_push(c, q2);
+            }
+            return 0;
+        }
+    }
     struct { const char *nm; int kind; int arity; } gates[] = {
         {"H", P_H, 1}, {"S", P_S, 1}, {"S_DAG", P_SDAG, 1}, {"X", P_X, 1}, {"Y", P_Y, 1}, {"Z", P_Z, 1},
         {"CX", P_CX, 2}, {"CNOT", P_CX, 2}, {"ZCX", P_CX, 2}, {"CZ", P_CZ, 2}, {"SWAP", P_SWAP, 2},
@@ -330,6 +422,47 @@ static int parse_instruction(circuit *c, char *line, lexer *L, int depth)
             o.b = -1;
             o.arg = th;
             circ_push(c, o);
+        }
+        return 0;
+    }
+    /* R_X(phi) = exp(-i phi X / 2), R_Y(phi) = exp(-i phi Y / 2) */
+    if (!strcmp(name, "R_X") || !strcmp(name, "R_Y")) {
+        if (!has_arg) { snprintf(c->err, sizeof c->err, "line %d: %s needs an angle", L->line, name); return -1; }
+        for (int i = 0; i < nt; i++) {
+            pop q;
+            memset(&q, 0, sizeof q);
+            q.kind = P_PROT;
+            q.arg = arg / 2;
+            q.np = 1;
+            q.pq = (int *)malloc(sizeof(int));
+            q.pl = (char *)malloc(1);
+            q.pq[0] = tg[i];
+            q.pl[0] = name[2];
+            circ_push(c, q);
+        }
+        return 0;
+    }
+    /* U3(theta, phi, lambda) = [[cos t, -e^{i l} sin t], [e^{i p} sin t,
+     * e^{i (p + l)} cos t]] with t = theta / 2, which is
+     * e^{i (p + l) / 2} R_Z(phi) R_Y(theta) R_Z(lambda) */
+    if (!strcmp(name, "U3")) {
+        if (nargs != 3) { snprintf(c->err, sizeof c->err, "line %d: U3 needs three angles", L->line); return -1; }
+        for (int i = 0; i < nt; i++) {
+            pop q;
+            memset(&q, 0, sizeof q);
+            q.kind = P_ROTZ; q.a = tg[i]; q.b = -1; q.arg = args[2] / 2;
+            circ_push(c, q);
+            memset(&q, 0, sizeof q);
+            q.kind = P_PROT; q.arg = args[0] / 2; q.np = 1;
+            q.pq = (int *)malloc(sizeof(int)); q.pl = (char *)malloc(1);
+            q.pq[0] = tg[i]; q.pl[0] = 'Y';
+            circ_push(c, q);
+            memset(&q, 0, sizeof q);
+            q.kind = P_ROTZ; q.a = tg[i]; q.b = -1; q.arg = args[1] / 2;
+            circ_push(c, q);
+            memset(&q, 0, sizeof q);
+            q.kind = P_GPHASE; q.arg = -(args[1] + args[2]) / 2;
+            circ_push(c, q);
         }
         return 0;
     }
@@ -407,7 +540,8 @@ enum {
     O_CPAULI,    /* conditional Pauli (reset correction) */
     O_NOISE,     /* stochastic Pauli site */
     O_DET,
-    O_OBS
+    O_OBS,
+    O_CFEED      /* Pauli `mask` if record `rec` is 1 (feed-forward) */
 };
 
 typedef struct {
@@ -620,13 +754,39 @@ static int any(const uint8_t *b, int n)
     return 0;
 }
 
+/* The virtual image U_C^dagger P U_C of a physical Pauli product (the
+ * letters' images multiplied; letters on different qubits commute). */
+static void map_product(compiler *C, int np, const int *pq, const char *pl, pauli *out)
+{
+    int n = C->n;
+    memset(out->x, 0, (size_t)n);
+    memset(out->z, 0, (size_t)n);
+    out->r = 0;
+    pauli t = pauli_new(n);
+    for (int i = 0; i < np; i++) {
+        map_pauli(C, pq[i], pl[i], &t);
+        int e = pauli_mul_into(out, &t, n, 0);
+        out->r = (e / 2) & 1;
+    }
+    pauli_free(&t);
+}
+
+static void compile_rotation_g(compiler *C, pauli g, double theta);
+
 /* Section 2.4 / Appendix B.1: a rotation exp(-i theta P) on physical
  * qubit q with P = Z. */
 static void compile_rotation(compiler *C, int q, double theta)
 {
-    int n = C->n;
-    pauli g = pauli_new(n);
+    pauli g = pauli_new(C->n);
     map_pauli(C, q, 'Z', &g);
+    compile_rotation_g(C, g, theta);
+}
+
+/* The same for any virtual generator g (owned by the call): a rotation
+ * exp(-i theta g). */
+static void compile_rotation_g(compiler *C, pauli g, double theta)
+{
+    int n = C->n;
     int vd = lowest(C, g.x, 0);
     int va = lowest(C, g.x, 1);
     oop o;
@@ -675,14 +835,22 @@ static void compile_rotation(compiler *C, int q, double theta)
     pauli_free(&g);
 }
 
+static int compile_measure_g(compiler *C, pauli g, int rec);
+
 /* Section 2.4 / Appendix B.2: a projective measurement of the physical
  * Pauli `letter` on qubit q.  Returns the measurement event ordinal. */
 static int compile_measure(compiler *C, int q, char letter, int rec)
 {
+    pauli g = pauli_new(C->n);
+    map_pauli(C, q, letter, &g);
+    return compile_measure_g(C, g, rec);
+}
+
+/* The same for any virtual observable g (owned by the call). */
+static int compile_measure_g(compiler *C, pauli g, int rec)
+{
     int n = C->n;
     program *P = C->P;
-    pauli g = pauli_new(n);
-    map_pauli(C, q, letter, &g);
     int j = P->nevents++;
     P->event_class = (int *)realloc(P->event_class, sizeof(int) * (size_t)P->nevents);
     P->event_rec = (int *)realloc(P->event_rec, sizeof(int) * (size_t)P->nevents);
@@ -845,6 +1013,33 @@ static program *compile_circuit(circuit *ci)
         case P_MR: { int j = compile_measure(&C, po->a, 'Z', rec++); compile_reset_fix(&C, po->a, j); break; }
         case P_R: { int j = compile_measure(&C, po->a, 'Z', -1); compile_reset_fix(&C, po->a, j); break; }
         case P_NOISE: compile_noise(&C, po); break;
+        case P_PROT: {
+            pauli g = pauli_new(n);
+            map_product(&C, po->np, po->pq, po->pl, &g);
+            compile_rotation_g(&C, g, po->arg);
+            break; }
+        case P_MPP: {
+            pauli g = pauli_new(n);
+            map_product(&C, po->np, po->pq, po->pl, &g);
+            compile_measure_g(&C, g, rec++);
+            break; }
+        case P_CFEED: {
+            oop o;
+            memset(&o, 0, sizeof o);
+            o.kind = O_CFEED;
+            o.rec = po->refs[0];
+            o.mask = pauli_new(n);
+            map_pauli(&C, po->a, po->pl[0], &o.mask);
+            emit(&C, o);
+            break; }
+        case P_GPHASE: {
+            oop o;
+            memset(&o, 0, sizeof o);
+            o.kind = O_PHASE;  /* empty Z string: parity 0 */
+            o.mask = pauli_new(n);
+            o.theta = po->arg;
+            emit(&C, o);
+            break; }
         case P_DET:
         case P_OBS: {
             oop o;
@@ -1306,6 +1501,11 @@ static void run_shot(const program *P, shot_state *S, uint64_t shot, uint64_t se
         case O_NOISE:
             if (faults[o->site] >= 0) apply_fault(S, P, o->site, faults[o->site]);
             break;
+        case O_CFEED:
+            /* feed-forward Pauli (Appendix B.3) on the full frame; the noise
+             * frame only follows physical faults */
+            if (S->rec[o->rec]) S->gamma *= ipow(frame_mul_left(S->tx, S->tz, o->mask.x, o->mask.z, o->mask.r, S->n));
+            break;
         case O_DET: {
             int d = 0;
             for (int r = 0; r < o->nref; r++) d ^= S->rec[o->refs[r]];
@@ -1331,13 +1531,13 @@ int oracle_compile(const char *text, size_t len, void **out, char *err, int errl
     int rc = parse_block(&c, &L, 0);
     if (rc < 0) {
         if (err && errlen > 0) snprintf(err, (size_t)errlen, "%s", c.err);
-        for (int i = 0; i < c.n; i++) free(c.ops[i].refs);
+        for (int i = 0; i < c.n; i++) { free(c.ops[i].refs); free(c.ops[i].pq); free(c.ops[i].pl); }
         free(c.ops);
         *out = NULL;
         return rc == -2 ? 2 : 1;
     }
     program *P = compile_circuit(&c);
-    for (int i = 0; i < c.n; i++) free(c.ops[i].refs);
+    for (int i = 0; i < c.n; i++) { free(c.ops[i].refs); free(c.ops[i].pq); free(c.ops[i].pl); }
     free(c.ops);
     P->ndet = P->ndet; /* counted during compilation */
     *out = P;

@@ -31,15 +31,22 @@ namespace clifft {
 namespace {
 
 // ---------------------------------------------------------------- parsing
-enum PK { K_H, K_S, K_SDAG, K_X, K_Y, K_Z, K_CX, K_CZ, K_SWAP, K_ROTZ, K_M, K_MX, K_MR, K_R, K_NOISE, K_DET, K_OBS };
+enum PK {
+  K_H, K_S, K_SDAG, K_X, K_Y, K_Z, K_CX, K_CZ, K_SWAP, K_ROTZ, K_M, K_MX, K_MR, K_R, K_NOISE, K_DET, K_OBS,
+  K_PROT,    // exp(-i theta P) for the Pauli product `prod`
+  K_MPP,     // measurement of the Pauli product `prod`
+  K_CFEED,   // Pauli prod[0] if record refs[0] is 1 (feed-forward)
+  K_GPHASE   // global phase exp(-i theta)
+};
 
 struct PhysOp {
   int kind;
   int a, b;
-  double arg;  // rotation angle theta of exp(-i theta Z), or probability
+  double arg;  // rotation angle theta of exp(-i theta P), or probability
   int ntype;
   int obs;
   std::vector<int> refs;  // absolute record indices
+  std::vector<std::pair<int, char>> prod;  // Pauli product: (qubit, 'X' / 'Y' / 'Z')
 };
 
 struct Parsed {
@@ -78,16 +85,29 @@ static bool parse_line(const std::string& raw, int line, Parsed& P, std::string&
   while (i < raw.size() && !isspace((unsigned char)raw[i]) && raw[i] != '(') name += (char)toupper((unsigned char)raw[i++]);
   while (i < raw.size() && isspace((unsigned char)raw[i])) i++;
   double arg = 0;
+  std::vector<double> args;
   bool has_arg = false;
   if (i < raw.size() && raw[i] == '(') {
     size_t e = raw.find(')', i);
     if (e == std::string::npos) return fail(err, code, 1, line, "missing ')'");
-    arg = strtod(raw.c_str() + i + 1, nullptr);
-    has_arg = true;
+    const char* a = raw.c_str() + i + 1;
+    const char* stop = raw.c_str() + e;
+    while (a < stop && args.size() < 3) {
+      char* end = nullptr;
+      double v = strtod(a, &end);
+      if (end == a) break;
+      args.push_back(v);
+      while (end < stop && isspace((unsigned char)*end)) end++;
+      if (end >= stop || *end != ',') break;
+      a = end + 1;
+    }
+    has_arg = !args.empty();
+    arg = has_arg ? args[0] : 0.0;
     i = e + 1;
   }
   std::vector<long> tg;
   std::vector<bool> isrec;
+  std::vector<std::vector<std::pair<int, char>>> prods;  // Pauli product targets (X0*Y3*Z5)
   while (i < raw.size()) {
     while (i < raw.size() && isspace((unsigned char)raw[i])) i++;
     if (i >= raw.size()) break;
@@ -95,6 +115,25 @@ static bool parse_line(const std::string& raw, int line, Parsed& P, std::string&
     while (j < raw.size() && !isspace((unsigned char)raw[j])) j++;
     std::string t = raw.substr(i, j - i);
     i = j;
+    if (strchr("XYZxyz", t[0])) {
+      std::vector<std::pair<int, char>> pr;
+      size_t k = 0;
+      while (k < t.size()) {
+        const char letter = (char)toupper((unsigned char)t[k]);
+        if (!strchr("XYZ", letter)) return fail(err, code, 1, line, "bad Pauli product '" + t + "'");
+        char* end = nullptr;
+        long v = strtol(t.c_str() + k + 1, &end, 10);
+        if (end == t.c_str() + k + 1 || v < 0 || v >= 65535 || (*end && *end != '*'))
+          return fail(err, code, 1, line, "bad Pauli product '" + t + "'");
+        for (auto& f : pr)
+          if (f.first == (int)v) return fail(err, code, 1, line, "repeated qubit in a product");
+        pr.push_back({(int)v, letter});
+        if (v + 1 > P.nq) P.nq = (int)v + 1;
+        k = (size_t)(end - t.c_str()) + (*end ? 1 : 0);
+      }
+      prods.push_back(pr);
+      continue;
+    }
     if (t.compare(0, 4, "rec[") == 0) {
       tg.push_back(strtol(t.c_str() + 4, nullptr, 10));
       isrec.push_back(true);
@@ -108,6 +147,73 @@ static bool parse_line(const std::string& raw, int line, Parsed& P, std::string&
     }
   }
   if (name == "TICK" || name == "QUBIT_COORDS" || name == "SHIFT_COORDS") return true;
+  const bool prod_gate = name == "MPP" || name == "R_PAULI";
+  if (!prods.empty() && !prod_gate) return fail(err, code, 1, line, "Pauli product target on " + name);
+  if (prod_gate) {
+    // MPP P...: one measurement per product; R_PAULI(phi) P...: exp(-i phi P / 2)
+    if (!tg.empty()) return fail(err, code, 1, line, name + " takes Pauli products");
+    if (name == "R_PAULI" && !has_arg) return fail(err, code, 1, line, "R_PAULI needs an angle");
+    for (auto& pr : prods) {
+      PhysOp o{};
+      o.kind = name == "MPP" ? K_MPP : K_PROT;
+      o.arg = arg / 2;
+      o.prod = pr;
+      P.ops.push_back(o);
+      if (o.kind == K_MPP) P.nrec++;
+    }
+    return true;
+  }
+  // a Pauli on a qubit controlled by a measurement record (feed-forward):
+  // CX / CY / CZ rec[-k] q (CZ also q rec[-k])
+  if (name == "CX" || name == "CNOT" || name == "ZCX" || name == "CY" || name == "ZCY" || name == "CZ" || name == "ZCZ") {
+    bool anyrec = false;
+    for (bool r : isrec) anyrec = anyrec || r;
+    if (anyrec) {
+      const char letter = (name == "CY" || name == "ZCY") ? 'Y' : (name == "CZ" || name == "ZCZ") ? 'Z' : 'X';
+      if (tg.size() % 2) return fail(err, code, 1, line, name + " needs target pairs");
+      for (size_t t = 0; t < tg.size(); t += 2) {
+        size_t r = t, q = t + 1;
+        if (letter == 'Z' && !isrec[t] && isrec[t + 1]) std::swap(r, q);
+        if (!isrec[r] || isrec[q]) return fail(err, code, 1, line, "feed-forward needs rec[-k] then a qubit");
+        if (tg[r] >= 0 || P.nrec + tg[r] < 0) return fail(err, code, 1, line, "bad record target");
+        PhysOp o{};
+        o.kind = K_CFEED;
+        o.a = (int)tg[q];
+        o.refs.push_back((int)(P.nrec + tg[r]));
+        o.prod.push_back({(int)tg[q], letter});
+        P.ops.push_back(o);
+      }
+      return true;
+    }
+  }
+  if (name == "R_X" || name == "R_Y") {
+    // R_X(phi) = exp(-i phi X / 2), R_Y(phi) = exp(-i phi Y / 2)
+    if (!has_arg) return fail(err, code, 1, line, name + " needs an angle");
+    for (long t : tg) {
+      PhysOp o{};
+      o.kind = K_PROT;
+      o.arg = arg / 2;
+      o.prod.push_back({(int)t, name[2]});
+      P.ops.push_back(o);
+    }
+    return true;
+  }
+  if (name == "U3") {
+    // U3(theta, phi, lambda) = e^{i (phi + lambda) / 2} R_Z(phi) R_Y(theta) R_Z(lambda)
+    if (args.size() != 3) return fail(err, code, 1, line, "U3 needs three angles");
+    for (long t : tg) {
+      PhysOp z1{}, y{}, z2{}, g{};
+      z1.kind = K_ROTZ; z1.a = (int)t; z1.b = -1; z1.arg = args[2] / 2;
+      y.kind = K_PROT; y.arg = args[0] / 2; y.prod.push_back({(int)t, 'Y'});
+      z2.kind = K_ROTZ; z2.a = (int)t; z2.b = -1; z2.arg = args[1] / 2;
+      g.kind = K_GPHASE; g.arg = -(args[1] + args[2]) / 2;
+      P.ops.push_back(z1);
+      P.ops.push_back(y);
+      P.ops.push_back(z2);
+      P.ops.push_back(g);
+    }
+    return true;
+  }
   struct G { const char* nm; int kind, arity; };
   static const G gates[] = {{"H", K_H, 1},    {"S", K_S, 1},     {"S_DAG", K_SDAG, 1}, {"X", K_X, 1},   {"Y", K_Y, 1},
                             {"Z", K_Z, 1},    {"CX", K_CX, 2},   {"CNOT", K_CX, 2},    {"ZCX", K_CX, 2}, {"CZ", K_CZ, 2},
@@ -444,6 +550,21 @@ struct Compiler {
     return r;
   }
 
+  // U_C^dagger P U_C for a physical Pauli product (letters on different qubits)
+  Pauli product(const std::vector<std::pair<int, char>>& pr) const {
+    Pauli r(W);
+    for (auto& f : pr) mul_into(r, image(f.first, f.second), 0);
+    return r;
+  }
+
+  // feed-forward Pauli with virtual image e if record `rec` is 1 (Appendix B.3)
+  void feed(const Pauli& e, int rec) { emit(OP_CFEED, e.r ? F_SIGN : 0, 0, 0, push_pauli(e), (uint32_t)rec); }
+
+  // a phase exp(-i theta) of the global scalar only
+  void global_phase(double theta) {
+    if (!drop_phases) emit(OP_PHASE, 0, 0, 0, push_mask(std::vector<uint64_t>(W, 0)), push_angle(theta));
+  }
+
   // Appendix B.1: rotation exp(-i theta g) about the virtual generator g.
   void rotation(Pauli g, double theta) {
     int vd = lowest(g.x, false);
@@ -563,7 +684,7 @@ struct Compiler {
 // active operation whose generator is mapped through the physical Cliffords
 // only (the virtual basis before any localization), in program order.
 struct HNode {
-  enum Kind { ROT, MEAS, NOISE, CPAULI, DET, OBS } kind;
+  enum Kind { ROT, MEAS, NOISE, CPAULI, DET, OBS, CFEED, GPHASE } kind;
   Pauli g;          // ROT: exp(-i theta g); MEAS: the measured observable;
                     // CPAULI: image of X on the reset qubit
   double theta = 0;
@@ -598,7 +719,7 @@ static bool noise_commutes(const HNode& n, const Pauli& g) {
 // whether node n commutes with the operator exp(-i theta g) or a measurement of g
 static bool node_commutes(const HNode& n, const Pauli& g) {
   switch (n.kind) {
-    case HNode::ROT: case HNode::MEAS: case HNode::CPAULI: return commutes(n.g, g);
+    case HNode::ROT: case HNode::MEAS: case HNode::CPAULI: case HNode::CFEED: return commutes(n.g, g);
     case HNode::NOISE: return noise_commutes(n, g);
     default: return true;  // detectors and observables are classical
   }
@@ -748,7 +869,7 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
       case OP_MRANDOM: c.int_ops += 22; break;
       case OP_MACTZ: c.flops += 5 * A; c.vector_bytes += 2 * A * a; c.int_ops += 110; break;
       case OP_MACTX: c.flops += 8 * A; c.vector_bytes += 2.5 * A * a; c.int_ops += 110; break;
-      case OP_CPAULI: c.int_ops += 16 * W; break;
+      case OP_CPAULI: case OP_CFEED: c.int_ops += 16 * W; break;
       case OP_NOISE: {
         double f = 0;
         for (uint32_t s = in.a; s < in.b; s++) f += P.site_p[s];
@@ -1008,8 +1129,9 @@ static void build_split(CompiledProgram& P) {
         P.vev_rec[in.b] = act++;
         break;
       }
-      case OP_CPAULI: {
-        const Dep d = ev_dep[in.b];
+      case OP_CPAULI: case OP_CFEED: {
+        // X^m of a reset (the event's outcome) or a feed-forward Pauli (a record)
+        const Dep d = in.op == OP_CPAULI ? ev_dep[in.b] : rows[in.b];
         each_bit(in.a, [&](int q) { xr(dx[q], d); });
         each_bit(in.a + W, [&](int q) { xr(dz[q], d); });
         P.fcode.push_back(in);
@@ -1106,6 +1228,10 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
           C.phys(o.kind, o.a, o.b);
           break;
         case K_ROTZ: C.rotation(C.iz[o.a], o.arg); break;
+        case K_PROT: C.rotation(C.product(o.prod), o.arg); break;
+        case K_MPP: C.measure(C.product(o.prod), rec++); break;
+        case K_CFEED: C.feed(C.image(o.a, o.prod[0].second), o.refs[0]); break;
+        case K_GPHASE: C.global_phase(o.arg); break;
         case K_M: C.measure(C.image(o.a, 'Z'), rec++); break;
         case K_MX: C.measure(C.image(o.a, 'X'), rec++); break;
         case K_MR: { int j = C.measure(C.image(o.a, 'Z'), rec++); C.reset_fix(C.ix[o.a], j); break; }
@@ -1134,6 +1260,16 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
           F.phys(o.kind, o.a, o.b);
           continue;
         case K_ROTZ: nd.kind = HNode::ROT; nd.g = F.iz[o.a]; nd.theta = o.arg; break;
+        case K_PROT: nd.kind = HNode::ROT; nd.g = F.product(o.prod); nd.theta = o.arg; break;
+        case K_CFEED: nd.kind = HNode::CFEED; nd.g = F.image(o.a, o.prod[0].second); nd.rec = o.refs[0]; break;
+        case K_GPHASE: nd.kind = HNode::GPHASE; nd.g = Pauli(P.W); nd.theta = o.arg; break;
+        case K_MPP:
+          nd.kind = HNode::MEAS;
+          nd.g = F.product(o.prod);
+          nd.event = nev++;
+          nd.rec = rec++;
+          h.push_back(nd);
+          continue;
         case K_M: case K_MX: case K_MR: case K_R:
           nd.kind = HNode::MEAS;
           nd.g = F.image(o.a, o.kind == K_MX ? 'X' : 'Z');
@@ -1176,6 +1312,8 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
         case HNode::ROT: C.rotation(C.map(nd.g), nd.theta); break;
         case HNode::MEAS: C.measure(C.map(nd.g), nd.rec, nd.event); break;
         case HNode::CPAULI: C.reset_fix(C.map(nd.g), nd.event); break;
+        case HNode::CFEED: C.feed(C.map(nd.g), nd.rec); break;
+        case HNode::GPHASE: C.global_phase(nd.theta); break;
         case HNode::NOISE: {
           const int m = nd.op->ntype == S_DEP2 ? 4 : 2;
           Pauli img[4];
@@ -1305,6 +1443,7 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
   }
   survival_tables(P);
   if (P.masks.empty()) P.masks.push_back(0);
+  for (const GInstr& in : P.code) P.has_cfeed = P.has_cfeed || in.op == OP_CFEED;
   build_split(P);
   if (P.consts.empty()) P.consts = {1.0, 0.0, 1.0, 0.0};
   if (P.refs.empty()) P.refs.push_back(0);

@@ -30,6 +30,7 @@ struct CompiledProgram {
   std::vector<uint32_t> rblk_off;              // 128-event block -> its dormant random events
   std::vector<uint8_t> rblk_ev;
   int rblk_max = 0;
+  bool has_cfeed = false;          // feed-forward Paulis (need record bits: not on the bit-sliced kernels)
   // split form (program.h): valid when split_ok
   bool split_ok = false;
   int nactive = 0;                 // active measurement events

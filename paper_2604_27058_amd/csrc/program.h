@@ -46,6 +46,8 @@ enum Op : uint8_t {
   OP_MACTF,    // frame side of an active measurement with outcome 0: write p
                //   (x_v, or z_v for F_XMEAS) to row u and the noise frame's to
                //   row u + 1; H_v for F_XMEAS; then x_v = sign; record 0  v, u, b=event
+  OP_CFEED,    // feed-forward Pauli (Appendix B.3): if record b is 1,     a=mask(x,z), b=record
+               //   the full frame takes the image (sign in F_SIGN)
   OP_COUNT
 };
 

@@ -281,8 +281,9 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
     // frame pass: bit-sliced (2), shot per lane with frames in VGPRs (3), or
     // (1) bit-sliced when its rows fit in LDS and its 2048-shot tiles fill
     // the device twice over
-    const bool fits = rows_bytes <= kLdsLimit;
-    if (c.split == 2 && !fits) return fail(CLIFFT_E_CAPACITY, "frame rows of the split form exceed LDS");
+    const bool fits = rows_bytes <= kLdsLimit && !H.has_cfeed;  // feed-forward needs per-shot record bits
+    if (c.split == 2 && !fits)
+      return fail(CLIFFT_E_CAPACITY, "the bit-sliced frame pass needs LDS rows and no feed-forward Paulis");
     const bool flane = c.split == 3 || !fits || (c.split == 1 && (shots + 2047) / 2048 < 2 * (uint64_t)device_cus());
     int fgrid;
     if (!flane) {
@@ -349,7 +350,7 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
     }
     const size_t rows_bytes = frames_lds_rows(tmp) * 64 * 4;
     const bool spec = c.specialize == 1;
-    const bool bs_ok = H.kmax == 0 && !trace && (spec || rows_bytes <= kLdsLimit);
+    const bool bs_ok = H.kmax == 0 && !trace && !H.has_cfeed && (spec || rows_bytes <= kLdsLimit);
     if (c.specialize == 1 && G != 0 && G != kBitSliced)
       return fail(CLIFFT_E_INVALID_ARG, "specialize applies to the bit-sliced tier only");
     if ((G == kBitSliced || spec) && !bs_ok)
@@ -1053,10 +1054,12 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
   // Stage 1: every tier at its default grid.  Stage 2: grids from one to
   // eight workgroups per CU for the two fastest tiers.
   std::vector<clifft_launch> tiers;
-  if (H.kmax == 0) {
+  if (H.kmax == 0 && !H.has_cfeed) {
     tiers.push_back(clifft_launch{precision, kBitSliced, 0, 0, -1, 0});
     if (spec_supported(H, nullptr) && ensure_spec(p) == CLIFFT_OK)
       tiers.push_back(clifft_launch{precision, kBitSliced, 0, 0, 1, 0});
+    tiers.push_back(clifft_launch{precision, 1, 0, 0, 0, -1});
+  } else if (H.kmax == 0) {
     tiers.push_back(clifft_launch{precision, 1, 0, 0, 0, -1});
   } else {
     for (int G : {1, 64, 256}) {
@@ -1070,7 +1073,8 @@ clifft_status clifft_autotune(clifft_program* p, uint64_t shots, int32_t precisi
     // without frame work to hide it)
     if (H.split_ok && H.kmax <= kLaneMaxK)
       for (int fp : {2, 3})
-        for (int hbm : {-1, 1}) tiers.push_back(clifft_launch{precision, 1, 0, hbm, 0, fp});
+        for (int hbm : {-1, 1})
+          if (fp == 3 || !H.has_cfeed) tiers.push_back(clifft_launch{precision, 1, 0, hbm, 0, fp});
   }
   const DevProgram* D = nullptr;
   const DeviceCopy* DC = nullptr;

@@ -1422,6 +1422,33 @@ struct Shot {
           frame_xor<W>(N, bx, bz);
           break;
         }
+        case OP_CFEED: {
+          // feed-forward Pauli (Appendix B.3) on the full frame when record b
+          // of this shot is 1; the noise frame only follows physical faults
+          uint32_t m;
+          if constexpr (G == 1) {
+            m = (uint32_t)(rec[in.b] >> (threadIdx.x & 63)) & 1u;
+          } else {
+            grp.sync();  // the record bit is staged by the group's first thread
+            m = (uint32_t)(rec[in.b] >> slane) & 1u;
+          }
+          if (m) {
+            uint64_t px[W], pz[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+              px[w] = masks[in.a + w];
+              pz[w] = masks[in.a + W + w];
+            }
+            if constexpr (DBG) {
+              int e = 2 * (int)(in.flags & F_SIGN);
+#pragma unroll
+              for (int w = 0; w < W; w++) e += __popcll(px[w] & pz[w]) + 2 * __popcll(pz[w] & T.x[w]);
+              g_ipow += e;
+            }
+            frame_xor<W>(T, px, pz);
+          }
+          break;
+        }
         case OP_NOISE: {
           if constexpr (DBG) {
             if (A.forced_faults) {

@@ -68,18 +68,21 @@ def parse(text):
                 out.extend(body * n)
                 i = j
                 continue
-            head, _, rest = s.partition(" ")
             arg = None
-            if "(" in head:
-                head, a = head.split("(")
-                arg = float(a.rstrip(")"))
-            elif rest.startswith("("):
-                a, _, rest = rest[1:].partition(")")
-                arg = float(a)
+            if "(" in s.split()[0] or (len(s.split()) > 1 and s.split()[1].startswith("(")):
+                head, _, tail = s.partition("(")
+                a, _, rest = tail.partition(")")
+                vals = [float(v) for v in a.split(",")]
+                arg = vals[0] if len(vals) == 1 else tuple(vals)
+                head = head.strip()
+            else:
+                head, _, rest = s.partition(" ")
             tg = []
             for t in rest.split():
                 if t.startswith("rec["):
                     tg.append(("rec", int(t[4:-1])))
+                elif t[0] in "XYZxyz":
+                    tg.append(("prod", [(int(f[1:]), "XYZ".index(f[0].upper()) + 1) for f in t.split("*")]))
                 else:
                     tg.append(int(t))
             out.append((head.upper(), arg, tg))
@@ -130,6 +133,21 @@ def apply_swap(psi, n, a, b):
     ba, bb = (idx >> a) & 1, (idx >> b) & 1
     src = idx ^ ((ba ^ bb) << a) ^ ((ba ^ bb) << b)
     return psi[src]
+
+
+def pauli_bits(n, letters):
+    """x and z bit vectors of a product of letters (1 X, 2 Y, 3 Z)."""
+    px = np.zeros(n, np.uint8)
+    pz = np.zeros(n, np.uint8)
+    for q, L in letters:
+        px[q] = L in (1, 2)
+        pz[q] = L in (2, 3)
+    return px, pz
+
+
+def u3(theta, phi, lam):
+    c, s = math.cos(theta / 2), math.sin(theta / 2)
+    return np.array([[c, -np.exp(1j * lam) * s], [np.exp(1j * phi) * s, np.exp(1j * (phi + lam)) * c]], complex)
 
 
 def apply_pauli_letters(psi, n, letters):
@@ -259,6 +277,8 @@ class Dense:
             for t in tg:
                 if not isinstance(t, tuple):
                     n = max(n, t + 1)
+                elif t[0] == "prod":
+                    n = max(n, max(q for q, _ in t[1]) + 1)
             if name in NOISE_OUT and arg:
                 ar = 2 if name == "DEPOLARIZE2" else 1
                 for i in range(0, len(tg), ar):
@@ -340,6 +360,43 @@ class Dense:
                 recs.append(m)
             return m, pn
 
+        def measure_product(letters):
+            """Measurement of a Pauli product (eigenvalue (-1)^m): projector
+            (I + (-1)^m P) / 2 applied directly."""
+            nonlocal psi, j
+            px, pz = pauli_bits(n, letters)
+            pn = anticommute(ex, ez, px, pz)
+            cls = G.measure(px, pz)
+            ppsi = apply_pauli_letters(psi, n, letters)
+            nrm = np.vdot(psi, psi).real
+            p1 = float(max(0.0, (nrm - np.vdot(psi, ppsi).real) / 2) / nrm)
+            if forced_m is not None:
+                m = int(forced_m[j])
+            elif cls == "static":
+                m = int(p1 > 0.5)
+            elif cls == "random":
+                blk = j >> 7
+                if blk not in rbits:
+                    w = draw(blk, RBIT, shot, seed)
+                    rbits[blk] = w[0] | (w[1] << 32) | (w[2] << 64) | (w[3] << 96)
+                m = ((rbits[blk] >> (j & 127)) & 1) ^ pn
+            else:
+                pref1 = p1 if pn == 0 else 1.0 - p1
+                m = int(u53(draw(j, AMEAS, shot, seed)) < pref1) ^ pn
+            psi = (psi + (-1) ** m * ppsi) / 2
+            psi = psi / np.sqrt(np.vdot(psi, psi).real)
+            probs.append(p1)
+            ms.append(m)
+            classes.append(cls)
+            j += 1
+            recs.append(m)
+
+        def rotate(letters, theta):
+            """exp(-i theta P) = cos(theta) I - i sin(theta) P."""
+            nonlocal psi
+            psi = math.cos(theta) * psi - 1j * math.sin(theta) * apply_pauli_letters(psi, n, letters)
+            G.rotation(*pauli_bits(n, letters))
+
         for name, arg, tg in self.ops:
             if name in GATES1:
                 for q in tg:
@@ -347,6 +404,30 @@ class Dense:
                     if name in ("H", "S", "S_DAG"):
                         conj_bits(ex, ez, name, q)
                         G.conj(name, q)
+            elif name in ("CX", "CNOT", "CY", "CZ") and any(isinstance(t, tuple) for t in tg):
+                # feed-forward: Pauli on the qubit if the record is 1 (the
+                # noise frame only follows physical faults)
+                L = {"CX": 1, "CNOT": 1, "CY": 2, "CZ": 3}[name]
+                for i in range(0, len(tg), 2):
+                    r, q = (tg[i], tg[i + 1]) if isinstance(tg[i], tuple) else (tg[i + 1], tg[i])
+                    if recs[len(recs) + r[1]]:
+                        psi = apply_pauli_letters(psi, n, [(q, L)])
+            elif name in ("R_X", "R_Y"):
+                for q in tg:
+                    rotate([(q, 1 if name == "R_X" else 2)], arg / 2)
+            elif name == "R_PAULI":
+                for t in tg:
+                    rotate(t[1], arg / 2)
+            elif name == "U3":
+                th, ph, la = arg
+                for q in tg:
+                    psi = apply1(psi, n, q, u3(th, ph, la))
+                    # as R_Z(phi) R_Y(theta) R_Z(lambda) for the active-set tracker
+                    for L in (3, 2, 3):
+                        G.rotation(*pauli_bits(n, [(q, L)]))
+            elif name == "MPP":
+                for t in tg:
+                    measure_product(t[1])
             elif name in ("CX", "CNOT", "CZ", "SWAP"):
                 g = "CX" if name == "CNOT" else name
                 for i in range(0, len(tg), 2):

@@ -159,3 +159,30 @@ def test_compile_options():
     a, b = pk.Program(ph), pk.Program(ph, drop_phases=1)
     assert a.k_max == b.k_max == 1
     assert a.num_instructions == b.num_instructions + 1
+
+
+@pytest.mark.parametrize("case", range(25))
+def test_compiler_agrees_with_oracle_on_wide_gate_set(case):
+    """R_X, R_Y, U3, rotations about Pauli products, MPP and feed-forward
+    Paulis: the host compiler's k_max, event classes and record counts
+    equal the oracle's (both lowered from the same circuit independently)."""
+    from test_oracle_pins import random_wide_circuit
+    import numpy as np
+    rng = np.random.default_rng(8300 + case)
+    text = random_wide_circuit(rng, int(rng.integers(2, 7)), int(rng.integers(10, 50)))
+    p, o = pk.Program(text), oracle.Program(text)
+    assert p.k_max == o.kmax
+    assert p.num_measurements == o.nrec and p.num_events == o.nevents and p.num_detectors == o.ndet
+    assert p.event_classes() == [int(c) for c in o.event_classes()]
+    for hp in (1, 2, 3, 4):
+        q = pk.Program(text, hir_passes=hp)
+        assert q.k_max <= p.k_max and q.num_measurements == p.num_measurements
+
+
+def test_wide_gate_parse_errors():
+    for bad in ("MPP X0*X0\n", "MPP X0*Q1\n", "R_PAULI X0*Y1\n", "U3(0.1, 0.2) 0\n", "CX rec[-1] 0\n",
+                "M 0\nCX 0 rec[-1]\n", "R_X 0\n", "H X0\n"):
+        with pytest.raises(pk.ClifftError):
+            pk.Program(bad)
+        with pytest.raises(oracle.OracleError):
+            oracle.Program(bad)

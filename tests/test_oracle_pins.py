@@ -209,6 +209,106 @@ def random_small_circuit(rng, n, nops, p_noise=0.08, rotations=True, repeat=True
     return "\n".join(out) + "\n"
 
 
+def _product(rng, n):
+    k = int(rng.integers(1, min(n, 3) + 1))
+    qs = [int(v) for v in rng.choice(n, k, replace=False)]
+    return "*".join("%s%d" % ("XYZ"[int(rng.integers(0, 3))], q) for q in qs)
+
+
+def random_wide_circuit(rng, n, nops, p_noise=0.08):
+    """random_small_circuit's operations plus the wider gate set: R_X, R_Y,
+    U3, rotations about Pauli products, product measurements (MPP) and
+    record-controlled Paulis."""
+    body = []
+    nrec = 0
+    for _ in range(nops):
+        r = rng.random()
+        q = int(rng.integers(0, n))
+        if r < 0.2:
+            body.append("%s %d" % (ONEQ[int(rng.integers(0, 6))], q))
+        elif r < 0.32:
+            a, b = [int(v) for v in rng.choice(n, 2, replace=False)]
+            body.append("%s %d %d" % (["CX", "CZ", "SWAP"][int(rng.integers(0, 3))], a, b))
+        elif r < 0.52:
+            k = int(rng.integers(0, 5))
+            ang = float(rng.uniform(-3, 3))
+            if k == 0:
+                body.append("R_X(%r) %d" % (ang, q))
+            elif k == 1:
+                body.append("R_Y(%r) %d" % (ang, q))
+            elif k == 2:
+                body.append("U3(%r, %r, %r) %d" % (ang, float(rng.uniform(-3, 3)), float(rng.uniform(-3, 3)), q))
+            elif k == 3:
+                body.append("R_PAULI(%r) %s" % (ang, _product(rng, n)))
+            else:
+                body.append("T %d" % q)
+        elif r < 0.7:
+            k = int(rng.integers(0, 4))
+            if k == 0:
+                body.append("MPP %s" % _product(rng, n))
+            else:
+                body.append("%s %d" % (["M", "MX", "MR"][k - 1], q))
+            nrec += 1
+            if nrec >= 2 and rng.random() < 0.4:
+                body.append("DETECTOR rec[-1] rec[-2]")
+            if rng.random() < 0.5:
+                body.append("%s rec[-%d] %d" % (["CX", "CY", "CZ"][int(rng.integers(0, 3))],
+                                                int(rng.integers(1, nrec + 1)), int(rng.integers(0, n))))
+        elif p_noise:
+            kind = int(rng.integers(0, 5))
+            pp = float(rng.uniform(0.02, p_noise))
+            if kind == 1:
+                a, b = [int(v) for v in rng.choice(n, 2, replace=False)]
+                body.append("DEPOLARIZE2(%r) %d %d" % (pp, a, b))
+            else:
+                body.append("%s(%r) %d" % (["DEPOLARIZE1", "", "X_ERROR", "Y_ERROR", "Z_ERROR"][kind], pp, q))
+    body.append("M " + " ".join(map(str, range(n))))
+    return "\n".join(body) + "\n"
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.0, 2.5, -0.7])
+def test_wide_gate_closed_forms(theta):
+    """R_X(t)|0>, R_Y(t)|0> and U3(t, p, l)|0> measured in Z give
+    sin^2(t/2); a rotation about X0*X1 from |00> gives the same for Z0;
+    U3(t, p, l) = e^{i(p+l)/2} R_Z(p) R_Y(t) R_Z(l) is checked through the
+    global scalar of the oracle's state against the dense matrix."""
+    s2 = math.sin(theta / 2) ** 2
+    for text in ("R_X(%r) 0\nM 0\n" % theta, "R_Y(%r) 0\nM 0\n" % theta, "U3(%r, 0.4, -1.1) 0\nM 0\n" % theta,
+                 "R_PAULI(%r) X0*X1\nM 0\n" % theta, "R_PAULI(%r) Y0*Z2\nM 0\n" % theta):
+        pr = oracle.Program(text).trace()["probs"][0]
+        assert abs(pr - s2) < 1e-14, text
+    _compare_shot("U3(%r, 0.4, -1.1) 0\nH 1\nCX 1 0\n" % theta, seed=0, shot=0)
+
+
+def test_product_measurements_and_feed_forward():
+    # Bell pair: X0X1 = +1, Z0Z1 = +1, Y0Y1 = -1, all deterministic
+    p = oracle.Program("H 0\nCX 0 1\nMPP X0*X1 Z0*Z1 Y0*Y1\n")
+    t = p.trace()
+    assert list(t["recs"]) == [0, 0, 1] and list(p.event_classes()) == [0, 0, 0]
+    # measuring one half of a Bell pair and correcting the other with the
+    # record leaves it in |0>: its measurement always reads 0
+    m, _, _ = oracle.Program("H 0\nCX 0 1\nM 0\nCX rec[-1] 1\nM 1\n").sample(4096, seed=3)
+    assert popcount_rows(m[0:1], 4096)[0] > 1500 and popcount_rows(m[1:2], 4096)[0] == 0
+    # a Z correction after an X-basis measurement, CZ with the record second
+    m, _, _ = oracle.Program("H 0\nCX 0 1\nMX 0\nCZ 1 rec[-1]\nH 1\nM 1\n").sample(4096, seed=4)
+    assert popcount_rows(m[1:2], 4096)[0] == 0
+
+
+@pytest.mark.parametrize("case", range(30))
+def test_oracle_matches_dense_wide_gate_set(case):
+    rng = np.random.default_rng(8100 + case)
+    text = random_wide_circuit(rng, int(rng.integers(2, 6)), int(rng.integers(10, 40)))
+    for shot in range(3):
+        _compare_shot(text, seed=case, shot=shot, check_state=(shot == 0))
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_oracle_matches_dense_wide_gate_set_forced(case):
+    rng = np.random.default_rng(8200 + case)
+    text = random_wide_circuit(rng, int(rng.integers(2, 6)), int(rng.integers(10, 40)))
+    _compare_shot(text, seed=case, shot=0, forced=True, rng=rng)
+
+
 def _compare_shot(text, seed, shot, check_state=True, forced=False, rng=None):
     prog = oracle.Program(text)
     dn = dense_ref.Dense(text)
