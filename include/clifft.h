@@ -18,7 +18,8 @@
  *     [e^{i p} s, e^{i (p + l)} c]], c = cos(theta/2), s = sin(theta/2));
  *     M MX MR R, MPP P... (one record per product, eigenvalue (-1)^m);
  *     record-controlled Paulis CX / CY / CZ rec[-k] q (a Pauli on q when the
- *     record is 1; Appendix B.3); noise DEPOLARIZE1(p) DEPOLARIZE2(p)
+ *     record is 1; Appendix B.3); EXP_VAL P... (expectation-value probes,
+ *     see clifft_sample_expval); noise DEPOLARIZE1(p) DEPOLARIZE2(p)
  *     X_ERROR(p) Y_ERROR(p) Z_ERROR(p); DETECTOR rec[-k]...;
  *     OBSERVABLE_INCLUDE(i) rec[-k]...; REPEAT n { ... }; TICK and
  *     coordinates are ignored.  At most 256 qubits, k_max <= 30.
@@ -73,6 +74,7 @@ typedef struct clifft_info {
   int32_t num_instructions;  /* length of the compiled stream */
   int32_t num_random_events; /* dormant random measurements (Appendix B.2) */
   int32_t num_active_events; /* measurements on the active vector */
+  int32_t num_probes;        /* expectation-value probes (EXP_VAL) */
 } clifft_info;
 
 /* Launch configuration; zero-initialize for automatic choices. */
@@ -230,6 +232,21 @@ clifft_status clifft_workspace_size(const clifft_program* p, const clifft_launch
 clifft_status clifft_sample(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
                             const clifft_launch* cfg, void* workspace, size_t workspace_bytes, uint64_t* meas,
                             uint64_t* det, uint64_t* obs, void* stream);
+
+/* Sampling with expectation-value probes (Section 3.2, post-selection
+ * overhead: probes read the frame-factored runtime state inline; Appendix C
+ * uses one for a logical <Y>).  Each EXP_VAL P instruction of the circuit
+ * is probe i (in program order) and gives, per shot, <psi|P|psi> of the
+ * shot's state at that point: with g = U_C^dagger P U_C, (-1)^c <phi|g_A|phi>
+ * / <phi|phi> where c is the commutation of the Pauli frame with g and g_A
+ * its letters on active axes, or 0 when g has X support on a dormant qubit.
+ * Same arguments as clifft_sample, plus expval: device [num_probes][shots]
+ * double (probe-major; NULL to skip).  The reduction is FP64 in both
+ * precisions.  Programs with probes do not run on the bit-sliced tier or in
+ * the split form, and the batched launch does not return probe values. */
+clifft_status clifft_sample_expval(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                                   const clifft_launch* cfg, void* workspace, size_t workspace_bytes, uint64_t* meas,
+                                   uint64_t* det, uint64_t* obs, double* expval, void* stream);
 
 /* Allocation-free sampling, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

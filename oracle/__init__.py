@@ -46,9 +46,9 @@ def lib():
         L.oracle_faults.argtypes = [vp, u64, u64, ctypes.POINTER(i32)]
         L.oracle_gap_next.argtypes = [ctypes.POINTER(ctypes.c_double), i32, i32, ctypes.c_double]
         L.oracle_gap_next.restype = i32
-        L.oracle_trace.argtypes = [vp, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.oracle_trace.argtypes = [vp, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_trace.restype = i32
-        L.oracle_sample.argtypes = [vp, u64, u64, u64, i32, vp, vp, vp]
+        L.oracle_sample.argtypes = [vp, u64, u64, u64, i32, vp, vp, vp, vp]
         L.oracle_sample.restype = i32
         _lib = L
     return _lib
@@ -68,7 +68,7 @@ def gap_next(S, cur, u):
 
 
 OP_NAMES = ["VCX", "VCZ", "VS", "VH", "EXPAND", "ROT", "PHASE", "MSTATIC", "MRANDOM", "MACTIVE_Z",
-            "MACTIVE_X", "CPAULI", "NOISE", "DET", "OBS", "CFEED"]
+            "MACTIVE_X", "CPAULI", "NOISE", "DET", "OBS", "CFEED", "EXPVAL"]
 
 
 class OracleError(RuntimeError):
@@ -87,10 +87,10 @@ class Program:
         if rc != 0:
             raise OracleError(err.value.decode())
         self._h = h
-        info = (ctypes.c_int64 * 9)()
+        info = (ctypes.c_int64 * 10)()
         L.oracle_info(h, info)
         (self.nq, self.kmax, self.nevents, self.nrec, self.ndet, self.nobs, self.nsites, self.nops,
-         self.nchunks) = [int(v) for v in info]
+         self.nchunks, self.nprobes) = [int(v) for v in info]
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -140,28 +140,32 @@ class Program:
         gamma = np.zeros(2)
         faults = np.zeros(max(self.nsites, 1), np.int32)
         frame = np.zeros(4 * self.nq, np.uint8)
+        expvals = np.zeros(max(self.nprobes, 1))
         fm = None if forced_m is None else np.ascontiguousarray(forced_m, dtype=np.uint8)
         ff = None if forced_faults is None else np.ascontiguousarray(forced_faults, dtype=np.int32)
         rc = lib().oracle_trace(self._h, seed, shot,
                                 None if fm is None else fm.ctypes.data, None if ff is None else ff.ctypes.data,
                                 probs.ctypes.data, ev_m.ctypes.data, recs.ctypes.data, dets.ctypes.data,
                                 obs.ctypes.data, phi.ctypes.data, slots.ctypes.data, ctypes.addressof(k),
-                                gamma.ctypes.data, faults.ctypes.data, frame.ctypes.data)
+                                gamma.ctypes.data, faults.ctypes.data, frame.ctypes.data, expvals.ctypes.data)
         kk = k.value
         return dict(error=rc, probs=probs[: self.nevents], m=ev_m[: self.nevents], recs=recs[: self.nrec],
                     dets=dets[: self.ndet], obs=obs[: self.nobs],
                     phi=(phi[0::2] + 1j * phi[1::2])[: 1 << kk], slots=slots[:kk], k=kk,
                     gamma=complex(gamma[0], gamma[1]), faults=faults[: self.nsites],
-                    frame=frame.reshape(4, self.nq))
+                    frame=frame.reshape(4, self.nq), expvals=expvals[: self.nprobes])
 
-    def sample(self, shots, seed=0, offset=0, threads=1):
-        """Bit-packed record-major outputs (meas, det, obs), each [count, ceil(shots/64)] uint64."""
+    def sample(self, shots, seed=0, offset=0, threads=1, expvals=False):
+        """Bit-packed record-major outputs (meas, det, obs), each [count, ceil(shots/64)] uint64,
+        and with expvals=True also the probes' values [nprobes, shots] (float64)."""
         words = (shots + 63) // 64
         meas = np.zeros((max(self.nrec, 1), max(words, 1)), np.uint64)
         det = np.zeros((max(self.ndet, 1), max(words, 1)), np.uint64)
         obs = np.zeros((max(self.nobs, 1), max(words, 1)), np.uint64)
+        ev = np.zeros((max(self.nprobes, 1), max(shots, 1))) if expvals else None
         rc = lib().oracle_sample(self._h, shots, seed, offset, threads, meas.ctypes.data, det.ctypes.data,
-                                 obs.ctypes.data)
+                                 obs.ctypes.data, None if ev is None else ev.ctypes.data)
         if rc:
             raise OracleError("oracle sample error %d" % rc)
-        return meas[: self.nrec, :words], det[: self.ndet, :words], obs[: self.nobs, :words]
+        out = (meas[: self.nrec, :words], det[: self.ndet, :words], obs[: self.nobs, :words])
+        return out + (ev[: self.nprobes, :shots],) if expvals else out

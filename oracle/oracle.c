@@ -170,7 +170,8 @@ enum {
     P_PROT,          /* exp(-i theta P) for a Pauli product P (pq, pl) */
     P_MPP,           /* measurement of a Pauli product P (pq, pl) */
     P_CFEED,         /* Pauli pl[0] on qubit a if record refs[0] is 1 */
-    P_GPHASE         /* global phase exp(-i theta) */
+    P_GPHASE,        /* global phase exp(-i theta) */
+    P_EXPVAL         /* expectation value of a Pauli product (probe obs) */
 };
 enum { N_DEP1, N_DEP2, N_XERR, N_YERR, N_ZERR };
 
@@ -193,6 +194,7 @@ typedef struct {
     int nq;
     int nrec;
     int ndet, nobs;
+    int nprobes;
     char err[256];
 } circuit;
 
@@ -321,7 +323,7 @@ static int parse_instruction(circuit *c, char *line, lexer *L, int depth)
     }
     pop o;
     memset(&o, 0, sizeof o);
-    int is_prod_gate = !strcmp(name, "MPP") || !strcmp(name, "R_PAULI");
+    int is_prod_gate = !strcmp(name, "MPP") || !strcmp(name, "R_PAULI") || !strcmp(name, "EXP_VAL");
     if (nprod && !is_prod_gate) { snprintf(c->err, sizeof c->err, "line %d: Pauli product target on %s", L->line, name); return -1; }
     if (is_prod_gate) {
         /* MPP P...: one measurement per product; R_PAULI(phi) P...:
@@ -331,8 +333,9 @@ static int parse_instruction(circuit *c, char *line, lexer *L, int depth)
         for (int k = 0; k < nprod; k++) {
             pop q;
             memset(&q, 0, sizeof q);
-            q.kind = !strcmp(name, "MPP") ? P_MPP : P_PROT;
+            q.kind = !strcmp(name, "MPP") ? P_MPP : !strcmp(name, "EXP_VAL") ? P_EXPVAL : P_PROT;
             q.arg = arg / 2;
+            if (q.kind == P_EXPVAL) q.obs = c->nprobes++;
             q.pq = (int *)malloc(sizeof(int) * 256);
             q.pl = (char *)malloc(256);
             char *s = prods[k];
@@ -541,7 +544,8 @@ enum {
     O_NOISE,     /* stochastic Pauli site */
     O_DET,
     O_OBS,
-    O_CFEED      /* Pauli `mask` if record `rec` is 1 (feed-forward) */
+    O_CFEED,     /* Pauli `mask` if record `rec` is 1 (feed-forward) */
+    O_EXPVAL     /* expectation value of the virtual observable `mask` (probe `obs`) */
 };
 
 typedef struct {
@@ -569,7 +573,7 @@ typedef struct {
 typedef struct {
     int nq;
     int kmax;
-    int nevents, nrec, ndet, nobs;
+    int nevents, nrec, ndet, nobs, nprobes;
     int nsites;
     oop *ops;
     int nops, capops;
@@ -1032,6 +1036,15 @@ static program *compile_circuit(circuit *ci)
             map_pauli(&C, po->a, po->pl[0], &o.mask);
             emit(&C, o);
             break; }
+        case P_EXPVAL: {
+            oop o;
+            memset(&o, 0, sizeof o);
+            o.kind = O_EXPVAL;
+            o.obs = po->obs;
+            o.mask = pauli_new(n);
+            map_product(&C, po->np, po->pq, po->pl, &o.mask);
+            emit(&C, o);
+            break; }
         case P_GPHASE: {
             oop o;
             memset(&o, 0, sizeof o);
@@ -1056,6 +1069,7 @@ static program *compile_circuit(circuit *ci)
     }
     P->nrec = rec;
     P->nobs = ci->nobs;
+    P->nprobes = ci->nprobes;
     build_survival(P);
     for (int q = 0; q < n; q++) { pauli_free(&C.ix[q]); pauli_free(&C.iz[q]); }
     free(C.ix);
@@ -1083,6 +1097,7 @@ typedef struct {
     uint8_t *ev_pn; /* per event: noise parity */
     uint8_t *det;
     uint8_t *obs;
+    double *probe;  /* per probe: expectation value */
 } shot_state;
 
 static double complex ipow(int e)
@@ -1184,6 +1199,7 @@ static shot_state *shot_alloc(const program *P)
     S->ev_pn = (uint8_t *)calloc((size_t)(P->nevents + 1), 1);
     S->det = (uint8_t *)calloc((size_t)(P->ndet + 1), 1);
     S->obs = (uint8_t *)calloc((size_t)(P->nobs + 1), 1);
+    S->probe = (double *)calloc((size_t)(P->nprobes + 1), sizeof(double));
     return S;
 }
 
@@ -1191,7 +1207,7 @@ static void shot_free(shot_state *S)
 {
     free(S->tx); free(S->tz); free(S->nx); free(S->nz);
     free(S->phi); free(S->tmp); free(S->slot_q); free(S->q_slot);
-    free(S->rec); free(S->ev_m); free(S->ev_pn); free(S->det); free(S->obs);
+    free(S->rec); free(S->ev_m); free(S->ev_pn); free(S->det); free(S->obs); free(S->probe);
     free(S);
 }
 
@@ -1501,6 +1517,38 @@ static void run_shot(const program *P, shot_state *S, uint64_t shot, uint64_t se
         case O_NOISE:
             if (faults[o->site] >= 0) apply_fault(S, P, o->site, faults[o->site]);
             break;
+        case O_EXPVAL: {
+            /* <psi|P|psi> with psi = gamma U_C P~ (phi (x) 0_D) and the
+             * virtual observable g = U_C^dagger P U_C: P~ g P~ = (-1)^c g,
+             * and g takes |0>_D to an orthogonal state when it has X
+             * support on a dormant qubit; otherwise only its letters on
+             * active qubits act on phi (Z on |0> is 1) */
+            const pauli *g = &o->mask;
+            int dormant_x = 0;
+            for (int q = 0; q < S->n; q++) dormant_x |= g->x[q] && S->q_slot[q] < 0;
+            double e = 0;
+            if (!dormant_x) {
+                size_t dim = (size_t)1 << S->k;
+                for (size_t i = 0; i < dim; i++) S->tmp[i] = S->phi[i];
+                for (int q = 0; q < S->n; q++) {
+                    if (!g->x[q] && !g->z[q]) continue;
+                    if (S->q_slot[q] < 0) continue; /* Z on |0>: 1 */
+                    size_t b = (size_t)1 << S->q_slot[q];
+                    for (size_t i = 0; i < dim; i++) {
+                        if (i & b) continue;
+                        double complex a0 = S->tmp[i], a1 = S->tmp[i | b];
+                        if (g->x[q] && g->z[q]) { S->tmp[i] = -I * a1; S->tmp[i | b] = I * a0; }     /* Y */
+                        else if (g->x[q]) { S->tmp[i] = a1; S->tmp[i | b] = a0; }                  /* X */
+                        else { S->tmp[i | b] = -a1; }                                               /* Z */
+                    }
+                }
+                double complex acc = 0;
+                for (size_t i = 0; i < dim; i++) acc += conj(S->phi[i]) * S->tmp[i];
+                int c = parity_and(S->tx, g->z, S->n) ^ parity_and(S->tz, g->x, S->n);
+                e = ((c ^ g->r) ? -1.0 : 1.0) * creal(acc);
+            }
+            S->probe[o->obs] = e;
+            break; }
         case O_CFEED:
             /* feed-forward Pauli (Appendix B.3) on the full frame; the noise
              * frame only follows physical faults */
@@ -1558,6 +1606,7 @@ void oracle_info(void *h, int64_t *info)
     info[6] = P->nsites;
     info[7] = P->nops;
     info[8] = P->nchunks;
+    info[9] = P->nprobes;
 }
 
 void oracle_event_classes(void *h, int *cls)
@@ -1610,7 +1659,7 @@ int oracle_faults(void *h, uint64_t seed, uint64_t shot, int *fault_at_site)
  * frame[4 * nq] (total x, total z, noise x, noise z). */
 int oracle_trace(void *h, uint64_t seed, uint64_t shot, const uint8_t *forced_m, const int *forced_faults,
                  double *probs, uint8_t *ev_m, uint8_t *recs, uint8_t *dets, uint8_t *obs, double *phi,
-                 int *slots, int *k, double *gamma, int *faults, uint8_t *frame)
+                 int *slots, int *k, double *gamma, int *faults, uint8_t *frame, double *expvals)
 {
     program *P = (program *)h;
     shot_state *S = shot_alloc(P);
@@ -1631,6 +1680,7 @@ int oracle_trace(void *h, uint64_t seed, uint64_t shot, const uint8_t *forced_m,
     if (k) *k = S->k;
     if (gamma) { gamma[0] = creal(S->gamma); gamma[1] = cimag(S->gamma); }
     if (faults) memcpy(faults, fl, sizeof(int) * (size_t)P->nsites);
+    if (expvals) memcpy(expvals, S->probe, sizeof(double) * (size_t)P->nprobes);
     if (frame) {
         memcpy(frame, S->tx, (size_t)P->nq);
         memcpy(frame + P->nq, S->tz, (size_t)P->nq);
@@ -1645,8 +1695,9 @@ int oracle_trace(void *h, uint64_t seed, uint64_t shot, const uint8_t *forced_m,
 
 typedef struct {
     program *P;
-    uint64_t s0, s1, offset, seed, words;
+    uint64_t s0, s1, offset, seed, words, shots;
     uint64_t *meas, *det, *obs;
+    double *expvals;  /* [nprobes][shots] or NULL */
     int error;
 } job;
 
@@ -1669,6 +1720,8 @@ static void *sample_worker(void *arg)
         if (J->obs)
             for (int d = 0; d < P->nobs; d++)
                 if (S->obs[d]) J->obs[(uint64_t)d * J->words + w] |= bit;
+        if (J->expvals)
+            for (int e = 0; e < P->nprobes; e++) J->expvals[(uint64_t)e * J->shots + s] = S->probe[e];
     }
     J->error = ro.error;
     free(fl);
@@ -1680,7 +1733,7 @@ static void *sample_worker(void *arg)
  * Outputs are record-major bit-packed: out[r * ceil(shots/64) + s/64] bit
  * s%64; the caller zero-fills them. */
 int oracle_sample(void *h, uint64_t shots, uint64_t seed, uint64_t offset, int nthreads, uint64_t *meas, uint64_t *det,
-                  uint64_t *obs)
+                  uint64_t *obs, double *expvals)
 {
     program *P = (program *)h;
     uint64_t words = (shots + 63) / 64;
@@ -1699,6 +1752,8 @@ int oracle_sample(void *h, uint64_t shots, uint64_t seed, uint64_t offset, int n
         jobs[t].meas = meas;
         jobs[t].det = det;
         jobs[t].obs = obs;
+        jobs[t].expvals = expvals;
+        jobs[t].shots = shots;
         pthread_create(&th[t], NULL, sample_worker, &jobs[t]);
     }
     int err = 0;

@@ -26,7 +26,8 @@ class ClifftError(RuntimeError):
 class clifft_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "num_qubits", "frame_words", "k_max", "num_events", "num_measurements", "num_detectors",
-        "num_observables", "num_noise_sites", "num_instructions", "num_random_events", "num_active_events")]
+        "num_observables", "num_noise_sites", "num_instructions", "num_random_events", "num_active_events",
+        "num_probes")]
 
 
 class clifft_cost(ctypes.Structure):
@@ -63,6 +64,8 @@ def lib():
         L.clifft_workspace_size.argtypes = [vp, ctypes.POINTER(clifft_launch), u64, ctypes.POINTER(sz)]
         L.clifft_sample.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, sz, vp, vp, vp, vp]
         L.clifft_sample_noalloc.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp]
+        L.clifft_sample_expval.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, sz, vp, vp, vp, vp,
+                                           vp]
         L.clifft_sample_trace.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp, vp, vp,
                                           sz, vp, vp, vp, vp]
         L.clifft_cost_model.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(clifft_cost)]
@@ -82,6 +85,7 @@ def lib():
         L.clifft_last_error.restype = ctypes.c_char_p
         for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
                   "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_noalloc",
+                  "clifft_sample_expval",
                   "clifft_sample_trace",
                   "clifft_cost_model", "clifft_resolve_launch", "clifft_batch_create", "clifft_batch_sizes",
                   "clifft_batch_layout", "clifft_batch_sample", "clifft_autotune", "clifft_specialize",
@@ -209,6 +213,22 @@ class Program:
                                    ptr(workspace), 0 if workspace is None else workspace.numel(), ptr(meas),
                                    ptr(det), ptr(obs), s.cuda_stream))
         return meas, det, obs
+
+    def sample_expval(self, shots, seed=0, offset=0, launch=None, outputs=None, workspace=None, stream=None):
+        """clifft_sample_expval: records as in sample() and the probes'
+        values, a [num_probes, shots] float64 device tensor."""
+        import torch
+        meas, det, obs = outputs if outputs is not None else self.alloc_outputs(shots)
+        if workspace is None:
+            workspace = self.alloc_workspace(launch, shots=shots)
+        ev = torch.zeros((max(self.num_probes, 1), shots), dtype=torch.float64, device="cuda")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        ptr = lambda t: t.data_ptr() if (t is not None and t.numel()) else None
+        _check(lib().clifft_sample_expval(self._h, shots, seed, offset,
+                                          None if launch is None else ctypes.byref(launch), ptr(workspace),
+                                          0 if workspace is None else workspace.numel(), ptr(meas), ptr(det),
+                                          ptr(obs), ptr(ev), s.cuda_stream))
+        return (meas, det, obs), ev[: self.num_probes]
 
     def sample_noalloc(self, shots, seed=0, offset=0, launch=None, outputs=None, stream=None):
         """Queue clifft_sample_noalloc (no workspace argument; the library's

@@ -36,7 +36,8 @@ enum PK {
   K_PROT,    // exp(-i theta P) for the Pauli product `prod`
   K_MPP,     // measurement of the Pauli product `prod`
   K_CFEED,   // Pauli prod[0] if record refs[0] is 1 (feed-forward)
-  K_GPHASE   // global phase exp(-i theta)
+  K_GPHASE,  // global phase exp(-i theta)
+  K_EXPVAL   // expectation value of the Pauli product `prod` (probe obs)
 };
 
 struct PhysOp {
@@ -55,6 +56,7 @@ struct Parsed {
   int nrec = 0;
   int ndet = 0;
   int nobs = 0;
+  int nprobes = 0;
 };
 
 struct Lines {
@@ -147,7 +149,7 @@ static bool parse_line(const std::string& raw, int line, Parsed& P, std::string&
     }
   }
   if (name == "TICK" || name == "QUBIT_COORDS" || name == "SHIFT_COORDS") return true;
-  const bool prod_gate = name == "MPP" || name == "R_PAULI";
+  const bool prod_gate = name == "MPP" || name == "R_PAULI" || name == "EXP_VAL";
   if (!prods.empty() && !prod_gate) return fail(err, code, 1, line, "Pauli product target on " + name);
   if (prod_gate) {
     // MPP P...: one measurement per product; R_PAULI(phi) P...: exp(-i phi P / 2)
@@ -155,9 +157,10 @@ static bool parse_line(const std::string& raw, int line, Parsed& P, std::string&
     if (name == "R_PAULI" && !has_arg) return fail(err, code, 1, line, "R_PAULI needs an angle");
     for (auto& pr : prods) {
       PhysOp o{};
-      o.kind = name == "MPP" ? K_MPP : K_PROT;
+      o.kind = name == "MPP" ? K_MPP : name == "EXP_VAL" ? K_EXPVAL : K_PROT;
       o.arg = arg / 2;
       o.prod = pr;
+      if (o.kind == K_EXPVAL) o.obs = P.nprobes++;
       P.ops.push_back(o);
       if (o.kind == K_MPP) P.nrec++;
     }
@@ -560,6 +563,24 @@ struct Compiler {
   // feed-forward Pauli with virtual image e if record `rec` is 1 (Appendix B.3)
   void feed(const Pauli& e, int rec) { emit(OP_CFEED, e.r ? F_SIGN : 0, 0, 0, push_pauli(e), (uint32_t)rec); }
 
+  // expectation-value probe of the virtual observable g: its W-word image,
+  // then the slot masks of its X and Z letters on active qubits; F_ZERO when
+  // it has X support on a dormant qubit (the value is then 0)
+  void probe(const Pauli& g, int idx) {
+    uint32_t xm = 0, zm = 0;
+    bool dormant_x = false;
+    for (int q = 0; q < n; q++) {
+      if (g.getx(q)) {
+        if (active(q)) xm |= 1u << slot_of[q];
+        else dormant_x = true;
+      }
+      if (g.getz(q) && active(q)) zm |= 1u << slot_of[q];
+    }
+    const uint32_t off = push_pauli(g);
+    push_mask(std::vector<uint64_t>{xm, zm});
+    emit(OP_EXPVAL, (uint8_t)((g.r ? F_SIGN : 0) | (dormant_x ? F_ZERO : 0)), 0, 0, off, (uint32_t)idx);
+  }
+
   // a phase exp(-i theta) of the global scalar only
   void global_phase(double theta) {
     if (!drop_phases) emit(OP_PHASE, 0, 0, 0, push_mask(std::vector<uint64_t>(W, 0)), push_angle(theta));
@@ -684,7 +705,7 @@ struct Compiler {
 // active operation whose generator is mapped through the physical Cliffords
 // only (the virtual basis before any localization), in program order.
 struct HNode {
-  enum Kind { ROT, MEAS, NOISE, CPAULI, DET, OBS, CFEED, GPHASE } kind;
+  enum Kind { ROT, MEAS, NOISE, CPAULI, DET, OBS, CFEED, GPHASE, PROBE } kind;
   Pauli g;          // ROT: exp(-i theta g); MEAS: the measured observable;
                     // CPAULI: image of X on the reset qubit
   double theta = 0;
@@ -719,7 +740,8 @@ static bool noise_commutes(const HNode& n, const Pauli& g) {
 // whether node n commutes with the operator exp(-i theta g) or a measurement of g
 static bool node_commutes(const HNode& n, const Pauli& g) {
   switch (n.kind) {
-    case HNode::ROT: case HNode::MEAS: case HNode::CPAULI: case HNode::CFEED: return commutes(n.g, g);
+    case HNode::ROT: case HNode::MEAS: case HNode::CPAULI: case HNode::CFEED: case HNode::PROBE:
+      return commutes(n.g, g);
     case HNode::NOISE: return noise_commutes(n, g);
     default: return true;  // detectors and observables are classical
   }
@@ -803,7 +825,9 @@ static void hir_reorder(std::vector<HNode>& h) {
     const size_t len = reset ? 2 : 1;
     while (j > 0) {
       const HNode& p = h[j - 1];
-      if (p.kind == HNode::CPAULI) break;  // a reset's correction stays with its measurement
+      // a reset's correction stays with its measurement; a probe's value
+      // would change if a measurement moved before it
+      if (p.kind == HNode::CPAULI || p.kind == HNode::PROBE) break;
       if (!node_commutes(p, h[j].g) || (reset && !node_commutes(p, h[j + 1].g))) break;
       // a measurement passed over must not be separated from its correction
       std::rotate(h.begin() + (long)(j - 1), h.begin() + (long)j, h.begin() + (long)(j + len));
@@ -870,6 +894,7 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
       case OP_MACTZ: c.flops += 5 * A; c.vector_bytes += 2 * A * a; c.int_ops += 110; break;
       case OP_MACTX: c.flops += 8 * A; c.vector_bytes += 2.5 * A * a; c.int_ops += 110; break;
       case OP_CPAULI: case OP_CFEED: c.int_ops += 16 * W; break;
+      case OP_EXPVAL: if (!(in.flags & F_ZERO)) { c.flops += 8 * A; c.vector_bytes += 2 * A * a; } break;
       case OP_NOISE: {
         double f = 0;
         for (uint32_t s = in.a; s < in.b; s++) f += P.site_p[s];
@@ -1004,7 +1029,7 @@ static void build_split(CompiledProgram& P) {
   int nact = 0;
   for (int cl : P.ev_class) nact += cl == 2;
   P.nactive = nact;
-  P.split_ok = P.kmax > 0 && nact <= kSplitMaxActive;
+  P.split_ok = P.kmax > 0 && nact <= kSplitMaxActive && P.nprobes == 0;
   if (!P.split_ok) return;
   const int DW = std::max(1, (nact + 63) / 64);
   P.dep_words = DW;
@@ -1232,6 +1257,7 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
         case K_MPP: C.measure(C.product(o.prod), rec++); break;
         case K_CFEED: C.feed(C.image(o.a, o.prod[0].second), o.refs[0]); break;
         case K_GPHASE: C.global_phase(o.arg); break;
+        case K_EXPVAL: C.probe(C.product(o.prod), o.obs); break;
         case K_M: C.measure(C.image(o.a, 'Z'), rec++); break;
         case K_MX: C.measure(C.image(o.a, 'X'), rec++); break;
         case K_MR: { int j = C.measure(C.image(o.a, 'Z'), rec++); C.reset_fix(C.ix[o.a], j); break; }
@@ -1263,6 +1289,7 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
         case K_PROT: nd.kind = HNode::ROT; nd.g = F.product(o.prod); nd.theta = o.arg; break;
         case K_CFEED: nd.kind = HNode::CFEED; nd.g = F.image(o.a, o.prod[0].second); nd.rec = o.refs[0]; break;
         case K_GPHASE: nd.kind = HNode::GPHASE; nd.g = Pauli(P.W); nd.theta = o.arg; break;
+        case K_EXPVAL: nd.kind = HNode::PROBE; nd.g = F.product(o.prod); nd.rec = o.obs; break;
         case K_MPP:
           nd.kind = HNode::MEAS;
           nd.g = F.product(o.prod);
@@ -1314,6 +1341,7 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
         case HNode::CPAULI: C.reset_fix(C.map(nd.g), nd.event); break;
         case HNode::CFEED: C.feed(C.map(nd.g), nd.rec); break;
         case HNode::GPHASE: C.global_phase(nd.theta); break;
+        case HNode::PROBE: C.probe(C.map(nd.g), nd.rec); break;
         case HNode::NOISE: {
           const int m = nd.op->ntype == S_DEP2 ? 4 : 2;
           Pauli img[4];
@@ -1413,7 +1441,7 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
   // and measurements whose successor's branch sums their collapse computes.
   {
     auto touches_vector = [](uint8_t op) {
-      return (op >= OP_APERM && op <= OP_AROT) || op == OP_MACTZ || op == OP_MACTX;
+      return (op >= OP_APERM && op <= OP_AROT) || op == OP_MACTZ || op == OP_MACTX || op == OP_EXPVAL;
     };
     auto is_meas = [](uint8_t op) { return op == OP_MACTZ || op == OP_MACTX; };
     std::vector<size_t> vecops;
@@ -1444,6 +1472,7 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
   survival_tables(P);
   if (P.masks.empty()) P.masks.push_back(0);
   for (const GInstr& in : P.code) P.has_cfeed = P.has_cfeed || in.op == OP_CFEED;
+  P.nprobes = ps.nprobes;
   build_split(P);
   if (P.consts.empty()) P.consts = {1.0, 0.0, 1.0, 0.0};
   if (P.refs.empty()) P.refs.push_back(0);

@@ -31,6 +31,7 @@ struct CompiledProgram {
   std::vector<uint8_t> rblk_ev;
   int rblk_max = 0;
   bool has_cfeed = false;          // feed-forward Paulis (need record bits: not on the bit-sliced kernels)
+  int nprobes = 0;                 // expectation-value probes (not on the bit-sliced kernels or the split form)
   // split form (program.h): valid when split_ok
   bool split_ok = false;
   int nactive = 0;                 // active measurement events

@@ -19,6 +19,7 @@ struct KArgs {
   double* probs;                 // [shots][nevents] P(m = 1) or null
   double* phi_out;               // [shots][2^kmax][2] or null
   double* gamma_out;             // [shots][2] global scalar (re, im) or null
+  double* expval;                // [nprobes][shots] expectation-value probes or null
   int* error;                    // device flag word (trace mode)
   // split form: needed-bit rows [nbits][ceil(shots/64)], written by the frame
   // stream and read by the vector stream

@@ -48,6 +48,8 @@ enum Op : uint8_t {
                //   row u + 1; H_v for F_XMEAS; then x_v = sign; record 0  v, u, b=event
   OP_CFEED,    // feed-forward Pauli (Appendix B.3): if record b is 1,     a=mask(x,z), b=record
                //   the full frame takes the image (sign in F_SIGN)
+  OP_EXPVAL,   // expectation value of a virtual observable (probe b):    a=mask(x,z) then the
+               //   slot masks of its active X and Z letters (2 words); F_SIGN, F_ZERO
   OP_COUNT
 };
 
@@ -65,6 +67,7 @@ constexpr uint8_t F_FOLD_NEXT = 8;
 // that one's branch sums (F_FUSE_NEXT), and it skips its own reduction.
 constexpr uint8_t F_FUSE_NEXT = 2;
 constexpr uint8_t F_XMEAS = 4;  // OP_MACTF: the measurement is X-type (interfere)
+constexpr uint8_t F_ZERO = 16;  // OP_EXPVAL: X support on a dormant qubit, the value is 0
 // Kernels that collapse out of place keep up to this many trailing
 // expansions unapplied: the vector is then the stored 2^(k-d) amplitudes
 // times one phase factor per deferred top slot (an expansion only multiplies
@@ -125,6 +128,7 @@ struct DevProgram {
   const uint8_t* rblk_ev;       // event ordinal mod 128 of each dormant random event of the block
   int32_t nq, W, kmax, ncode;
   int32_t nevents, nrec, ndet, nobs;
+  int32_t nprobes;
   int32_t nsites, nchunks;
   int32_t rblk_max;             // most dormant random events in one 128-event block
   int32_t ndet_rows;            // detector accumulator rows (observables follow them)

@@ -114,6 +114,7 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out, co
   v.nrec = H.nrec;
   v.ndet = H.ndet;
   v.nobs = H.nobs;
+  v.nprobes = H.nprobes;
   v.nsites = (int)H.site_p.size();
   v.nchunks = H.nchunks;
   v.rblk_max = H.rblk_max;
@@ -350,7 +351,7 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
     }
     const size_t rows_bytes = frames_lds_rows(tmp) * 64 * 4;
     const bool spec = c.specialize == 1;
-    const bool bs_ok = H.kmax == 0 && !trace && !H.has_cfeed && (spec || rows_bytes <= kLdsLimit);
+    const bool bs_ok = H.kmax == 0 && !trace && !H.has_cfeed && H.nprobes == 0 && (spec || rows_bytes <= kLdsLimit);
     if (c.specialize == 1 && G != 0 && G != kBitSliced)
       return fail(CLIFFT_E_INVALID_ARG, "specialize applies to the bit-sliced tier only");
     if ((G == kBitSliced || spec) && !bs_ok)
@@ -486,7 +487,7 @@ hipError_t launch_plan(const CompiledProgram& H, const DeviceCopy& dc, const Lau
 clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t offset,
                         const clifft_launch* cfg, void* ws, size_t ws_bytes, uint64_t* meas, uint64_t* det,
                         uint64_t* obs, void* stream, const uint32_t* forced_m, const int32_t* forced_faults,
-                        double* probs, double* phi, double* gamma, bool trace) {
+                        double* probs, double* phi, double* gamma, bool trace, double* expval = nullptr) {
   if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
   if (shots == 0) return CLIFFT_OK;
   const DevProgram* D = nullptr;
@@ -511,6 +512,7 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
   A.det = det;
   A.obs = obs;
   A.workspace = ws;
+  A.expval = expval;
   A.list_cap = 0xFFFFFFFFu;
   if (const char* cap = getenv("CLIFFT_FRAMES_LIST_CAP")) A.list_cap = (uint32_t)strtoul(cap, nullptr, 10);
   hipStream_t s = (hipStream_t)stream;
@@ -617,6 +619,7 @@ clifft_status clifft_program_info(const clifft_program* p, clifft_info* o) {
   for (int c : H.ev_class) { nr += c == 1; na += c == 2; }
   o->num_random_events = nr;
   o->num_active_events = na;
+  o->num_probes = H.nprobes;
   return CLIFFT_OK;
 }
 
@@ -704,6 +707,13 @@ clifft_status clifft_sample(const clifft_program* p, uint64_t shots, uint64_t se
                             uint64_t* det, uint64_t* obs, void* stream) {
   return do_sample(p, shots, seed, shot_offset, cfg, workspace, workspace_bytes, meas, det, obs, stream, nullptr,
                    nullptr, nullptr, nullptr, nullptr, false);
+}
+
+clifft_status clifft_sample_expval(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                                   const clifft_launch* cfg, void* workspace, size_t workspace_bytes, uint64_t* meas,
+                                   uint64_t* det, uint64_t* obs, double* expval, void* stream) {
+  return do_sample(p, shots, seed, shot_offset, cfg, workspace, workspace_bytes, meas, det, obs, stream, nullptr,
+                   nullptr, nullptr, nullptr, nullptr, false, expval);
 }
 
 clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,

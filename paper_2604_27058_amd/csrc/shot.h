@@ -1422,6 +1422,47 @@ struct Shot {
           frame_xor<W>(N, bx, bz);
           break;
         }
+        case OP_EXPVAL: {
+          // <psi|P|psi> (expectation-value probe): with the virtual observable
+          // g = U_C^dagger P U_C, the Pauli frame contributes (-1)^c (its
+          // commutation with g), and g acts on the active vector through its
+          // letters on active slots (Z on a dormant |0> is 1; X there gives 0):
+          // <phi|g_A|phi> / <phi|phi>, summed in FP64
+          uint64_t gx[W], gz[W];
+#pragma unroll
+          for (int w = 0; w < W; w++) {
+            gx[w] = masks[in.a + w];
+            gz[w] = masks[in.a + W + w];
+          }
+          const uint32_t c = parity_and<W>(T.x, gz) ^ parity_and<W>(T.z, gx) ^ (uint32_t)(in.flags & F_SIGN);
+          double e = 0;
+          if (!(in.flags & F_ZERO)) {
+            if constexpr (VEC) {
+              materialize();
+              const uint32_t xm = (uint32_t)masks[in.a + 2 * W], zm = (uint32_t)masks[in.a + 2 * W + 1];
+              double sre = 0, sim = 0, nrm = 0;
+              FOR_GROUP(i, (1u << k)) {
+                const cpx<R> a = vec[i], b = vec[i ^ xm];
+                // conj(a) * (-1)^{|(i ^ xm) & zm|} * b
+                const double sg = (__popc((i ^ xm) & zm) & 1) ? -1.0 : 1.0;
+                sre += sg * ((double)a.re * b.re + (double)a.im * b.im);
+                sim += sg * ((double)a.re * b.im - (double)a.im * b.re);
+                nrm += norm2(a);
+              }
+              sre = grp.sum(sre, red);
+              sim = grp.sum(sim, red);
+              nrm = grp.sum(nrm, red);
+              // times i^{|xm & zm|} (one i per Y letter), real part
+              const int ny = __popc(xm & zm) & 3;
+              const double re = ny == 0 ? sre : ny == 1 ? -sim : ny == 2 ? -sre : sim;
+              e = re / nrm;
+            } else {
+              e = 1.0;  // k_max = 0: the active vector is [1] and g has no X support
+            }
+          }
+          if (A.expval && writer()) A.expval[(size_t)in.b * A.shots + local] = c ? -e : e;
+          break;
+        }
         case OP_CFEED: {
           // feed-forward Pauli (Appendix B.3) on the full frame when record b
           // of this shot is 1; the noise frame only follows physical faults

@@ -316,7 +316,7 @@ class Dense:
         ez = np.zeros(n, np.uint8)
         G = Stabilizers(n)
         faults = forced_faults if forced_faults is not None else self.faults(seed, shot)
-        recs, ms, probs, classes, ks, dets, obs = [], [], [], [], [], [], {}
+        recs, ms, probs, classes, ks, dets, obs, exps = [], [], [], [], [], [], {}, []
         site = 0
         j = 0
         rbits = {}
@@ -428,6 +428,10 @@ class Dense:
             elif name == "MPP":
                 for t in tg:
                     measure_product(t[1])
+            elif name == "EXP_VAL":
+                for t in tg:
+                    nrm = np.vdot(psi, psi).real
+                    exps.append(float(np.vdot(psi, apply_pauli_letters(psi, n, t[1])).real / nrm))
             elif name in ("CX", "CNOT", "CZ", "SWAP"):
                 g = "CX" if name == "CNOT" else name
                 for i in range(0, len(tg), 2):
@@ -476,7 +480,8 @@ class Dense:
         nobs = max(obs) + 1 if obs else 0
         return dict(psi=psi, recs=np.array(recs, np.uint8), m=np.array(ms, np.uint8), probs=np.array(probs),
                     classes=classes, kmax=max(ks) if ks else 0, dets=np.array(dets, np.uint8),
-                    obs=np.array([obs.get(i, 0) for i in range(nobs)], np.uint8), faults=faults)
+                    obs=np.array([obs.get(i, 0) for i in range(nobs)], np.uint8), faults=faults,
+                    expvals=np.array(exps))
 
 
 # ---------------------------------------------------------------- oracle state -> dense vector

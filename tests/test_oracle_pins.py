@@ -215,13 +215,16 @@ def _product(rng, n):
     return "*".join("%s%d" % ("XYZ"[int(rng.integers(0, 3))], q) for q in qs)
 
 
-def random_wide_circuit(rng, n, nops, p_noise=0.08):
+def random_wide_circuit(rng, n, nops, p_noise=0.08, probes=False):
     """random_small_circuit's operations plus the wider gate set: R_X, R_Y,
     U3, rotations about Pauli products, product measurements (MPP) and
-    record-controlled Paulis."""
+    record-controlled Paulis; with probes, expectation-value probes of
+    random Pauli products (EXP_VAL) between them."""
     body = []
     nrec = 0
     for _ in range(nops):
+        if probes and rng.random() < 0.15:
+            body.append("EXP_VAL %s" % _product(rng, n))
         r = rng.random()
         q = int(rng.integers(0, n))
         if r < 0.2:
@@ -294,6 +297,28 @@ def test_product_measurements_and_feed_forward():
     assert popcount_rows(m[1:2], 4096)[0] == 0
 
 
+def test_expectation_probes_t_state():
+    """Appendix C: for |T> = T H |0>, <X> = <Y> = 1/sqrt(2) and <Z> = 0;
+    the probes read the state without changing it (the measurement after
+    them still sees P(X = -1) of the T state)."""
+    t = oracle.Program("H 0\nT 0\nEXP_VAL X0 Y0 Z0\nMX 0\n").trace()
+    r = 1 / math.sqrt(2)
+    np.testing.assert_allclose(t["expvals"], [r, r, 0.0], atol=1e-15)
+    assert abs(t["probs"][0] - (1 - r) / 2) < 1e-15
+    # a probe behind a Clifford frame and a Pauli frame: X on the T state
+    # conjugated by CX into a two-qubit observable, and a frame flip by X
+    t = oracle.Program("H 0\nT 0\nCX 0 1\nX 1\nEXP_VAL X0*X1 Y0*X1 Z0*Z1 Z1\n").trace()
+    np.testing.assert_allclose(t["expvals"], [r, r, -1.0, 0.0], atol=1e-15)
+
+
+@pytest.mark.parametrize("case", range(20))
+def test_oracle_matches_dense_probes(case):
+    rng = np.random.default_rng(8600 + case)
+    text = random_wide_circuit(rng, int(rng.integers(2, 6)), int(rng.integers(10, 40)), probes=True)
+    for shot in range(3):
+        _compare_shot(text, seed=case, shot=shot, check_state=(shot == 0))
+
+
 @pytest.mark.parametrize("case", range(30))
 def test_oracle_matches_dense_wide_gate_set(case):
     rng = np.random.default_rng(8100 + case)
@@ -333,6 +358,7 @@ def _compare_shot(text, seed, shot, check_state=True, forced=False, rng=None):
     assert np.array_equal(t["dets"], d["dets"])
     assert np.array_equal(t["obs"], d["obs"][: len(t["obs"])])
     np.testing.assert_allclose(t["probs"], d["probs"], atol=1e-12)
+    np.testing.assert_allclose(t["expvals"], d["expvals"], atol=1e-12)
     if check_state:
         fr = t["frame"]
         psi_o = dense_ref.oracle_state_to_dense(prog.nq, prog.uclog(), fr[0], fr[1], t["phi"], t["slots"],
