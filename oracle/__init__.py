@@ -48,8 +48,16 @@ def lib():
         L.oracle_gap_next.restype = i32
         L.oracle_trace.argtypes = [vp, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_trace.restype = i32
-        L.oracle_sample.argtypes = [vp, u64, u64, u64, i32, vp, vp, vp, vp]
+        L.oracle_sample.argtypes = [vp, u64, u64, u64, i32, vp, vp, vp, vp, i32]
         L.oracle_sample.restype = i32
+        L.oracle_fault_pmf.argtypes = [vp, i32, vp]
+        L.oracle_fault_pmf.restype = i32
+        L.oracle_faults_strat.argtypes = [vp, i32, u64, u64, vp]
+        L.oracle_faults_strat.restype = i32
+        L.oracle_strat_survival.argtypes = [vp, i32, i32, i32]
+        L.oracle_strat_survival.restype = ctypes.c_double
+        L.oracle_set_postselect.argtypes = [vp, vp, i32]
+        L.oracle_set_postselect.restype = i32
         _lib = L
     return _lib
 
@@ -78,7 +86,9 @@ class OracleError(RuntimeError):
 class Program:
     """A circuit compiled by the oracle (the Stim-like text subset its parser accepts)."""
 
-    def __init__(self, text):
+    def __init__(self, text, postselect=None):
+        """postselect: None, "all", or an iterable of detector indices whose
+        reading 1 rejects the shot (Section 3.2, post-selection)."""
         L = lib()
         h = ctypes.c_void_p()
         err = ctypes.create_string_buffer(512)
@@ -91,6 +101,15 @@ class Program:
         L.oracle_info(h, info)
         (self.nq, self.kmax, self.nevents, self.nrec, self.ndet, self.nobs, self.nsites, self.nops,
          self.nchunks, self.nprobes) = [int(v) for v in info]
+        if postselect is not None:
+            idx = range(self.ndet) if isinstance(postselect, str) and postselect == "all" else list(postselect)
+            mask = np.zeros(max((self.ndet + 63) // 64, 1), np.uint64)
+            for d in idx:
+                if not 0 <= d < self.ndet:
+                    raise OracleError("post-selected detector %d out of range" % d)
+                mask[d // 64] |= np.uint64(1) << np.uint64(d % 64)
+            if L.oracle_set_postselect(h, mask.ctypes.data, len(mask)) != 0:
+                raise OracleError("bad post-selection mask")
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -126,6 +145,25 @@ class Program:
         lib().oracle_faults(self._h, seed, shot, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
         return out[: self.nsites]
 
+    def fault_pmf(self, rmax):
+        """P(exactly r noise sites fire), r = 0 .. rmax (Poisson-binomial)."""
+        out = np.zeros(rmax + 1)
+        if lib().oracle_fault_pmf(self._h, rmax, out.ctypes.data) != 0:
+            raise OracleError("bad rmax")
+        return out
+
+    def faults_strat(self, r, seed, shot):
+        """Per-site fault outcome (or -1) of one shot conditioned on r faults."""
+        out = np.zeros(max(self.nsites, 1), dtype=np.int32)
+        rc = lib().oracle_faults_strat(self._h, r, seed, shot, out.ctypes.data)
+        if rc:
+            raise OracleError("stratum of %d faults: error %d" % (r, rc))
+        return out[: self.nsites]
+
+    def strat_survival(self, s, j, t):
+        """P(next fault at or after site t | s faults left among sites j..N-1)."""
+        return float(lib().oracle_strat_survival(self._h, s, j, t))
+
     def trace(self, seed=0, shot=0, forced_m=None, forced_faults=None):
         """Run one shot and return everything it produced (dict)."""
         ne, nr = max(self.nevents, 1), max(self.nrec, 1)
@@ -155,16 +193,18 @@ class Program:
                     gamma=complex(gamma[0], gamma[1]), faults=faults[: self.nsites],
                     frame=frame.reshape(4, self.nq), expvals=expvals[: self.nprobes])
 
-    def sample(self, shots, seed=0, offset=0, threads=1, expvals=False):
+    def sample(self, shots, seed=0, offset=0, threads=1, expvals=False, faults=None):
         """Bit-packed record-major outputs (meas, det, obs), each [count, ceil(shots/64)] uint64,
-        and with expvals=True also the probes' values [nprobes, shots] (float64)."""
+        and with expvals=True also the probes' values [nprobes, shots] (float64).
+        faults=r: every shot conditioned on exactly r faults (stratified)."""
         words = (shots + 63) // 64
         meas = np.zeros((max(self.nrec, 1), max(words, 1)), np.uint64)
         det = np.zeros((max(self.ndet, 1), max(words, 1)), np.uint64)
         obs = np.zeros((max(self.nobs, 1), max(words, 1)), np.uint64)
         ev = np.zeros((max(self.nprobes, 1), max(shots, 1))) if expvals else None
         rc = lib().oracle_sample(self._h, shots, seed, offset, threads, meas.ctypes.data, det.ctypes.data,
-                                 obs.ctypes.data, None if ev is None else ev.ctypes.data)
+                                 obs.ctypes.data, None if ev is None else ev.ctypes.data,
+                                 -1 if faults is None else int(faults))
         if rc:
             raise OracleError("oracle sample error %d" % rc)
         out = (meas[: self.nrec, :words], det[: self.ndet, :words], obs[: self.nobs, :words])

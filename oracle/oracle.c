@@ -67,6 +67,7 @@ static void philox(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out
 #define PURPOSE_NOISE 0x4E000000u /* | chunk */
 #define PURPOSE_RBIT 0x52000000u
 #define PURPOSE_AMEAS 0x41000000u
+#define PURPOSE_STRAT 0x53000000u /* stratified sampling: fault i of the shot */
 
 static void draw(uint32_t index, uint32_t purpose, uint64_t shot, uint64_t seed, uint32_t out[4])
 {
@@ -589,6 +590,9 @@ typedef struct {
      * side 1 = right by V^dagger of a virtual gate. */
     int *uclog;
     int nuclog, capuclog;
+    /* post-selected detectors (Section 3.2, post-selection): per detector 1
+     * if a shot whose detector reads 1 is rejected there */
+    uint8_t *det_post;
 } program;
 
 static void prog_push(program *P, oop o)
@@ -973,6 +977,7 @@ static void prog_free(program *P)
     free(P->sites);
     free(P->event_class);
     free(P->event_rec);
+    free(P->det_post);
     for (int c = 0; c < P->nchunks; c++) free(P->surv[c]);
     free(P->surv);
     free(P->chunk_len);
@@ -1098,6 +1103,7 @@ typedef struct {
     uint8_t *det;
     uint8_t *obs;
     double *probe;  /* per probe: expectation value */
+    int rejected;   /* a post-selected detector read 1 */
 } shot_state;
 
 static double complex ipow(int e)
@@ -1180,6 +1186,8 @@ static void shot_init(shot_state *S, const program *P)
     memset(S->ev_pn, 0, (size_t)(P->nevents + 1));
     memset(S->det, 0, (size_t)(P->ndet + 1));
     memset(S->obs, 0, (size_t)(P->nobs + 1));
+    memset(S->probe, 0, sizeof(double) * (size_t)(P->nprobes + 1));
+    S->rejected = 0;
 }
 
 static shot_state *shot_alloc(const program *P)
@@ -1278,6 +1286,8 @@ typedef struct {
     const int *fault_at_site; /* per site forced outcome index or -1, or NULL */
     double *probs;            /* per event P(m = 1), or NULL */
     int error;
+    int strat_r;              /* >= 0: exactly this many faults (stratified) */
+    const double *strat_q;    /* its tail pmf table (strat_tail_pmf) */
 } run_opts;
 
 /* Outcome index -> (x,z) letters of the fired Pauli on each qubit. */
@@ -1355,6 +1365,72 @@ static void draw_faults(const program *P, uint64_t shot, uint64_t seed, int *fau
     }
 }
 
+/* Stratified fault sampling (Section 3.2, rare-event sampling).  Shots are
+ * conditioned on exactly r of the N noise sites firing.  Site l fires on its
+ * own with probability p_l, so the fault count is Poisson-binomial, and
+ *   Q[t][s] = P(exactly s of the sites t .. N-1 fire)
+ * satisfies Q[N][0] = 1, Q[N][s > 0] = 0 and
+ *   Q[t][s] = (1 - p_t) Q[t+1][s] + p_t Q[t+1][s-1]
+ * (condition on site t).  Layout Q[t * (r + 1) + s], t = 0..N, s = 0..r.
+ * Plain FP64 products: the table underflows once the probability of no
+ * fault at all drops below about 1e-300. */
+static double *strat_tail_pmf(const program *P, int r)
+{
+    const int N = P->nsites;
+    const size_t R = (size_t)r + 1;
+    double *Q = (double *)calloc((size_t)(N + 1) * R, sizeof(double));
+    Q[(size_t)N * R] = 1.0;
+    for (int t = N - 1; t >= 0; t--) {
+        const double p = P->sites[t].p;
+        for (int s = 0; s <= r; s++) {
+            double v = (1.0 - p) * Q[(size_t)(t + 1) * R + s];
+            if (s > 0) v += p * Q[(size_t)(t + 1) * R + s - 1];
+            Q[(size_t)t * R + s] = v;
+        }
+    }
+    return Q;
+}
+
+/* The next fault, given that s faults are still to be placed among the
+ * sites j .. N-1, lies at or after site t >= j with probability
+ *   survival(t) = P(none of j .. t-1 fires) Q[t][s] / Q[j][s]
+ * (no fault in between, all s of them from t on).  Inverse transform: for
+ * a uniform u the fault is at the smallest t >= j with survival(t+1) <= u,
+ * which is at most N - s because Q[t][s] = 0 when fewer than s sites
+ * remain. */
+static int strat_next(const program *P, const double *Q, int r, int s, int j, double u)
+{
+    const size_t R = (size_t)r + 1;
+    const double qj = Q[(size_t)j * R + s];
+    double none = 1.0; /* P(none of j .. t fires) */
+    int t = j;
+    for (;; t++) {
+        none *= 1.0 - P->sites[t].p;
+        if (none * Q[(size_t)(t + 1) * R + s] / qj <= u || t + 1 >= P->nsites) break;
+    }
+    return t;
+}
+
+/* Exactly r faults per shot: fault i (i = 0 .. r-1, in site order) is placed
+ * by draw i of purpose STRAT from one past the previous fault; its fired
+ * Pauli comes from the same draw's 64-bit word as in draw_faults.  Returns
+ * 4 when no configuration has r faults (Q[0][r] = 0). */
+static int draw_faults_strat(const program *P, int r, const double *Q, uint64_t shot, uint64_t seed, int *fault_at_site)
+{
+    for (int s = 0; s < P->nsites; s++) fault_at_site[s] = -1;
+    if (!(Q[r] > 0.0)) return 4;
+    int j = 0;
+    for (int i = 0; i < r; i++) {
+        uint32_t w[4];
+        draw((uint32_t)i, PURPOSE_STRAT, shot, seed, w);
+        const int t = strat_next(P, Q, r, r - i, j, uniform53(w));
+        const uint64_t w64 = ((uint64_t)w[3] << 32) | w[2];
+        fault_at_site[t] = (int)(((unsigned __int128)w64 * (unsigned)noise_nout(P->sites[t].type)) >> 64);
+        j = t + 1;
+    }
+    return 0;
+}
+
 static int rbit(uint64_t shot, uint64_t seed, int j)
 {
     uint32_t w[4];
@@ -1388,6 +1464,7 @@ static void run_shot(const program *P, shot_state *S, uint64_t shot, uint64_t se
 {
     shot_init(S, P);
     if (ro->fault_at_site) memcpy(faults, ro->fault_at_site, sizeof(int) * (size_t)P->nsites);
+    else if (ro->strat_r >= 0) draw_faults_strat(P, ro->strat_r, ro->strat_q, shot, seed, faults);
     else draw_faults(P, shot, seed, faults);
     const double rs2 = 1.0 / sqrt(2.0);
     for (int oi = 0; oi < P->nops; oi++) {
@@ -1558,6 +1635,13 @@ static void run_shot(const program *P, shot_state *S, uint64_t shot, uint64_t se
             int d = 0;
             for (int r = 0; r < o->nref; r++) d ^= S->rec[o->refs[r]];
             S->det[o->rec] = (uint8_t)d;
+            if (d && P->det_post && P->det_post[o->rec]) {
+                /* rejected: the shot ends here; its observables read 0 and
+                 * every later record stays 0 */
+                S->rejected = 1;
+                memset(S->obs, 0, (size_t)(P->nobs + 1));
+                return;
+            }
             break; }
         case O_OBS: {
             int d = 0;
@@ -1663,7 +1747,7 @@ int oracle_trace(void *h, uint64_t seed, uint64_t shot, const uint8_t *forced_m,
 {
     program *P = (program *)h;
     shot_state *S = shot_alloc(P);
-    run_opts ro = {forced_m, forced_faults, probs, 0};
+    run_opts ro = {forced_m, forced_faults, probs, 0, -1, NULL};
     int *fl = (int *)malloc(sizeof(int) * (size_t)(P->nsites + 1));
     run_shot(P, S, shot, seed, &ro, fl);
     if (ev_m) memcpy(ev_m, S->ev_m, (size_t)P->nevents);
@@ -1698,6 +1782,8 @@ typedef struct {
     uint64_t s0, s1, offset, seed, words, shots;
     uint64_t *meas, *det, *obs;
     double *expvals;  /* [nprobes][shots] or NULL */
+    int strat_r;      /* stratified: faults per shot, or -1 */
+    const double *strat_q;
     int error;
 } job;
 
@@ -1707,7 +1793,7 @@ static void *sample_worker(void *arg)
     program *P = J->P;
     shot_state *S = shot_alloc(P);
     int *fl = (int *)malloc(sizeof(int) * (size_t)(P->nsites + 1));
-    run_opts ro = {NULL, NULL, NULL, 0};
+    run_opts ro = {NULL, NULL, NULL, 0, J->strat_r, J->strat_q};
     for (uint64_t s = J->s0; s < J->s1; s++) {
         run_shot(P, S, J->offset + s, J->seed, &ro, fl);
         uint64_t w = s >> 6, bit = (uint64_t)1 << (s & 63);
@@ -1731,12 +1817,19 @@ static void *sample_worker(void *arg)
 
 /* Sample `shots` shots with global indices offset .. offset+shots-1.
  * Outputs are record-major bit-packed: out[r * ceil(shots/64) + s/64] bit
- * s%64; the caller zero-fills them. */
+ * s%64; the caller zero-fills them.  strat_r >= 0: every shot has exactly
+ * that many faults (draw_faults_strat); returns 4 if that count is
+ * impossible. */
 int oracle_sample(void *h, uint64_t shots, uint64_t seed, uint64_t offset, int nthreads, uint64_t *meas, uint64_t *det,
-                  uint64_t *obs, double *expvals)
+                  uint64_t *obs, double *expvals, int strat_r)
 {
     program *P = (program *)h;
     uint64_t words = (shots + 63) / 64;
+    double *Q = NULL;
+    if (strat_r >= 0) {
+        Q = strat_tail_pmf(P, strat_r);
+        if (!(Q[strat_r] > 0.0)) { free(Q); return 4; }
+    }
     if (nthreads < 1) nthreads = 1;
     if ((uint64_t)nthreads > words) nthreads = (int)(words ? words : 1);
     job *jobs = (job *)calloc((size_t)nthreads, sizeof(job));
@@ -1754,6 +1847,8 @@ int oracle_sample(void *h, uint64_t shots, uint64_t seed, uint64_t offset, int n
         jobs[t].obs = obs;
         jobs[t].expvals = expvals;
         jobs[t].shots = shots;
+        jobs[t].strat_r = strat_r;
+        jobs[t].strat_q = Q;
         pthread_create(&th[t], NULL, sample_worker, &jobs[t]);
     }
     int err = 0;
@@ -1763,5 +1858,57 @@ int oracle_sample(void *h, uint64_t shots, uint64_t seed, uint64_t offset, int n
     }
     free(jobs);
     free(th);
+    free(Q);
     return err;
+}
+
+/* Poisson-binomial distribution of the number of faults over all noise
+ * sites (Section 3.2, rare-event sampling: the weight of the stratum of r
+ * faults): pmf[r] = Q[0][r], r = 0 .. rmax. */
+int oracle_fault_pmf(void *h, int rmax, double *pmf)
+{
+    program *P = (program *)h;
+    if (rmax < 0) return -1;
+    double *Q = strat_tail_pmf(P, rmax);
+    memcpy(pmf, Q, sizeof(double) * (size_t)(rmax + 1));
+    free(Q);
+    return 0;
+}
+
+/* The faults of one stratified shot (per site: outcome index or -1). */
+int oracle_faults_strat(void *h, int r, uint64_t seed, uint64_t shot, int *fault_at_site)
+{
+    program *P = (program *)h;
+    if (r < 0) return -1;
+    double *Q = strat_tail_pmf(P, r);
+    int rc = draw_faults_strat(P, r, Q, shot, seed, fault_at_site);
+    free(Q);
+    return rc;
+}
+
+/* survival(t) of strat_next for s faults left among the sites j .. N-1. */
+double oracle_strat_survival(void *h, int s, int j, int t)
+{
+    program *P = (program *)h;
+    double *Q = strat_tail_pmf(P, s);
+    const size_t R = (size_t)s + 1;
+    double none = 1.0;
+    for (int l = j; l < t; l++) none *= 1.0 - P->sites[l].p;
+    double v = none * Q[(size_t)t * R + s] / Q[(size_t)j * R + s];
+    free(Q);
+    return v;
+}
+
+/* Mark post-selected detectors: bit d of mask[d / 64] (nwords words).
+ * Returns -1 if a set bit names no detector. */
+int oracle_set_postselect(void *h, const uint64_t *mask, int nwords)
+{
+    program *P = (program *)h;
+    for (int w = 0; w < nwords; w++)
+        for (int b = 0; b < 64; b++)
+            if (((mask[w] >> b) & 1u) && (int64_t)w * 64 + b >= P->ndet) return -1;
+    free(P->det_post);
+    P->det_post = (uint8_t *)calloc((size_t)P->ndet + 1, 1);
+    for (int d = 0; d < P->ndet && d / 64 < nwords; d++) P->det_post[d] = (uint8_t)((mask[d / 64] >> (d % 64)) & 1u);
+    return 0;
 }
