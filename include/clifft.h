@@ -75,6 +75,7 @@ typedef struct clifft_info {
   int32_t num_random_events; /* dormant random measurements (Appendix B.2) */
   int32_t num_active_events; /* measurements on the active vector */
   int32_t num_probes;        /* expectation-value probes (EXP_VAL) */
+  int32_t num_postselected;  /* post-selected detectors (clifft_compile_opts) */
 } clifft_info;
 
 /* Launch configuration; zero-initialize for automatic choices. */
@@ -130,6 +131,24 @@ typedef struct clifft_compile_opts {
                           phase of the global scalar (rotations about dormant
                           Z strings, Appendix B.1 case 1); the trace call's
                           global scalar then misses those phases.  0: keep */
+  const uint64_t* postselect; /* post-selected detectors (Section 3.2,
+                          post-selection overhead), host memory read during
+                          the call: bit d % 64 of word d / 64 set for
+                          detector d, in the order DETECTOR instructions
+                          appear; NULL for none.  Each becomes an
+                          OP_POSTSELECT instruction: a shot whose detector
+                          reads 1 is rejected and ends there.  Its records up
+                          to that detector (which reads 1) are written as
+                          usual; every later measurement and detector record,
+                          every observable record and every probe not yet
+                          reached read 0.  So a shot was kept iff all its
+                          post-selected detectors read 0.  Records of kept
+                          shots equal those of the same program without
+                          post-selection.  Such programs do not use the split
+                          form or the specialized kernel.  E_INVALID_ARG if a
+                          set bit names no detector. */
+  int32_t postselect_words; /* words in postselect (0 with NULL), or -1 to
+                          post-select every detector (postselect ignored) */
 } clifft_compile_opts;
 
 /* Compile circuit text (len bytes, need not be NUL-terminated) into a
@@ -247,6 +266,35 @@ clifft_status clifft_sample(const clifft_program* p, uint64_t shots, uint64_t se
 clifft_status clifft_sample_expval(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
                                    const clifft_launch* cfg, void* workspace, size_t workspace_bytes, uint64_t* meas,
                                    uint64_t* det, uint64_t* obs, double* expval, void* stream);
+
+/* Stratified sampling (Section 3.2, rare-event sampling: batches conditioned
+ * on a fixed number of realized faults, weighted by the probability of that
+ * number).  Like clifft_sample, except that every shot has exactly `faults`
+ * noise sites firing, the set drawn from the distribution of independent
+ * sites conditioned on that count: fault i of shot s (in site order) is the
+ * inverse-transform draw i of the Philox stream of purpose 0x53000000 from
+ * one past the previous fault, with P(next fault at or after site t | f
+ * faults left from site j on) = e_f(t) / e_f(j), e_f(t) the elementary
+ * symmetric polynomial of degree f of the odds p / (1 - p) of the sites
+ * t .. N-1; the fired Pauli comes from the same draw as in plain sampling.
+ * Weight the stratum by clifft_fault_count_pmf.  The first call for a fault
+ * count uploads tables of (faults x num_noise_sites) doubles to the device
+ * (kept with the program; at most 1 GiB, else E_CAPACITY).  Runs on the
+ * interpreter tiers and the bit-sliced tier; E_INVALID_ARG if cfg asks for
+ * the split form or the specialized kernel, if faults < 0 or exceeds the
+ * number of sites, or if no configuration has that many faults;
+ * E_UNSUPPORTED if a site has probability 1. */
+clifft_status clifft_sample_stratified(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                                       int32_t faults, const clifft_launch* cfg, void* workspace,
+                                       size_t workspace_bytes, uint64_t* meas, uint64_t* det, uint64_t* obs,
+                                       void* stream);
+
+/* Weights of the strata (Section 3.2, rare-event sampling): pmf[r] = the
+ * probability that exactly r noise sites fire, r = 0 .. rmax (Poisson-
+ * binomial over the sites' probabilities), into host memory of rmax + 1
+ * doubles.  Host only.  E_UNSUPPORTED if a site has probability 1,
+ * E_CAPACITY if the weights overflow. */
+clifft_status clifft_fault_count_pmf(const clifft_program* p, int32_t rmax, double* pmf);
 
 /* Allocation-free sampling, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -27,7 +27,7 @@ class clifft_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "num_qubits", "frame_words", "k_max", "num_events", "num_measurements", "num_detectors",
         "num_observables", "num_noise_sites", "num_instructions", "num_random_events", "num_active_events",
-        "num_probes")]
+        "num_probes", "num_postselected")]
 
 
 class clifft_cost(ctypes.Structure):
@@ -37,7 +37,8 @@ class clifft_cost(ctypes.Structure):
 
 
 class clifft_compile_opts(ctypes.Structure):
-    _fields_ = [("hir_passes", ctypes.c_int32), ("k_limit", ctypes.c_int32), ("drop_phases", ctypes.c_int32)]
+    _fields_ = [("hir_passes", ctypes.c_int32), ("k_limit", ctypes.c_int32), ("drop_phases", ctypes.c_int32),
+                ("postselect", ctypes.POINTER(ctypes.c_uint64)), ("postselect_words", ctypes.c_int32)]
 
 
 class clifft_launch(ctypes.Structure):
@@ -68,6 +69,9 @@ def lib():
                                            vp]
         L.clifft_sample_trace.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, vp, vp, vp, vp, vp,
                                           sz, vp, vp, vp, vp]
+        L.clifft_sample_stratified.argtypes = [vp, u64, u64, u64, ctypes.c_int32, ctypes.POINTER(clifft_launch), vp,
+                                               sz, vp, vp, vp, vp]
+        L.clifft_fault_count_pmf.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
         L.clifft_cost_model.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(clifft_cost)]
         L.clifft_resolve_launch.argtypes = [vp, ctypes.POINTER(clifft_launch), u64, ctypes.POINTER(clifft_launch)]
         L.clifft_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(u64), ctypes.POINTER(u64),
@@ -85,7 +89,7 @@ def lib():
         L.clifft_last_error.restype = ctypes.c_char_p
         for f in ("clifft_compile", "clifft_program_info", "clifft_k_profile", "clifft_event_classes",
                   "clifft_final_slots", "clifft_workspace_size", "clifft_sample", "clifft_sample_noalloc",
-                  "clifft_sample_expval",
+                  "clifft_sample_expval", "clifft_sample_stratified", "clifft_fault_count_pmf",
                   "clifft_sample_trace",
                   "clifft_cost_model", "clifft_resolve_launch", "clifft_batch_create", "clifft_batch_sizes",
                   "clifft_batch_layout", "clifft_batch_sample", "clifft_autotune", "clifft_specialize",
@@ -115,12 +119,27 @@ def make_launch(precision="f32", threads_per_shot=0, grid=0, vector_in_hbm=0, sp
 
 class Program:
     """A compiled circuit (clifft_compile; keyword options as in
-    clifft_compile_opts)."""
+    clifft_compile_opts; postselect: None, "all" or detector indices)."""
 
-    def __init__(self, text, hir_passes=0, k_limit=0, drop_phases=0):
+    def __init__(self, text, hir_passes=0, k_limit=0, drop_phases=0, postselect=None):
         h = ctypes.c_void_p()
         b = text.encode()
         opts = clifft_compile_opts(hir_passes, k_limit, drop_phases)
+        mask = None
+        if isinstance(postselect, str):
+            if postselect != "all":
+                raise ValueError("postselect: 'all' or detector indices")
+            opts.postselect_words = -1  # every detector
+        elif postselect is not None:
+            idx = [int(d) for d in postselect]
+            if any(d < 0 for d in idx):
+                raise ValueError("postselect: negative detector index")
+            words = max((max(idx, default=-1) + 64) // 64, 1)
+            mask = (ctypes.c_uint64 * words)()
+            for d in idx:
+                mask[d // 64] |= 1 << (d % 64)
+            opts.postselect = ctypes.cast(mask, ctypes.POINTER(ctypes.c_uint64))
+            opts.postselect_words = words
         _check(lib().clifft_compile(b, len(b), ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
         inf = clifft_info()
@@ -128,6 +147,12 @@ class Program:
         self.info = {f: getattr(inf, f) for f, _ in clifft_info._fields_}
         for f, _ in clifft_info._fields_:
             setattr(self, f, getattr(inf, f))
+        if postselect is None:
+            self.postselected = []
+        elif isinstance(postselect, str):
+            self.postselected = list(range(self.num_detectors))
+        else:
+            self.postselected = sorted(set(int(d) for d in postselect))
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib is not None:
@@ -229,6 +254,38 @@ class Program:
                                           0 if workspace is None else workspace.numel(), ptr(meas), ptr(det),
                                           ptr(obs), ptr(ev), s.cuda_stream))
         return (meas, det, obs), ev[: self.num_probes]
+
+    def sample_stratified(self, shots, faults, seed=0, offset=0, launch=None, outputs=None, workspace=None,
+                          stream=None):
+        """clifft_sample_stratified: every shot with exactly `faults` faults;
+        returns (meas, det, obs) as sample() does."""
+        import torch
+        meas, det, obs = outputs if outputs is not None else self.alloc_outputs(shots)
+        if workspace is None:
+            workspace = self.alloc_workspace(launch, shots=shots)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        ptr = lambda t: t.data_ptr() if (t is not None and t.numel()) else None
+        _check(lib().clifft_sample_stratified(self._h, shots, seed, offset, faults,
+                                              None if launch is None else ctypes.byref(launch), ptr(workspace),
+                                              0 if workspace is None else workspace.numel(), ptr(meas), ptr(det),
+                                              ptr(obs), s.cuda_stream))
+        return meas, det, obs
+
+    def fault_count_pmf(self, rmax):
+        """clifft_fault_count_pmf: P(exactly r faults), r = 0 .. rmax (list)."""
+        out = (ctypes.c_double * (rmax + 1))()
+        _check(lib().clifft_fault_count_pmf(self._h, rmax, out))
+        return list(out)
+
+    def kept(self, det):
+        """Kept-shot mask words (int64 tensor, one row) from the detector
+        rows of a post-selected program: a shot is kept iff all its
+        post-selected detectors read 0."""
+        import torch
+        keep = torch.full((det.shape[1],), -1, dtype=torch.int64, device=det.device)
+        for d in self.postselected:
+            keep &= ~det[d]
+        return keep
 
     def sample_noalloc(self, shots, seed=0, offset=0, launch=None, outputs=None, stream=None):
         """Queue clifft_sample_noalloc (no workspace argument; the library's

@@ -902,7 +902,7 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
         c.int_ops += 2 + f * (158 + 24 * W);
         break;
       }
-      case OP_DET: case OP_OBS: c.int_ops += in.u * 2.0 / 64.0; break;
+      case OP_DET: case OP_POSTSELECT: case OP_OBS: c.int_ops += in.u * 2.0 / 64.0; break;
       default: break;
     }
   }
@@ -1006,7 +1006,7 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
           per_shot += f * 166;
           break;
         }
-        case OP_DET: shared += 1; break;
+        case OP_DET: case OP_POSTSELECT: shared += 1; break;
         default: break;
       }
     }
@@ -1474,6 +1474,27 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
   for (const GInstr& in : P.code) P.has_cfeed = P.has_cfeed || in.op == OP_CFEED;
   P.nprobes = ps.nprobes;
   build_split(P);
+  // Post-selected detectors (Section 3.2, post-selection): their OP_DET
+  // becomes OP_POSTSELECT, which ends a shot that reads 1.  The split form's
+  // frame pass cannot end shots, so such programs do not use it.
+  for (size_t w = 0; w < opts.postselect.size(); w++)
+    for (int b = 0; b < 64; b++)
+      if (((opts.postselect[w] >> b) & 1u) && (int64_t)w * 64 + b >= P.ndet) {
+        err = "post-selected detector " + std::to_string(w * 64 + b) + " does not exist (the circuit has " +
+              std::to_string(P.ndet) + ")";
+        return 4;
+      }
+  for (GInstr& in : P.code)
+    if (in.op == OP_DET && (opts.postselect_all || (in.b / 64 < opts.postselect.size() &&
+                                                    ((opts.postselect[in.b / 64] >> (in.b % 64)) & 1u)))) {
+      in.op = OP_POSTSELECT;
+      P.npost++;
+    }
+  if (P.npost) {
+    P.split_ok = false;
+    P.fcode.clear();
+    P.vcode.clear();
+  }
   if (P.consts.empty()) P.consts = {1.0, 0.0, 1.0, 0.0};
   if (P.refs.empty()) P.refs.push_back(0);
   if (P.ev_rec.empty()) P.ev_rec.push_back(-1);

@@ -32,6 +32,7 @@ struct CompiledProgram {
   int rblk_max = 0;
   bool has_cfeed = false;          // feed-forward Paulis (need record bits: not on the bit-sliced kernels)
   int nprobes = 0;                 // expectation-value probes (not on the bit-sliced kernels or the split form)
+  int npost = 0;                   // post-selected detectors (OP_POSTSELECT; not in the split form)
   // split form (program.h): valid when split_ok
   bool split_ok = false;
   int nactive = 0;                 // active measurement events
@@ -65,9 +66,12 @@ struct CompileOptions {
   int hir_passes = 0;     // bit 1 peephole, bit 2 commuting reorder
   int k_limit = 0;        // reject k_max above this (0: kMaxK)
   bool drop_phases = false;  // omit OP_PHASE instructions
+  std::vector<uint64_t> postselect;  // bit d: detector d is post-selected
+  bool postselect_all = false;       // every detector is post-selected
 };
 
-// Returns 0 on success, 1 parse error, 2 unsupported instruction, 3 capacity.
+// Returns 0 on success, 1 parse error, 2 unsupported instruction, 3 capacity,
+// 4 invalid option (a post-selected detector the circuit does not have).
 int compile_text(const char* text, size_t len, const CompileOptions& opts, CompiledProgram& out, std::string& err);
 
 }  // namespace clifft

@@ -135,6 +135,7 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   uint32_t* det32 = (uint32_t*)A.det;
   uint32_t* obs32 = (uint32_t*)A.obs;
   uint32_t* bits32 = (uint32_t*)A.nbits;  // split form: needed-bit rows
+  const bool strat = A.strat_r >= 0;      // stratified sampling (P.strat)
   cptr<uint64_t> masks = as_const(P.masks);
   cptr<uint32_t> rec_tgt_off = as_const(P.rec_tgt_off), rec_tgt = as_const(P.rec_tgt);
   for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -151,6 +152,19 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
       // every fault of the lane's 32 shots, as (site << 9 | shot << 4 | outcome)
       for (int j = 0; j < kShotsPerLane; j++) {
         const uint64_t shot = A.offset + s0 + j;
+        if (strat) {
+          // stratified: exactly strat_r faults, in site order
+          uint32_t cur = 0;
+          for (uint32_t i = 0; i < (uint32_t)A.strat_r; i++) {
+            const U4 w = draw(i, kPurposeStrat, shot, seed);
+            const uint32_t nf = strat_site(P, (uint32_t)A.strat_r - i, cur, w);
+            if (lcnt < lcap) F(NF + lcnt) = (nf << 9) | ((uint32_t)j << 4) | fault_outcome(P, nf, w);
+            else lovf = true;
+            lcnt++;
+            cur = nf + 1;
+          }
+          continue;
+        }
         for (uint32_t c = 0; c < (uint32_t)P.nchunks; c++) {
           const uint32_t cend = min((c + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
           uint32_t ord = 0, cur = 0;
@@ -176,22 +190,25 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
         F(NF + kk) = e;
       }
     }
-    // per-shot noise cursors
+    // per-shot noise cursors (stratified: the next fault and the faults
+    // placed so far)
     if (!LIST && P.nsites > 0) {
       for (int j = 0; j < kShotsPerLane; j++) {
-        uint32_t ord = 0;
-        uint32_t nf = bs_next_fault<LDS_SURV>(P, surv, 0, 0, &ord, A.offset + s0 + j, seed);
+        uint32_t ord = 0, nf = 0xFFFFFFFFu;
+        if (!strat) nf = bs_next_fault<LDS_SURV>(P, surv, 0, 0, &ord, A.offset + s0 + j, seed);
+        else if (A.strat_r > 0) nf = strat_site(P, (uint32_t)A.strat_r, 0, draw(ord++, kPurposeStrat, A.offset + s0 + j, seed));
         F(NF + j) = nf;
         F(OC + j) = ord;
         min_nf = min(min_nf, nf);
       }
     }
+    uint32_t alive = valid;  // shots not rejected by post-selection
     uint32_t last_m = 0, last_pn = 0;
     uint32_t rblk = 0xFFFFFFFFu;
     for (int pc = 0;; pc++) {
       const GInstr in = load_instr(P.code, pc);
       const uint32_t v = in.v;
-      if (in.op == OP_END) break;
+      if (in.op == OP_END || (P.has_post && !alive)) break;
       switch (in.op) {
         case OP_FANCX:
         case OP_FANCZ:
@@ -317,7 +334,7 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
           last_pn = pn;
           const int r = as_const(P.ev_rec)[in.b];
           if (r >= 0) {
-            if (meas32 && store) meas32[(size_t)r * 2 * words64 + col] = mm & valid;
+            if (meas32 && store) meas32[(size_t)r * 2 * words64 + col] = mm & alive;
             // accumulators fed by this record, four per round trip
             const uint32_t t1 = rec_tgt_off[r + 1];
             for (uint32_t t = rec_tgt_off[r]; t < t1; t += 4) {
@@ -377,6 +394,16 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
               const uint32_t lo = in.a;
               for (int j = 0; j < kShotsPerLane; j++) {
                 const uint64_t shot = A.offset + s0 + j;
+                if (strat) {
+                  uint32_t cur = 0;
+                  for (uint32_t i = 0; i < (uint32_t)A.strat_r && cur < hi; i++) {
+                    const U4 w = draw(i, kPurposeStrat, shot, seed);
+                    const uint32_t nf = strat_site(P, (uint32_t)A.strat_r - i, cur, w);
+                    if (nf >= lo && nf < hi) bs_apply_fault<W>(P, F, N, nf, fault_outcome(P, nf, w), 1u << j);
+                    cur = nf + 1;
+                  }
+                  continue;
+                }
                 for (uint32_t c = lo / (uint32_t)kChunk; c * (uint32_t)kChunk < hi; c++) {
                   const uint32_t cend = min(min((c + 1) * (uint32_t)kChunk, (uint32_t)P.nsites), hi);
                   uint32_t ord = 0, cur = 0;
@@ -402,7 +429,21 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
               const int s = __ffs(due) - 1;
               due &= due - 1;
               uint32_t nf = F(NF + s);
-              {
+              if (strat) {
+                uint32_t ord = F(OC + s);
+                const uint64_t shot = A.offset + s0 + s;
+                while (nf < hi) {
+                  // the outcome comes from the draw that placed this fault
+                  bs_apply_fault<W>(P, F, N, nf, fault_outcome(P, nf, draw(ord - 1, kPurposeStrat, shot, seed)), 1u << s);
+                  if (ord == (uint32_t)A.strat_r) nf = 0xFFFFFFFFu;
+                  else {
+                    nf = strat_site(P, (uint32_t)A.strat_r - ord, nf + 1, draw(ord, kPurposeStrat, shot, seed));
+                    ord++;
+                  }
+                }
+                F(NF + s) = nf;
+                F(OC + s) = ord;
+              } else {
                 uint32_t oc = F(OC + s);
                 uint32_t chunk = oc >> 16, ord = oc & 0xFFFFu;
                 const uint64_t shot = A.offset + s0 + s;
@@ -433,9 +474,19 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
           break;
         }
         case OP_DET:
-          if (det32 && store) det32[(size_t)in.b * 2 * words64 + col] = F(ACC + in.s) & valid;
+          if (det32 && store) det32[(size_t)in.b * 2 * words64 + col] = F(ACC + in.s) & alive;
           F(ACC + in.s) = 0;  // the row is reused by a later detector
           break;
+        case OP_POSTSELECT: {
+          // post-selection (Section 3.2): shots whose detector reads 1 are
+          // rejected; the lane leaves once all of its shots are (the record
+          // rows were zero-filled, so the rows it skips read 0)
+          const uint32_t d = F(ACC + in.s);
+          if (det32 && store) det32[(size_t)in.b * 2 * words64 + col] = d & alive;
+          F(ACC + in.s) = 0;
+          alive &= ~d;
+          break;
+        }
         case OP_EMIT:
           // frame-only stream of the split form: a rotation's sign bit
           if (bits32 && store) bits32[(size_t)in.u * 2 * words64 + col] = F(v) & valid;
@@ -468,7 +519,7 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
       }
     }
     if (obs32 && store)
-      for (int o = 0; o < P.nobs; o++) obs32[(size_t)o * 2 * words64 + col] = F(ACC + P.ndet_rows + o) & valid;
+      for (int o = 0; o < P.nobs; o++) obs32[(size_t)o * 2 * words64 + col] = F(ACC + P.ndet_rows + o) & alive;
   }
 }
 

@@ -25,6 +25,7 @@ struct KArgs {
   // stream and read by the vector stream
   uint64_t* nbits;
   uint32_t list_cap = 0xFFFFFFFFu;  // bit-sliced fault-list capacity (tests may lower it)
+  int32_t strat_r = -1;             // stratified: exactly this many faults per shot (P.strat), or -1
 };
 
 struct LaunchShape {

@@ -71,9 +71,10 @@ hipError_t launch_vector_pass(const DevProgram& P, const KArgs& A, const LaunchS
 
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool debug,
                          hipStream_t st) {
-  if (L.G < 0) return launch_frames(P, A, L.grid, st);
-  if (L.G == 256 || L.G == 64) {
-    // shot-granular tiers OR their record bits into zero-filled rows
+  if (L.G == 256 || L.G == 64 || (L.G < 0 && P.has_post)) {
+    // shot-granular tiers OR their record bits into zero-filled rows; the
+    // bit-sliced kernel skips the rows of lanes whose shots were all
+    // rejected by post-selection
     const size_t words = (A.shots + 63) / 64;
     uint64_t* rows[3] = {A.meas, A.det, A.obs};
     const size_t counts[3] = {(size_t)P.nrec, (size_t)P.ndet, (size_t)P.nobs};
@@ -84,6 +85,13 @@ hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape&
       hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, rows[i], n);
     }
   }
+  if (P.has_post && A.expval && P.nprobes > 0) {
+    // probes a rejected shot does not reach read 0
+    const size_t n = (size_t)P.nprobes * A.shots;
+    hipLaunchKernelGGL(k_zero, dim3((int)std::min<size_t>(1024, (n + 255) / 256)), dim3(256), 0, st,
+                       (uint64_t*)A.expval, n);
+  }
+  if (L.G < 0) return launch_frames(P, A, L.grid, st);
   if (fp64) return debug ? launch_trace_f64(P, A, L, st) : launch_sample_f64(P, A, L, st);
   return debug ? launch_trace_f32(P, A, L, st) : launch_sample_f32(P, A, L, st);
 }

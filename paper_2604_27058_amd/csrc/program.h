@@ -50,6 +50,8 @@ enum Op : uint8_t {
                //   the full frame takes the image (sign in F_SIGN)
   OP_EXPVAL,   // expectation value of a virtual observable (probe b):    a=mask(x,z) then the
                //   slot masks of its active X and Z letters (2 words); F_SIGN, F_ZERO
+  OP_POSTSELECT,  // post-selected detector (Section 3.2): as OP_DET; a shot whose detector
+               //   reads 1 ends there, its observables read 0 and its later records stay 0
   OP_COUNT
 };
 
@@ -93,6 +95,7 @@ enum SiteType : uint8_t { S_DEP1 = 0, S_DEP2 = 1, S_XERR = 2, S_YERR = 3, S_ZERR
 constexpr uint32_t kPurposeNoise = 0x4E000000u;  // | chunk
 constexpr uint32_t kPurposeRbit = 0x52000000u;
 constexpr uint32_t kPurposeAmeas = 0x41000000u;
+constexpr uint32_t kPurposeStrat = 0x53000000u;  // stratified sampling: fault i of the shot
 
 // Split form.  Every frame bit and every record of a shot is an affine
 // function over GF(2) of the shot's faults, dormant random bits and active
@@ -139,6 +142,14 @@ struct DevProgram {
   const uint64_t* vdep;
   int32_t nbits;                // needed-bit rows
   int32_t dep_words;            // words per dependency mask actually used (<= kSplitWords)
+  int32_t has_post;             // the stream holds OP_POSTSELECT (shots may end early)
+  // Stratified sampling (Section 3.2, rare-event sampling): row s - 1 holds
+  // e_s(t), t = 0 .. nsites, the elementary symmetric polynomial of degree s
+  // of the odds p / (1 - p) of the sites t .. nsites - 1; given s faults
+  // left from site j on, the next one lies at or after t with probability
+  // e_s(t) / e_s(j).  Null until a stratified call uploads it.
+  const double* strat;
+  int32_t strat_rows;
 };
 
 }  // namespace clifft

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -41,6 +42,10 @@ struct DeviceCopy {
   const uint32_t* xdep_off = nullptr;
   const uint32_t* xdep = nullptr;
   std::vector<void*> allocs;
+  // stratified sampling tables (DevProgram::strat), uploaded by the first
+  // stratified call and grown when a call needs more rows
+  const double* strat = nullptr;
+  int strat_rows = 0;
   hipModule_t spec_mod = nullptr;  // specialized kernel, loaded at its first launch
   hipFunction_t spec_fn = nullptr;
 };
@@ -119,6 +124,7 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out, co
   v.nchunks = H.nchunks;
   v.rblk_max = H.rblk_max;
   v.ndet_rows = H.ndet_rows;
+  v.has_post = H.npost > 0;
   {
     double f = 0;
     for (double q : H.site_p) f += q;
@@ -244,7 +250,8 @@ int device_cus() {
 // and storage), the grid fills the device with persistent workgroups.
 clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const clifft_launch* cfg, uint64_t shots,
                            LaunchShape* L, bool* fp64,
-                           const std::map<std::pair<int, int>, clifft_launch>* tuned = nullptr, bool trace = false) {
+                           const std::map<std::pair<int, int>, clifft_launch>* tuned = nullptr, bool trace = false,
+                           bool strat = false) {
   clifft_launch c{};
   if (cfg) c = *cfg;
   if (c.precision != CLIFFT_FP32 && c.precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
@@ -253,9 +260,12 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
     int dev = 0;
     (void)hipGetDevice(&dev);
     auto it = tuned->find({dev, c.precision});
-    if (it != tuned->end() && !(trace && (it->second.threads_per_shot == kBitSliced || it->second.split >= 1)))
+    if (it != tuned->end() && !(trace && (it->second.threads_per_shot == kBitSliced || it->second.split >= 1)) &&
+        !(strat && (it->second.split >= 1 || it->second.specialize == 1)))
       c = it->second;
   }
+  if (strat && (c.split >= 1 || c.specialize == 1))
+    return fail(CLIFFT_E_INVALID_ARG, "stratified sampling runs on the interpreter tiers (no split form, no specialized kernel)");
   const size_t amp = *fp64 ? 16 : 8;
   const size_t vec = (size_t)1 << H.kmax;
   if (c.split < -1 || c.split > 3) return fail(CLIFFT_E_INVALID_ARG, "split must be -1, 0, 1, 2 or 3");
@@ -437,8 +447,8 @@ size_t workspace_bytes(const CompiledProgram& H, const LaunchShape& L, bool fp64
 // One sampling launch sequence on `s`: the whole-program kernel, or the
 // split form's frame pass, vector pass and record fix-up.
 hipError_t launch_plan(const CompiledProgram& H, const DeviceCopy& dc, const LaunchShape& L, const KArgs& A,
-                       bool fp64, bool trace, hipStream_t s) {
-  if (!L.split) return launch_sample(dc.view, A, L, fp64, trace, s);
+                       bool fp64, bool trace, hipStream_t s, const DevProgram* view = nullptr) {
+  if (!L.split) return launch_sample(view ? *view : dc.view, A, L, fp64, trace, s);
   const uint64_t words = (A.shots + 63) / 64;
   unsigned char* ws = (unsigned char*)A.workspace;
   uint64_t* bits = (uint64_t*)ws;
@@ -484,19 +494,86 @@ hipError_t launch_plan(const CompiledProgram& H, const DeviceCopy& dc, const Lau
   return launch_fixup(X, s);
 }
 
+// Stratified sampling tables (Section 3.2, rare-event sampling).  With odds
+// w_l = p_l / (1 - p_l), e_s(t) = sum over s-subsets of the sites t .. N-1 of
+// the product of their odds; P(exactly s of them fire) = e_s(t) prod(1 - p),
+// so given s faults from site j on, the next one lies at or after t with
+// probability e_s(t) / e_s(j).  Recurrence: e_0 = 1, e_s(N) = 0 for s >= 1,
+// e_s(t) = e_s(t+1) + w_t e_{s-1}(t+1) (site t fires or not).  Every term is
+// non-negative, so the relative rounding error stays within N ulps.
+clifft_status strat_check(const CompiledProgram& H, int32_t r) {
+  const int N = (int)H.site_p.size();
+  if (r < 0) return fail(CLIFFT_E_INVALID_ARG, "the fault count must be >= 0");
+  if (r > N) return fail(CLIFFT_E_INVALID_ARG, "more faults than noise sites");
+  for (double q : H.site_p)
+    if (!(q < 1.0)) return fail(CLIFFT_E_UNSUPPORTED, "stratified sampling needs every site probability below 1");
+  return CLIFFT_OK;
+}
+
+std::vector<double> strat_rows(const CompiledProgram& H, int rows) {
+  const size_t N = H.site_p.size();
+  std::vector<double> E((size_t)rows * (N + 1));
+  std::vector<double> prev(N + 1, 1.0), cur(N + 1);
+  for (int s = 1; s <= rows; s++) {
+    cur[N] = 0.0;
+    for (size_t t = N; t-- > 0;) {
+      const double w = H.site_p[t] / (1.0 - H.site_p[t]);
+      cur[t] = cur[t + 1] + w * prev[t + 1];
+    }
+    std::copy(cur.begin(), cur.end(), E.begin() + (size_t)(s - 1) * (N + 1));
+    prev.swap(cur);
+  }
+  return E;
+}
+
+clifft_status ensure_strat(const clifft_program* cp, const DeviceCopy* dc, int32_t r) {
+  clifft_program* p = const_cast<clifft_program*>(cp);
+  const CompiledProgram& H = p->host;
+  clifft_status st = strat_check(H, r);
+  if (st != CLIFFT_OK) return st;
+  std::lock_guard<std::mutex> lock(p->mu);
+  DeviceCopy* d = const_cast<DeviceCopy*>(dc);
+  if (r == 0 || d->strat_rows >= r) return CLIFFT_OK;
+  const size_t N = H.site_p.size();
+  int rows = std::min<int>((int)N, std::max<int>(r, 2 * d->strat_rows));
+  if ((size_t)rows * (N + 1) * sizeof(double) > ((size_t)1 << 30)) rows = r;
+  if ((size_t)rows * (N + 1) * sizeof(double) > ((size_t)1 << 30))
+    return fail(CLIFFT_E_CAPACITY, "stratified tables (faults x noise sites) exceed 1 GiB");
+  std::vector<double> E = strat_rows(H, rows);
+  const double er = E[(size_t)(r - 1) * (N + 1)];
+  if (!(er > 0.0)) return fail(CLIFFT_E_INVALID_ARG, "the stratum has probability zero");
+  if (!std::isfinite(er)) return fail(CLIFFT_E_CAPACITY, "stratified tables overflow for this fault count");
+  // the previous (smaller) table stays allocated until the program is
+  // freed: launches already queued may still read it
+  const double* dst = nullptr;
+  hipError_t e = upload_vec(E, &dst, d->allocs);
+  if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("stratified table upload failed: ") + hipGetErrorString(e));
+  d->strat = dst;
+  d->strat_rows = rows;
+  return CLIFFT_OK;
+}
+
 clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t offset,
                         const clifft_launch* cfg, void* ws, size_t ws_bytes, uint64_t* meas, uint64_t* det,
                         uint64_t* obs, void* stream, const uint32_t* forced_m, const int32_t* forced_faults,
-                        double* probs, double* phi, double* gamma, bool trace, double* expval = nullptr) {
+                        double* probs, double* phi, double* gamma, bool trace, double* expval = nullptr,
+                        int32_t strat_r = -1) {
   if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
   if (shots == 0) return CLIFFT_OK;
   const DevProgram* D = nullptr;
   const DeviceCopy* DC = nullptr;
   clifft_status st = ensure_device(p, &D, &DC);
   if (st != CLIFFT_OK) return st;
+  DevProgram V = *D;
+  if (strat_r >= 0) {
+    st = ensure_strat(p, DC, strat_r);
+    if (st != CLIFFT_OK) return st;
+    V.strat = DC->strat;
+    V.strat_rows = DC->strat_rows;
+  }
   LaunchShape L{};
   bool fp64 = false;
-  st = choose_shape(p->host, D, cfg, shots, &L, &fp64, &p->tuned, trace);
+  st = choose_shape(p->host, D, cfg, shots, &L, &fp64, &p->tuned, trace, strat_r >= 0);
   if (st != CLIFFT_OK) return st;
   size_t need = workspace_bytes(p->host, L, fp64, shots);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) {
@@ -513,6 +590,7 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
   A.obs = obs;
   A.workspace = ws;
   A.expval = expval;
+  A.strat_r = strat_r;
   A.list_cap = 0xFFFFFFFFu;
   if (const char* cap = getenv("CLIFFT_FRAMES_LIST_CAP")) A.list_cap = (uint32_t)strtoul(cap, nullptr, 10);
   hipStream_t s = (hipStream_t)stream;
@@ -534,7 +612,7 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
     if (st != CLIFFT_OK) return st;
     e = launch_spec(fn, *D, A, L.grid, s);
   } else {
-    e = launch_plan(p->host, *DC, L, A, fp64, trace, s);
+    e = launch_plan(p->host, *DC, L, A, fp64, trace, s, &V);
   }
   if (e != hipSuccess) {
     if (dflag) (void)hipFree(dflag);
@@ -591,13 +669,21 @@ clifft_status clifft_compile(const char* text, size_t len, const clifft_compile_
     co.hir_passes = opts->hir_passes;
     co.k_limit = opts->k_limit;
     co.drop_phases = opts->drop_phases == 1;
+    if (opts->postselect_words < -1 || (opts->postselect_words > 0 && !opts->postselect))
+      return fail(CLIFFT_E_INVALID_ARG, "postselect: bad mask");
+    if (opts->postselect_words == -1) co.postselect_all = true;
+    else if (opts->postselect_words > 0) co.postselect.assign(opts->postselect, opts->postselect + opts->postselect_words);
   }
   clifft_program* p = new clifft_program();
   std::string err;
   int rc = compile_text(text, len, co, p->host, err);
   if (rc != 0) {
     delete p;
-    return fail(rc == 1 ? CLIFFT_E_PARSE : rc == 2 ? CLIFFT_E_UNSUPPORTED : CLIFFT_E_CAPACITY, err);
+    return fail(rc == 1   ? CLIFFT_E_PARSE
+                : rc == 2 ? CLIFFT_E_UNSUPPORTED
+                : rc == 4 ? CLIFFT_E_INVALID_ARG
+                          : CLIFFT_E_CAPACITY,
+                err);
   }
   *out = p;
   return CLIFFT_OK;
@@ -620,6 +706,7 @@ clifft_status clifft_program_info(const clifft_program* p, clifft_info* o) {
   o->num_random_events = nr;
   o->num_active_events = na;
   o->num_probes = H.nprobes;
+  o->num_postselected = H.npost;
   return CLIFFT_OK;
 }
 
@@ -714,6 +801,39 @@ clifft_status clifft_sample_expval(const clifft_program* p, uint64_t shots, uint
                                    uint64_t* det, uint64_t* obs, double* expval, void* stream) {
   return do_sample(p, shots, seed, shot_offset, cfg, workspace, workspace_bytes, meas, det, obs, stream, nullptr,
                    nullptr, nullptr, nullptr, nullptr, false, expval);
+}
+
+clifft_status clifft_sample_stratified(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                                       int32_t faults, const clifft_launch* cfg, void* workspace,
+                                       size_t workspace_bytes, uint64_t* meas, uint64_t* det, uint64_t* obs,
+                                       void* stream) {
+  if (!p) return fail(CLIFFT_E_INVALID_ARG, "null program");
+  clifft_status st = strat_check(p->host, faults);
+  if (st != CLIFFT_OK) return st;
+  return do_sample(p, shots, seed, shot_offset, cfg, workspace, workspace_bytes, meas, det, obs, stream, nullptr,
+                   nullptr, nullptr, nullptr, nullptr, false, nullptr, faults);
+}
+
+clifft_status clifft_fault_count_pmf(const clifft_program* p, int32_t rmax, double* pmf) {
+  if (!p || !pmf || rmax < 0) return fail(CLIFFT_E_INVALID_ARG, "null argument or rmax < 0");
+  const CompiledProgram& H = p->host;
+  for (double q : H.site_p)
+    if (!(q < 1.0)) return fail(CLIFFT_E_UNSUPPORTED, "the fault-count weights need every site probability below 1");
+  // pmf[r] = prod(1 - p) e_r over all sites: the log of the product, and
+  // e_r accumulated site by site (e_r += w e_{r-1}, highest degree first)
+  double lp0 = 0.0;
+  std::vector<double> e((size_t)rmax + 1, 0.0);
+  e[0] = 1.0;
+  for (double q : H.site_p) {
+    lp0 += std::log1p(-q);
+    const double w = q / (1.0 - q);
+    for (int r = rmax; r >= 1; r--) e[r] += w * e[r - 1];
+  }
+  for (int r = 0; r <= rmax; r++) {
+    if (!std::isfinite(e[r])) return fail(CLIFFT_E_CAPACITY, "fault-count weights overflow");
+    pmf[r] = e[r] > 0.0 ? std::exp(lp0 + std::log(e[r])) : 0.0;
+  }
+  return CLIFFT_OK;
 }
 
 clifft_status clifft_sample_noalloc(const clifft_program* p, uint64_t shots, uint64_t seed, uint64_t shot_offset,

@@ -361,6 +361,40 @@ DEV void next_fault(const DevProgram& P, Noise& ns, uint32_t cur, uint64_t shot,
   }
 }
 
+DEV uint32_t fault_outcome(const DevProgram& P, uint32_t site, const U4& w) {
+  const uint64_t w64 = ((uint64_t)w.w3 << 32) | w.w2;
+  return (uint32_t)__umul64hi(w64, (uint64_t)nout_of(P.site_type[site]));
+}
+
+// Stratified sampling (Section 3.2, rare-event sampling): with s >= 1 faults
+// left from site cur on, the next one is at the smallest t >= cur with
+// e_s(t + 1) <= u e_s(cur) (the tables of DevProgram::strat); t <= nsites - s
+// since e_s vanishes once fewer than s sites remain.
+DEV uint32_t strat_site(const DevProgram& P, uint32_t s, uint32_t cur, const U4& w) {
+  const double* E = P.strat + (size_t)(s - 1) * (uint32_t)(P.nsites + 1);
+  const double tau = uniform53(w) * E[cur];
+  uint32_t lo = cur, hi = (uint32_t)P.nsites - s;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (E[mid + 1] <= tau) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Noise state of a stratified shot: chunk counts the faults still to place
+// and ord the faults placed (fault i comes from draw i of kPurposeStrat).
+DEV void next_fault_strat(const DevProgram& P, Noise& ns, uint32_t cur, uint64_t shot, uint64_t seed) {
+  if (ns.chunk == 0) {
+    ns.nf = 0xFFFFFFFFu;
+    return;
+  }
+  const U4 w = draw(ns.ord++, kPurposeStrat, shot, seed);
+  ns.nf = strat_site(P, ns.chunk, cur, w);
+  ns.nf_out = fault_outcome(P, ns.nf, w);
+  ns.chunk--;
+}
+
 template <int W>
 DEV void apply_fault(const DevProgram& P, Frame<W>& T, Frame<W>& N, uint32_t site, uint32_t o) {
   uint32_t t = P.site_type[site];
@@ -480,10 +514,17 @@ struct Shot {
 
   MDEV bool writer() const { return (G == 1 || grp.tid == 0) && local < A.shots; }
 
+  // G == 1: the wave's first active lane (lanes whose shot was rejected by
+  // post-selection have left the instruction loop)
+  MDEV bool first_lane() const {
+    const uint32_t l = threadIdx.x & 63;
+    return rfl(l) == l;
+  }
+
   MDEV void put(uint32_t r, uint32_t m) {
     if constexpr (G == 1) {
       uint64_t word = __ballot(m);
-      if ((threadIdx.x & 63) == 0) rec[r] = word;
+      if (first_lane()) rec[r] = word;
     } else {
       if (grp.tid == 0) rec[r] |= (uint64_t)m << slane;
     }
@@ -633,7 +674,10 @@ struct Shot {
     Noise ns{0, 0, 0xFFFFFFFFu, 0};
     if (P.nsites > 0) {
       if (DBG && A.forced_faults) ns.nf = 0xFFFFFFFFu;
-      else next_fault(P, ns, 0, shot, seed);
+      else if (A.strat_r >= 0) {
+        ns.chunk = (uint32_t)A.strat_r;
+        next_fault_strat(P, ns, 0, shot, seed);
+      } else next_fault(P, ns, 0, shot, seed);
     }
     if (VEC && P.kmax > 0) {
       FOR_GROUP(p, 1u) vec[p] = cpx<R>{(R)1, (R)0};
@@ -1504,23 +1548,51 @@ struct Shot {
             }
           }
           const uint32_t hi = in.b;
+          const bool strat = A.strat_r >= 0;
           while (ns.nf < hi) {
-            uint32_t cend = min((ns.chunk + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
-            if (ns.nf >= cend) {
-              ns.chunk++;
-              ns.ord = 0;
-              next_fault(P, ns, 0, shot, seed);
-              continue;
+            if (!strat) {
+              uint32_t cend = min((ns.chunk + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
+              if (ns.nf >= cend) {
+                ns.chunk++;
+                ns.ord = 0;
+                next_fault(P, ns, 0, shot, seed);
+                continue;
+              }
             }
             if constexpr (DBG) g_ipow += fault_phase<W>(P, T.x, ns.nf, ns.nf_out);
             apply_fault<W>(P, T, N, ns.nf, ns.nf_out);
-            next_fault(P, ns, ns.nf - ns.chunk * (uint32_t)kChunk + 1, shot, seed);
+            if (strat) next_fault_strat(P, ns, ns.nf + 1, shot, seed);
+            else next_fault(P, ns, ns.nf - ns.chunk * (uint32_t)kChunk + 1, shot, seed);
           }
           break;
         }
         case OP_DET: {
           uint32_t d = xor_refs(in.a, in.u);
           put((uint32_t)P.nrec + in.b, d);
+          break;
+        }
+        case OP_POSTSELECT: {
+          // post-selection (Section 3.2): the detector is recorded, then a
+          // shot reading 1 ends here with its observables cleared (records
+          // not yet written stay 0)
+          if constexpr (G > 1) grp.sync();  // record bits are staged by the group's first thread
+          const uint32_t d = xor_refs(in.a, in.u);
+          put((uint32_t)P.nrec + in.b, d);
+          const uint32_t r0 = (uint32_t)(P.nrec + P.ndet);
+          if constexpr (G == 1) {
+            const uint64_t rej = __ballot(d);
+            if (rej) {
+              if (first_lane())
+                for (uint32_t o = 0; o < (uint32_t)P.nobs; o++) rec[r0 + o] &= ~rej;
+              if (d) goto done;
+            }
+          } else {
+            if (d) {
+              if (grp.tid == 0)
+                for (uint32_t o = 0; o < (uint32_t)P.nobs; o++) rec[r0 + o] &= ~(1ull << slane);
+              goto done;
+            }
+          }
           break;
         }
         case OP_EMIT:
@@ -1561,7 +1633,7 @@ struct Shot {
           uint32_t r = (uint32_t)P.nrec + (uint32_t)P.ndet + in.b;
           if constexpr (G == 1) {
             uint64_t word = __ballot(d);
-            if ((threadIdx.x & 63) == 0) rec[r] ^= word;
+            if (first_lane()) rec[r] ^= word;
           } else {
             if (grp.tid == 0) rec[r] ^= (uint64_t)d << slane;
           }

@@ -293,6 +293,7 @@ bool spec_supported(const CompiledProgram& P, std::string* why) {
   if (P.kmax != 0) return no("specialized kernels need k_max = 0");
   if (P.has_cfeed) return no("feed-forward Paulis need per-shot record bits");
   if (P.nprobes) return no("expectation-value probes need the interpreter");
+  if (P.npost) return no("post-selection ends shots early: interpreter tiers only");
   if (4 * P.nq + P.ndet_rows + P.nobs + P.rblk_max > kSpecMaxRegs) return no("too many frame and accumulator rows");
   if (P.code.size() > kSpecMaxCode) return no("program too long to specialize");
   double f = 0;

@@ -186,3 +186,55 @@ def test_wide_gate_parse_errors():
             pk.Program(bad)
         with pytest.raises(oracle.OracleError):
             oracle.Program(bad)
+
+
+def test_postselect_compile_option():
+    """Post-selected detectors (Section 3.2): counted in the program info,
+    checked against the detectors the circuit has, kept out of the split
+    form and the specialized kernel; the rest of the program is unchanged."""
+    text = circuits.surface_code_memory(d=3, rounds=2, p=0.01, t_rotations=2, seed=1)
+    plain = pk.Program(text)
+    allp = pk.Program(text, postselect="all")
+    some = pk.Program(text, postselect=[0, 3, 5])
+    assert allp.num_postselected == plain.num_detectors > 5
+    assert some.num_postselected == 3 and plain.num_postselected == 0
+    assert allp.num_instructions == plain.num_instructions and allp.k_max == plain.k_max
+    assert some.postselected == [0, 3, 5]
+    with pytest.raises(pk.ClifftError) as e:
+        pk.Program(text, postselect=[plain.num_detectors])
+    assert e.value.status == 4
+    assert allp.resolve_launch(1 << 16, pk.make_launch("f32"))["split"] == 0
+    with pytest.raises(pk.ClifftError):
+        allp.resolve_launch(1 << 16, pk.make_launch("f32", split=2))
+    k0 = circuits.surface_code_memory(d=3, rounds=2, p=0.01)
+    spec = pk.Program(k0, postselect=[0])
+    with pytest.raises(pk.ClifftError):
+        spec.resolve_launch(1 << 16, pk.make_launch("f32", threads_per_shot=-32, specialize=1))
+
+
+@pytest.mark.parametrize("name", ["surface_d5_r5_t10", "large_active_k20"])
+def test_fault_count_pmf_matches_oracle(name):
+    """The library's stratum weights (host Poisson-binomial, accumulated in
+    odds) against the oracle's probability recurrence."""
+    import numpy as np
+    text = circuits.workload(name)["texts"][0]
+    p, o = pk.Program(text), oracle.Program(text)
+    a = np.array(p.fault_count_pmf(25))
+    b = o.fault_pmf(25)
+    # both sums of non-negative terms over N sites: relative error within a
+    # few N ulps each
+    tol = 4 * o.nsites * 2.0 ** -53
+    assert np.all(np.abs(a - b) <= tol * b + 1e-300), np.max(np.abs(a - b) / b)
+    assert abs(a.sum() - 1.0) < 1e-6 or a.sum() < 1.0
+
+
+def test_stratified_argument_checks_host_only():
+    text = circuits.surface_code_memory(d=3, rounds=2, p=0.01)
+    p = pk.Program(text)
+    for bad in (-1, p.num_noise_sites + 1):
+        with pytest.raises(pk.ClifftError) as e:  # checked before any device work
+            pk._check(pk.lib().clifft_sample_stratified(p._h, 64, 0, 0, bad, None, None, 0, None, None, None, None))
+        assert e.value.status == 4
+    with pytest.raises(pk.ClifftError) as e:
+        pk.Program("X_ERROR(1) 0\nM 0\n").fault_count_pmf(2)
+    assert e.value.status == 2
