@@ -12,6 +12,10 @@ graph (--no-graph: launched eagerly).  Prints one JSON line.
 
 Single-program workloads (--workload): one clifft_sample call over the
 workload's shots per step, reported under their own metric name.
+--postselect all post-selects every detector (shots end at their first
+firing detector) and --faults R samples the stratum of exactly R faults
+(clifft_sample_stratified); either way the plain form of the same program
+is timed beside it.
 """
 import argparse
 import json
@@ -105,20 +109,20 @@ def load_traffic(workload, precision, kernel):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(text, shots_hint, seed):
+def cpu_baseline(text, shots_hint, seed, postselect=None, faults=None):
     """The FP64 oracle timed on the host cores on a bounded sample."""
     import oracle
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    prog = oracle.Program(text)
+    prog = oracle.Program(text, postselect=postselect)
     n = 4096
     t0 = time.perf_counter()
-    prog.sample(n, seed=seed, threads=threads)
+    prog.sample(n, seed=seed, threads=threads, faults=faults)
     dt = time.perf_counter() - t0
     # scale the sample to about 10 s of CPU time, within the workload's shots
     target = min(shots_hint, max(64, int(n * 10.0 / max(dt, 1e-6))))
     target = (target + 63) // 64 * 64
     t0 = time.perf_counter()
-    meas, det, obs = prog.sample(target, seed=seed, threads=threads)
+    meas, det, obs = prog.sample(target, seed=seed, threads=threads, faults=faults)
     dt = time.perf_counter() - t0
     return dict(value=target / dt, unit="shots/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
                 sample="first %d shots of the workload (seed %d), FP64 oracle, %d threads, %.1f s"
@@ -406,6 +410,10 @@ def main():
     ap.add_argument("--specialize", type=int, default=0, choices=(-1, 0, 1),
                     help="bit-sliced tier: 1 the program-specialized kernel, -1 the interpreter, 0 automatic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--postselect", default="none", choices=("none", "all"),
+                    help="single-program workloads: post-select every detector")
+    ap.add_argument("--faults", type=int, default=-1,
+                    help="single-program workloads: sample the stratum of exactly this many faults")
     ap.add_argument("--no-autotune", action="store_true", help="skip clifft_autotune before timing")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a captured graph")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -431,7 +439,9 @@ def main():
         bench_batch(args, w, pk, torch)
         return
     text = w["texts"][0]
-    prog = pk.Program(text)
+    post = None if args.postselect == "none" else "all"
+    faults = args.faults if args.faults >= 0 else None
+    prog = pk.Program(text, postselect=post)
     tuned = None
     explicit = args.threads_per_shot or args.grid or args.vector_in_hbm or args.specialize
     if not args.no_autotune and not explicit:
@@ -446,7 +456,10 @@ def main():
 
     if args.calibrate_copy:
         calibration_copy(args.calibrate_copy, torch)
-    step = lambda: prog.sample(shots, seed=seed, launch=launch, outputs=outs, workspace=ws)
+    if faults is None:
+        step = lambda: prog.sample(shots, seed=seed, launch=launch, outputs=outs, workspace=ws)
+    else:
+        step = lambda: prog.sample_stratified(shots, faults, seed=seed, launch=launch, outputs=outs, workspace=ws)
     if not args.no_graph:
         step, graph = captured(step, torch)
     for _ in range(args.warmup):
@@ -506,10 +519,17 @@ def main():
         roof["traffic_over_algorithmic"] = traffic / max(1.0, (vb + cost["record_bytes"]) * shots)
     roof["kernel_ms"] = kernel_ms
     roof["work_per_shot"] = {kk: round(v, 3) for kk, v in cost.items()}
+    if post:
+        roof["note"] = "work model counts every instruction of every shot; rejected shots skip their tail"
     add_measured_peak(roof, pk, torch)
 
+    variant = ""
+    if post:
+        variant += ", every detector post-selected"
+    if faults is not None:
+        variant += ", stratum of %d faults" % faults
     line = {
-        "metric": METRIC_SINGLE % (args.workload, "u64 frames" if k == 0 else precision), "value": value,
+        "metric": METRIC_SINGLE % (args.workload + variant, "u64 frames" if k == 0 else precision), "value": value,
         "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64" if k == 0 else precision, "data": "synthetic",
@@ -522,9 +542,31 @@ def main():
                    "parallelism": "shots across lanes/waves of one GPU"},
         "roofline": roof,
     }
+    if post or faults is not None:
+        import numpy as np
+        if post:
+            words = (shots + 63) // 64
+            d = outs[1].cpu().numpy().view(np.uint64)
+            rej = np.bitwise_or.reduce(d, axis=0) if d.size else np.zeros(words, np.uint64)
+            nrej = sum(bin(int(x)).count("1") for x in rej)
+            line["config"]["kept_fraction"] = 1.0 - nrej / shots
+        if faults is not None:
+            line["config"]["stratum_weight"] = prog.fault_count_pmf(faults)[faults]
+        # the same program sampled plainly (no post-selection, no stratum),
+        # same launch and timing
+        plain = pk.Program(text)
+        if tuned is not None:
+            plain.autotune(shots, precision)
+        pouts = plain.alloc_outputs(shots)
+        pws = plain.alloc_workspace(launch, shots=shots)
+        pstep = lambda: plain.sample(shots, seed=seed, launch=launch, outputs=pouts, workspace=pws)
+        pwall, pev, _ = time_steps(pstep, args.steps, args.warmup, torch, graph=not args.no_graph)
+        line["plain_form"] = {"value": shots * args.steps / pwall, "unit": "shots/s",
+                              "kernel_ms": sum(pev) / len(pev),
+                              "speedup": (shots * args.steps / wall) / (shots * args.steps / pwall)}
     if not args.no_cpu_baseline:
         import numpy as np
-        cb, (n, om, od, oo) = cpu_baseline(text, shots, seed)
+        cb, (n, om, od, oo) = cpu_baseline(text, shots, seed, postselect=post, faults=faults)
         line["cpu_baseline"] = cb
         # records of the sampled shots must equal the oracle's
         words = (n + 63) // 64

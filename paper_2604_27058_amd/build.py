@@ -17,6 +17,7 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
 # The interpreter's instantiations are spread over several translation units
 # so that they compile in parallel; the slowest ones are listed first.
 SOURCES = [("sample_f32.hip", True), ("sample_f64.hip", True), ("trace_f32.hip", True), ("trace_f64.hip", True),
+           ("sample_ext_f32.hip", True), ("sample_ext_f64.hip", True), ("batch_ext.hip", True),
            ("vsample_f32.hip", True), ("vsample_f64.hip", True),
            ("batch.hip", True), ("frames.hip", True), ("kernels.hip", True), ("probe.hip", True),
            ("runtime.cpp", True), ("specialize.cpp", True), ("compiler.cpp", False)]

@@ -84,18 +84,28 @@ DEV void bs_apply_fault(const DevProgram& P, const FrameRows& F, uint32_t N, uin
 // need no branches), then the survival products when they fit.
 constexpr int kSurvLdsMax = 2048;  // survival products staged in LDS (single chunk, up to this many sites)
 constexpr int kListCap = 24;       // faults per lane kept in the precomputed list
+constexpr size_t kStratLdsMax = 16384;  // stratified tables staged in LDS up to this many bytes
 DEV_HOST_INLINE bool frames_surv_in_lds(const DevProgram& P) { return P.nchunks == 1 && P.nsites < kSurvLdsMax; }
 // Low-noise programs precompute each lane's faults into a site-sorted list
-// (expected faults per lane at most a quarter of the list); others keep one
-// sampler cursor per shot.
-DEV_HOST_INLINE bool frames_fault_list(const DevProgram& P) {
+// (expected faults per lane at most a quarter of the list; stratified: all
+// 32 shots' faults fit the list); others keep one sampler cursor per shot.
+DEV_HOST_INLINE bool frames_fault_list(const DevProgram& P, int strat_r) {
+  if (strat_r >= 0) return P.nsites < (1 << 23) && strat_r * kShotsPerLane <= kListCap;
   return P.nsites < (1 << 23) && (double)P.exp_faults * kShotsPerLane <= kListCap / 4;
 }
-size_t frames_lds_rows(const DevProgram& P) {
+// Stratified tables e_1 .. e_r (nsites + 1 doubles each) staged in LDS.
+DEV_HOST_INLINE bool frames_strat_in_lds(const DevProgram& P, int strat_r) {
+  return strat_r > 0 && (size_t)strat_r * (size_t)(P.nsites + 1) * 8 <= kStratLdsMax;
+}
+DEV_HOST_INLINE size_t frames_surv_rows(const DevProgram& P) {
+  return frames_surv_in_lds(P) ? ((size_t)(P.nsites + 1) * 8 + 255) / 256 : 0;  // doubles, in 256-byte rows
+}
+size_t frames_lds_rows(const DevProgram& P, int strat_r) {
   size_t rows = (size_t)4 * P.nq + P.ndet_rows + P.nobs + (P.rblk_max > 0 ? P.rblk_max : 1);
-  rows += frames_fault_list(P) ? kListCap : 2 * kShotsPerLane;
+  rows += frames_fault_list(P, strat_r) ? kListCap : 2 * kShotsPerLane;
   rows += 2;  // zero row, dump row
-  if (frames_surv_in_lds(P)) rows += ((size_t)(P.nsites + 1) * 8 + 255) / 256;  // doubles, in 256-byte rows
+  rows += frames_surv_rows(P);
+  if (frames_strat_in_lds(P, strat_r)) rows += ((size_t)strat_r * (P.nsites + 1) * 8 + 255) / 256;
   return rows;
 }
 
@@ -112,7 +122,8 @@ MDEV int take4(uint64_t& m, uint32_t wbase, uint32_t (&q)[4]) {
   return n;
 }
 
-template <int W, bool LDS_SURV, bool LIST>
+// EXT: post-selection and stratified sampling compiled in.
+template <int W, bool LDS_SURV, bool LIST, bool EXT>
 __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   extern __shared__ __align__(16) uint32_t sm[];
   const int lane = threadIdx.x;
@@ -124,9 +135,17 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   const uint32_t NF = RB + (uint32_t)(P.rblk_max > 0 ? P.rblk_max : 1), OC = NF + kShotsPerLane;
   const uint32_t ZR = NF + (LIST ? kListCap : 2 * kShotsPerLane), DR = ZR + 1;
   double* surv = (double*)(sm + (size_t)(DR + 1) * 64);
+  // stratified tables: staged after the survival products when small
+  const bool strat = EXT && A.strat_r >= 0;
+  const bool strat_lds = EXT && frames_strat_in_lds(P, A.strat_r);
+  double* strat_tab_lds = (double*)(sm + (size_t)(DR + 1 + frames_surv_rows(P)) * 64);
+  const double* stab = strat_lds ? strat_tab_lds : P.strat;
+  const uint32_t NS = (uint32_t)P.nsites;
   F(ZR) = 0;
   if (LDS_SURV)
     for (int i = lane; i <= P.nsites; i += 64) surv[i] = P.surv[i];
+  if (strat_lds)
+    for (int i = lane; i < A.strat_r * (P.nsites + 1); i += 64) strat_tab_lds[i] = P.strat[i];
   __syncthreads();
   const uint64_t seed = A.seed;
   const uint64_t words64 = (A.shots + 63) / 64;
@@ -135,7 +154,6 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   uint32_t* det32 = (uint32_t*)A.det;
   uint32_t* obs32 = (uint32_t*)A.obs;
   uint32_t* bits32 = (uint32_t*)A.nbits;  // split form: needed-bit rows
-  const bool strat = A.strat_r >= 0;      // stratified sampling (P.strat)
   cptr<uint64_t> masks = as_const(P.masks);
   cptr<uint32_t> rec_tgt_off = as_const(P.rec_tgt_off), rec_tgt = as_const(P.rec_tgt);
   for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -157,7 +175,7 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
           uint32_t cur = 0;
           for (uint32_t i = 0; i < (uint32_t)A.strat_r; i++) {
             const U4 w = draw(i, kPurposeStrat, shot, seed);
-            const uint32_t nf = strat_site(P, (uint32_t)A.strat_r - i, cur, w);
+            const uint32_t nf = strat_site(stab, NS, (uint32_t)A.strat_r - i, cur, w);
             if (lcnt < lcap) F(NF + lcnt) = (nf << 9) | ((uint32_t)j << 4) | fault_outcome(P, nf, w);
             else lovf = true;
             lcnt++;
@@ -196,7 +214,7 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
       for (int j = 0; j < kShotsPerLane; j++) {
         uint32_t ord = 0, nf = 0xFFFFFFFFu;
         if (!strat) nf = bs_next_fault<LDS_SURV>(P, surv, 0, 0, &ord, A.offset + s0 + j, seed);
-        else if (A.strat_r > 0) nf = strat_site(P, (uint32_t)A.strat_r, 0, draw(ord++, kPurposeStrat, A.offset + s0 + j, seed));
+        else if (A.strat_r > 0) nf = strat_site(stab, NS, (uint32_t)A.strat_r, 0, draw(ord++, kPurposeStrat, A.offset + s0 + j, seed));
         F(NF + j) = nf;
         F(OC + j) = ord;
         min_nf = min(min_nf, nf);
@@ -208,7 +226,9 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
     for (int pc = 0;; pc++) {
       const GInstr in = load_instr(P.code, pc);
       const uint32_t v = in.v;
-      if (in.op == OP_END || (P.has_post && !alive)) break;
+      // leave when every shot of the wave is rejected by post-selection
+      // (a wave-uniform exit; a lane with no live shot writes only zeros)
+      if (in.op == OP_END || (EXT && P.has_post && !__ballot(alive != 0))) break;
       switch (in.op) {
         case OP_FANCX:
         case OP_FANCZ:
@@ -398,7 +418,7 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
                   uint32_t cur = 0;
                   for (uint32_t i = 0; i < (uint32_t)A.strat_r && cur < hi; i++) {
                     const U4 w = draw(i, kPurposeStrat, shot, seed);
-                    const uint32_t nf = strat_site(P, (uint32_t)A.strat_r - i, cur, w);
+                    const uint32_t nf = strat_site(stab, NS, (uint32_t)A.strat_r - i, cur, w);
                     if (nf >= lo && nf < hi) bs_apply_fault<W>(P, F, N, nf, fault_outcome(P, nf, w), 1u << j);
                     cur = nf + 1;
                   }
@@ -437,7 +457,7 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
                   bs_apply_fault<W>(P, F, N, nf, fault_outcome(P, nf, draw(ord - 1, kPurposeStrat, shot, seed)), 1u << s);
                   if (ord == (uint32_t)A.strat_r) nf = 0xFFFFFFFFu;
                   else {
-                    nf = strat_site(P, (uint32_t)A.strat_r - ord, nf + 1, draw(ord, kPurposeStrat, shot, seed));
+                    nf = strat_site(stab, NS, (uint32_t)A.strat_r - ord, nf + 1, draw(ord, kPurposeStrat, shot, seed));
                     ord++;
                   }
                 }
@@ -479,12 +499,13 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
           break;
         case OP_POSTSELECT: {
           // post-selection (Section 3.2): shots whose detector reads 1 are
-          // rejected; the lane leaves once all of its shots are (the record
-          // rows were zero-filled, so the rows it skips read 0)
-          const uint32_t d = F(ACC + in.s);
-          if (det32 && store) det32[(size_t)in.b * 2 * words64 + col] = d & alive;
-          F(ACC + in.s) = 0;
-          alive &= ~d;
+          // rejected; later record words carry only the live shots' bits
+          if constexpr (EXT) {
+            const uint32_t d = F(ACC + in.s);
+            if (det32 && store) det32[(size_t)in.b * 2 * words64 + col] = d & alive;
+            F(ACC + in.s) = 0;
+            alive &= ~d;
+          }
           break;
         }
         case OP_EMIT:
@@ -523,32 +544,41 @@ __global__ __launch_bounds__(64) void k_frames(DevProgram P, KArgs A) {
   }
 }
 
-template <bool LS, bool LI>
+template <bool LS, bool LI, bool EXT>
 static hipError_t launch_frames_t(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
   static bool attr[5] = {false, false, false, false, false};
-  const void* fn = P.W == 1 ? (const void*)k_frames<1, LS, LI> : P.W == 2 ? (const void*)k_frames<2, LS, LI>
-                   : P.W == 3 ? (const void*)k_frames<3, LS, LI> : (const void*)k_frames<4, LS, LI>;
+  const void* fn = P.W == 1   ? (const void*)k_frames<1, LS, LI, EXT>
+                   : P.W == 2 ? (const void*)k_frames<2, LS, LI, EXT>
+                   : P.W == 3 ? (const void*)k_frames<3, LS, LI, EXT>
+                              : (const void*)k_frames<4, LS, LI, EXT>;
   if (!attr[P.W]) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr[P.W] = true;
   }
   switch (P.W) {
-    case 1: hipLaunchKernelGGL((k_frames<1, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
-    case 2: hipLaunchKernelGGL((k_frames<2, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
-    case 3: hipLaunchKernelGGL((k_frames<3, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
-    default: hipLaunchKernelGGL((k_frames<4, LS, LI>), dim3(grid), dim3(64), lds, st, P, A); break;
+    case 1: hipLaunchKernelGGL((k_frames<1, LS, LI, EXT>), dim3(grid), dim3(64), lds, st, P, A); break;
+    case 2: hipLaunchKernelGGL((k_frames<2, LS, LI, EXT>), dim3(grid), dim3(64), lds, st, P, A); break;
+    case 3: hipLaunchKernelGGL((k_frames<3, LS, LI, EXT>), dim3(grid), dim3(64), lds, st, P, A); break;
+    default: hipLaunchKernelGGL((k_frames<4, LS, LI, EXT>), dim3(grid), dim3(64), lds, st, P, A); break;
   }
   return hipGetLastError();
 }
 
+template <bool EXT>
+static hipError_t launch_frames_e(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
+  const bool ls = frames_surv_in_lds(P), li = frames_fault_list(P, A.strat_r);
+  if (ls && li) return launch_frames_t<true, true, EXT>(P, A, grid, lds, st);
+  if (ls) return launch_frames_t<true, false, EXT>(P, A, grid, lds, st);
+  if (li) return launch_frames_t<false, true, EXT>(P, A, grid, lds, st);
+  return launch_frames_t<false, false, EXT>(P, A, grid, lds, st);
+}
+
 hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStream_t st) {
-  const size_t lds = frames_lds_rows(P) * 64 * 4;
-  const bool ls = frames_surv_in_lds(P), li = frames_fault_list(P);
-  if (ls && li) return launch_frames_t<true, true>(P, A, grid, lds, st);
-  if (ls) return launch_frames_t<true, false>(P, A, grid, lds, st);
-  if (li) return launch_frames_t<false, true>(P, A, grid, lds, st);
-  return launch_frames_t<false, false>(P, A, grid, lds, st);
+  const size_t lds = frames_lds_rows(P, A.strat_r) * 64 * 4;
+  // post-selected programs and stratified calls take the EXT kernels
+  if (P.has_post || A.strat_r >= 0) return launch_frames_e<true>(P, A, grid, lds, st);
+  return launch_frames_e<false>(P, A, grid, lds, st);
 }
 
 }  // namespace clifft

@@ -73,6 +73,9 @@ struct BatchArgs {
 // groups.counter + 2 and groups.counter + 4.
 hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArgs& waves, int grid_waves,
                         const BatchArgs& lanes, int grid_lanes, size_t lds_bytes, bool fp64, hipStream_t stream);
+// The same with post-selection compiled in (batches holding post-selected programs).
+hipError_t launch_batch_ext(const BatchArgs& groups, int grid_groups, const BatchArgs& waves, int grid_waves,
+                            const BatchArgs& lanes, int grid_lanes, size_t lds_bytes, bool fp64, hipStream_t stream);
 
 hipError_t launch_zero(uint64_t* p, size_t n, hipStream_t stream);
 // The allocation-free entry point's fixed device workspace: kScratchBytes at
@@ -83,7 +86,7 @@ hipError_t scratch_region(void** ptr);
 // Bit-sliced Pauli-frame kernel (k_max = 0): 32 shots per lane, one 64-thread
 // workgroup per 2048-shot tile.
 hipError_t launch_frames(const DevProgram& P, const KArgs& A, int grid, hipStream_t stream);
-size_t frames_lds_rows(const DevProgram& P);
+size_t frames_lds_rows(const DevProgram& P, int strat_r = -1);
 hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape& L, bool fp64, bool trace,
                          hipStream_t stream);
 size_t lds_bytes_for(const DevProgram& P, int G, bool global_vec, bool fp64);
@@ -91,6 +94,9 @@ size_t lds_bytes_for(const DevProgram& P, int G, bool global_vec, bool fp64);
 hipError_t launch_sample_f32(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
 hipError_t launch_sample_f64(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
 hipError_t launch_trace_f32(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
+// With post-selection and stratified sampling compiled in (sample_ext_*.hip).
+hipError_t launch_sample_ext_f32(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
+hipError_t launch_sample_ext_f64(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
 hipError_t launch_trace_f64(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t stream);
 // Split form: the vector-only stream (vsample_*.hip) and the record fix-up:
 // rows[i] (an output row: meas, then det, then obs) ^= XOR of the outcome

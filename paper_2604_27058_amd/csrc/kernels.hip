@@ -73,8 +73,8 @@ hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape&
                          hipStream_t st) {
   if (L.G == 256 || L.G == 64 || (L.G < 0 && P.has_post)) {
     // shot-granular tiers OR their record bits into zero-filled rows; the
-    // bit-sliced kernel skips the rows of lanes whose shots were all
-    // rejected by post-selection
+    // bit-sliced kernel skips the rows left once post-selection has
+    // rejected every shot of a wave
     const size_t words = (A.shots + 63) / 64;
     uint64_t* rows[3] = {A.meas, A.det, A.obs};
     const size_t counts[3] = {(size_t)P.nrec, (size_t)P.ndet, (size_t)P.nobs};
@@ -92,8 +92,12 @@ hipError_t launch_sample(const DevProgram& P, const KArgs& A, const LaunchShape&
                        (uint64_t*)A.expval, n);
   }
   if (L.G < 0) return launch_frames(P, A, L.grid, st);
-  if (fp64) return debug ? launch_trace_f64(P, A, L, st) : launch_sample_f64(P, A, L, st);
-  return debug ? launch_trace_f32(P, A, L, st) : launch_sample_f32(P, A, L, st);
+  // post-selected programs and stratified calls take the kernels that have
+  // those paths compiled in (the trace kernels always do)
+  const bool ext = P.has_post || A.strat_r >= 0;
+  if (fp64) return debug ? launch_trace_f64(P, A, L, st) : ext ? launch_sample_ext_f64(P, A, L, st)
+                                                              : launch_sample_f64(P, A, L, st);
+  return debug ? launch_trace_f32(P, A, L, st) : ext ? launch_sample_ext_f32(P, A, L, st) : launch_sample_f32(P, A, L, st);
 }
 
 // Record fix-up of the split form: one thread per word of a dependent row.

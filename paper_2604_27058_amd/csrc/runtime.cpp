@@ -251,7 +251,8 @@ int device_cus() {
 clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const clifft_launch* cfg, uint64_t shots,
                            LaunchShape* L, bool* fp64,
                            const std::map<std::pair<int, int>, clifft_launch>* tuned = nullptr, bool trace = false,
-                           bool strat = false) {
+                           int strat_r = -1) {
+  const bool strat = strat_r >= 0;
   clifft_launch c{};
   if (cfg) c = *cfg;
   if (c.precision != CLIFFT_FP32 && c.precision != CLIFFT_FP64) return fail(CLIFFT_E_INVALID_ARG, "bad precision");
@@ -359,7 +360,7 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
       for (double q : H.site_p) f += q;
       tmp.exp_faults = (float)f;
     }
-    const size_t rows_bytes = frames_lds_rows(tmp) * 64 * 4;
+    const size_t rows_bytes = frames_lds_rows(tmp, strat_r) * 64 * 4;
     const bool spec = c.specialize == 1;
     const bool bs_ok = H.kmax == 0 && !trace && !H.has_cfeed && H.nprobes == 0 && (spec || rows_bytes <= kLdsLimit);
     if (c.specialize == 1 && G != 0 && G != kBitSliced)
@@ -573,7 +574,7 @@ clifft_status do_sample(const clifft_program* p, uint64_t shots, uint64_t seed, 
   }
   LaunchShape L{};
   bool fp64 = false;
-  st = choose_shape(p->host, D, cfg, shots, &L, &fp64, &p->tuned, trace, strat_r >= 0);
+  st = choose_shape(p->host, D, cfg, shots, &L, &fp64, &p->tuned, trace, strat_r);
   if (st != CLIFFT_OK) return st;
   size_t need = workspace_bytes(p->host, L, fp64, shots);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) {
@@ -1101,7 +1102,13 @@ clifft_status clifft_batch_sample(const clifft_batch* b, void* workspace, size_t
   L.nitems = b->items_l.size();
   L.counter = (uint32_t*)b->d_counter + 4;
   L.slot_bytes = b->slot_l;
-  if (e == hipSuccess) e = launch_batch(G, b->grid_g, Wv, b->grid_w, L, b->grid_l, b->lds, b->fp64, s);
+  if (e == hipSuccess) {
+    // batches holding post-selected programs take the kernels with that path
+    bool ext = false;
+    for (const clifft_program* q : b->progs) ext = ext || q->host.npost > 0;
+    e = ext ? launch_batch_ext(G, b->grid_g, Wv, b->grid_w, L, b->grid_l, b->lds, b->fp64, s)
+            : launch_batch(G, b->grid_g, Wv, b->grid_w, L, b->grid_l, b->lds, b->fp64, s);
+  }
   if (e != hipSuccess) return fail(CLIFFT_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
   return CLIFFT_OK;
 }

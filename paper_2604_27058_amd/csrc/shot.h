@@ -368,12 +368,13 @@ DEV uint32_t fault_outcome(const DevProgram& P, uint32_t site, const U4& w) {
 
 // Stratified sampling (Section 3.2, rare-event sampling): with s >= 1 faults
 // left from site cur on, the next one is at the smallest t >= cur with
-// e_s(t + 1) <= u e_s(cur) (the tables of DevProgram::strat); t <= nsites - s
-// since e_s vanishes once fewer than s sites remain.
-DEV uint32_t strat_site(const DevProgram& P, uint32_t s, uint32_t cur, const U4& w) {
-  const double* E = P.strat + (size_t)(s - 1) * (uint32_t)(P.nsites + 1);
+// e_s(t + 1) <= u e_s(cur) (tab: the rows of DevProgram::strat, in HBM or
+// staged in LDS); t <= nsites - s since e_s vanishes once fewer than s
+// sites remain.
+DEV uint32_t strat_site(const double* tab, uint32_t nsites, uint32_t s, uint32_t cur, const U4& w) {
+  const double* E = tab + (size_t)(s - 1) * (nsites + 1);
   const double tau = uniform53(w) * E[cur];
-  uint32_t lo = cur, hi = (uint32_t)P.nsites - s;
+  uint32_t lo = cur, hi = nsites - s;
   while (lo < hi) {
     const uint32_t mid = (lo + hi) >> 1;
     if (E[mid + 1] <= tau) hi = mid;
@@ -390,7 +391,7 @@ DEV void next_fault_strat(const DevProgram& P, Noise& ns, uint32_t cur, uint64_t
     return;
   }
   const U4 w = draw(ns.ord++, kPurposeStrat, shot, seed);
-  ns.nf = strat_site(P, ns.chunk, cur, w);
+  ns.nf = strat_site(P.strat, (uint32_t)P.nsites, ns.chunk, cur, w);
   ns.nf_out = fault_outcome(P, ns.nf, w);
   ns.chunk--;
 }
@@ -480,9 +481,14 @@ DEV int fault_phase(const DevProgram& P, const Words<W>& fx, uint32_t site, uint
 // ------------------------------------------------------------------ one shot
 // OOP: active vectors in HBM with a second buffer of the same size; active
 // measurements collapse out of place (alternating buffers) and read through
-// their folded localization passes.
-template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OOP = false, bool VONLY = false>
+// their folded localization passes.  EXT: post-selection (OP_POSTSELECT) and
+// stratified fault sampling are compiled in (always in trace mode); the
+// plain kernels leave them out so that their code and registers stay those
+// of plain sampling.
+template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OOP = false, bool VONLY = false,
+          bool EXT = false>
 struct Shot {
+  static constexpr bool kExt = EXT || DBG;
   const DevProgram& P;
   const KArgs& A;
   Group<G> grp;
@@ -493,6 +499,10 @@ struct Shot {
   uint64_t shot;  // global shot index (G == 1: per lane)
   uint64_t local; // shot index relative to the call (debug buffers)
   cpx<R>* alt = nullptr;  // OOP: the other buffer
+  // G == 1: the lane's shot was rejected by post-selection.  The lane keeps
+  // executing the stream (its wave-uniform state must stay uniform) but
+  // writes nothing more; G > 1 units end the shot at once instead.
+  bool post_dead = false;
 
   // The next active measurement after instruction pc (whose collapse fuses
   // it): its slot and type and the localization passes folded into it.
@@ -512,19 +522,12 @@ struct Shot {
     }
   }
 
-  MDEV bool writer() const { return (G == 1 || grp.tid == 0) && local < A.shots; }
-
-  // G == 1: the wave's first active lane (lanes whose shot was rejected by
-  // post-selection have left the instruction loop)
-  MDEV bool first_lane() const {
-    const uint32_t l = threadIdx.x & 63;
-    return rfl(l) == l;
-  }
+  MDEV bool writer() const { return (G == 1 || grp.tid == 0) && local < A.shots && !(kExt && post_dead); }
 
   MDEV void put(uint32_t r, uint32_t m) {
     if constexpr (G == 1) {
-      uint64_t word = __ballot(m);
-      if (first_lane()) rec[r] = word;
+      uint64_t word = __ballot(m && !(kExt && post_dead));
+      if ((threadIdx.x & 63) == 0) rec[r] = word;
     } else {
       if (grp.tid == 0) rec[r] |= (uint64_t)m << slane;
     }
@@ -674,10 +677,11 @@ struct Shot {
     Noise ns{0, 0, 0xFFFFFFFFu, 0};
     if (P.nsites > 0) {
       if (DBG && A.forced_faults) ns.nf = 0xFFFFFFFFu;
-      else if (A.strat_r >= 0) {
+      else if (kExt && A.strat_r >= 0) {
         ns.chunk = (uint32_t)A.strat_r;
         next_fault_strat(P, ns, 0, shot, seed);
-      } else next_fault(P, ns, 0, shot, seed);
+      } else
+        next_fault(P, ns, 0, shot, seed);
     }
     if (VEC && P.kmax > 0) {
       FOR_GROUP(p, 1u) vec[p] = cpx<R>{(R)1, (R)0};
@@ -688,6 +692,11 @@ struct Shot {
       const GInstr in = load_instr(P.code, pc);
       const int v = in.v;
       const int s = in.s;
+      if constexpr (G == 1 && kExt) {
+        // every lane of the wave rejected by post-selection: leave together
+        // (a wave-uniform exit, so that the instruction fetch stays scalar)
+        if (P.has_post && !__ballot(!post_dead)) goto done;
+      }
       switch (in.op) {
         case OP_END:
           goto done;
@@ -1548,51 +1557,34 @@ struct Shot {
             }
           }
           const uint32_t hi = in.b;
-          const bool strat = A.strat_r >= 0;
-          while (ns.nf < hi) {
-            if (!strat) {
-              uint32_t cend = min((ns.chunk + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
-              if (ns.nf >= cend) {
-                ns.chunk++;
-                ns.ord = 0;
-                next_fault(P, ns, 0, shot, seed);
-                continue;
+          if constexpr (kExt) {
+            if (A.strat_r >= 0) {
+              // stratified: the faults come in site order, no chunks
+              while (ns.nf < hi) {
+                if constexpr (DBG) g_ipow += fault_phase<W>(P, T.x, ns.nf, ns.nf_out);
+                apply_fault<W>(P, T, N, ns.nf, ns.nf_out);
+                next_fault_strat(P, ns, ns.nf + 1, shot, seed);
               }
+              break;
+            }
+          }
+          while (ns.nf < hi) {
+            uint32_t cend = min((ns.chunk + 1) * (uint32_t)kChunk, (uint32_t)P.nsites);
+            if (ns.nf >= cend) {
+              ns.chunk++;
+              ns.ord = 0;
+              next_fault(P, ns, 0, shot, seed);
+              continue;
             }
             if constexpr (DBG) g_ipow += fault_phase<W>(P, T.x, ns.nf, ns.nf_out);
             apply_fault<W>(P, T, N, ns.nf, ns.nf_out);
-            if (strat) next_fault_strat(P, ns, ns.nf + 1, shot, seed);
-            else next_fault(P, ns, ns.nf - ns.chunk * (uint32_t)kChunk + 1, shot, seed);
+            next_fault(P, ns, ns.nf - ns.chunk * (uint32_t)kChunk + 1, shot, seed);
           }
           break;
         }
         case OP_DET: {
           uint32_t d = xor_refs(in.a, in.u);
           put((uint32_t)P.nrec + in.b, d);
-          break;
-        }
-        case OP_POSTSELECT: {
-          // post-selection (Section 3.2): the detector is recorded, then a
-          // shot reading 1 ends here with its observables cleared (records
-          // not yet written stay 0)
-          if constexpr (G > 1) grp.sync();  // record bits are staged by the group's first thread
-          const uint32_t d = xor_refs(in.a, in.u);
-          put((uint32_t)P.nrec + in.b, d);
-          const uint32_t r0 = (uint32_t)(P.nrec + P.ndet);
-          if constexpr (G == 1) {
-            const uint64_t rej = __ballot(d);
-            if (rej) {
-              if (first_lane())
-                for (uint32_t o = 0; o < (uint32_t)P.nobs; o++) rec[r0 + o] &= ~rej;
-              if (d) goto done;
-            }
-          } else {
-            if (d) {
-              if (grp.tid == 0)
-                for (uint32_t o = 0; o < (uint32_t)P.nobs; o++) rec[r0 + o] &= ~(1ull << slane);
-              goto done;
-            }
-          }
           break;
         }
         case OP_EMIT:
@@ -1632,20 +1624,44 @@ struct Shot {
           uint32_t d = xor_refs(in.a, in.u);
           uint32_t r = (uint32_t)P.nrec + (uint32_t)P.ndet + in.b;
           if constexpr (G == 1) {
-            uint64_t word = __ballot(d);
-            if (first_lane()) rec[r] ^= word;
+            uint64_t word = __ballot(d && !(kExt && post_dead));
+            if ((threadIdx.x & 63) == 0) rec[r] ^= word;
           } else {
             if (grp.tid == 0) rec[r] ^= (uint64_t)d << slane;
           }
           break;
         }
         default:
+          // post-selection (Section 3.2): the detector is recorded, then a
+          // shot reading 1 ends here with its observables cleared (records
+          // not yet written stay 0).  Only the EXT kernels have this path;
+          // programs holding OP_POSTSELECT run on them alone.
+          if constexpr (kExt) {
+            if (in.op == OP_POSTSELECT) {
+              if constexpr (G > 1) grp.sync();  // record bits are staged by the group's first thread
+              const uint32_t d = xor_refs(in.a, in.u);
+              put((uint32_t)P.nrec + in.b, d);
+              const uint32_t r0 = (uint32_t)(P.nrec + P.ndet);
+              if constexpr (G == 1) {
+                const uint64_t rej = __ballot(d && !post_dead);
+                if (rej && (threadIdx.x & 63) == 0)
+                  for (uint32_t o = 0; o < (uint32_t)P.nobs; o++) rec[r0 + o] &= ~rej;
+                post_dead = post_dead || d;
+              } else {
+                if (rfl(d)) {  // one shot per group: the same value in every wave
+                  if (grp.tid == 0)
+                    for (uint32_t o = 0; o < (uint32_t)P.nobs; o++) rec[r0 + o] &= ~(1ull << slane);
+                  goto done;
+                }
+              }
+            }
+          }
           break;
       }
     }
   done:
     if constexpr (DBG) {
-      if (A.gamma_out && local < A.shots && (G == 1 || grp.tid == 0)) {
+      if (A.gamma_out && writer()) {
         const double sc = exp2(-0.5 * (double)g_nexp);
         const int e = g_ipow & 3;
         // i^e (g_re + i g_im) 2^{-n/2}
@@ -1656,11 +1672,11 @@ struct Shot {
       }
       if (A.phi_out && local < A.shots && P.kmax == 0) {
         // no active vector exists: the state is the trivial [1]
-        if (G == 1 || grp.tid == 0) {
+        if (writer()) {
           A.phi_out[local * 2] = 1.0;
           A.phi_out[local * 2 + 1] = 0.0;
         }
-      } else if (VEC && A.phi_out && local < A.shots) {
+      } else if (VEC && A.phi_out && local < A.shots && !(kExt && post_dead)) {
         if constexpr (OOP) materialize();
         // final active vector (its length 2^k is program-determined)
         FOR_GROUP(p, (1u << k)) {
@@ -1677,7 +1693,7 @@ struct Shot {
 // ------------------------------------------------------------------ kernel
 // One persistent launch: units (lanes-of-a-wave for G = 1, waves for G = 64,
 // workgroups for G = 256) take 64-shot tiles round-robin.
-template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false>
+template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false, bool EXT = false>
 __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int units_per_block = G == 256 ? 1 : 4;
@@ -1718,7 +1734,7 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
       for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += G) rec[r] = 0;
       unit_sync();
       uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0,
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY, EXT> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0,
                                                                   A.offset + g, g, alt};
       sh.run();
       unit_sync();
@@ -1741,14 +1757,14 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if constexpr (G == 1) {
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY, EXT> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
                                                                   A.offset + tile * 64 + lane, tile * 64 + lane, alt};
       sh.run();
     } else {
       uint32_t nsh = (uint32_t)min((uint64_t)64, A.shots - tile * 64);
       for (uint32_t sl = 0; sl < nsh; sl++) {
         uint64_t g = rfl((uint32_t)(tile * 64 + sl)) | ((tile * 64 + sl) & 0xFFFFFFFF00000000ull);
-        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red,
+        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY, EXT> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red,
                                                                     (int)sl, A.offset + g, g, alt};
         sh.run();
       }
@@ -1774,16 +1790,16 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
 }
 
 // ------------------------------------------------------------------ dispatch table
-template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false>
+template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false, bool EXT = false>
 inline hipError_t launch_one(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
   static bool attr = false;  // allow the whole 160 KB of LDS for dynamic use
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY, EXT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY>), dim3(grid), dim3(256), lds, st, P, A);
+  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY, EXT>), dim3(grid), dim3(256), lds, st, P, A);
   return hipGetLastError();
 }
 
@@ -1802,31 +1818,33 @@ inline hipError_t launch_vonly(const DevProgram& P, const KArgs& A, const Launch
   return launch_one<1, 256, R, false, false, true, true>(P, A, L.grid, L.lds_bytes, st);
 }
 
-template <int G, typename R, bool GLOBAL, bool DBG, bool VEC = true>
+template <int G, typename R, bool GLOBAL, bool DBG, bool VEC = true, bool EXT = false>
 inline hipError_t launch_w(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
   switch (P.W) {
-    case 1: return launch_one<1, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
-    case 2: return launch_one<2, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
-    case 3: return launch_one<3, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
-    case 4: return launch_one<4, G, R, GLOBAL, DBG, VEC>(P, A, grid, lds, st);
+    case 1: return launch_one<1, G, R, GLOBAL, DBG, VEC, false, EXT>(P, A, grid, lds, st);
+    case 2: return launch_one<2, G, R, GLOBAL, DBG, VEC, false, EXT>(P, A, grid, lds, st);
+    case 3: return launch_one<3, G, R, GLOBAL, DBG, VEC, false, EXT>(P, A, grid, lds, st);
+    case 4: return launch_one<4, G, R, GLOBAL, DBG, VEC, false, EXT>(P, A, grid, lds, st);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename R, bool DBG>
+// EXT: the instantiations with post-selection and stratified sampling
+// (sample_ext_*.hip), for programs and calls that use them.
+template <typename R, bool DBG, bool EXT = false>
 inline hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t st) {
   if (L.G == 1) {
     // Pauli-frame-only programs get an instantiation without any active-vector code
-    if (P.kmax == 0) return launch_w<1, R, false, DBG, false>(P, A, L.grid, L.lds_bytes, st);
-    if (L.global_vec) return launch_w<1, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
-    return launch_w<1, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+    if (P.kmax == 0) return launch_w<1, R, false, DBG, false, EXT>(P, A, L.grid, L.lds_bytes, st);
+    if (L.global_vec) return launch_w<1, R, true, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
+    return launch_w<1, R, false, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
   }
   if (L.G == 64) {
-    if (L.global_vec) return launch_w<64, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
-    return launch_w<64, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+    if (L.global_vec) return launch_w<64, R, true, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
+    return launch_w<64, R, false, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
   }
-  if (L.global_vec) return launch_w<256, R, true, DBG>(P, A, L.grid, L.lds_bytes, st);
-  return launch_w<256, R, false, DBG>(P, A, L.grid, L.lds_bytes, st);
+  if (L.global_vec) return launch_w<256, R, true, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
+  return launch_w<256, R, false, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
 }
 
 }  // namespace clifft
