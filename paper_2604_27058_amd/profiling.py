@@ -30,7 +30,7 @@ def code_tokens(text):
 # Sources that decide what a kernel family executes: the device code and the
 # host compiler that produces the instruction stream it runs.
 FAMILY_SOURCES = {
-    "interpreter": ("shot.h", "kernels.hip", "frames.hip", "batch.hip", "sample_f32.hip", "sample_f64.hip",
+    "interpreter": ("shot.h", "kernels.hip", "frames.hip", "batch.hip", "batch_kernel.h", "sample_f32.hip", "sample_f64.hip",
                     "kernels.h", "program.h", "philox.h", "compiler.cpp", "compiler.h"),
     "specialized": ("specialize.cpp", "spec_prelude.h", "spec_args.h", "program.h", "philox.h", "compiler.cpp",
                     "compiler.h"),
