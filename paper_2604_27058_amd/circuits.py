@@ -347,7 +347,11 @@ def large_active(n=200, depth=300, k_target=20, n_t=40, p=1e-4, seed=5000):
 # The five benchmark workloads and their shot counts.
 # --------------------------------------------------------------------------
 def workload(name):
-    """Returns dict(texts=[...], shots=int, precision='f64'|'f32', kmax=int|None)."""
+    """Returns dict(texts=[...], shots=int, precision='f64'|'f32', kmax=int|None).
+    "batched64[i]" is circuit i of the batched set alone (its 1e5 shots)."""
+    if name.startswith("batched64[") and name.endswith("]"):
+        c = batched_set()[int(name[len("batched64["):-1])]
+        return dict(texts=[c["text"]], shots=100_000, precision="f32", kmax=c["k"])
     if name == "random_clifford_t_n8":
         return dict(texts=[random_clifford_t(8, 40, 4, 1e-3, seed=1000)], shots=10_000, precision="f64", kmax=4)
     if name == "surface_d3_r3":

@@ -223,6 +223,9 @@ constexpr int kUnroll = 4;        // iterations in flight per lane, vectors on c
 constexpr int kUnrollGlobal = 8;  // FP32 vectors in HBM: more bytes in flight per wave
 template <typename R, bool GLOBAL>
 constexpr int unroll_for() { return GLOBAL && sizeof(R) == 4 ? kUnrollGlobal : kUnroll; }
+// log2 of the amplitudes in one 128-byte line
+template <typename R>
+constexpr int kLineBits() { return sizeof(R) == 4 ? 4 : 3; }
 
 // Read-modify-write of one element per iteration: i = idx(p).
 template <int G, typename R, int U, typename IdxF, typename BodyF>
@@ -286,6 +289,80 @@ DEV void pass21(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx,
   }
 }
 
+// Work-item order of the cooperative HBM passes (one shot per wave or
+// workgroup).  Such a pass reads each element pair at affine images of its
+// item index q; when a pair's partner mask crosses 128-byte lines while the
+// measured axis lies inside a line, the natural order touches every line
+// for half its elements and fetches it again from HBM for the other half.
+// Here the items of one aligned group of 2^nv lanes share q >> nv and span
+// v[0..nv), chosen so that the group's reads fill whole lines: q maps to
+// dep(q >> nv) ^ sum_i q_i v_i, dep inserting zeros at the pivots of v
+// (the highest bit of each, distinct after elimination) and at the pass's
+// fixed-zero bit.
+struct LineEnum {
+  uint32_t v[4];
+  int nv;
+  int pos[5];  // ascending zero-insertion positions (unused entries last)
+  int npos;
+  MDEV uint32_t operator()(uint32_t q) const {
+    uint32_t j = q >> nv;
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+      if (i < npos) j = ins0(j, pos[i]);
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      if (i < nv && ((q >> i) & 1u)) j ^= v[i];
+    return j;
+  }
+};
+
+// cand: candidate spanning vectors (0 = none; zero at the fixed bit `zero`,
+// or zero < 0 for none), in order of preference; at most four are kept
+// after elimination.  Constant indices only, so that everything stays in
+// registers.
+template <int NC>
+DEV LineEnum line_enum(const uint32_t (&cand)[NC], int zero) {
+  LineEnum E;
+  E.nv = 0;
+  int piv[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 4; i++) E.v[i] = 0;
+#pragma unroll
+  for (int c = 0; c < NC; c++) {
+    uint32_t x = cand[c];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      if (i < E.nv && ((x >> piv[i]) & 1u)) x ^= E.v[i];
+    if (x && E.nv < 4) {
+      const int pb = 31 - __clz(x);
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+        if (i < E.nv && ((E.v[i] >> pb) & 1u)) E.v[i] ^= x;
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+        if (i == E.nv) {
+          E.v[i] = x;
+          piv[i] = pb;
+        }
+      E.nv++;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; i++) E.pos[i] = i < E.nv ? piv[i] : 64;
+  E.pos[4] = zero >= 0 ? zero : 64;
+  E.npos = E.nv + (zero >= 0 ? 1 : 0);
+#pragma unroll
+  for (int i = 0; i < 4; i++)  // sorting network, ascending
+#pragma unroll
+    for (int j = 0; j < 4 - i; j++)
+      if (E.pos[j] > E.pos[j + 1]) {
+        const int t = E.pos[j];
+        E.pos[j] = E.pos[j + 1];
+        E.pos[j + 1] = t;
+      }
+  return E;
+}
+
 // Read-only pairs accumulated into two FP64 sums (the body also gets the
 // iteration index).
 template <int G, typename R, int U, typename IdxF, typename BodyF>
@@ -307,22 +384,25 @@ DEV void reduce2(const Group<G>& grp, const Vec<G, R>& vec, uint32_t n, IdxF idx
   }
 }
 
-// Gather pass into another buffer: dst[p] = gen(p) for p in [0, n) (gen
-// reads the source); all U values of a batch are formed before the stores.
-template <int G, typename R, int U, typename GenF>
-DEV void pass1_to(const Group<G>& grp, const Vec<G, R>& dst, uint32_t n, GenF gen) {
+// Gather pass into another buffer: dst[o] = gen(o) for o = ord(p), p in
+// [0, n) (ord a permutation of [0, n); gen reads the source); all U values
+// of a batch are formed before the stores.
+template <int G, typename R, int U, typename OrdF, typename GenF>
+DEV void pass1_to(const Group<G>& grp, const Vec<G, R>& dst, uint32_t n, OrdF ord, GenF gen) {
   const uint32_t st = G == 1 ? 1u : (uint32_t)G;
   for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n; base += U * st) {
     cpx<R> v[U];
+    uint32_t o[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const uint32_t p = base + u * st;
-      if (p < n) v[u] = gen(p);
+      o[u] = ord(p < n ? p : base);
+      if (p < n) v[u] = gen(o[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const uint32_t p = base + u * st;
-      if (p < n) dst[p] = v[u];
+      if (p < n) dst[o[u]] = v[u];
     }
   }
 }
@@ -486,9 +566,12 @@ DEV int fault_phase(const DevProgram& P, const Words<W>& fx, uint32_t site, uint
 // plain kernels leave them out so that their code and registers stay those
 // of plain sampling.
 template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OOP = false, bool VONLY = false,
-          bool EXT = false>
+          bool EXT = false, bool LINE = true>
 struct Shot {
   static constexpr bool kExt = EXT || DBG;
+  // line-complete item orders in the cooperative HBM passes (LineEnum);
+  // the batched queue kernels, held to 128 VGPRs, run faster without them
+  static constexpr bool kLine = G > 1 && OOP && LINE;
   const DevProgram& P;
   const KArgs& A;
   Group<G> grp;
@@ -1112,10 +1195,30 @@ struct Shot {
             s0 = grp.sum(s0, red);
             s1 = grp.sum(s1, red);
           } else {
+            // the pairs' first members (bit s clear); on the cooperative HBM
+            // tiers in line-complete order: the line bits other than s, and
+            // the partner mask's bits outside them when s is a line bit
+            LineEnum E{};
+            if constexpr (kLine) {
+              constexpr int LB = kLineBits<R>();
+              uint32_t cand[LB + 1];
+              uint32_t inc = 0;
+#pragma unroll
+              for (int b = 0; b < LB; b++) {
+                cand[b] = (b != (int)s && b < k) ? 1u << b : 0u;
+                inc |= cand[b];
+              }
+              cand[LB] = (int)s < LB ? tm & ~inc : 0u;
+              E = line_enum(cand, s);
+            }
+            auto first = [&](uint32_t q) -> uint32_t {
+              if constexpr (kLine) return E(q);
+              else return ins0(q, s);
+            };
             reduce2<G, R, U>(grp, vec, half,
-                             [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = ins0(q, s); i1 = (i0 | bs) ^ tm; },
+                             [&](uint32_t q, uint32_t& i0, uint32_t& i1) { i0 = first(q); i1 = (i0 | bs) ^ tm; },
                              [&](cpx<R> a, cpx<R> c, uint32_t q, double& x0, double& x1) {
-                               branch_sums(isx, a, partner(c, ins0(q, s) | bs), x0, x1);
+                               branch_sums(isx, a, partner(c, first(q) | bs), x0, x1);
                              },
                              s0, s1);
             s0 = grp.sum(s0, red);
@@ -1307,13 +1410,42 @@ struct Shot {
               // folded passes, summed as it is written
               constexpr int UP = U >= 2 ? U / 2 : 1;
               const uint32_t n2 = half >> 1;
+              // j0 (bit s2 clear) in line-complete order on the cooperative
+              // tiers: each group of lanes reads whole lines through both
+              // partner masks (m of this measurement, m2 of the next)
+              LineEnum E{};
+              if constexpr (kLine) {
+                const uint32_t m2 = b2 ^ tm2;
+                auto sig_inv = [&](uint32_t x) { return s == top ? x : ((x & ~tb) | (((x >> top) & 1u) << s)); };
+                constexpr int LB = kLineBits<R>();
+                uint32_t cand[LB + 2];
+                uint32_t inc = 0;
+#pragma unroll
+                for (int b = 0; b < LB; b++) {
+                  cand[b] = (b != (int)s && b != (int)s2 && b < top) ? 1u << b : 0u;
+                  inc |= cand[b];
+                }
+                cand[LB] = 0u;
+                if ((int)s < LB && (tm & ~inc)) {
+                  uint32_t x = sig_inv(tm & ~inc);
+                  if ((x >> s2) & 1u) x ^= m2;
+                  cand[LB] = x;
+                }
+                cand[LB + 1] = 0u;
+                if (s2 != s && (int)s2 < LB) {
+                  const uint32_t sm2 = s == top ? m2 : ((m2 & ~bs) | (((m2 >> s) & 1u) << top));
+                  cand[LB + 1] = sig_inv((sm2 ^ b2) & ~inc);
+                }
+                E = line_enum(cand, s2);
+              }
               for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n2; base += UP * st) {
                 uint32_t j0[UP];
                 cpx<R> y0[UP], y1[UP];
 #pragma unroll
                 for (int u = 0; u < UP; u++) {
                   const uint32_t q = base + u * st;
-                  j0[u] = ins0(q < n2 ? q : base, s2);
+                  if constexpr (kLine) j0[u] = E(q < n2 ? q : base);
+                  else j0[u] = ins0(q < n2 ? q : base, s2);
                   if (q < n2) {
                     y0[u] = one(j0[u]);
                     y1[u] = one((j0[u] | b2) ^ tm2);
@@ -1329,7 +1461,27 @@ struct Shot {
               }
               fused_sums = true;
             } else {
-              pass1_to<G, R, U>(grp, dst, half, one);
+              // outputs in line-complete order on the cooperative tiers
+              LineEnum E{};
+              if constexpr (kLine) {
+                auto sig_inv = [&](uint32_t x) { return s == top ? x : ((x & ~tb) | (((x >> top) & 1u) << s)); };
+                constexpr int LB = kLineBits<R>();
+                uint32_t cand[LB + 1];
+                uint32_t inc = 0;
+#pragma unroll
+                for (int b = 0; b < LB; b++) {
+                  cand[b] = (b != (int)s && b < top) ? 1u << b : 0u;
+                  inc |= cand[b];
+                }
+                cand[LB] = (int)s < LB ? sig_inv(tm & ~inc) : 0u;
+                E = line_enum(cand, -1);
+              }
+              pass1_to<G, R, U>(grp, dst, half,
+                                [&](uint32_t p) -> uint32_t {
+                                  if constexpr (kLine) return E(p);
+                                  else return p;
+                                },
+                                one);
             }
             cpx<R>* t = vec.base;
             vec.base = alt;
