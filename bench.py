@@ -262,8 +262,9 @@ def bench_batch(args, w, pk, torch):
     t_tune = time.perf_counter()
     if not args.no_autotune and not args.threads_per_shot:
         for i, (p, s) in enumerate(zip(progs, shots)):
-            p.autotune(s, "f32")
-            p.autotune(s, "f64")  # the plain FP64 form uses its own tuned shapes
+            # the plain FP64 form's per-program shapes (the batched launch
+            # places programs by its own k_max rule)
+            p.autotune(s, "f64")
             if i % 16 == 15:
                 progress("autotuned %d of %d circuits (%.0f s)" % (i + 1, n, time.perf_counter() - t_tune))
         tuned = True
@@ -409,6 +410,8 @@ def main():
                     help="1 active vectors in HBM, -1 on chip, 0 automatic")
     ap.add_argument("--specialize", type=int, default=0, choices=(-1, 0, 1),
                     help="bit-sliced tier: 1 the program-specialized kernel, -1 the interpreter, 0 automatic")
+    ap.add_argument("--split", type=int, default=0, choices=(-1, 0, 1, 2, 3),
+                    help="single-program workloads: clifft_launch.split (the split form's frame pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--postselect", default="none", choices=("none", "all"),
                     help="single-program workloads: post-select every detector")
@@ -443,13 +446,13 @@ def main():
     faults = args.faults if args.faults >= 0 else None
     prog = pk.Program(text, postselect=post)
     tuned = None
-    explicit = args.threads_per_shot or args.grid or args.vector_in_hbm or args.specialize
+    explicit = args.threads_per_shot or args.grid or args.vector_in_hbm or args.specialize or args.split
     if not args.no_autotune and not explicit:
         tuned = prog.autotune(shots, precision)
     if args.specialize == 1:
         prog.specialize()
     launch = pk.make_launch(precision, threads_per_shot=args.threads_per_shot, grid=args.grid,
-                            vector_in_hbm=args.vector_in_hbm, specialize=args.specialize)
+                            vector_in_hbm=args.vector_in_hbm, specialize=args.specialize, split=args.split)
     outs = prog.alloc_outputs(shots)
     ws = prog.alloc_workspace(launch, shots=shots)
     stream = torch.cuda.current_stream()

@@ -2,6 +2,8 @@
 // templates, instantiated without (batch.hip) and with (batch_ext.hip) the
 // post-selection and stratified-sampling paths.
 #pragma once
+#include <algorithm>
+
 #include "shot.h"
 
 namespace clifft {
@@ -38,11 +40,11 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
       const size_t per = 64 * ((size_t)1 << P.kmax);  // each wave: two buffers
       cpx<R>* base = (cpx<R>*)slot + (size_t)wv * 2 * per;
       if (P.kmax == 0) {
-        Shot<W, 1, R, false, false, kUnroll, false, false, EXT, false> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
+        Shot<W, 1, R, false, false, kUnroll, false, false, EXT> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
                                        A.offset + tile * 64 + lane, tile * 64 + lane};
         sh.run();
       } else {
-        Shot<W, 1, R, false, true, kUnroll, true, false, EXT, false> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
+        Shot<W, 1, R, false, true, kUnroll, true, false, EXT> sh{P, A, Group<1>{lane}, Vec<1, R>{base, lane}, wrec, red, lane,
                                                       A.offset + tile * 64 + lane, tile * 64 + lane, base + per};
         sh.run();
       }
@@ -73,7 +75,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
       const uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
       const size_t per = (size_t)1 << P.kmax;
       cpx<R>* base = (cpx<R>*)slot + (size_t)wv * 2 * per;
-      Shot<W, 64, R, false, true, unroll_for<R, true>(), true, false, EXT, false> sh{P, A, Group<64>{lane}, Vec<64, R>{base, lane}, wrec,
+      Shot<W, 64, R, false, true, unroll_for<R, true>(), true, false, EXT> sh{P, A, Group<64>{lane}, Vec<64, R>{base, lane}, wrec,
                                                                red, 0, A.offset + g, g, base + per};
       sh.run();
       __builtin_amdgcn_wave_barrier();
@@ -93,7 +95,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
     const uint64_t g = rfl((uint32_t)it.first) | (it.first & 0xFFFFFFFF00000000ull);
     for (uint32_t r = threadIdx.x; r < nwords_rec; r += 256) rec[r] = 0;
     __syncthreads();
-    Shot<W, 256, R, false, true, unroll_for<R, true>(), true, false, EXT, false> sh{P, A, Group<256>{(int)threadIdx.x},
+    Shot<W, 256, R, false, true, unroll_for<R, true>(), true, false, EXT> sh{P, A, Group<256>{(int)threadIdx.x},
                                                               Vec<256, R>{(cpx<R>*)slot, lane}, rec, red, 0, A.offset + g,
                                                               g, (cpx<R>*)slot + ((size_t)1 << P.kmax)};
     sh.run();
@@ -118,7 +120,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
 // kinds inline the interpreter for every frame width and would need about
 // 200 VGPRs (two waves per SIMD); they are held to four waves per SIMD,
 // which spills a few values to scratch and runs the batched set 1.2x faster.
-template <typename R, int KIND, bool EXT>
+template <typename R, int KIND, bool EXT, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == 1 ? 1 : 4))) void k_batch(BatchArgs B) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* rec = (uint64_t*)smem;  // 4 * rec_words
@@ -133,33 +135,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == 1 ?
     if ((uint64_t)item >= B.nitems) break;
     const BatchItem it = B.items[item];
     const BatchProgram& bp = B.progs[it.prog];
-    switch (bp.P.W) {
-      case 1: batch_item<1, R, KIND, EXT>(B, bp, it, rec, red, slot); break;
-      case 2: batch_item<2, R, KIND, EXT>(B, bp, it, rec, red, slot); break;
-      case 3: batch_item<3, R, KIND, EXT>(B, bp, it, rec, red, slot); break;
-      default: batch_item<4, R, KIND, EXT>(B, bp, it, rec, red, slot); break;
-    }
+    batch_item<W, R, KIND, EXT>(B, bp, it, rec, red, slot);
   }
 }
 
-template <typename R, int KIND, bool EXT>
-static hipError_t launch_batch_t(const BatchArgs& B, int grid, size_t lds_bytes, hipStream_t st) {
+template <typename R, int KIND, bool EXT, int W>
+static hipError_t launch_batch_w(const BatchArgs& B, int grid, size_t lds_bytes, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_batch<R, KIND, EXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void*)k_batch<R, KIND, EXT, W>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_batch<R, KIND, EXT>), dim3(grid), dim3(256), lds_bytes, st, B);
+  hipLaunchKernelGGL((k_batch<R, KIND, EXT, W>), dim3(grid), dim3(256), lds_bytes, st, B);
   return hipGetLastError();
+}
+
+// One queue: a kernel per frame width present, on that width's items (a
+// kernel instantiated for one width needs far fewer registers than one
+// that inlines the interpreter for all four).
+template <typename R, int KIND, bool EXT>
+static hipError_t launch_batch_t(const BatchArgs& B, int grid, size_t lds_bytes, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int w = 1; w <= 4 && e == hipSuccess; w++) {
+    const uint64_t n = B.wstart[w] - B.wstart[w - 1];
+    if (!n) continue;
+    BatchArgs S = B;
+    S.items = B.items + B.wstart[w - 1];
+    S.nitems = n;
+    S.counter = B.counter + 2 * (w - 1);
+    const int g = (int)std::min<uint64_t>((uint64_t)grid, n);
+    if (w == 1) e = launch_batch_w<R, KIND, EXT, 1>(S, g, lds_bytes, st);
+    else if (w == 2) e = launch_batch_w<R, KIND, EXT, 2>(S, g, lds_bytes, st);
+    else if (w == 3) e = launch_batch_w<R, KIND, EXT, 3>(S, g, lds_bytes, st);
+    else e = launch_batch_w<R, KIND, EXT, 4>(S, g, lds_bytes, st);
+  }
+  return e;
 }
 
 template <bool EXT>
 hipError_t launch_batch_impl(const BatchArgs& groups, int grid_groups, const BatchArgs& waves, int grid_waves,
                              const BatchArgs& lanes, int grid_lanes, size_t lds_bytes, bool fp64, hipStream_t st) {
-  // the three claim counters (32-bit words at the starts of three 64-bit slots)
-  hipError_t e = launch_zero((uint64_t*)groups.counter, 3, st);
+  // the claim counters: three blocks of four 64-bit slots (one per width)
+  hipError_t e = launch_zero((uint64_t*)groups.counter, 12, st);
   if (e == hipSuccess && groups.nitems)
     e = fp64 ? launch_batch_t<double, 256, EXT>(groups, grid_groups, lds_bytes, st)
              : launch_batch_t<float, 256, EXT>(groups, grid_groups, lds_bytes, st);

@@ -56,21 +56,24 @@ struct BatchItem {
   uint32_t kind;   // 1: four 64-shot tiles (one per wave); 256: one shot
   uint64_t first;  // first tile (kind 1), first of four shots (kind 64) or the shot (kind 256)
 };
-// One queue of a batched launch (all items of one kind).
+// One queue of a batched launch (all items of one kind), its items grouped
+// by the frame width W of their program: items [wstart[W-1], wstart[W]).
 struct BatchArgs {
   const BatchProgram* progs;
   const BatchItem* items;
   uint64_t nitems;
-  uint32_t* counter;      // claim counter, zeroed before the launch
+  uint64_t wstart[5];
+  uint32_t* counter;      // claim counters (one 64-bit slot per width), zeroed before the launch
   uint64_t *meas, *det, *obs;
   void* workspace;
   uint64_t slot_bytes;    // workspace bytes per workgroup
   uint32_t rec_words;     // max records + detectors + observables over programs
 };
 // The shot-per-workgroup queue, the shot-per-wave queue, then the
-// shot-per-lane queue, as three persistent kernels on the stream (they share
-// the workspace).  The counters are the 32-bit words at groups.counter,
-// groups.counter + 2 and groups.counter + 4.
+// shot-per-lane queue, each as one persistent kernel per frame width present
+// (instantiated for that width), in turn on the stream (they share the
+// workspace).  The queues' counter blocks are the 32-bit words at
+// groups.counter + 8 q + 2 (W - 1), q = 0, 1, 2: twelve 64-bit slots.
 hipError_t launch_batch(const BatchArgs& groups, int grid_groups, const BatchArgs& waves, int grid_waves,
                         const BatchArgs& lanes, int grid_lanes, size_t lds_bytes, bool fp64, hipStream_t stream);
 // The same with post-selection compiled in (batches holding post-selected programs).

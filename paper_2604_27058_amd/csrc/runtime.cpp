@@ -261,8 +261,11 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
     int dev = 0;
     (void)hipGetDevice(&dev);
     auto it = tuned->find({dev, c.precision});
+    // a stratum with faults runs faster shot per lane than bit-sliced (whose
+    // per-shot fault cursors serialise on dependent LDS reads)
     if (it != tuned->end() && !(trace && (it->second.threads_per_shot == kBitSliced || it->second.split >= 1)) &&
-        !(strat && (it->second.split >= 1 || it->second.specialize == 1)))
+        !(strat && (it->second.split >= 1 || it->second.specialize == 1 ||
+                    (strat_r > 0 && it->second.threads_per_shot == kBitSliced))))
       c = it->second;
   }
   if (strat && (c.split >= 1 || c.specialize == 1))
@@ -372,7 +375,7 @@ clifft_status choose_shape(const CompiledProgram& H, const DevProgram* D, const 
       spec_supported(H, &why);
       return fail(CLIFFT_E_UNSUPPORTED, why);
     }
-    if (G == 0 && bs_ok) G = kBitSliced;
+    if (G == 0 && bs_ok && strat_r <= 0) G = kBitSliced;
     if (G == kBitSliced) {
       const uint64_t tiles = (shots + 2047) / 2048;
       // the specialized kernel keeps its rows in registers (about 8 waves per
@@ -639,6 +642,7 @@ struct clifft_batch {
   // four shots of shot-per-wave programs, and 64-shot tile groups of
   // shot-per-lane programs; each sorted longest first
   std::vector<BatchItem> items_g, items_w, items_l;
+  uint64_t wstart_g[5] = {}, wstart_w[5] = {}, wstart_l[5] = {};  // per-width item ranges
   bool fp64 = false;
   int device = 0;
   int grid_g = 0, grid_w = 0, grid_l = 0;
@@ -955,13 +959,9 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
     int G = c.threads_per_shot == 256 || c.threads_per_shot == 64 || c.threads_per_shot == 1
                 ? c.threads_per_shot
                 : (H.kmax <= kBatchLaneMaxK ? 1 : H.kmax <= kWaveMaxK ? 64 : 256);
-    if (c.threads_per_shot == 0) {
-      // an autotuned program keeps its tier inside the batch
-      auto it = progs[i]->tuned.find({b->device, c.precision});
-      if (it != progs[i]->tuned.end() && it->second.threads_per_shot > 0 && it->second.split < 1 &&
-          (H.kmax <= kLaneMaxK || it->second.threads_per_shot != 1))
-        G = it->second.threads_per_shot;
-    }
+    // (an autotuned program's standalone tier is not used here: the queue
+    // kernels' costs differ, and on the batched set the k_max rule above
+    // ran the step faster than the standalone choices)
     bp.G = G;
     const uint64_t vec = (uint64_t)1 << H.kmax;
     // two buffers per shot vector (out-of-place collapses)
@@ -1007,6 +1007,21 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
   longest_first(b->items_g, cost_g);
   longest_first(b->items_w, cost_w);
   longest_first(b->items_l, cost_l);
+  // each queue runs one kernel per frame width: group its items by width
+  // (stable, so each group stays longest first)
+  auto by_width = [&](std::vector<BatchItem>& items, uint64_t* ws) {
+    std::stable_sort(items.begin(), items.end(), [&](const BatchItem& x, const BatchItem& y) {
+      return b->table[x.prog].P.W < b->table[y.prog].P.W;
+    });
+    ws[0] = 0;
+    for (int w = 1; w <= 4; w++) {
+      ws[w] = ws[w - 1];
+      while (ws[w] < items.size() && b->table[items[ws[w]].prog].P.W == w) ws[w]++;
+    }
+  };
+  by_width(b->items_g, b->wstart_g);
+  by_width(b->items_w, b->wstart_w);
+  by_width(b->items_l, b->wstart_l);
   b->rec_words = (b->rec_words + 1) & ~1u;
   b->lds = (size_t)4 * b->rec_words * 8 + 64 + 64;
   if (b->lds > kLdsLimit) { delete b; return fail(CLIFFT_E_CAPACITY, "too many records for the batched launch"); }
@@ -1027,7 +1042,7 @@ clifft_status clifft_batch_create(const clifft_program* const* progs, int32_t n,
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_items_g, sizeof(BatchItem) * std::max<size_t>(1, b->items_g.size()));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_items_w, sizeof(BatchItem) * std::max<size_t>(1, b->items_w.size()));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_items_l, sizeof(BatchItem) * std::max<size_t>(1, b->items_l.size()));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, 64);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, 128);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_table, b->table.data(), sizeof(BatchProgram) * b->table.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !b->items_g.empty())
@@ -1085,6 +1100,7 @@ clifft_status clifft_batch_sample(const clifft_batch* b, void* workspace, size_t
   G.progs = b->d_table;
   G.items = b->d_items_g;
   G.nitems = b->items_g.size();
+  std::copy(b->wstart_g, b->wstart_g + 5, G.wstart);
   G.counter = (uint32_t*)b->d_counter;
   G.meas = meas;
   G.det = det;
@@ -1095,12 +1111,14 @@ clifft_status clifft_batch_sample(const clifft_batch* b, void* workspace, size_t
   BatchArgs Wv = G;
   Wv.items = b->d_items_w;
   Wv.nitems = b->items_w.size();
-  Wv.counter = (uint32_t*)b->d_counter + 2;
+  std::copy(b->wstart_w, b->wstart_w + 5, Wv.wstart);
+  Wv.counter = (uint32_t*)b->d_counter + 8;
   Wv.slot_bytes = b->slot_w;
   BatchArgs L = G;
   L.items = b->d_items_l;
   L.nitems = b->items_l.size();
-  L.counter = (uint32_t*)b->d_counter + 4;
+  std::copy(b->wstart_l, b->wstart_l + 5, L.wstart);
+  L.counter = (uint32_t*)b->d_counter + 16;
   L.slot_bytes = b->slot_l;
   if (e == hipSuccess) {
     // batches holding post-selected programs take the kernels with that path

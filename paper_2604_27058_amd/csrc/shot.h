@@ -304,15 +304,21 @@ struct LineEnum {
   int nv;
   int pos[5];  // ascending zero-insertion positions (unused entries last)
   int npos;
+  uint32_t xo;  // sum of v over the low bits of the lane's items (bind)
+  // The passes step q by multiples of 64 from the lane's own index, so the
+  // low nv (<= 4) bits of q are the lane's: their part of the sum is fixed.
+  MDEV void bind(uint32_t lane_q) {
+    xo = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      if (i < nv && ((lane_q >> i) & 1u)) xo ^= v[i];
+  }
   MDEV uint32_t operator()(uint32_t q) const {
     uint32_t j = q >> nv;
 #pragma unroll
     for (int i = 0; i < 5; i++)
       if (i < npos) j = ins0(j, pos[i]);
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-      if (i < nv && ((q >> i) & 1u)) j ^= v[i];
-    return j;
+    return j ^ xo;
   }
 };
 
@@ -569,8 +575,7 @@ template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OO
           bool EXT = false, bool LINE = true>
 struct Shot {
   static constexpr bool kExt = EXT || DBG;
-  // line-complete item orders in the cooperative HBM passes (LineEnum);
-  // the batched queue kernels, held to 128 VGPRs, run faster without them
+  // line-complete item orders in the cooperative HBM passes (LineEnum)
   static constexpr bool kLine = G > 1 && OOP && LINE;
   const DevProgram& P;
   const KArgs& A;
@@ -1210,6 +1215,7 @@ struct Shot {
               }
               cand[LB] = (int)s < LB ? tm & ~inc : 0u;
               E = line_enum(cand, s);
+              E.bind((uint32_t)grp.tid);
             }
             auto first = [&](uint32_t q) -> uint32_t {
               if constexpr (kLine) return E(q);
@@ -1437,6 +1443,7 @@ struct Shot {
                   cand[LB + 1] = sig_inv((sm2 ^ b2) & ~inc);
                 }
                 E = line_enum(cand, s2);
+                E.bind((uint32_t)grp.tid);
               }
               for (uint32_t base = G == 1 ? 0u : (uint32_t)grp.tid; base < n2; base += UP * st) {
                 uint32_t j0[UP];
@@ -1475,6 +1482,7 @@ struct Shot {
                 }
                 cand[LB] = (int)s < LB ? sig_inv(tm & ~inc) : 0u;
                 E = line_enum(cand, -1);
+                E.bind((uint32_t)grp.tid);
               }
               pass1_to<G, R, U>(grp, dst, half,
                                 [&](uint32_t p) -> uint32_t {
