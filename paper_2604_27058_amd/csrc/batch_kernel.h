@@ -75,7 +75,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
       const uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
       const size_t per = (size_t)1 << P.kmax;
       cpx<R>* base = (cpx<R>*)slot + (size_t)wv * 2 * per;
-      Shot<W, 64, R, false, true, unroll_for<R, true>(), true, false, EXT> sh{P, A, Group<64>{lane}, Vec<64, R>{base, lane}, wrec,
+      Shot<W, 64, R, false, true, unroll_for<R, true>(), true, false, EXT, true, false> sh{P, A, Group<64>{lane}, Vec<64, R>{base, lane}, wrec,
                                                                red, 0, A.offset + g, g, base + per};
       sh.run();
       __builtin_amdgcn_wave_barrier();
@@ -95,7 +95,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs& B, const BatchProgra
     const uint64_t g = rfl((uint32_t)it.first) | (it.first & 0xFFFFFFFF00000000ull);
     for (uint32_t r = threadIdx.x; r < nwords_rec; r += 256) rec[r] = 0;
     __syncthreads();
-    Shot<W, 256, R, false, true, unroll_for<R, true>(), true, false, EXT> sh{P, A, Group<256>{(int)threadIdx.x},
+    Shot<W, 256, R, false, true, unroll_for<R, true>(), true, false, EXT, true, false> sh{P, A, Group<256>{(int)threadIdx.x},
                                                               Vec<256, R>{(cpx<R>*)slot, lane}, rec, red, 0, A.offset + g,
                                                               g, (cpx<R>*)slot + ((size_t)1 << P.kmax)};
     sh.run();

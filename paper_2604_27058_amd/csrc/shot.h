@@ -570,9 +570,11 @@ DEV int fault_phase(const DevProgram& P, const Words<W>& fx, uint32_t site, uint
 // their folded localization passes.  EXT: post-selection (OP_POSTSELECT) and
 // stratified fault sampling are compiled in (always in trace mode); the
 // plain kernels leave them out so that their code and registers stay those
-// of plain sampling.
+// of plain sampling.  PAIR: paired measurement collapses on the cooperative
+// HBM tiers (left out of the batched kernels, whose vectors mostly stay in
+// the caches and whose registers are tighter).
 template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OOP = false, bool VONLY = false,
-          bool EXT = false, bool LINE = true>
+          bool EXT = false, bool LINE = true, bool PAIR = true>
 struct Shot {
   static constexpr bool kExt = EXT || DBG;
   // line-complete item orders in the cooperative HBM passes (LineEnum)
@@ -606,6 +608,77 @@ struct Shot {
         s2 = g.s;
         x2 = g.op == OP_MACTX;
         return;
+      }
+    }
+  }
+
+  // An active measurement ahead of pc and the localization passes folded
+  // into it (pc = -1 at the end of the stream).
+  struct MeasAhead {
+    int pc;
+    uint32_t s, tm, sm;
+    bool as, x;
+    uint8_t flags;
+  };
+  MDEV MeasAhead peek_meas(int pc) const {
+    MeasAhead m{-1, 0u, 0u, 0u, false, false, 0};
+    for (int q = pc + 1;; q++) {
+      const GInstr g = load_instr(P.code, q);
+      if (g.op == OP_APERM) m.tm = g.a;
+      else if (g.op == OP_ASIGN) m.sm = g.a;
+      else if (g.op == OP_AS) m.as = true;
+      else if (g.op == OP_MACTZ || g.op == OP_MACTX || g.op == OP_END) {
+        m.pc = g.op == OP_END ? -1 : q;
+        m.s = g.s;
+        m.x = g.op == OP_MACTX;
+        m.flags = g.flags;
+        return m;
+      }
+    }
+  }
+  // Paired collapses: a partner read through folded localization passes
+  // (the sign from its index, then the factor i), and the unnormalised kept
+  // branch b of a pair (a, c): a or c, or a +- c for an X-type measurement.
+  static MDEV cpx<R> pair_phase(cpx<R> x, uint32_t i1, uint32_t sm, bool as) {
+    const cpx<R> y = (__popc(i1 & sm) & 1) ? cpx<R>{-x.re, -x.im} : x;
+    return as ? cpx<R>{-y.im, y.re} : y;
+  }
+  static MDEV cpx<R> pair_comb(cpx<R> a, cpx<R> c, bool x, uint32_t b) {
+    if (x) return b ? cpx<R>{a.re - c.re, a.im - c.im} : cpx<R>{a.re + c.re, a.im + c.im};
+    return b ? c : a;
+  }
+  // Quad q of a vector of kq slots under measurement a and then b (on a's
+  // result, whose slot a.s holds the former top slot kq-1): o[0], o[1] are
+  // a's pair that gives b's first member u1 (top slot kq-2 moved into b.s),
+  // o[2], o[3] the pair that gives b's partner, read at u2i ^ b.tm.
+  static MDEV void pair_quad(uint32_t q, int kq, const MeasAhead& a, const MeasAhead& b, uint32_t (&o)[4],
+                             uint32_t& u2i) {
+    const int ta = kq - 1, tb = kq - 2;
+    const uint32_t ba = 1u << a.s, bb = 1u << b.s;
+    const uint32_t u1 = (int)b.s == tb ? q : ((q & ~bb) | (((q >> b.s) & 1u) << tb));
+    u2i = u1 | bb;
+    const uint32_t u2 = u2i ^ b.tm;
+    o[0] = (int)a.s == ta ? u1 : ((u1 & ~ba) | (((u1 >> a.s) & 1u) << ta));
+    o[1] = (o[0] | ba) ^ a.tm;
+    o[2] = (int)a.s == ta ? u2 : ((u2 & ~ba) | (((u2 >> a.s) & 1u) << ta));
+    o[3] = (o[2] | ba) ^ a.tm;
+  }
+  // the quad's part of the joint branch sums t[2 ba + bb] (raw: a factor
+  // 1/2 per X-type measurement left out)
+  static MDEV void pair_sums(const cpx<R> (&y)[4], const uint32_t (&o)[4], uint32_t u2i, const MeasAhead& a,
+                             const MeasAhead& b, double (&t)[4]) {
+    const uint32_t ba = 1u << a.s;
+    const cpx<R> c1 = pair_phase(y[1], o[0] | ba, a.sm, a.as), c2 = pair_phase(y[3], o[2] | ba, a.sm, a.as);
+#pragma unroll
+    for (uint32_t e = 0; e < 2; e++) {
+      const cpx<R> y1 = pair_comb(y[0], c1, a.x, e);
+      const cpx<R> y2 = pair_phase(pair_comb(y[2], c2, a.x, e), u2i, b.sm, b.as);
+      if (b.x) {
+        t[2 * e] += norm2(cpx<R>{y1.re + y2.re, y1.im + y2.im});
+        t[2 * e + 1] += norm2(cpx<R>{y1.re - y2.re, y1.im - y2.im});
+      } else {
+        t[2 * e] += norm2(y1);
+        t[2 * e + 1] += norm2(y2);
       }
     }
   }
@@ -692,6 +765,22 @@ struct Shot {
     U4 rb{0, 0, 0, 0};
     double carry0 = 0, carry1 = 0;  // branch sums of the next active measurement (fused)
     bool carry_valid = false;
+    // Paired collapses (the cooperative HBM tiers, Appendix B.2 for two
+    // measurements A and B with only frame work between them): from the
+    // joint branch sums S[bA][bB], A is sampled from the marginals and its
+    // collapse waits; B, sampled from S[bA][.], collapses the vector along
+    // both axes in one pass (reads 2^k, writes 2^(k-2)) instead of two
+    // (2^k + 2^(k-1) read, 2^(k-1) + 2^(k-2) written).  The joint sums are
+    // taken by the collapse before A as it writes its outputs (by quads of
+    // A and B), or with nothing carried by one pass over the vector.  B's
+    // frame bits are read at B as usual.
+    constexpr bool kPair = G > 1 && OOP && PAIR;
+    bool pj_valid = false;                 // joint sums carried
+    double pj00 = 0, pj01 = 0, pj10 = 0, pj11 = 0;
+    bool pair_pend = false;                // A sampled, collapse pending
+    uint32_t pa_s = 0, pa_tm = 0, pa_sm = 0, pa_b = 0;
+    bool pa_as = false, pa_x = false;
+    double pb0 = 0, pb1 = 0;               // B's raw sums given A's branch
     uint32_t pend_tm = 0, pend_sm = 0;  // folded localization passes of the next measurement
     bool pend_as = false;
     // Out of place: the last dfr expansions are not applied yet; element x
@@ -840,6 +929,7 @@ struct Shot {
             break;
           }
           carry_valid = false;
+          pj_valid = false;
           materialize();
           // control slot s, targets tm: i -> i ^ tm for i with bit s set; each
           // pair is visited once from the member with target bit t0 clear
@@ -861,6 +951,7 @@ struct Shot {
             break;
           }
           carry_valid = false;
+          pj_valid = false;
           materialize();
           // -1 on i with bit s set and odd parity of i & sm: enumerate i with
           // bits s and c (lowest of sm) free, then fix bit c to make it odd
@@ -881,6 +972,7 @@ struct Shot {
           if constexpr (!VEC) break;
           else {
           carry_valid = false;
+          pj_valid = false;
           materialize();
           // flip bit s where parity(i & sm) is odd: pairs along s with odd parity
           const uint32_t sm = in.a, bs = 1u << s;
@@ -905,6 +997,7 @@ struct Shot {
             break;
           }
           carry_valid = false;
+          pj_valid = false;
           materialize();
           const uint32_t bs = 1u << s;
           pass1<G, R, U>(grp, vec, 1u << (k - 1), [&](uint32_t p) { return ins0(p, s) | bs; },
@@ -917,6 +1010,7 @@ struct Shot {
           if constexpr (!VEC) break;
           else {
           carry_valid = false;
+          pj_valid = false;
           if constexpr (!OOP) materialize();
           const R h = (R)0.70710678118654752440;
           const uint32_t bs = 1u << s;
@@ -994,6 +1088,7 @@ struct Shot {
           if constexpr (!VEC) break;
           else {
           carry_valid = false;
+          pj_valid = false;
           // Appendix B.1 case 2: H_v takes |0>_v to |+>_v (frames conjugated);
           // then exp(-i theta' Z_v) on the new axis, theta' sign-flipped by
           // x_v of the frame.  The common phase e^{-i theta'} is global, so
@@ -1044,6 +1139,7 @@ struct Shot {
           if constexpr (!VEC) break;
           else {
           carry_valid = false;
+          pj_valid = false;
           materialize();
           double c2 = P.consts[4 * in.a], s2 = P.consts[4 * in.a + 1];
           const bool flip = VONLY ? nbit(v, mb) != 0 : getbit<W>(T.x, v) != 0;
@@ -1120,6 +1216,18 @@ struct Shot {
           }
           const uint32_t bs = 1u << s;
           const uint32_t half = 1u << (k - 1);
+          // paired collapses (see kPair): A of a pair (its collapse waits)
+          // or B (the collapse along both axes)
+          int pmode = 0;
+          MeasAhead pmB{};
+          if constexpr (kPair) {
+            if (pair_pend) {
+              pmode = 2;
+            } else if ((in.flags & F_FUSE_NEXT) && k >= 3 && dfr == 0 && (pj_valid || !carry_valid)) {
+              pmode = 1;
+              pmB = peek_meas(pc);
+            }
+          }
           // branch sums (Appendix B.2): |a|^2 per half along the axis, or
           // |a +- b|^2 of the fold for an X-type measurement
           auto branch_sums = [](bool x, cpx<R> a, cpx<R> b, double& x0, double& x1) {
@@ -1159,7 +1267,33 @@ struct Shot {
             cpx<R> y = (__popc((lo | bsl) & sml) & 1) ? cpx<R>{-x.re, -x.im} : x;
             return fas ? cpx<R>{-y.im, y.re} : y;
           };
-          if (carry_valid) {
+          if (kPair && pmode == 2) {
+            // B: its sums given A's branch
+            s0 = pb0;
+            s1 = pb1;
+          } else if (kPair && pmode == 1) {
+            // A: the marginals of the joint sums of A and B (carried, or
+            // from one pass over the vector)
+            if (!pj_valid) {
+              const MeasAhead me{pc, (uint32_t)s, tm, sm, fas, isx, in.flags};
+              double t[4] = {0, 0, 0, 0};
+              for (uint32_t q = (uint32_t)grp.tid; q < (1u << (k - 2)); q += (uint32_t)G) {
+                uint32_t o[4], u2i;
+                pair_quad(q, k, me, pmB, o, u2i);
+                cpx<R> y[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) y[e] = vec[o[e]];
+                pair_sums(y, o, u2i, me, pmB, t);
+              }
+              pj00 = grp.sum(t[0], red);
+              pj01 = grp.sum(t[1], red);
+              pj10 = grp.sum(t[2], red);
+              pj11 = grp.sum(t[3], red);
+            }
+            const double f = pmB.x ? 0.5 : 1.0;
+            s0 = f * (pj00 + pj01);
+            s1 = f * (pj10 + pj11);
+          } else if (carry_valid) {
             // accumulated by the previous measurement's collapse pass
             s0 = carry0;
             s1 = carry1;
@@ -1274,9 +1408,22 @@ struct Shot {
             cpx<R> y = (__popc(i1 & sm2) & 1) ? cpx<R>{-x.re, -x.im} : x;
             return as2 ? cpx<R>{-y.im, y.re} : y;
           };
+          // a pair follows: the joint sums of the next two measurements
+          // instead (cooperative HBM tiers)
+          MeasAhead pm2{}, pm3{};
+          bool joint2 = false;
+          if constexpr (kPair) {
+            if (fuse && !dfd && k - 1 >= 3) {
+              pm2 = peek_meas(pc);
+              if (pm2.flags & F_FUSE_NEXT) {
+                pm3 = peek_meas(pm2.pc);
+                joint2 = true;
+              }
+            }
+          }
           const uint32_t st = G == 1 ? 1u : (uint32_t)G;
           double n0 = 0, n1 = 0;
-          bool fused_sums = false;
+          bool fused_sums = false, pj_new = false;
           if constexpr (OOP) {
             // out of place into the other buffer: output o (new slot s holds
             // the former top bit) reads its pair through the folded passes
@@ -1286,7 +1433,66 @@ struct Shot {
               const uint32_t i1 = base | bs;
               return out1(vec[base], partner(vec[i1 ^ tm], i1));
             };
-            if (dfd) {
+            if (kPair && pmode == 1) {
+              // A: sampled and recorded; its collapse waits for B
+              pa_s = (uint32_t)s;
+              pa_tm = tm;
+              pa_sm = sm;
+              pa_as = fas;
+              pa_x = isx;
+              pa_b = b;
+              pb0 = b ? pj10 : pj00;
+              pb1 = b ? pj11 : pj01;
+              pair_pend = true;
+            } else if (kPair && pmode == 2) {
+              // B: the vector (k + 1 slots, A not collapsed yet) collapses
+              // along both axes; element u of A's result (unnormalised) and
+              // element w of the result
+              const int topA = k, topB = k - 1;
+              const uint32_t bsA = 1u << pa_s;
+              auto ua = [&](uint32_t u) {
+                const uint32_t v0 = (int)pa_s == topA ? u : ((u & ~bsA) | (((u >> pa_s) & 1u) << topA));
+                return pair_comb(vec[v0], pair_phase(vec[(v0 | bsA) ^ pa_tm], v0 | bsA, pa_sm, pa_as), pa_x, pa_b);
+              };
+              const R f = isx ? fs * scale : scale;
+              auto wv = [&](uint32_t w) {
+                const uint32_t u1 = s == topB ? w : ((w & ~bs) | (((w >> s) & 1u) << topB));
+                const uint32_t u2i = u1 | bs;
+                const cpx<R> r = pair_comb(ua(u1), partner(ua(u2i ^ tm), u2i), isx, b);
+                return cpx<R>{f * r.re, f * r.im};
+              };
+              const uint32_t nw = half;  // k - 1 slots
+              if (joint2) {
+                double jt[4] = {0, 0, 0, 0};
+                for (uint32_t q = (uint32_t)grp.tid; q < (nw >> 2); q += st) {
+                  uint32_t o[4], u2i;
+                  pair_quad(q, k - 1, pm2, pm3, o, u2i);
+                  cpx<R> y[4];
+#pragma unroll
+                  for (int e = 0; e < 4; e++) y[e] = wv(o[e]);
+#pragma unroll
+                  for (int e = 0; e < 4; e++) dst[o[e]] = y[e];
+                  pair_sums(y, o, u2i, pm2, pm3, jt);
+                }
+                pj00 = grp.sum(jt[0], red);
+                pj01 = grp.sum(jt[1], red);
+                pj10 = grp.sum(jt[2], red);
+                pj11 = grp.sum(jt[3], red);
+                pj_new = true;
+              } else if (fuse) {
+                for (uint32_t q = (uint32_t)grp.tid; q < (nw >> 1); q += st) {
+                  const uint32_t j0 = ins0(q, (int)s2), j1 = (j0 | b2) ^ tm2;
+                  const cpx<R> y0 = wv(j0), y1 = wv(j1);
+                  dst[j0] = y0;
+                  dst[j1] = y1;
+                  branch_sums(nx, y0, partner2(y1, j0 | b2), n0, n1);
+                }
+                fused_sums = true;
+              } else {
+                for (uint32_t q = (uint32_t)grp.tid; q < nw; q += st) dst[q] = wv(q);
+              }
+              pair_pend = false;
+            } else if (dfd) {
               // each stored pair is read once; the outputs of its deferred
               // combinations follow a Gray-code walk over c (one factor per
               // step on each side)
@@ -1411,6 +1617,25 @@ struct Shot {
                 else walk(IntC<4 <= ND ? 4 : 1>{});
               }
               dfr = 0;
+            } else if (kPair && joint2) {
+              // outputs by quads of the next two measurements, summed as
+              // they are written
+              double jt[4] = {0, 0, 0, 0};
+              for (uint32_t q = (uint32_t)grp.tid; q < (half >> 2); q += st) {
+                uint32_t o[4], u2i;
+                pair_quad(q, k - 1, pm2, pm3, o, u2i);
+                cpx<R> y[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) y[e] = one(o[e]);
+#pragma unroll
+                for (int e = 0; e < 4; e++) dst[o[e]] = y[e];
+                pair_sums(y, o, u2i, pm2, pm3, jt);
+              }
+              pj00 = grp.sum(jt[0], red);
+              pj01 = grp.sum(jt[1], red);
+              pj10 = grp.sum(jt[2], red);
+              pj11 = grp.sum(jt[3], red);
+              pj_new = true;
             } else if (fuse) {
               // outputs (j0, j1): the next measurement's pair through its own
               // folded passes, summed as it is written
@@ -1491,9 +1716,11 @@ struct Shot {
                                 },
                                 one);
             }
-            cpx<R>* t = vec.base;
-            vec.base = alt;
-            alt = t;
+            if (!(kPair && pmode == 1)) {
+              cpx<R>* t = vec.base;
+              vec.base = alt;
+              alt = t;
+            }
           } else {
             // in place (on-chip vectors; folded passes are never skipped here,
             // so only a directly following measurement is fused): the kept
@@ -1585,6 +1812,7 @@ struct Shot {
           pend_tm = pend_sm = 0;
           pend_as = false;
           carry_valid = fused_sums;
+          pj_valid = pj_new;
           if (fused_sums) {
             carry0 = grp.sum(n0, red);
             carry1 = grp.sum(n1, red);

@@ -290,6 +290,51 @@ def test_forced_active_rotations(case, precision, tol, tier):
     _forced_check(text, case, precision, tol, tier, rng)
 
 
+def measurement_burst_circuit(rng, n):
+    """n qubits expanded and entangled, then n - 1 of them measured one after
+    another (X or Z basis, single-qubit Cliffords and Z faults between them):
+    a chain of active measurements with only frame work and folded
+    localization passes between consecutive ones, the case of paired
+    collapses on the cooperative HBM tiers."""
+    lines = ["H %d" % q for q in range(n)] + ["T %d" % q for q in range(n)]
+    for _ in range(2 * n):
+        a, b = [int(v) for v in rng.choice(n, 2, replace=False)]
+        lines.append("%s %d %d" % (["CX", "CZ"][int(rng.integers(0, 2))], a, b))
+        lines.append("%s %d" % (["T", "T_DAG", "H", "S"][int(rng.integers(0, 4))], int(rng.integers(0, n))))
+    for q in [int(v) for v in rng.permutation(n)][: n - 1]:
+        if rng.random() < 0.5:
+            lines.append("%s %d" % (["H", "S", "S_DAG", "X", "Z"][int(rng.integers(0, 5))], q))
+        if rng.random() < 0.3:
+            lines.append("Z_ERROR(0.05) %d" % q)
+        lines.append("%s %d" % (["MX", "M"][int(rng.integers(0, 2))], q))
+    return "\n".join(lines) + "\n"
+
+
+@pytest.mark.parametrize("case", range(8))
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
+@pytest.mark.parametrize("tier", [(64, 1), (256, 1), (1, 1)], ids=["wave-hbm", "group-hbm", "lane-hbm"])
+def test_forced_measurement_chains(case, precision, tol, tier):
+    """Chains of 5..7 active measurements (k from 6..8 down to 1): on the
+    wave and group HBM tiers consecutive measurements are sampled from joint
+    branch sums and collapse in one pass; every forced outcome's probability
+    and the final vector against the oracle, as on the lane tier."""
+    rng = np.random.default_rng(1500 + case)
+    n = int(rng.integers(6, 9))
+    _forced_check(measurement_burst_circuit(rng, n), case, precision, tol, tier, rng)
+
+
+@pytest.mark.parametrize("G,hbm", [(64, 1), (256, 1)])
+def test_measurement_chains_fp64_records(G, hbm):
+    """The same chains sampled freely: FP64 records equal the oracle's."""
+    for case in range(8):
+        rng = np.random.default_rng(1500 + case)
+        text = measurement_burst_circuit(rng, int(rng.integers(6, 9)))
+        shots = 2000
+        om, od, oo = oracle.Program(text).sample(shots, seed=case, threads=4)
+        gm, gd, go = gpu_sample(text, shots, seed=case, precision="f64", threads_per_shot=G, vector_in_hbm=hbm)
+        assert np.array_equal(gm, om)
+
+
 TIERS = [(1, -1), (1, 1), (64, -1), (64, 1), (256, -1), (256, 1)]  # (threads per shot, vector in HBM)
 
 
