@@ -840,6 +840,211 @@ static void hir_reorder(std::vector<HNode>& h) {
 
 // Survival products of the cumulative hazard (Section 3.2) per chunk:
 // S[0] = 1, S[i+1] = S[i] * (1 - p_i) in FP64 with no contraction.
+// Paired collapses (PairLine in program.h): the pass each active
+// measurement runs on the cooperative HBM tiers, decided as the kernel
+// decides it (deferred expansions, carried sums), and the line-complete
+// item order of that pass for lines of 2^LB elements (LB = 4 in FP32, 3 in
+// FP64).  A pass's items q touch, in each array, L(q) ^ span(offsets), L a
+// chain of bit moves and zero insertions; a lane group whose items span
+// the directions D reads whole lines when L(D) + span(offsets) holds every
+// line bit, so for each line bit the candidate direction is the preimage of
+// the bit reduced by the offsets (triangular: offset i has a bit, its
+// pivot, that no later offset and no image of L has).
+namespace {
+struct BitMove {
+  int s, top;  // bit s moves to top (top == s: none); top < 0: a zero is inserted at s
+};
+uint32_t move_fwd(uint32_t x, BitMove t) {
+  if (t.top < 0) return ((x >> t.s) << (t.s + 1)) | (x & ((1u << t.s) - 1u));
+  if (t.s == t.top) return x;
+  return (x & ~(1u << t.s)) | (((x >> t.s) & 1u) << t.top);
+}
+uint32_t move_inv(uint32_t y, BitMove t) {
+  if (t.top < 0) return (((y >> t.s) >> 1) << t.s) | (y & ((1u << t.s) - 1u));
+  if (t.s == t.top) return y;
+  return (y & ~(1u << t.top)) | (((y >> t.top) & 1u) << t.s);
+}
+int move_pos(int p, BitMove t) { return t.top < 0 ? (p >= t.s ? p + 1 : p) : (p == t.s ? t.top : p); }
+struct PassArray {
+  std::vector<BitMove> moves;                   // from the item index outwards
+  std::vector<std::pair<uint32_t, int>> offs;  // member offsets and their pivots, triangular
+  int width = 0;                                // index bits of the array
+};
+void line_candidates(const PassArray& a, int LB, std::vector<uint32_t>& out) {
+  for (int b = 0; b < LB; b++) {
+    uint32_t y = b < a.width ? 1u << b : 0u;
+    for (const auto& o : a.offs)
+      if ((y >> o.second) & 1u) y ^= o.first;
+    for (size_t i = a.moves.size(); i-- > 0;) y = move_inv(y, a.moves[i]);
+    out.push_back(y);
+  }
+}
+// the LineEnum of the kernels: up to four spanning directions in reduced
+// echelon form (pivot: the highest bit), kept in the order of the candidates
+// (items: q < 2^n; a direction outside them is dropped, so that the order
+// stays a permutation of the items whatever the offsets)
+PairLine pair_line(int kind, const PassArray& first, const PassArray& second, int LB, int n) {
+  std::vector<uint32_t> cand;
+  line_candidates(first, LB, cand);
+  line_candidates(second, LB, cand);
+  for (uint32_t& x : cand)
+    if (n < 32 && (x >> n) != 0) x = 0;
+  PairLine L{};
+  uint32_t v[4] = {0, 0, 0, 0};
+  int piv[4] = {0, 0, 0, 0}, nv = 0;
+  for (uint32_t x : cand) {
+    for (int i = 0; i < nv; i++)
+      if ((x >> piv[i]) & 1u) x ^= v[i];
+    if (!x || nv == 4) continue;
+    const int pb = 31 - __builtin_clz(x);
+    for (int i = 0; i < nv; i++)
+      if ((v[i] >> pb) & 1u) v[i] ^= x;
+    v[nv] = x;
+    piv[nv++] = pb;
+  }
+  std::vector<int> pos(piv, piv + nv);
+  std::sort(pos.begin(), pos.end());
+  for (int i = 0; i < 4; i++) L.v[i] = v[i];
+  for (int i = 0; i < 5; i++) L.pos[i] = (int8_t)(i < nv ? pos[i] : 64);
+  L.nv = (int8_t)nv;
+  L.npos = (int8_t)nv;
+  L.kind = (int8_t)kind;
+  return L;
+}
+}  // namespace
+
+static void pair_lines(CompiledProgram& P) {
+  P.pline.assign(2, PairLine{});
+  std::vector<GInstr>& C = P.code;
+  auto is_meas = [](uint8_t op) { return op == OP_MACTZ || op == OP_MACTX; };
+  auto next_meas = [&](size_t i) -> long {
+    for (size_t q = i + 1; q < C.size(); q++)
+      if (is_meas(C[q].op)) return (long)q;
+    return -1;
+  };
+  // the folded localization pass that permutes a measurement's pairs
+  auto fold_tm = [&](size_t m) -> uint32_t {
+    for (size_t q = m; q-- > 0;) {
+      const uint8_t op = C[q].op;
+      if (op == OP_APERM && (C[q].flags & F_FOLD_NEXT)) return C[q].a;
+      if ((op == OP_ASIGN || op == OP_AS) && (C[q].flags & F_FOLD_NEXT)) continue;
+      if ((op >= OP_APERM && op <= OP_AROT) || is_meas(op) || op == OP_EXPVAL) return 0;
+    }
+    return 0;
+  };
+  int carried = 0, dfr = 0;  // carried: 1 the next measurement's sums, 2 the next two's joint sums
+  bool pend = false;
+  size_t pa = 0;
+  for (size_t i = 0; i < C.size(); i++) {
+    const GInstr in = C[i];
+    const int k = i == 0 ? 0 : P.k_after[i - 1];
+    switch (in.op) {
+      case OP_APERM: case OP_ASIGN: case OP_AS:
+        if (!(in.flags & F_FOLD_NEXT)) { dfr = 0; carried = 0; }
+        break;
+      case OP_AROT: case OP_APERM2: case OP_AH: case OP_EXPVAL: dfr = 0; carried = 0; break;
+      case OP_EXPAND:
+        if (dfr == kDeferMax) dfr--;
+        dfr++;
+        carried = 0;
+        break;
+      case OP_MACTZ: case OP_MACTX: {
+        const bool fuse = (in.flags & F_FUSE_NEXT) && k >= 2;
+        const long nx = fuse ? next_meas(i) : -1;
+        const bool joint = fuse && !dfr && k - 1 >= 3 && nx >= 0 && (C[nx].flags & F_FUSE_NEXT);
+        const long nnx = joint ? next_meas((size_t)nx) : -1;
+        int kind = PP_NONE, nitems = 0;  // the pass's items: q < 2^nitems
+        PassArray a1, a2;
+        auto bit = [](int s) { return 1u << s; };
+        if (pend) {
+          // B (this) of the pair with A: the vector has k + 1 slots, the result k - 1
+          const int kv = k + 1, kw = k - 1;
+          const int sA = C[pa].s, sB = in.s;
+          const BitMove mb{sB, kv - 2}, ma{sA, kv - 1};
+          const uint32_t dA = bit(sA) ^ fold_tm(pa), dB = move_fwd(bit(sB) ^ fold_tm(i), ma);
+          a1.moves = {mb, ma};
+          a1.offs = {{dA, sA}, {dB, move_pos(sB, ma)}};
+          a1.width = kv;
+          a2.width = kw;
+          auto up = [&](uint32_t x) { return move_fwd(move_fwd(x, mb), ma); };
+          auto upp = [&](int p) { return move_pos(move_pos(p, mb), ma); };
+          if (joint) {
+            kind = PP_PAIR_JOINT;
+            nitems = kw - 2;
+            const int sC = C[nx].s, sD = C[nnx].s;
+            const BitMove mc{sC, kw - 1}, md{sD, kw - 2};
+            const uint32_t oc = bit(sC) ^ fold_tm(nx), od = move_fwd(bit(sD) ^ fold_tm(nnx), mc);
+            const int pc = sC, pd = move_pos(sD, mc);
+            a2.moves = {md, mc};
+            a2.offs = {{oc, pc}, {od, pd}};
+            a1.moves = {md, mc, mb, ma};
+            a1.offs.push_back({up(oc), upp(pc)});
+            a1.offs.push_back({up(od), upp(pd)});
+          } else if (fuse) {
+            kind = PP_PAIR_NEXT;
+            nitems = kw - 1;
+            const int sC = C[nx].s;
+            const BitMove mc{sC, -1};
+            const uint32_t oc = bit(sC) ^ fold_tm(nx);
+            a2.moves = {mc};
+            a2.offs = {{oc, sC}};
+            a1.moves = {mc, mb, ma};
+            a1.offs.push_back({up(oc), upp(sC)});
+          } else {
+            kind = PP_PAIR;
+            nitems = kw;
+          }
+          pend = false;
+          carried = joint ? 2 : fuse ? 1 : 0;
+        } else if ((in.flags & F_FUSE_NEXT) && k >= 3 && !dfr && carried != 1) {
+          // A of a pair with the next measurement: a read pass for the joint
+          // sums unless they are carried
+          if (!carried) {
+            kind = PP_JOINT_READ;
+            nitems = k - 2;
+            const long b = next_meas(i);
+            const int sA = in.s, sB = C[b].s;
+            const BitMove mb{sB, k - 2}, ma{sA, k - 1};
+            a1.moves = {mb, ma};
+            a1.offs = {{bit(sA) ^ fold_tm(i), sA}, {move_fwd(bit(sB) ^ fold_tm((size_t)b), ma), move_pos(sB, ma)}};
+            a1.width = k;
+          }
+          pend = true;
+          pa = i;
+          carried = 0;
+        } else if (dfr) {
+          carried = 0;  // the cooperative tiers carry nothing out of a deferred collapse
+        } else {
+          if (joint) {
+            // a single collapse (k slots to k - 1) taking the joint sums of C, D
+            kind = PP_SINGLE_JOINT;
+            nitems = k - 3;
+            const int s = in.s, sC = C[nx].s, sD = C[nnx].s;
+            const BitMove mc{sC, k - 2}, md{sD, k - 3}, ms{s, k - 1};
+            const uint32_t oc = bit(sC) ^ fold_tm(nx), od = move_fwd(bit(sD) ^ fold_tm(nnx), mc);
+            const int pc = sC, pd = move_pos(sD, mc);
+            a2.moves = {md, mc};
+            a2.offs = {{oc, pc}, {od, pd}};
+            a2.width = k - 1;
+            a1.moves = {md, mc, ms};
+            a1.offs = {{bit(s) ^ fold_tm(i), s}, {move_fwd(oc, ms), move_pos(pc, ms)}, {move_fwd(od, ms), move_pos(pd, ms)}};
+            a1.width = k;
+          }
+          carried = joint ? 2 : fuse ? 1 : 0;
+        }
+        dfr = 0;
+        if (kind != PP_NONE && P.pline.size() / 2 < 65536) {
+          C[i].u = (uint16_t)(P.pline.size() / 2);
+          P.pline.push_back(pair_line(kind, a1, a2, 4, nitems));
+          P.pline.push_back(pair_line(kind, a1, a2, 3, nitems));
+        }
+        break;
+      }
+      default: break;
+    }
+  }
+}
+
 static void survival_tables(CompiledProgram& P) {
   int ns = (int)P.site_p.size();
   P.nchunks = (ns + kChunk - 1) / kChunk;
@@ -921,10 +1126,21 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
   // applies the oldest one (reads and writes 2^(k-d) elements), and any
   // other vector instruction first writes the deferred part; a collapse
   // reads the vector and writes half of it; its reduction pass is skipped
-  // when the previous measurement's collapse carried its branch sums.
+  // when the previous measurement's collapse carried its branch sums.  On
+  // the cooperative tiers (no carry out of a collapse that reads deferred
+  // expansions) two consecutive measurements A and B with only frame work
+  // between them collapse together: A moves nothing (its joint branch sums
+  // with B carried by the previous collapse, else one read pass), B reads
+  // the 2^(k+1) elements and writes 2^(k-1).
+  auto next_fused = [&](size_t i) -> const GInstr* {
+    for (size_t q = i + 1; q < P.code.size(); q++)
+      if (P.code[q].op == OP_MACTZ || P.code[q].op == OP_MACTX) return &P.code[q];
+    return nullptr;
+  };
   for (int lane_tier = 1; lane_tier >= 0; lane_tier--) {
     double& bytes = lane_tier ? c.vector_bytes_fused : c.vector_bytes_fused_group;
-    bool carried = false;
+    int carried = 0;  // 1: the next measurement's sums, 2: the next two's joint sums
+    bool pend = false;
     int dfr = 0;
     for (size_t i = 0; i < P.code.size(); i++) {
       const GInstr& in = P.code[i];
@@ -937,31 +1153,47 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
       };
       switch (in.op) {
         case OP_APERM: case OP_ASIGN: case OP_AS:
-          if (!(in.flags & F_FOLD_NEXT)) { materialize(); bytes += A * a; carried = false; }
+          if (!(in.flags & F_FOLD_NEXT)) { materialize(); bytes += A * a; carried = 0; }
           break;
         case OP_AROT:
           // directly after an H on its slot, the H pass applies it
           if (i > 0 && P.code[i - 1].op == OP_AH && P.code[i - 1].s == in.s) break;
           materialize();
           bytes += A * a;
-          carried = false;
+          carried = 0;
           break;
-        case OP_APERM2: materialize(); bytes += A * a; carried = false; break;
-        case OP_AH: bytes += 2 * A * a; dfr = 0; carried = false; break;  // reads through deferred factors
+        case OP_APERM2: materialize(); bytes += A * a; carried = 0; break;
+        case OP_AH: bytes += 2 * A * a; dfr = 0; carried = 0; break;  // reads through deferred factors
         case OP_EXPAND:
           if (dfr == kDeferMax) {
             bytes += 2 * stored * a;
             dfr--;
           }
           dfr++;
-          carried = false;
+          carried = 0;
           break;
-        case OP_MACTZ: case OP_MACTX:
-          if (dfr) bytes += 2 * stored * a + 0.5 * A * a;
-          else bytes += (carried ? 0.0 : A * a) + 1.5 * A * a;
-          carried = (in.flags & F_FUSE_NEXT) != 0 && (lane_tier || !dfr);
+        case OP_MACTZ: case OP_MACTX: {
+          const bool fuse = (in.flags & F_FUSE_NEXT) && k >= 2;
+          const GInstr* nx = fuse ? next_fused(i) : nullptr;
+          const int carry = !fuse || (!lane_tier && dfr) ? 0
+                            : (!lane_tier && !dfr && k - 1 >= 3 && nx && (nx->flags & F_FUSE_NEXT)) ? 2 : 1;
+          if (pend) {
+            bytes += 2.5 * A * a;
+            pend = false;
+          } else if (!lane_tier && (in.flags & F_FUSE_NEXT) && k >= 3 && !dfr && carried != 1) {
+            if (!carried) bytes += A * a;
+            pend = true;
+            carried = 0;
+            break;
+          } else if (dfr) {
+            bytes += 2 * stored * a + 0.5 * A * a;
+          } else {
+            bytes += (carried ? 0.0 : A * a) + 1.5 * A * a;
+          }
+          carried = carry;
           dfr = 0;
           break;
+        }
         default: break;
       }
     }
@@ -1469,6 +1701,7 @@ int compile_text(const char* text, size_t len, const CompileOptions& opts, Compi
       if (j < vecops.size() && is_meas(P.code[vecops[j]].op)) in.flags |= F_FUSE_NEXT;
     }
   }
+  pair_lines(P);
   survival_tables(P);
   if (P.masks.empty()) P.masks.push_back(0);
   for (const GInstr& in : P.code) P.has_cfeed = P.has_cfeed || in.op == OP_CFEED;

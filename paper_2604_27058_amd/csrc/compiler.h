@@ -33,6 +33,7 @@ struct CompiledProgram {
   bool has_cfeed = false;          // feed-forward Paulis (need record bits: not on the bit-sliced kernels)
   int nprobes = 0;                 // expectation-value probes (not on the bit-sliced kernels or the split form)
   int npost = 0;                   // post-selected detectors (OP_POSTSELECT; not in the split form)
+  std::vector<PairLine> pline;     // paired-pass item orders (program.h), two per entry, entry 0 unused
   // split form (program.h): valid when split_ok
   bool split_ok = false;
   int nactive = 0;                 // active measurement events

@@ -114,6 +114,22 @@ constexpr uint32_t kPurposeStrat = 0x53000000u;  // stratified sampling: fault i
 constexpr int kSplitMaxActive = 256;
 constexpr int kSplitWords = kSplitMaxActive / 64;
 
+// Paired measurement collapses on the cooperative HBM tiers: the pass an
+// active measurement runs for a pair (the joint-sum read pass of its first
+// measurement A; the collapse of a single measurement that takes the joint
+// sums of the next two; the collapse of B, carrying the next two's joint
+// sums, the next one's sums, or none) and its line-complete item order,
+// precomputed per element size.  GInstr.u of an active measurement indexes
+// the table (entry 2u for FP32, 2u + 1 for FP64; u = 0: none); the kernel
+// uses an entry only when its kind is the pass it runs.
+enum PairPass : int8_t { PP_NONE = 0, PP_JOINT_READ = 1, PP_SINGLE_JOINT = 2, PP_PAIR_JOINT = 3, PP_PAIR_NEXT = 4, PP_PAIR = 5 };
+struct PairLine {
+  uint32_t v[4];  // spanning directions of a lane group's items
+  int8_t pos[5];  // zero-insertion positions, ascending
+  int8_t nv, npos, kind;
+};
+static_assert(sizeof(PairLine) == 24, "pair order entry must be 24 bytes");
+
 // Device-side view of one program (all pointers are device addresses).
 struct DevProgram {
   const GInstr* code;
@@ -150,6 +166,7 @@ struct DevProgram {
   // e_s(t) / e_s(j).  Null until a stratified call uploads it.
   const double* strat;
   int32_t strat_rows;
+  const PairLine* pline;  // paired-pass item orders (see PairLine)
 };
 
 }  // namespace clifft

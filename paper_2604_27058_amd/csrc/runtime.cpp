@@ -107,6 +107,7 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out, co
   if (e == hipSuccess) e = upload_vec(H.rec_tgt, &v.rec_tgt, dc.allocs);
   if (e == hipSuccess) e = upload_vec(H.rblk_off, &v.rblk_off, dc.allocs);
   if (e == hipSuccess) e = upload_vec(H.rblk_ev, &v.rblk_ev, dc.allocs);
+  if (e == hipSuccess) e = upload_vec(H.pline, &v.pline, dc.allocs);
   if (e != hipSuccess) {
     for (void* a : dc.allocs) (void)hipFree(a);
     return fail(CLIFFT_E_DEVICE, std::string("program upload failed: ") + hipGetErrorString(e));

@@ -579,6 +579,7 @@ struct Shot {
   static constexpr bool kExt = EXT || DBG;
   // line-complete item orders in the cooperative HBM passes (LineEnum)
   static constexpr bool kLine = G > 1 && OOP && LINE;
+  static constexpr bool kPairLine = kLine && sizeof(R) == 8;
   const DevProgram& P;
   const KArgs& A;
   Group<G> grp;
@@ -683,6 +684,51 @@ struct Shot {
     }
   }
 
+  // The lane's items of this measurement's paired pass in the line-complete
+  // order precomputed with the program (identity when it has none of this
+  // kind, and in FP32, where the order's registers cost the workgroup tier
+  // a wave per SIMD and its time more than the order saves).  The order inserts zero bits at its pivots and adds the lane's
+  // combination xo; the items of a lane step by G, so the inserted value
+  // steps by a constant carried across the pivot bits.
+  struct PairWalk {
+    uint32_t j, holes, inc, xo;
+    MDEV uint32_t cur() const { return j ^ xo; }
+    MDEV void next() { j = ((j | holes) + inc) & ~holes; }
+  };
+  MDEV PairWalk pair_walk(const GInstr& in, int kind) const {
+    uint32_t v[4] = {0u, 0u, 0u, 0u}, holes = 0;
+    int nv = 0;
+    if (kPairLine && in.u != 0) {
+      const PairLine& L = P.pline[2u * in.u + (sizeof(R) == 8 ? 1u : 0u)];
+      if (L.kind == kind) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) v[i] = L.v[i];
+        nv = L.nv;
+#pragma unroll
+        for (int i = 0; i < 5; i++)
+          if (i < L.npos) holes |= 1u << L.pos[i];
+      }
+    }
+    auto deposit = [&](uint32_t a) {
+      uint32_t h = holes;
+      while (h) {
+        a = ins0(a, __builtin_ctz(h));
+        h &= h - 1u;
+      }
+      return a;
+    };
+    const uint32_t tid = (uint32_t)grp.tid;
+    PairWalk w;
+    w.holes = holes;
+    w.j = deposit(tid >> nv);
+    w.inc = deposit((uint32_t)G >> nv);
+    w.xo = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      if (i < nv && ((tid >> i) & 1u)) w.xo ^= v[i];
+    return w;
+  }
+
   MDEV bool writer() const { return (G == 1 || grp.tid == 0) && local < A.shots && !(kExt && post_dead); }
 
   MDEV void put(uint32_t r, uint32_t m) {
@@ -750,7 +796,7 @@ struct Shot {
     return b ^ ((uint32_t)__popcll(acc) & 1u);
   }
 
-  __device__ void run() {
+  __device__ __forceinline__ void run() {
     Frame<W> T, N;
     uint64_t mb[kSplitWords];  // vector-only stream: active outcomes so far (bit = active index)
 #pragma unroll
@@ -1276,10 +1322,11 @@ struct Shot {
             // from one pass over the vector)
             if (!pj_valid) {
               const MeasAhead me{pc, (uint32_t)s, tm, sm, fas, isx, in.flags};
+              PairWalk E = pair_walk(in, PP_JOINT_READ);
               double t[4] = {0, 0, 0, 0};
-              for (uint32_t q = (uint32_t)grp.tid; q < (1u << (k - 2)); q += (uint32_t)G) {
+              for (uint32_t q = (uint32_t)grp.tid; q < (1u << (k - 2)); q += (uint32_t)G, E.next()) {
                 uint32_t o[4], u2i;
-                pair_quad(q, k, me, pmB, o, u2i);
+                pair_quad(E.cur(), k, me, pmB, o, u2i);
                 cpx<R> y[4];
 #pragma unroll
                 for (int e = 0; e < 4; e++) y[e] = vec[o[e]];
@@ -1463,10 +1510,11 @@ struct Shot {
               };
               const uint32_t nw = half;  // k - 1 slots
               if (joint2) {
+                PairWalk E = pair_walk(in, PP_PAIR_JOINT);
                 double jt[4] = {0, 0, 0, 0};
-                for (uint32_t q = (uint32_t)grp.tid; q < (nw >> 2); q += st) {
+                for (uint32_t q = (uint32_t)grp.tid; q < (nw >> 2); q += st, E.next()) {
                   uint32_t o[4], u2i;
-                  pair_quad(q, k - 1, pm2, pm3, o, u2i);
+                  pair_quad(E.cur(), k - 1, pm2, pm3, o, u2i);
                   cpx<R> y[4];
 #pragma unroll
                   for (int e = 0; e < 4; e++) y[e] = wv(o[e]);
@@ -1480,8 +1528,9 @@ struct Shot {
                 pj11 = grp.sum(jt[3], red);
                 pj_new = true;
               } else if (fuse) {
-                for (uint32_t q = (uint32_t)grp.tid; q < (nw >> 1); q += st) {
-                  const uint32_t j0 = ins0(q, (int)s2), j1 = (j0 | b2) ^ tm2;
+                PairWalk E = pair_walk(in, PP_PAIR_NEXT);
+                for (uint32_t q = (uint32_t)grp.tid; q < (nw >> 1); q += st, E.next()) {
+                  const uint32_t j0 = ins0(E.cur(), (int)s2), j1 = (j0 | b2) ^ tm2;
                   const cpx<R> y0 = wv(j0), y1 = wv(j1);
                   dst[j0] = y0;
                   dst[j1] = y1;
@@ -1489,7 +1538,11 @@ struct Shot {
                 }
                 fused_sums = true;
               } else {
-                for (uint32_t q = (uint32_t)grp.tid; q < nw; q += st) dst[q] = wv(q);
+                PairWalk E = pair_walk(in, PP_PAIR);
+                for (uint32_t q = (uint32_t)grp.tid; q < nw; q += st, E.next()) {
+                  const uint32_t w = E.cur();
+                  dst[w] = wv(w);
+                }
               }
               pair_pend = false;
             } else if (dfd) {
@@ -1620,10 +1673,11 @@ struct Shot {
             } else if (kPair && joint2) {
               // outputs by quads of the next two measurements, summed as
               // they are written
+              PairWalk E = pair_walk(in, PP_SINGLE_JOINT);
               double jt[4] = {0, 0, 0, 0};
-              for (uint32_t q = (uint32_t)grp.tid; q < (half >> 2); q += st) {
+              for (uint32_t q = (uint32_t)grp.tid; q < (half >> 2); q += st, E.next()) {
                 uint32_t o[4], u2i;
-                pair_quad(q, k - 1, pm2, pm3, o, u2i);
+                pair_quad(E.cur(), k - 1, pm2, pm3, o, u2i);
                 cpx<R> y[4];
 #pragma unroll
                 for (int e = 0; e < 4; e++) y[e] = one(o[e]);
