@@ -300,7 +300,7 @@ def bench_batch(args, w, pk, torch):
 
     cost = [p.cost_model("f32") for p in progs]
     tiers = B.threads_per_shot
-    vec_bytes = sum(c["vector_bytes_fused" if g == 1 else "vector_bytes_fused_group"] * s
+    vec_bytes = sum(c["vector_bytes_fused" if g == 1 else "vector_bytes_fused_batch"] * s
                     for c, s, g in zip(cost, shots, tiers))
     rec_bytes = sum(c["record_bytes"] * s for c, s in zip(cost, shots))
     table_bytes = sum(c["vector_bytes"] * s for c, s in zip(cost, shots))

@@ -193,7 +193,11 @@ typedef struct clifft_cost {
                                expansions move nothing, a collapse reads the vector and writes
                                half, carried branch sums skip the reduction) */
   double vector_bytes_fused_group; /* the same for a shot per wave or per workgroup (a collapse
-                               through deferred expansions carries no branch sums there) */
+                               through deferred expansions carries no branch sums there; two
+                               consecutive measurements with only frame work between them
+                               collapse together, Appendix B.2 applied to both) */
+  double vector_bytes_fused_batch; /* the group tiers of the batched launch, which collapse one
+                               measurement at a time */
 } clifft_cost;
 clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clifft_cost* out);
 

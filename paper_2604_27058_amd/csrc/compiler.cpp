@@ -1137,8 +1137,9 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
       if (P.code[q].op == OP_MACTZ || P.code[q].op == OP_MACTX) return &P.code[q];
     return nullptr;
   };
-  for (int lane_tier = 1; lane_tier >= 0; lane_tier--) {
-    double& bytes = lane_tier ? c.vector_bytes_fused : c.vector_bytes_fused_group;
+  for (int tier = 0; tier < 3; tier++) {  // lane, group, group of the batched launch
+    const bool lane_tier = tier == 0, pairs = tier == 1;
+    double& bytes = tier == 0 ? c.vector_bytes_fused : tier == 1 ? c.vector_bytes_fused_group : c.vector_bytes_fused_batch;
     int carried = 0;  // 1: the next measurement's sums, 2: the next two's joint sums
     bool pend = false;
     int dfr = 0;
@@ -1176,11 +1177,11 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
           const bool fuse = (in.flags & F_FUSE_NEXT) && k >= 2;
           const GInstr* nx = fuse ? next_fused(i) : nullptr;
           const int carry = !fuse || (!lane_tier && dfr) ? 0
-                            : (!lane_tier && !dfr && k - 1 >= 3 && nx && (nx->flags & F_FUSE_NEXT)) ? 2 : 1;
+                            : (pairs && !dfr && k - 1 >= 3 && nx && (nx->flags & F_FUSE_NEXT)) ? 2 : 1;
           if (pend) {
             bytes += 2.5 * A * a;
             pend = false;
-          } else if (!lane_tier && (in.flags & F_FUSE_NEXT) && k >= 3 && !dfr && carried != 1) {
+          } else if (pairs && (in.flags & F_FUSE_NEXT) && k >= 3 && !dfr && carried != 1) {
             if (!carried) bytes += A * a;
             pend = true;
             carried = 0;

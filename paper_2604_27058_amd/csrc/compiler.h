@@ -59,6 +59,7 @@ struct CostModel {
   double int_ops_bitsliced = 0;  // integer lane-operations per shot when 32 shots share each frame word
   double vector_bytes_fused = 0;        // active-vector bytes of the fused passes, shot per lane in HBM
   double vector_bytes_fused_group = 0;  // the same for a shot per wave or per workgroup
+  double vector_bytes_fused_batch = 0;  // the group tiers of the batched launch (no paired collapses)
 };
 CostModel cost_model(const CompiledProgram& P, bool fp64);
 
