@@ -201,6 +201,19 @@ typedef struct clifft_cost {
 } clifft_cost;
 clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clifft_cost* out);
 
+/* The item orders the compiler stored for the paired measurement passes of
+ * the cooperative HBM tiers (Appendix B.2 applied to two consecutive active
+ * measurements; the orders only make the passes read whole cache lines).
+ * out (capacity cap int32 values; may be NULL) receives 25 values per
+ * measurement that runs such a pass: its instruction index, the pass kind
+ * (1 the read pass of a pair's first measurement, 2 a single collapse taking
+ * the next two's joint sums, 3/4/5 a pair's collapse carrying the next two's
+ * joint sums / the next one's sums / nothing), n (the pass's items are
+ * q < 2^n), then for FP32 and for FP64: nv, npos, pos[5], v[4] (item q maps
+ * to the zero insertion of q >> nv at pos[0..npos) XOR the v[i] of q's low
+ * bits).  *n_out receives the total count.  Host only. */
+clifft_status clifft_pair_orders(const clifft_program* p, int32_t* out, size_t cap, size_t* n_out);
+
 /* The launch configuration a sample call of `shots` shots would use with
  * `cfg` (NULL = automatic): *out receives precision, threads_per_shot,
  * grid and vector_in_hbm (1 HBM workspace, -1 LDS) after the automatic

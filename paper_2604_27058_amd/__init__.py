@@ -61,6 +61,7 @@ def lib():
         L.clifft_program_info.argtypes = [vp, ctypes.POINTER(clifft_info)]
         L.clifft_k_profile.argtypes = [vp, i32p, sz, ctypes.POINTER(sz)]
         L.clifft_event_classes.argtypes = [vp, i32p, sz, ctypes.POINTER(sz)]
+        L.clifft_pair_orders.argtypes = [vp, i32p, sz, ctypes.POINTER(sz)]
         L.clifft_final_slots.argtypes = [vp, i32p, i32p]
         L.clifft_workspace_size.argtypes = [vp, ctypes.POINTER(clifft_launch), u64, ctypes.POINTER(sz)]
         L.clifft_sample.argtypes = [vp, u64, u64, u64, ctypes.POINTER(clifft_launch), vp, sz, vp, vp, vp, vp]
@@ -171,6 +172,20 @@ class Program:
 
     def event_classes(self):
         return self._arr(lib().clifft_event_classes)
+
+    def pair_orders(self):
+        """The compiler's paired-pass item orders (clifft_pair_orders): a
+        list of dicts (instr, kind, n, and per element size f32/f64: nv,
+        pos, v)."""
+        a = self._arr(lib().clifft_pair_orders)
+        out = []
+        for i in range(0, len(a), 25):
+            e = dict(instr=a[i], kind=a[i + 1], n=a[i + 2])
+            for j, prec in enumerate(("f32", "f64")):
+                b = i + 3 + 11 * j
+                e[prec] = dict(nv=a[b], pos=a[b + 2: b + 2 + a[b + 1]], v=[x & 0xFFFFFFFF for x in a[b + 7: b + 11]][: a[b]])
+            out.append(e)
+        return out
 
     def final_slots(self):
         out = (ctypes.c_int32 * max(self.k_max, 1))()

@@ -915,6 +915,7 @@ PairLine pair_line(int kind, const PassArray& first, const PassArray& second, in
 
 static void pair_lines(CompiledProgram& P) {
   P.pline.assign(2, PairLine{});
+  P.pline_items.assign(1, 0);
   std::vector<GInstr>& C = P.code;
   auto is_meas = [](uint8_t op) { return op == OP_MACTZ || op == OP_MACTX; };
   auto next_meas = [&](size_t i) -> long {
@@ -1037,6 +1038,7 @@ static void pair_lines(CompiledProgram& P) {
           C[i].u = (uint16_t)(P.pline.size() / 2);
           P.pline.push_back(pair_line(kind, a1, a2, 4, nitems));
           P.pline.push_back(pair_line(kind, a1, a2, 3, nitems));
+          P.pline_items.push_back(nitems);
         }
         break;
       }

@@ -34,6 +34,7 @@ struct CompiledProgram {
   int nprobes = 0;                 // expectation-value probes (not on the bit-sliced kernels or the split form)
   int npost = 0;                   // post-selected detectors (OP_POSTSELECT; not in the split form)
   std::vector<PairLine> pline;     // paired-pass item orders (program.h), two per entry, entry 0 unused
+  std::vector<int> pline_items;    // per entry: the pass's items are q < 2^pline_items
   // split form (program.h): valid when split_ok
   bool split_ok = false;
   int nactive = 0;                 // active measurement events

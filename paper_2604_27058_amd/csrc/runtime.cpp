@@ -724,6 +724,29 @@ clifft_status clifft_k_profile(const clifft_program* p, int32_t* out, size_t cap
   return CLIFFT_OK;
 }
 
+clifft_status clifft_pair_orders(const clifft_program* p, int32_t* out, size_t cap, size_t* n) {
+  if (!p || !n) return fail(CLIFFT_E_INVALID_ARG, "null argument");
+  const CompiledProgram& H = p->host;
+  std::vector<int32_t> v;
+  for (size_t i = 0; i < H.code.size(); i++) {
+    const GInstr& in = H.code[i];
+    if ((in.op != OP_MACTZ && in.op != OP_MACTX) || in.u == 0) continue;
+    v.push_back((int32_t)i);
+    v.push_back(H.pline[2u * in.u].kind);
+    v.push_back(H.pline_items[in.u]);
+    for (int e = 0; e < 2; e++) {
+      const PairLine& L = H.pline[2u * in.u + e];
+      v.push_back(L.nv);
+      v.push_back(L.npos);
+      for (int j = 0; j < 5; j++) v.push_back(L.pos[j]);
+      for (int j = 0; j < 4; j++) v.push_back((int32_t)L.v[j]);
+    }
+  }
+  *n = v.size();
+  for (size_t i = 0; out && i < v.size() && i < cap; i++) out[i] = v[i];
+  return CLIFFT_OK;
+}
+
 clifft_status clifft_event_classes(const clifft_program* p, int32_t* out, size_t cap, size_t* n) {
   if (!p || !n) return fail(CLIFFT_E_INVALID_ARG, "null argument");
   const auto& v = p->host.ev_class;

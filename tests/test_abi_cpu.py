@@ -242,3 +242,43 @@ def test_stratified_argument_checks_host_only():
     with pytest.raises(pk.ClifftError) as e:
         pk.Program("X_ERROR(1) 0\nM 0\n").fault_count_pmf(2)
     assert e.value.status == 2
+
+
+def _enum(order, q):
+    j = q >> order["nv"]
+    for p in order["pos"]:
+        j = ((j >> p) << (p + 1)) | (j & ((1 << p) - 1))
+    for i, v in enumerate(order["v"]):
+        if (q >> i) & 1:
+            j ^= v
+    return j
+
+
+@pytest.mark.parametrize("name", ["large_active_k20", "surface_d5_r5_t10", "batched64"])
+def test_pair_orders_are_permutations(name):
+    """The compiler's item orders for the paired measurement passes (Appendix
+    B.2 on two measurements; clifft_pair_orders) map the items q < 2^n onto
+    themselves one to one in both element sizes: directions in reduced
+    echelon form with their pivots among the zero-insertion positions, all
+    below 2^n, and a brute-force check of the whole map up to n = 16."""
+    texts = circuits.workload(name)["texts"]
+    kinds = set()
+    for text in texts[:24]:
+        for e in pk.Program(text).pair_orders():
+            kinds.add(e["kind"])
+            assert 1 <= e["kind"] <= 5 and e["n"] >= 0
+            n = e["n"]
+            for prec in ("f32", "f64"):
+                o = e[prec]
+                assert 0 <= o["nv"] <= 4 and len(o["pos"]) == o["nv"] == len(o["v"])
+                assert list(o["pos"]) == sorted(o["pos"]) and all(p < n for p in o["pos"])
+                for i, v in enumerate(o["v"]):
+                    assert 0 < v < (1 << n)
+                    assert v.bit_length() - 1 in o["pos"]
+                    for jj, w in enumerate(o["v"]):
+                        if jj != i:
+                            assert not (w >> (v.bit_length() - 1)) & 1
+                if n <= 16:
+                    img = sorted(_enum(o, q) for q in range(1 << n))
+                    assert img == list(range(1 << n))
+    assert kinds, "no paired passes"
