@@ -323,16 +323,45 @@ def test_forced_measurement_chains(case, precision, tol, tier):
     _forced_check(measurement_burst_circuit(rng, n), case, precision, tol, tier, rng)
 
 
+def deferred_chain_circuit(rng, n):
+    """n fresh qubits expanded (H, then T or T_DAG) with at most two CX among
+    them, then n - 1 of them measured one after another: the chain's first
+    measurement reads four deferred expansions, so on the cooperative HBM
+    tiers the first pair's sums and its double collapse go through the
+    deferred phase factors."""
+    lines = ["H %d" % q for q in range(n)] + ["%s %d" % (["T", "T_DAG"][int(rng.integers(0, 2))], q) for q in range(n)]
+    for _ in range(int(rng.integers(0, 3))):
+        a, b = [int(v) for v in rng.choice(n, 2, replace=False)]
+        lines.append("CX %d %d" % (a, b))
+    for q in [int(v) for v in rng.permutation(n)][: n - 1]:
+        if rng.random() < 0.5:
+            lines.append("%s %d" % (["S", "S_DAG", "X", "Z"][int(rng.integers(0, 4))], q))
+        lines.append("%s %d" % (["MX", "M"][int(rng.integers(0, 2))], q))
+    return "\n".join(lines) + "\n"
+
+
+@pytest.mark.parametrize("case", range(8))
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
+@pytest.mark.parametrize("tier", [(64, 1), (256, 1)], ids=["wave-hbm", "group-hbm"])
+def test_forced_deferred_measurement_chains(case, precision, tol, tier):
+    """Chains whose first measurement reads deferred expansions: every forced
+    outcome's probability and the final vector against the oracle."""
+    rng = np.random.default_rng(1700 + case)
+    n = int(rng.integers(5, 9))
+    _forced_check(deferred_chain_circuit(rng, n), case, precision, tol, tier, rng)
+
+
 @pytest.mark.parametrize("G,hbm", [(64, 1), (256, 1)])
 def test_measurement_chains_fp64_records(G, hbm):
-    """The same chains sampled freely: FP64 records equal the oracle's."""
+    """Both kinds of chain sampled freely: FP64 records equal the oracle's."""
     for case in range(8):
-        rng = np.random.default_rng(1500 + case)
-        text = measurement_burst_circuit(rng, int(rng.integers(6, 9)))
-        shots = 2000
-        om, od, oo = oracle.Program(text).sample(shots, seed=case, threads=4)
-        gm, gd, go = gpu_sample(text, shots, seed=case, precision="f64", threads_per_shot=G, vector_in_hbm=hbm)
-        assert np.array_equal(gm, om)
+        for gen, base in ((measurement_burst_circuit, 1500), (deferred_chain_circuit, 1700)):
+            rng = np.random.default_rng(base + case)
+            text = gen(rng, int(rng.integers(6, 9)) if base == 1500 else int(rng.integers(5, 9)))
+            shots = 2000
+            om, od, oo = oracle.Program(text).sample(shots, seed=case, threads=4)
+            gm, gd, go = gpu_sample(text, shots, seed=case, precision="f64", threads_per_shot=G, vector_in_hbm=hbm)
+            assert np.array_equal(gm, om), (gen.__name__, case)
 
 
 TIERS = [(1, -1), (1, 1), (64, -1), (64, 1), (256, -1), (256, 1)]  # (threads per shot, vector in HBM)
