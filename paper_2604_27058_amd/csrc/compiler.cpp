@@ -1178,15 +1178,23 @@ CostModel cost_model(const CompiledProgram& P, bool fp64) {
         case OP_MACTZ: case OP_MACTX: {
           const bool fuse = (in.flags & F_FUSE_NEXT) && k >= 2;
           const GInstr* nx = fuse ? next_fused(i) : nullptr;
+          const GInstr* nnx = nx && (nx->flags & F_FUSE_NEXT) ? next_fused((size_t)(nx - P.code.data())) : nullptr;
+          // FP32 pairs only measurements whose slots lie above the line bits
+          // (the kernels' rule; FP64 walks line-complete orders instead)
+          auto slot_ok = [&](const GInstr* g) { return g && (fp64 || g->s >= 4); };
+          const int min_k = fp64 ? 3 : 17;  // and FP32 pairs vectors of 2^17 amplitudes or more
           const int carry = !fuse || (!lane_tier && dfr) ? 0
-                            : (pairs && !dfr && k - 1 >= 3 && nx && (nx->flags & F_FUSE_NEXT)) ? 2 : 1;
+                            : (pairs && !dfr && k - 1 >= min_k && nx && (nx->flags & F_FUSE_NEXT) &&
+                               (pend || slot_ok(&in)) && slot_ok(nx) && slot_ok(nnx)) ? 2 : 1;
           if (pend) {
             bytes += 2.5 * A * a;
             pend = false;
-          } else if (pairs && (in.flags & F_FUSE_NEXT) && k >= 3 && !dfr && carried != 1) {
+          } else if (pairs && (in.flags & F_FUSE_NEXT) && k >= min_k && !dfr && carried != 1 && slot_ok(&in) &&
+                     slot_ok(next_fused(i))) {
             if (!carried) bytes += A * a;
             pend = true;
             carried = 0;
+            c.pair_starts++;
             break;
           } else if (dfr) {
             bytes += 2 * stored * a + 0.5 * A * a;

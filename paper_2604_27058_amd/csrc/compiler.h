@@ -61,6 +61,7 @@ struct CostModel {
   double vector_bytes_fused = 0;        // active-vector bytes of the fused passes, shot per lane in HBM
   double vector_bytes_fused_group = 0;  // the same for a shot per wave or per workgroup
   double vector_bytes_fused_batch = 0;  // the group tiers of the batched launch (no paired collapses)
+  int pair_starts = 0;                  // measurements that start a pair on the group tiers
 };
 CostModel cost_model(const CompiledProgram& P, bool fp64);
 

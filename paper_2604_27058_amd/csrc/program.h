@@ -167,6 +167,7 @@ struct DevProgram {
   const double* strat;
   int32_t strat_rows;
   const PairLine* pline;  // paired-pass item orders (see PairLine)
+  int32_t has_pairs[2];   // some measurements collapse in pairs (FP32, FP64)
 };
 
 }  // namespace clifft

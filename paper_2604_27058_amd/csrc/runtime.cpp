@@ -126,6 +126,8 @@ clifft_status ensure_device(const clifft_program* cp, const DevProgram** out, co
   v.rblk_max = H.rblk_max;
   v.ndet_rows = H.ndet_rows;
   v.has_post = H.npost > 0;
+  v.has_pairs[0] = cost_model(H, false).pair_starts > 0;
+  v.has_pairs[1] = cost_model(H, true).pair_starts > 0;
   {
     double f = 0;
     for (double q : H.site_p) f += q;

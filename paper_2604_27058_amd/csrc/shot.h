@@ -574,12 +574,21 @@ DEV int fault_phase(const DevProgram& P, const Words<W>& fx, uint32_t site, uint
 // HBM tiers (left out of the batched kernels, whose vectors mostly stay in
 // the caches and whose registers are tighter).
 template <int W, int G, typename R, bool DBG, bool VEC, int U = kUnroll, bool OOP = false, bool VONLY = false,
-          bool EXT = false, bool LINE = true, bool PAIR = true>
+          bool EXT = false, bool LINE = true, bool PAIR = false>
 struct Shot {
   static constexpr bool kExt = EXT || DBG;
   // line-complete item orders in the cooperative HBM passes (LineEnum)
   static constexpr bool kLine = G > 1 && OOP && LINE;
   static constexpr bool kPairLine = kLine && sizeof(R) == 8;
+  // Without that order (FP32) a pair's passes read whole lines only when
+  // every slot they move (the measured slots of the pair and of the pair
+  // whose joint sums they take, and a single collapse's own) lies above the
+  // line bits; lower ones cost 2-8 lines per line of data, more than the
+  // pair saves, so FP32 pairs only such measurements, and only on vectors
+  // of 2^17 amplitudes or more (measured: below that the pairs' passes cost
+  // FP32 more than the bytes they save).
+  static constexpr int kPairMinSlot = kPairLine ? 0 : kLineBits<R>();
+  static constexpr int kPairMinK = kPairLine ? 3 : 17;
   const DevProgram& P;
   const KArgs& A;
   Group<G> grp;
@@ -1269,9 +1278,10 @@ struct Shot {
           if constexpr (kPair) {
             if (pair_pend) {
               pmode = 2;
-            } else if ((in.flags & F_FUSE_NEXT) && k >= 3 && dfr == 0 && (pj_valid || !carry_valid)) {
-              pmode = 1;
+            } else if ((in.flags & F_FUSE_NEXT) && k >= kPairMinK && dfr == 0 && (pj_valid || !carry_valid) &&
+                       s >= kPairMinSlot) {
               pmB = peek_meas(pc);
+              if ((int)pmB.s >= kPairMinSlot) pmode = 1;
             }
           }
           // branch sums (Appendix B.2): |a|^2 per half along the axis, or
@@ -1460,11 +1470,11 @@ struct Shot {
           MeasAhead pm2{}, pm3{};
           bool joint2 = false;
           if constexpr (kPair) {
-            if (fuse && !dfd && k - 1 >= 3) {
+            if (fuse && !dfd && k - 1 >= kPairMinK && (pmode == 2 || s >= kPairMinSlot)) {
               pm2 = peek_meas(pc);
-              if (pm2.flags & F_FUSE_NEXT) {
+              if ((pm2.flags & F_FUSE_NEXT) && (int)pm2.s >= kPairMinSlot) {
                 pm3 = peek_meas(pm2.pc);
-                joint2 = true;
+                joint2 = (int)pm3.s >= kPairMinSlot;
               }
             }
           }
@@ -2135,7 +2145,8 @@ struct Shot {
 // ------------------------------------------------------------------ kernel
 // One persistent launch: units (lanes-of-a-wave for G = 1, waves for G = 64,
 // workgroups for G = 256) take 64-shot tiles round-robin.
-template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false, bool EXT = false>
+template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false, bool EXT = false,
+          bool PAIR = false>
 __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int units_per_block = G == 256 ? 1 : 4;
@@ -2176,7 +2187,7 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
       for (uint32_t r = (uint32_t)tid; r < nwords_rec; r += G) rec[r] = 0;
       unit_sync();
       uint64_t g = rfl((uint32_t)sh_i) | (sh_i & 0xFFFFFFFF00000000ull);
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY, EXT> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0,
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY, EXT, true, PAIR> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, 0,
                                                                   A.offset + g, g, alt};
       sh.run();
       unit_sync();
@@ -2199,14 +2210,14 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if constexpr (G == 1) {
-      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY, EXT> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
+      Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY, EXT, true, PAIR> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red, lane,
                                                                   A.offset + tile * 64 + lane, tile * 64 + lane, alt};
       sh.run();
     } else {
       uint32_t nsh = (uint32_t)min((uint64_t)64, A.shots - tile * 64);
       for (uint32_t sl = 0; sl < nsh; sl++) {
         uint64_t g = rfl((uint32_t)(tile * 64 + sl)) | ((tile * 64 + sl) & 0xFFFFFFFF00000000ull);
-        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY, EXT> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red,
+        Shot<W, G, R, DBG, VEC, unroll_for<R, GLOBAL>(), GLOBAL, VONLY, EXT, true, PAIR> sh{P, A, Group<G>{tid}, Vec<G, R>{base, lane}, rec, red,
                                                                     (int)sl, A.offset + g, g, alt};
         sh.run();
       }
@@ -2232,16 +2243,17 @@ __global__ __launch_bounds__(256) void k_sample(DevProgram P, KArgs A) {
 }
 
 // ------------------------------------------------------------------ dispatch table
-template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false, bool EXT = false>
+template <int W, int G, typename R, bool GLOBAL, bool DBG, bool VEC, bool VONLY = false, bool EXT = false,
+          bool PAIR = false>
 inline hipError_t launch_one(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
   static bool attr = false;  // allow the whole 160 KB of LDS for dynamic use
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY, EXT>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY, EXT, PAIR>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY, EXT>), dim3(grid), dim3(256), lds, st, P, A);
+  hipLaunchKernelGGL((k_sample<W, G, R, GLOBAL, DBG, VEC, VONLY, EXT, PAIR>), dim3(grid), dim3(256), lds, st, P, A);
   return hipGetLastError();
 }
 
@@ -2260,19 +2272,24 @@ inline hipError_t launch_vonly(const DevProgram& P, const KArgs& A, const Launch
   return launch_one<1, 256, R, false, false, true, true>(P, A, L.grid, L.lds_bytes, st);
 }
 
-template <int G, typename R, bool GLOBAL, bool DBG, bool VEC = true, bool EXT = false>
+template <int G, typename R, bool GLOBAL, bool DBG, bool VEC = true, bool EXT = false, bool PAIR = false>
 inline hipError_t launch_w(const DevProgram& P, const KArgs& A, int grid, size_t lds, hipStream_t st) {
   switch (P.W) {
-    case 1: return launch_one<1, G, R, GLOBAL, DBG, VEC, false, EXT>(P, A, grid, lds, st);
-    case 2: return launch_one<2, G, R, GLOBAL, DBG, VEC, false, EXT>(P, A, grid, lds, st);
-    case 3: return launch_one<3, G, R, GLOBAL, DBG, VEC, false, EXT>(P, A, grid, lds, st);
-    case 4: return launch_one<4, G, R, GLOBAL, DBG, VEC, false, EXT>(P, A, grid, lds, st);
+    case 1: return launch_one<1, G, R, GLOBAL, DBG, VEC, false, EXT, PAIR>(P, A, grid, lds, st);
+    case 2: return launch_one<2, G, R, GLOBAL, DBG, VEC, false, EXT, PAIR>(P, A, grid, lds, st);
+    case 3: return launch_one<3, G, R, GLOBAL, DBG, VEC, false, EXT, PAIR>(P, A, grid, lds, st);
+    case 4: return launch_one<4, G, R, GLOBAL, DBG, VEC, false, EXT, PAIR>(P, A, grid, lds, st);
   }
   return hipErrorInvalidValue;
 }
 
 // EXT: the instantiations with post-selection and stratified sampling
-// (sample_ext_*.hip), for programs and calls that use them.
+// (sample_ext_*.hip), for programs and calls that use them.  The
+// cooperative HBM tiers of plain sampling take the instantiation with paired
+// collapses only for programs that pair some measurements at this precision
+// (DevProgram::has_pairs): compiled in, the pair code alone costs the
+// interpreter up to 15% on programs that never use it.  The trace kernels
+// always have it.
 template <typename R, bool DBG, bool EXT = false>
 inline hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShape& L, hipStream_t st) {
   if (L.G == 1) {
@@ -2281,11 +2298,19 @@ inline hipError_t launch_g(const DevProgram& P, const KArgs& A, const LaunchShap
     if (L.global_vec) return launch_w<1, R, true, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
     return launch_w<1, R, false, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
   }
+  constexpr bool kPairs = !EXT;
+  const bool pairs = DBG || P.has_pairs[sizeof(R) == 8 ? 1 : 0] != 0;
   if (L.G == 64) {
-    if (L.global_vec) return launch_w<64, R, true, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
+    if (L.global_vec) {
+      if (kPairs && pairs) return launch_w<64, R, true, DBG, true, EXT, kPairs>(P, A, L.grid, L.lds_bytes, st);
+      if constexpr (!DBG) return launch_w<64, R, true, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
+    }
     return launch_w<64, R, false, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
   }
-  if (L.global_vec) return launch_w<256, R, true, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
+  if (L.global_vec) {
+    if (kPairs && pairs) return launch_w<256, R, true, DBG, true, EXT, kPairs>(P, A, L.grid, L.lds_bytes, st);
+    if constexpr (!DBG) return launch_w<256, R, true, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
+  }
   return launch_w<256, R, false, DBG, true, EXT>(P, A, L.grid, L.lds_bytes, st);
 }
 
