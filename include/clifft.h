@@ -198,6 +198,9 @@ typedef struct clifft_cost {
                                collapse together, Appendix B.2 applied to both) */
   double vector_bytes_fused_batch; /* the group tiers of the batched launch, which collapse one
                                measurement at a time */
+  double paired_measurements; /* measurements that start a paired collapse on the group tiers at
+                               this precision (0: the launch takes the instantiation without
+                               the pair code) */
 } clifft_cost;
 clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clifft_cost* out);
 

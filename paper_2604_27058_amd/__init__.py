@@ -33,7 +33,8 @@ class clifft_info(ctypes.Structure):
 class clifft_cost(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "int_ops", "flops", "vector_bytes", "record_bytes", "expected_faults", "instructions",
-        "int_ops_bitsliced", "vector_bytes_fused", "vector_bytes_fused_group", "vector_bytes_fused_batch")]
+        "int_ops_bitsliced", "vector_bytes_fused", "vector_bytes_fused_group", "vector_bytes_fused_batch",
+        "paired_measurements")]
 
 
 class clifft_compile_opts(ctypes.Structure):

@@ -779,6 +779,7 @@ clifft_status clifft_cost_model(const clifft_program* p, int32_t precision, clif
   out->vector_bytes_fused = c.vector_bytes_fused;
   out->vector_bytes_fused_group = c.vector_bytes_fused_group;
   out->vector_bytes_fused_batch = c.vector_bytes_fused_batch;
+  out->paired_measurements = c.pair_starts;
   return CLIFFT_OK;
 }
 

@@ -282,3 +282,25 @@ def test_pair_orders_are_permutations(name):
                     img = sorted(_enum(o, q) for q in range(1 << n))
                     assert img == list(range(1 << n))
     assert kinds, "no paired passes"
+
+
+def test_pairs_follow_the_precision_rule():
+    """Paired collapses (Appendix B.2 on two measurements): FP64 pairs every
+    eligible measurement; FP32 only on vectors of 2^17 amplitudes or more
+    whose moved slots lie above the line bits, so of these workloads only
+    k = 20 pairs in FP32.  The group byte model counts the pairs it prices."""
+    k20 = pk.Program(circuits.workload("large_active_k20")["texts"][0])
+    b3 = pk.Program(circuits.workload("batched64")["texts"][3])
+    d5 = pk.Program(circuits.workload("surface_d5_r5_t10")["texts"][0])
+    assert k20.cost_model("f32")["paired_measurements"] > 0
+    assert k20.cost_model("f64")["paired_measurements"] >= k20.cost_model("f32")["paired_measurements"]
+    assert b3.k_max == 16 and b3.cost_model("f32")["paired_measurements"] == 0
+    assert b3.cost_model("f64")["paired_measurements"] > 0
+    assert d5.cost_model("f32")["paired_measurements"] == 0
+    for p in (k20, b3, d5):
+        for prec in ("f32", "f64"):
+            c = p.cost_model(prec)
+            if c["paired_measurements"] == 0:
+                assert c["vector_bytes_fused_group"] == c["vector_bytes_fused_batch"]
+            else:
+                assert c["vector_bytes_fused_group"] < c["vector_bytes_fused_batch"]
