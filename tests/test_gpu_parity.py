@@ -314,10 +314,12 @@ def measurement_burst_circuit(rng, n):
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-5)])
 @pytest.mark.parametrize("tier", [(64, 1), (256, 1), (1, 1)], ids=["wave-hbm", "group-hbm", "lane-hbm"])
 def test_forced_measurement_chains(case, precision, tol, tier):
-    """Chains of 5..7 active measurements (k from 6..8 down to 1): on the
-    wave and group HBM tiers consecutive measurements are sampled from joint
-    branch sums and collapse in one pass; every forced outcome's probability
-    and the final vector against the oracle, as on the lane tier."""
+    """Chains of 5..7 active measurements (k from 6..8 down to 1): in FP64 on
+    the wave and group HBM tiers consecutive measurements are sampled from
+    joint branch sums and collapse in one pass (FP32 pairs only vectors of
+    2^17 amplitudes or more, so here it checks the single collapses of the
+    same kernels); every forced outcome's probability and the final vector
+    against the oracle, as on the lane tier."""
     rng = np.random.default_rng(1500 + case)
     n = int(rng.integers(6, 9))
     _forced_check(measurement_burst_circuit(rng, n), case, precision, tol, tier, rng)
