@@ -355,8 +355,9 @@ def test_forced_deferred_measurement_chains(case, precision, tol, tier):
 
 @pytest.mark.parametrize("G,hbm", [(64, 1), (256, 1)])
 def test_measurement_chains_fp64_records(G, hbm):
-    """Both kinds of chain sampled freely: FP64 records equal the oracle's."""
-    for case in range(8):
+    """Both kinds of chain sampled freely (24 circuits each): FP64 records
+    equal the oracle's."""
+    for case in range(24):
         for gen, base in ((measurement_burst_circuit, 1500), (deferred_chain_circuit, 1700)):
             rng = np.random.default_rng(base + case)
             text = gen(rng, int(rng.integers(6, 9)) if base == 1500 else int(rng.integers(5, 9)))
