@@ -304,3 +304,18 @@ def test_pairs_follow_the_precision_rule():
                 assert c["vector_bytes_fused_group"] == c["vector_bytes_fused_batch"]
             else:
                 assert c["vector_bytes_fused_group"] < c["vector_bytes_fused_batch"]
+
+
+@pytest.mark.parametrize("name", ["large_active_k20", "surface_d5_r5_t10", "batched64"])
+def test_pair_orders_agree_with_the_byte_model(name):
+    """The compiler's two walks over the kernels' pairing decisions (the
+    item orders and the byte model) agree in FP64, where every eligible
+    measurement pairs: one second-measurement pass (kinds 3-5) per pair
+    start, and a first measurement's read pass (kind 1) only where no joint
+    sums were carried to it (so never more read passes than pairs)."""
+    for text in circuits.workload(name)["texts"][:24]:
+        p = pk.Program(text)
+        kinds = [e["kind"] for e in p.pair_orders()]
+        starts = p.cost_model("f64")["paired_measurements"]
+        assert sum(k in (3, 4, 5) for k in kinds) == starts
+        assert kinds.count(1) <= starts
