@@ -423,7 +423,7 @@ def main():
                     help="run one plain device copy of this many bytes first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (shards would run "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (shards would run "
               "independent shot ranges keyed by the global shot index); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
